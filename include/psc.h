@@ -1,0 +1,190 @@
+/*
+ * psc.h -- C ABI of libpsc, an MI355X (gfx950) engine for the lattice walk of
+ * pSpatiocyte (Miyauchi, Iwamoto, Arjunan, Takahashi: "pSpatiocyte: A
+ * Parallel Stochastic Method for Particle Reaction-Diffusion Systems").
+ *
+ * Model (paper section in brackets):
+ *   - space is a hexagonal close-packed lattice of voxels of radius r, held
+ *     in twisted Cartesian coordinates (i, j, k); each voxel holds at most one
+ *     molecule and has 12 neighbours at distance 2r          [2.1, Fig. 3]
+ *   - every species s with D_s > 0 has diffusion events every
+ *     tau_s = 2 r^2 / (3 D_s); in an event each of its molecules picks one of
+ *     its 12 neighbours at random and hops there only if it is vacant  [2.3]
+ *   - a hop onto a molecule of a registered partner species fires the
+ *     second-order reaction with p = k / (6 sqrt2 (DA + DB) r)    [2.4.2]
+ *   - first-order reactions are applied once per diffusion event over the
+ *     time elapsed since the previous event                      [2.2, 2.4.1]
+ *
+ * Conventions shared by every entry point:
+ *   - Functions return psc_status: 0 on success, a negative code on error.
+ *     Nothing is thrown or aborted across the ABI.  After an error other than
+ *     PSC_EDEVICE the handle is unchanged; after PSC_EDEVICE it is poisoned
+ *     (every later call but psc_destroy / psc_last_error returns
+ *     PSC_EDEVICE).  psc_last_error(h) describes the last error on h.
+ *   - Pointers in psc_state_view are HOST pointers.  They are borrowed for the
+ *     duration of the call only.
+ *   - Streams are hipStream_t passed as void*; NULL means the default stream.
+ *   - One handle must not be used from two threads at once; distinct handles
+ *     are independent.
+ *   - Lattice dimensions must each be >= 4 and a multiple of 4 (the paper
+ *     requires even counts, 2.1; multiples of 4 make the 16-colour stage
+ *     schedule conflict-free on the periodic lattice).  ni*nj*nk <= 2^32.
+ *   - Boundaries are periodic.
+ */
+#ifndef PSC_H
+#define PSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t psc_status;
+#define PSC_OK 0
+#define PSC_EINVAL (-1)     /* bad argument */
+#define PSC_ESTATE (-2)     /* call not allowed in the handle's state */
+#define PSC_ENOMEM (-3)     /* device or host allocation failed */
+#define PSC_ECAPACITY (-4)  /* molecule capacity / vacant voxels exhausted */
+#define PSC_EDEVICE (-5)    /* HIP error or device-side failure; poisoned */
+
+/* species id 0 is the vacant voxel; registered species are 1, 2, ... */
+#define PSC_MAX_SPECIES 63
+#define PSC_MAX_REACTIONS 255
+#define PSC_MAX_PRODUCTS 11
+
+/* lattice flags */
+#define PSC_TRACK_DISPLACEMENT 1u /* keep unwrapped per-molecule displacement */
+
+/* Device memory allocator hooks.  alloc returns a device pointer of at least
+ * `bytes` bytes usable on `stream` (or NULL on failure); free releases it.
+ * When both are NULL the library uses hipMalloc / hipFree. */
+typedef void *(*psc_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*psc_free_fn)(void *ptr, void *user);
+
+typedef struct psc_lattice psc_lattice;
+
+typedef struct psc_lattice_desc {
+  uint32_t ni, nj, nk;     /* voxels along the straight axis i and the two
+                              zigzag axes j, k (2.1) */
+  double voxel_radius;     /* r, metres, > 0 */
+  uint64_t seed;           /* key of every random draw of this lattice */
+  uint64_t max_molecules;  /* capacity: live molecules at any time */
+  uint32_t flags;          /* PSC_TRACK_DISPLACEMENT */
+  int32_t device;          /* HIP device ordinal */
+  psc_alloc_fn alloc;      /* optional allocator hooks (both or neither) */
+  psc_free_fn free;
+  void *alloc_user;
+} psc_lattice_desc;
+
+typedef struct psc_counters {
+  uint64_t attempts;           /* hop attempts (one per participating
+                                  molecule per diffusion event) */
+  uint64_t hops;               /* attempts that moved */
+  uint64_t collisions;         /* attempts whose target voxel was occupied */
+  uint64_t placement_failures; /* first-order reactions that found too few
+                                  vacant neighbours for their products */
+} psc_counters;
+
+/* A full lattice state.  For psc_load_state every array holds n_molecules
+ * entries (dx, dy, dz may be NULL = zero); ids strictly ascending, each below
+ * next_id; occupancy[voxel[q]] == species[q]; every other voxel 0.
+ * For psc_read_state the caller provides arrays of capacity n_molecules (set
+ * n_molecules to that capacity; any array pointer may be NULL to skip it) and
+ * the call sets n_molecules to the number of live molecules; molecules are
+ * returned in ascending id. */
+typedef struct psc_state_view {
+  uint16_t *occupancy;       /* [ni*nj*nk], v = i + ni*(j + nj*k) */
+  uint64_t n_molecules;
+  uint32_t *id;
+  uint32_t *voxel;
+  uint16_t *species;
+  int32_t *dx, *dy, *dz;     /* unwrapped displacement: dx in r, dy in r/sqrt3,
+                                dz in 2 sqrt(2/3) r */
+  uint64_t event;            /* diffusion events completed */
+  uint32_t next_id;          /* id the next newborn molecule will take */
+  double time;               /* read: simulated time of the last event, s */
+  psc_counters counters;     /* read: cumulative counters */
+  uint64_t *reactions_fired; /* read: [n_reactions] or NULL */
+} psc_state_view;
+
+/* ---- lattice life cycle --------------------------------------------------- */
+
+/* Creates a lattice with no species.  EINVAL on bad dimensions, radius or
+ * capacity; ENOMEM if the occupancy lattice cannot be allocated. */
+psc_status psc_create_lattice(const psc_lattice_desc *desc, psc_lattice **out);
+
+/* Frees every device and host resource of h (NULL is ignored).  Pending work
+ * on the lattice's streams is waited for first. */
+void psc_destroy(psc_lattice *h);
+
+/* Message for the last error on h; for h == NULL, the last psc_create_lattice
+ * failure of this thread.  The string lives until the next call on h. */
+const char *psc_last_error(const psc_lattice *h);
+
+/* ---- model (2.3, 2.4) ----------------------------------------------------- */
+
+/* Registers a species with diffusion coefficient D (m^2/s).  D == 0 makes it
+ * immobile (an obstacle unless it reacts).  EINVAL if D < 0 or not finite or
+ * more than PSC_MAX_SPECIES species; ESTATE after the first psc_step. */
+psc_status psc_add_species(psc_lattice *h, const char *name, double D,
+                           uint16_t *out_id);
+
+/* Registers a reaction.  n_r == 1: first-order, k in 1/s, 0..PSC_MAX_PRODUCTS
+ * products: the first stays in the reactant's voxel (keeping its id), the
+ * others go to distinct vacant neighbours (new ids), and the reaction fails
+ * with no change if too few are vacant (2.4.1).  n_r == 2: second-order,
+ * k in m^3/s, 1 or 2 products: on collision the first product takes the
+ * partner's voxel and id, the second the mover's voxel and id (with one
+ * product the mover's voxel is vacated) (2.4.2).  EINVAL for a second pair
+ * on the same unordered reactant pair, two immobile reactants, unknown
+ * species, or k < 0; ESTATE after the first psc_step. */
+psc_status psc_add_reaction(psc_lattice *h, const uint16_t *reactants,
+                            uint32_t n_r, const uint16_t *products, uint32_t n_p,
+                            double k, uint32_t *out_id);
+
+/* ---- initial state -------------------------------------------------------- */
+
+/* Places `count` molecules of `species` at uniformly random vacant voxels
+ * (the paper's homogeneous start, 3.4).  The c-th call draws candidate voxel
+ * floor(r * nv / 2^32) for attempt a from Philox(seed; c, a, 3, 0) word 0 and
+ * keeps it if vacant; new molecules take ids next_id, next_id + 1, ...
+ * ECAPACITY if there are too few vacant voxels or capacity; ESTATE after the
+ * first psc_step. */
+psc_status psc_place_uniform(psc_lattice *h, uint16_t species, uint64_t count);
+
+/* Replaces the whole state with a copy of `state` (see psc_state_view).
+ * EINVAL if it is inconsistent; ECAPACITY if it exceeds max_molecules;
+ * ESTATE after the first psc_step. */
+psc_status psc_load_state(psc_lattice *h, const psc_state_view *state);
+
+/* ---- running ---------------------------------------------------------------- */
+
+/* Runs n_events diffusion events, asynchronously on `stream`.  The first
+ * call freezes the model: probabilities become 32-bit integer thresholds
+ * (computed in FP64 on the host) and the state moves to the device.
+ * Device-side failures (capacity overflow) surface at the next
+ * psc_read_state or psc_sync as ECAPACITY / EDEVICE. */
+psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream);
+
+/* Waits for the lattice's pending work; reports device-side failures. */
+psc_status psc_sync(psc_lattice *h);
+
+/* Copies the current state to host arrays (see psc_state_view) and waits.
+ * ECAPACITY if the caller's arrays are too small (n_molecules is then set to
+ * the required count and nothing else is written). */
+psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream);
+
+/* Sizes needed to read the state. */
+psc_status psc_query_sizes(const psc_lattice *h, uint64_t *n_voxels,
+                           uint64_t *n_molecules, uint32_t *n_species,
+                           uint32_t *n_reactions);
+
+/* Device bytes held by the lattice (for admission control). */
+psc_status psc_device_bytes(const psc_lattice *h, uint64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,259 @@
+// psc_core.h -- definitions shared by the host core and the gfx950 kernels of
+// libpsc: the device-side lattice record, the counter-based generator, the HCP
+// stencil in twisted Cartesian coordinates and division by invariant integers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psc {
+
+// ---- occupancy words -------------------------------------------------------
+// uint16 per voxel: species id (0 = vacant) in the low 15 bits.  Bit 15 marks
+// a voxel whose molecule took part, as the partner, in a collision reaction
+// during the current walk: that molecule does not walk again in this event.
+// The flag is cleared before the walk ends.
+constexpr uint16_t kSpeciesMask = 0x7FFF;
+constexpr uint16_t kReactedFlag = 0x8000;
+
+constexpr uint32_t kDeadId = 0xFFFFFFFFu;   // entry of a molecule that died
+constexpr int kColours = 16;
+constexpr int kMaxSpecies = 63;
+constexpr int kMaxProducts = 11;
+
+// Philox counter phase word
+constexpr uint32_t kPhaseWalk = 0, kPhaseFirst = 1, kPhaseStage = 2, kPhasePlace = 3;
+
+// device error bits
+constexpr uint32_t kErrBinOverflow = 1u, kErrCandOverflow = 2u, kErrFlagOverflow = 4u,
+                   kErrBirthOverflow = 8u, kErrTape = 16u, kErrIds = 32u,
+                   kErrCapacity = 64u;
+
+// species flags
+constexpr uint8_t kSpMobile = 1, kSpFirstOrder = 2;
+
+// ---- Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ---------------------
+// Counter (c0, c1, c2, c3) = (event, molecule id, phase, block), key = seed.
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__host__ __device__ inline uint32_t mulhi32(uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umulhi(a, b);
+#else
+  return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
+#endif
+}
+
+__host__ __device__ inline U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = mulhi32(M0, c0), lo0 = M0 * c0;
+    const uint32_t hi1 = mulhi32(M1, c2), lo1 = M1 * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// floor(r * m / 2^32): a uniform integer in [0, m) from one 32-bit word
+__host__ __device__ inline uint32_t scale32(uint32_t r, uint32_t m) {
+  return (uint32_t)(((uint64_t)r * (uint64_t)m) >> 32);
+}
+
+// ---- division by an invariant 32-bit divisor ------------------------------
+// Granlund & Montgomery, "Division by invariant integers using
+// multiplication" (PLDI 1994), unsigned case: with l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1, q = (t + ((n - t) >> s1)) >> s2 where
+// t = mulhi(m, n), s1 = min(l, 1), s2 = max(l - 1, 0); exact for all n < 2^32.
+struct DivU32 {
+  uint32_t d, m, s1, s2;
+};
+
+inline DivU32 make_div(uint32_t d) {
+  uint32_t l = 0;
+  while (l < 32 && (1ull << l) < d) ++l;
+  DivU32 q;
+  q.d = d;
+  q.m = (uint32_t)((((1ull << l) - d) << 32) / d + 1ull);
+  q.s1 = l < 1 ? l : 1;
+  q.s2 = l > 0 ? l - 1 : 0;
+  return q;
+}
+
+__host__ __device__ inline uint32_t divu(uint32_t n, const DivU32 &q) {
+  const uint32_t t = mulhi32(q.m, n);
+  return (t + ((n - t) >> q.s1)) >> q.s2;
+}
+
+// ---- geometry -----------------------------------------------------------------
+// Voxel (i, j, k), v = i + ni (j + nj k); s = (j + k) & 1, p = k & 1.  The 12
+// neighbours n = 0..11 as (di, dj, dk):
+//   0:(+1,0,0) 1:(-1,0,0) 2:(s,+1,0) 3:(s-1,+1,0) 4:(s,-1,0) 5:(s-1,-1,0)
+//   6:(s,0,+1) 7:(s-1,0,+1) 8:(0,2p-1,+1) 9:(s,0,-1) 10:(s-1,0,-1)
+//   11:(0,2p-1,-1)
+// and the hop vector (X in r, Y in r/sqrt3, Z in 2 sqrt(2/3) r):
+//   X = 2,-2,1,-1,1,-1,1,-1,0,1,-1,0   Z = 0,0,0,0,0,0,1,1,1,-1,-1,-1
+//   Y = 0,0,3,3,-3,-3,c,c,d,c,c,d  with c = 1-2p, d = 4p-2.
+// Tables are bit-packed so that lanes taking different directions do not
+// diverge.
+struct Geo {
+  uint32_t ni, nj, nk;
+  DivU32 dni, dnj;
+};
+
+struct Coord {
+  int32_t i, j, k;
+};
+
+__host__ __device__ inline Coord coord_of(const Geo &g, uint32_t v) {
+  const uint32_t a = divu(v, g.dni);
+  const uint32_t k = divu(a, g.dnj);
+  Coord c;
+  c.i = (int32_t)(v - a * g.ni);
+  c.j = (int32_t)(a - k * g.nj);
+  c.k = (int32_t)k;
+  return c;
+}
+
+__host__ __device__ inline uint32_t colour_of(const Coord &c) {
+  return 8u * (uint32_t)(c.k & 1) + 4u * (uint32_t)(c.j & 1) +
+         (uint32_t)((c.i + 3 * c.j + c.k) & 3);
+}
+
+__host__ __device__ inline uint32_t index_of(const Geo &g, const Coord &c) {
+  return (uint32_t)c.i + g.ni * ((uint32_t)c.j + g.nj * (uint32_t)c.k);
+}
+
+// target coordinate of hop n from c (periodic)
+__host__ __device__ inline Coord step_coord(const Geo &g, const Coord &c, uint32_t n) {
+  const int32_t s = (c.j + c.k) & 1, p = c.k & 1;
+  // rows 2..7, 9, 10 have di = s (even rows of each pair) or s - 1 (rows
+  // 3, 5, 7, 10); rows 0, 1 have di = +1, -1; rows 8, 11 have di = 0
+  constexpr uint32_t kUsesS = 0x6FCu, kMinusOne = 0x4A8u;
+  int32_t di;
+  if ((kUsesS >> n) & 1u)
+    di = s - (int32_t)((kMinusOne >> n) & 1u);
+  else
+    di = (n == 0) ? 1 : (n == 1 ? -1 : 0);
+  int32_t dj = 0;
+  if (n == 2 || n == 3) dj = 1;
+  else if (n == 4 || n == 5) dj = -1;
+  else if (n == 8 || n == 11) dj = 2 * p - 1;
+  const int32_t dk = (n >= 6 && n <= 8) ? 1 : (n >= 9 ? -1 : 0);
+  Coord t;
+  t.i = c.i + di;
+  t.j = c.j + dj;
+  t.k = c.k + dk;
+  if (t.i < 0) t.i += (int32_t)g.ni;
+  else if (t.i >= (int32_t)g.ni) t.i -= (int32_t)g.ni;
+  if (t.j < 0) t.j += (int32_t)g.nj;
+  else if (t.j >= (int32_t)g.nj) t.j -= (int32_t)g.nj;
+  if (t.k < 0) t.k += (int32_t)g.nk;
+  else if (t.k >= (int32_t)g.nk) t.k -= (int32_t)g.nk;
+  return t;
+}
+
+__host__ __device__ inline void hop_vector(uint32_t n, int32_t p, int32_t &X, int32_t &Y,
+                                           int32_t &Z) {
+  // X + 2 packed 4 bits per row: 4,0,3,1,3,1,3,1,2,3,1,2
+  constexpr uint64_t kX = 0x213213131304ull;
+  X = (int32_t)((kX >> (4 * n)) & 0xFu) - 2;
+  const int32_t c = 1 - 2 * p, d = 4 * p - 2;
+  if (n < 2) Y = 0;
+  else if (n < 4) Y = 3;
+  else if (n < 6) Y = -3;
+  else if (n == 8 || n == 11) Y = d;
+  else Y = c;
+  Z = (n >= 6 && n <= 8) ? 1 : (n >= 9 ? -1 : 0);
+}
+
+// ---- device-side lattice record ----------------------------------------------
+// Molecules live in per-colour bins (the colour of their voxel), double
+// buffered by event parity: the walk of event e reads bins[e & 1] and appends
+// every surviving molecule to bins[(e + 1) & 1] under its new colour.  The
+// order inside a bin carries no meaning: same-colour updates commute.
+struct Bins {
+  uint32_t *vox;    // [16 * cap]
+  uint32_t *id;     // [16 * cap]
+  int32_t *disp;    // [3 * 16 * cap] (dx | dy | dz planes) or nullptr
+  uint32_t *count;  // [16]
+};
+
+struct LatDev {
+  Geo geo;
+  uint64_t nv;
+  uint32_t key0, key1;
+  uint16_t *occ;
+  uint64_t cap;        // per colour bin
+  Bins bins[2];
+
+  // first-order candidates for the next event: (colour, position, id) of
+  // molecules whose first draw can fire some first-order reaction
+  uint32_t *cand_pos[2];
+  uint32_t *cand_id[2];
+  uint8_t *cand_col[2];
+  uint32_t *cand_count;   // [2]
+  uint64_t cand_cap;
+
+  // voxels carrying the reacted flag in this walk
+  uint32_t *flag_vox;
+  uint32_t *flag_count;
+  uint64_t flag_cap;
+
+  // first-order newborns of one event: key = parent id << 4 | product index
+  uint64_t *birth_key;
+  uint32_t *birth_vox;
+  uint16_t *birth_sp;
+  uint32_t *birth_count;
+  uint64_t birth_cap;
+
+  // model
+  uint32_t n_species, n_rx, n_fo;  // n_fo: first-order slots (see fo_rx)
+  const uint8_t *sp_flags;         // [64]
+  const int16_t *pair_rx;          // [64 * 64] second-order reaction or -1
+  const uint32_t *rx_thr;          // [n_rx] fire iff r1 < thr, unless always
+  const uint8_t *rx_always;        // [n_rx]
+  const uint8_t *rx_nprod;         // [n_rx]
+  const uint16_t *rx_prod;         // [n_rx * 12]
+  const uint16_t *fo_first;        // [64] first slot of the species
+  const uint8_t *fo_n;             // [64] slots of the species
+  const uint16_t *fo_rx;           // [n_fo] reaction of each slot
+
+  // event tape (host-computed): due species mask, cumulative first-order
+  // thresholds per slot, and their maximum, for each event
+  const uint64_t *tape_due;
+  const uint32_t *tape_thr;        // [horizon * n_fo]
+  const uint32_t *tape_cmax;
+  uint64_t tape_horizon;
+
+  // event state
+  uint64_t *ev;                    // events completed
+  uint32_t *perm;                  // [16] stage order of the running event
+  uint32_t *next_id;
+  unsigned long long *cnt;         // attempts, hops, collisions, placement failures
+  unsigned long long *fired;       // [n_rx]
+  uint32_t *error;
+};
+
+// scratch of k_begin: molecules firing a first-order reaction this event
+struct FireScratch {
+  uint32_t *pos, *id;
+  uint8_t *col, *rx;
+};
+
+hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
+hipError_t launch_event(const LatDev *dL, const FireScratch &f, int grid, hipStream_t s);
+int stage_items();
+int stage_threads();
+
+}  // namespace psc

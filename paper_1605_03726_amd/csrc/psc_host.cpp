@@ -1,0 +1,902 @@
+// psc_host.cpp -- host core of libpsc: model registry, the FP64 -> uint32
+// "freeze" of every probability, the diffusion-event tape, uniform placement,
+// state upload / read-back, and the C ABI declared in include/psc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "psc.h"
+#include "psc_core.h"
+
+using namespace psc;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct SpeciesDef {
+  std::string name;
+  double D = 0.0;
+  double tau = 0.0;  // 2 r^2 / (3 D), eq. (2) of 2.3; 0 if immobile
+};
+
+struct ReactionDef {
+  uint32_t nr = 0, np = 0;
+  uint16_t r[2] = {0, 0};
+  uint16_t p[kMaxProducts] = {};
+  double k = 0.0;
+};
+
+// interval between diffusion events of a species, tau = 2 r^2 / (3 D) (2.3)
+double diffusion_interval(double rv, double D) {
+  double num = 2.0 * rv;
+  num = num * rv;
+  const double den = 3.0 * D;
+  return num / den;
+}
+
+// collision reaction probability, p = k / (6 sqrt2 (DA + DB) r) (2.4.2, eq. 6),
+// as a threshold on a uniform 32-bit word: fire iff r1 < thr, or always
+void second_order_threshold(double k, double DA, double DB, double rv, uint32_t *thr,
+                            uint8_t *always) {
+  double den = 6.0 * std::sqrt(2.0);
+  den = den * (DA + DB);
+  den = den * rv;
+  const double p = k / den;
+  if (p >= 1.0) {
+    *thr = 0xFFFFFFFFu;
+    *always = 1;
+    return;
+  }
+  *always = 0;
+  *thr = p > 0.0 ? (uint32_t)std::floor(p * 4294967296.0) : 0u;
+}
+
+// probability -> threshold on a uniform 32-bit word (capped at 2^32 - 1)
+uint32_t prob_threshold(double p) {
+  if (!(p > 0.0)) return 0u;
+  const double x = p * 4294967296.0;
+  if (x >= 4294967295.0) return 0xFFFFFFFFu;
+  return (uint32_t)std::floor(x);
+}
+
+uint64_t pow2_at_least(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+}  // namespace
+
+struct psc_lattice {
+  psc_lattice_desc desc{};
+  uint64_t nv = 0;
+  Geo geo{};
+  std::vector<SpeciesDef> species{1};  // index 0 = vacant
+  std::vector<ReactionDef> rx;
+  bool frozen = false;
+  bool poisoned = false;
+  std::string err;
+
+  // state before the freeze (host)
+  std::vector<uint16_t> occ;
+  std::vector<uint32_t> mid, mvox;
+  std::vector<int32_t> mdx, mdy, mdz;
+  uint32_t next_id = 0;
+  uint64_t event0 = 0;
+  uint64_t place_calls = 0;
+
+  // static molecules: immobile species that react with nothing never change,
+  // so they stay out of the walk's bins
+  std::vector<uint32_t> st_id, st_vox;
+
+  // event tape (absolute event index)
+  std::vector<uint64_t> n_walks;
+  uint64_t tape_end = 0;
+  double t_prev = 0.0;
+  std::vector<double> tape_time;
+  std::vector<uint64_t> tape_due;
+  std::vector<uint32_t> tape_thr, tape_cmax;
+  uint64_t events_done = 0;  // events enqueued on the device
+
+  // first-order slots: for each species, its first-order reactions in
+  // registration order
+  std::vector<uint16_t> fo_first, fo_rx;
+  std::vector<uint8_t> fo_n;
+  uint32_t n_fo = 0;
+
+  // device
+  struct Block {
+    void *p;
+    size_t bytes;
+  };
+  std::vector<Block> blocks;
+  uint64_t device_bytes = 0;
+  LatDev L{};
+  LatDev *dL = nullptr;
+  FireScratch fire{};
+  uint64_t *d_tape_due = nullptr;
+  uint32_t *d_tape_thr = nullptr, *d_tape_cmax = nullptr;
+  uint64_t d_tape_rows = 0;
+  int grid = 1;
+  hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+psc_status fail(psc_lattice *h, psc_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  h->err = buf;
+  if (code == PSC_EDEVICE) h->poisoned = true;
+  return code;
+}
+
+#define HIP_OK(h, call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail((h), PSC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+void *dev_alloc(psc_lattice *h, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  bytes = (bytes + 255) & ~size_t(255);
+  void *p = nullptr;
+  if (h->desc.alloc) {
+    p = h->desc.alloc(bytes, nullptr, h->desc.alloc_user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) {
+    h->blocks.push_back({p, bytes});
+    h->device_bytes += bytes;
+  }
+  return p;
+}
+
+void dev_free_all(psc_lattice *h) {
+  for (auto &b : h->blocks) {
+    if (h->desc.free) h->desc.free(b.p, h->desc.alloc_user);
+    else (void)hipFree(b.p);
+  }
+  h->blocks.clear();
+  h->device_bytes = 0;
+}
+
+bool mobile(const psc_lattice *h, uint16_t s) { return h->species[s].D > 0.0; }
+
+// ---- the event tape ---------------------------------------------------------
+// Next event time t_e = min over mobile species of (n_s + 1) tau_s, computed
+// by multiplication (no accumulated drift); due species are those attaining
+// it (2.2).  For each first-order species, the chance that one molecule reacts
+// during dt_e = t_e - t_{e-1} is q = 1 - exp(-K dt) (K = sum of its rate
+// constants, eq. 4 with the propensity of one molecule), shared among its
+// reactions in proportion to k_j (eq. 5); the cumulative sums become 32-bit
+// thresholds.
+void extend_tape(psc_lattice *h, uint64_t end) {
+  const size_t S = h->species.size();
+  if (h->n_walks.size() != S) h->n_walks.assign(S, 0);
+  while (h->tape_end < end) {
+    double tmin = std::numeric_limits<double>::infinity();
+    for (size_t s = 1; s < S; ++s) {
+      if (!mobile(h, (uint16_t)s)) continue;
+      const double ts = (double)(h->n_walks[s] + 1) * h->species[s].tau;
+      if (ts < tmin) tmin = ts;
+    }
+    uint64_t due = 0;
+    for (size_t s = 1; s < S; ++s) {
+      if (!mobile(h, (uint16_t)s)) continue;
+      if ((double)(h->n_walks[s] + 1) * h->species[s].tau == tmin) due |= 1ull << s;
+    }
+    const double dt = tmin - h->t_prev;
+    uint32_t cmax = 0;
+    for (size_t s = 1; s < S; ++s) {
+      const uint32_t n = h->fo_n[s];
+      if (!n) continue;
+      double K = 0.0;
+      for (uint32_t a = 0; a < n; ++a) K += h->rx[h->fo_rx[h->fo_first[s] + a]].k;
+      const double q = -std::expm1(-K * dt);
+      double acc = 0.0;
+      uint32_t C = 0;
+      for (uint32_t a = 0; a < n; ++a) {
+        const double kj = h->rx[h->fo_rx[h->fo_first[s] + a]].k;
+        acc = acc + q * kj / K;
+        C = prob_threshold(acc);
+        h->tape_thr.push_back(C);
+      }
+      cmax = std::max(cmax, C);
+    }
+    h->tape_due.push_back(due);
+    h->tape_cmax.push_back(cmax);
+    h->tape_time.push_back(tmin);
+    for (size_t s = 1; s < S; ++s)
+      if ((due >> s) & 1ull) h->n_walks[s]++;
+    h->t_prev = tmin;
+    h->tape_end++;
+  }
+}
+
+// time of the last of the first e events (the clock alone, before the freeze)
+double clock_time(const psc_lattice *h, uint64_t e) {
+  const size_t S = h->species.size();
+  std::vector<uint64_t> nw(S, 0);
+  double t = 0.0;
+  for (uint64_t z = 0; z < e; ++z) {
+    double tmin = std::numeric_limits<double>::infinity();
+    for (size_t s = 1; s < S; ++s)
+      if (mobile(h, (uint16_t)s)) tmin = std::min(tmin, (double)(nw[s] + 1) * h->species[s].tau);
+    if (tmin == std::numeric_limits<double>::infinity()) return 0.0;
+    for (size_t s = 1; s < S; ++s)
+      if (mobile(h, (uint16_t)s) && (double)(nw[s] + 1) * h->species[s].tau == tmin) nw[s]++;
+    t = tmin;
+  }
+  return t;
+}
+
+// uploads tape rows [0, tape_end) when the device copy is too short
+psc_status sync_tape(psc_lattice *h, hipStream_t stream) {
+  if (h->d_tape_rows >= h->tape_end) return PSC_OK;
+  HIP_OK(h, hipStreamSynchronize(stream));
+  const uint64_t rows = h->tape_end;
+  auto *due = (uint64_t *)dev_alloc(h, rows * sizeof(uint64_t));
+  auto *thr = (uint32_t *)dev_alloc(h, std::max<uint64_t>(1, rows * h->n_fo) * sizeof(uint32_t));
+  auto *cmax = (uint32_t *)dev_alloc(h, rows * sizeof(uint32_t));
+  if (!due || !thr || !cmax) return fail(h, PSC_ENOMEM, "tape allocation failed");
+  HIP_OK(h, hipMemcpy(due, h->tape_due.data(), rows * sizeof(uint64_t), hipMemcpyHostToDevice));
+  if (h->n_fo)
+    HIP_OK(h, hipMemcpy(thr, h->tape_thr.data(), rows * h->n_fo * sizeof(uint32_t),
+                        hipMemcpyHostToDevice));
+  HIP_OK(h, hipMemcpy(cmax, h->tape_cmax.data(), rows * sizeof(uint32_t), hipMemcpyHostToDevice));
+  // the previous tape stays allocated until destroy (it is small and may
+  // still be referenced by work captured earlier)
+  h->d_tape_due = due;
+  h->d_tape_thr = thr;
+  h->d_tape_cmax = cmax;
+  h->d_tape_rows = rows;
+  h->L.tape_due = due;
+  h->L.tape_thr = thr;
+  h->L.tape_cmax = cmax;
+  h->L.tape_horizon = rows;
+  HIP_OK(h, hipMemcpy(h->dL, &h->L, sizeof(LatDev), hipMemcpyHostToDevice));
+  return PSC_OK;
+}
+
+template <class T>
+T *alloc_n(psc_lattice *h, uint64_t n) {
+  return (T *)dev_alloc(h, (size_t)std::max<uint64_t>(n, 1) * sizeof(T));
+}
+
+// ---- freeze: model tables, buffers, upload ---------------------------------------
+psc_status freeze(psc_lattice *h, hipStream_t stream) {
+  const size_t S = h->species.size();
+  bool any_mobile = false;
+  for (size_t s = 1; s < S; ++s) any_mobile |= mobile(h, (uint16_t)s);
+  if (!any_mobile) return fail(h, PSC_EINVAL, "no mobile species: no diffusion events");
+
+  // model tables
+  std::vector<uint8_t> sp_flags(64, 0);
+  std::vector<int16_t> pair(64 * 64, -1);
+  const uint32_t R = (uint32_t)h->rx.size();
+  std::vector<uint32_t> thr(std::max<uint32_t>(R, 1), 0);
+  std::vector<uint8_t> always(std::max<uint32_t>(R, 1), 0), nprod(std::max<uint32_t>(R, 1), 0);
+  std::vector<uint16_t> prod(std::max<uint32_t>(R, 1) * 12, 0);
+  std::vector<bool> reactant(S, false);
+  h->fo_first.assign(64, 0);
+  h->fo_n.assign(64, 0);
+  h->fo_rx.clear();
+  for (size_t s = 1; s < S; ++s) {
+    if (mobile(h, (uint16_t)s)) sp_flags[s] |= kSpMobile;
+    h->fo_first[s] = (uint16_t)h->fo_rx.size();
+    for (uint32_t r = 0; r < R; ++r)
+      if (h->rx[r].nr == 1 && h->rx[r].r[0] == s) {
+        h->fo_rx.push_back((uint16_t)r);
+        h->fo_n[s]++;
+      }
+    if (h->fo_n[s]) sp_flags[s] |= kSpFirstOrder;
+  }
+  h->n_fo = (uint32_t)h->fo_rx.size();
+  for (uint32_t r = 0; r < R; ++r) {
+    const ReactionDef &d = h->rx[r];
+    nprod[r] = (uint8_t)d.np;
+    for (uint32_t a = 0; a < d.np; ++a) prod[r * 12 + a] = d.p[a];
+    for (uint32_t a = 0; a < d.nr; ++a) reactant[d.r[a]] = true;
+    if (d.nr == 2) {
+      const uint16_t A = d.r[0], B = d.r[1];
+      pair[A * 64 + B] = pair[B * 64 + A] = (int16_t)r;
+      second_order_threshold(d.k, h->species[A].D, h->species[B].D, h->desc.voxel_radius,
+                             &thr[r], &always[r]);
+    }
+  }
+
+  // split molecules into the walk's bins and the static list
+  h->st_id.clear();
+  h->st_vox.clear();
+  const uint64_t nmol = h->mid.size();
+  std::vector<uint8_t> colour(nmol);
+  uint64_t bin_count[16] = {0};
+  std::vector<uint64_t> walkers;
+  walkers.reserve(nmol);
+  for (uint64_t q = 0; q < nmol; ++q) {
+    const uint16_t s = h->occ[h->mvox[q]];
+    if (!mobile(h, s) && !reactant[s]) {
+      h->st_id.push_back(h->mid[q]);
+      h->st_vox.push_back(h->mvox[q]);
+      continue;
+    }
+    colour[q] = (uint8_t)colour_of(coord_of(h->geo, h->mvox[q]));
+    bin_count[colour[q]]++;
+    walkers.push_back(q);
+  }
+
+  // buffers
+  const uint64_t cap = std::max<uint64_t>(h->desc.max_molecules, 1);
+  const bool disp = (h->desc.flags & PSC_TRACK_DISPLACEMENT) != 0;
+  LatDev &L = h->L;
+  L.geo = h->geo;
+  L.nv = h->nv;
+  L.key0 = (uint32_t)h->desc.seed;
+  L.key1 = (uint32_t)(h->desc.seed >> 32);
+  L.occ = alloc_n<uint16_t>(h, h->nv);
+  L.cap = cap;
+  for (int b = 0; b < 2; ++b) {
+    L.bins[b].vox = alloc_n<uint32_t>(h, 16 * cap);
+    L.bins[b].id = alloc_n<uint32_t>(h, 16 * cap);
+    L.bins[b].disp = disp ? alloc_n<int32_t>(h, 3 * 16 * cap) : nullptr;
+    L.bins[b].count = alloc_n<uint32_t>(h, 16);
+    L.cand_pos[b] = alloc_n<uint32_t>(h, cap);
+    L.cand_id[b] = alloc_n<uint32_t>(h, cap);
+    L.cand_col[b] = alloc_n<uint8_t>(h, cap);
+    if (!L.bins[b].vox || !L.bins[b].id || (disp && !L.bins[b].disp) || !L.bins[b].count ||
+        !L.cand_pos[b] || !L.cand_id[b] || !L.cand_col[b])
+      return fail(h, PSC_ENOMEM, "device allocation of molecule bins failed");
+  }
+  L.cand_count = alloc_n<uint32_t>(h, 2);
+  L.cand_cap = cap;
+  L.flag_vox = alloc_n<uint32_t>(h, cap);
+  L.flag_count = alloc_n<uint32_t>(h, 1);
+  L.flag_cap = cap;
+  L.birth_cap = std::min<uint64_t>(pow2_at_least(cap), 1ull << 27);
+  L.birth_key = alloc_n<uint64_t>(h, L.birth_cap);
+  L.birth_vox = alloc_n<uint32_t>(h, L.birth_cap);
+  L.birth_sp = alloc_n<uint16_t>(h, L.birth_cap);
+  L.birth_count = alloc_n<uint32_t>(h, 1);
+  h->fire.pos = alloc_n<uint32_t>(h, cap);
+  h->fire.id = alloc_n<uint32_t>(h, cap);
+  h->fire.col = alloc_n<uint8_t>(h, cap);
+  h->fire.rx = alloc_n<uint8_t>(h, cap);
+  L.n_species = (uint32_t)(S - 1);
+  L.n_rx = R;
+  L.n_fo = h->n_fo;
+  auto *d_flags = alloc_n<uint8_t>(h, 64);
+  auto *d_pair = alloc_n<int16_t>(h, 64 * 64);
+  auto *d_thr = alloc_n<uint32_t>(h, thr.size());
+  auto *d_always = alloc_n<uint8_t>(h, always.size());
+  auto *d_nprod = alloc_n<uint8_t>(h, nprod.size());
+  auto *d_prod = alloc_n<uint16_t>(h, prod.size());
+  auto *d_fo_first = alloc_n<uint16_t>(h, 64);
+  auto *d_fo_n = alloc_n<uint8_t>(h, 64);
+  auto *d_fo_rx = alloc_n<uint16_t>(h, std::max<size_t>(h->fo_rx.size(), 1));
+  L.ev = alloc_n<uint64_t>(h, 1);
+  L.perm = alloc_n<uint32_t>(h, 16);
+  L.next_id = alloc_n<uint32_t>(h, 1);
+  L.cnt = alloc_n<unsigned long long>(h, 4);
+  L.fired = alloc_n<unsigned long long>(h, std::max<uint32_t>(R, 1));
+  L.error = alloc_n<uint32_t>(h, 1);
+  h->dL = alloc_n<LatDev>(h, 1);
+  if (!L.occ || !L.cand_count || !L.flag_vox || !L.flag_count || !L.birth_key || !L.birth_vox ||
+      !L.birth_sp || !L.birth_count || !h->fire.pos || !h->fire.id || !h->fire.col ||
+      !h->fire.rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod ||
+      !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.next_id || !L.cnt ||
+      !L.fired || !L.error || !h->dL)
+    return fail(h, PSC_ENOMEM, "device allocation failed");
+  L.sp_flags = d_flags;
+  L.pair_rx = d_pair;
+  L.rx_thr = d_thr;
+  L.rx_always = d_always;
+  L.rx_nprod = d_nprod;
+  L.rx_prod = d_prod;
+  L.fo_first = d_fo_first;
+  L.fo_n = d_fo_n;
+  L.fo_rx = d_fo_rx;
+
+  auto up = [&](void *dst, const void *src, size_t bytes) {
+    return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  HIP_OK(h, up(d_flags, sp_flags.data(), 64));
+  HIP_OK(h, up(d_pair, pair.data(), pair.size() * sizeof(int16_t)));
+  HIP_OK(h, up(d_thr, thr.data(), thr.size() * sizeof(uint32_t)));
+  HIP_OK(h, up(d_always, always.data(), always.size()));
+  HIP_OK(h, up(d_nprod, nprod.data(), nprod.size()));
+  HIP_OK(h, up(d_prod, prod.data(), prod.size() * sizeof(uint16_t)));
+  HIP_OK(h, up(d_fo_first, h->fo_first.data(), 64 * sizeof(uint16_t)));
+  HIP_OK(h, up(d_fo_n, h->fo_n.data(), 64));
+  if (!h->fo_rx.empty()) HIP_OK(h, up(d_fo_rx, h->fo_rx.data(), h->fo_rx.size() * sizeof(uint16_t)));
+  HIP_OK(h, up(L.occ, h->occ.data(), h->nv * sizeof(uint16_t)));
+
+  // bins of the current event parity, by colour (counting sort)
+  const int cur = (int)(h->event0 & 1);
+  {
+    std::vector<uint32_t> vox(walkers.size()), id(walkers.size());
+    std::vector<int32_t> d3(disp ? 3 * walkers.size() : 0);
+    uint64_t start[17] = {0};
+    for (int c = 0; c < 16; ++c) start[c + 1] = start[c] + bin_count[c];
+    uint64_t fill[16];
+    for (int c = 0; c < 16; ++c) fill[c] = start[c];
+    for (uint64_t q : walkers) {
+      const uint64_t at = fill[colour[q]]++;
+      vox[at] = h->mvox[q];
+      id[at] = h->mid[q];
+      if (disp) {
+        d3[3 * at + 0] = h->mdx[q];
+        d3[3 * at + 1] = h->mdy[q];
+        d3[3 * at + 2] = h->mdz[q];
+      }
+    }
+    uint32_t counts[16];
+    for (int c = 0; c < 16; ++c) {
+      if (bin_count[c] > cap) return fail(h, PSC_ECAPACITY, "more molecules than max_molecules");
+      counts[c] = (uint32_t)bin_count[c];
+      if (!bin_count[c]) continue;
+      HIP_OK(h, up(L.bins[cur].vox + c * cap, vox.data() + start[c], bin_count[c] * 4));
+      HIP_OK(h, up(L.bins[cur].id + c * cap, id.data() + start[c], bin_count[c] * 4));
+      if (disp) {
+        std::vector<int32_t> plane(bin_count[c]);
+        for (int a = 0; a < 3; ++a) {
+          for (uint64_t z = 0; z < bin_count[c]; ++z) plane[z] = d3[3 * (start[c] + z) + a];
+          HIP_OK(h, up(L.bins[cur].disp + (a * 16 + c) * cap, plane.data(), bin_count[c] * 4));
+        }
+      }
+    }
+    HIP_OK(h, up(L.bins[cur].count, counts, sizeof counts));
+    HIP_OK(h, hipMemset(L.bins[cur ^ 1].count, 0, 16 * sizeof(uint32_t)));
+  }
+  HIP_OK(h, hipMemset(L.cand_count, 0, 2 * sizeof(uint32_t)));
+  HIP_OK(h, hipMemset(L.flag_count, 0, sizeof(uint32_t)));
+  HIP_OK(h, hipMemset(L.birth_count, 0, sizeof(uint32_t)));
+  HIP_OK(h, hipMemset(L.cnt, 0, 4 * sizeof(unsigned long long)));
+  HIP_OK(h, hipMemset(L.fired, 0, std::max<uint32_t>(R, 1) * sizeof(unsigned long long)));
+  HIP_OK(h, hipMemset(L.error, 0, sizeof(uint32_t)));
+  HIP_OK(h, up(L.ev, &h->event0, sizeof(uint64_t)));
+  HIP_OK(h, up(L.next_id, &h->next_id, sizeof(uint32_t)));
+
+  // tape covering the events already done (a loaded state may start late)
+  extend_tape(h, h->event0 + 1024);
+  h->events_done = h->event0;
+  HIP_OK(h, up(h->dL, &L, sizeof(LatDev)));
+  psc_status st = sync_tape(h, stream);
+  if (st) return st;
+
+  // launch shape of the stage kernel: enough workgroups for the expected
+  // bin size, grid-striding beyond
+  const uint64_t per_block = (uint64_t)stage_threads() * stage_items();
+  const uint64_t expect = std::max<uint64_t>(cap / 16, 1);
+  h->grid = (int)std::min<uint64_t>(std::max<uint64_t>((expect + per_block - 1) / per_block, 1),
+                                    4096);
+  HIP_OK(h, launch_scan(h->dL, std::min(h->grid * 4, 4096), stream));
+  h->frozen = true;
+  // the host copy of the walkers is no longer authoritative
+  std::vector<uint16_t>().swap(h->occ);
+  std::vector<uint32_t>().swap(h->mid);
+  std::vector<uint32_t>().swap(h->mvox);
+  std::vector<int32_t>().swap(h->mdx);
+  std::vector<int32_t>().swap(h->mdy);
+  std::vector<int32_t>().swap(h->mdz);
+  return PSC_OK;
+}
+
+psc_status check_device_error(psc_lattice *h) {
+  uint32_t e = 0;
+  HIP_OK(h, hipMemcpy(&e, h->L.error, sizeof e, hipMemcpyDeviceToHost));
+  if (!e) return PSC_OK;
+  if (e & (kErrBinOverflow | kErrCandOverflow | kErrFlagOverflow | kErrBirthOverflow | kErrIds))
+    return fail(h, PSC_EDEVICE, "device capacity exceeded (error bits 0x%x); state is invalid", e);
+  return fail(h, PSC_EDEVICE, "device error bits 0x%x", e);
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+// =============================================================================
+extern "C" {
+
+psc_status psc_create_lattice(const psc_lattice_desc *desc, psc_lattice **out) {
+  if (!out) return PSC_EINVAL;
+  *out = nullptr;
+  if (!desc) {
+    g_create_error = "desc is NULL";
+    return PSC_EINVAL;
+  }
+  const uint32_t ni = desc->ni, nj = desc->nj, nk = desc->nk;
+  if (ni < 4 || nj < 4 || nk < 4 || ni % 4 || nj % 4 || nk % 4) {
+    g_create_error = "dimensions must be >= 4 and multiples of 4";
+    return PSC_EINVAL;
+  }
+  const uint64_t nv = (uint64_t)ni * nj * nk;
+  if (nv > (1ull << 32)) {
+    g_create_error = "more than 2^32 voxels";
+    return PSC_EINVAL;
+  }
+  if (!(desc->voxel_radius > 0.0) || !std::isfinite(desc->voxel_radius)) {
+    g_create_error = "voxel_radius must be positive";
+    return PSC_EINVAL;
+  }
+  if (desc->max_molecules == 0 || desc->max_molecules > nv || desc->max_molecules >= 0xFFFFFFFFull) {
+    g_create_error = "max_molecules must be in [1, voxels]";
+    return PSC_EINVAL;
+  }
+  if ((desc->alloc == nullptr) != (desc->free == nullptr)) {
+    g_create_error = "alloc and free hooks come together";
+    return PSC_EINVAL;
+  }
+  if (desc->flags & ~PSC_TRACK_DISPLACEMENT) {
+    g_create_error = "unknown flags";
+    return PSC_EINVAL;
+  }
+  if (desc->device < 0) {
+    g_create_error = "device ordinal must be >= 0";
+    return PSC_EINVAL;
+  }
+  psc_lattice *h = new (std::nothrow) psc_lattice();
+  if (!h) return PSC_ENOMEM;
+  h->desc = *desc;
+  h->nv = nv;
+  h->geo.ni = ni;
+  h->geo.nj = nj;
+  h->geo.nk = nk;
+  h->geo.dni = make_div(ni);
+  h->geo.dnj = make_div(nj);
+  try {
+    h->occ.assign(nv, 0);
+  } catch (...) {
+    delete h;
+    g_create_error = "host allocation of the lattice failed";
+    return PSC_ENOMEM;
+  }
+  *out = h;
+  return PSC_OK;
+}
+
+void psc_destroy(psc_lattice *h) {
+  if (!h) return;
+  if (h->frozen && !h->poisoned) {
+    (void)hipSetDevice(h->desc.device);
+    (void)hipDeviceSynchronize();
+  }
+  dev_free_all(h);
+  delete h;
+}
+
+const char *psc_last_error(const psc_lattice *h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+psc_status psc_add_species(psc_lattice *h, const char *name, double D, uint16_t *out_id) {
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (h->frozen) return fail(h, PSC_ESTATE, "model is frozen after the first step");
+  if (!(D >= 0.0) || !std::isfinite(D)) return fail(h, PSC_EINVAL, "D must be finite and >= 0");
+  if (h->species.size() > (size_t)PSC_MAX_SPECIES)
+    return fail(h, PSC_EINVAL, "at most %d species", PSC_MAX_SPECIES);
+  SpeciesDef s;
+  s.name = name ? name : "";
+  s.D = D;
+  s.tau = D > 0.0 ? diffusion_interval(h->desc.voxel_radius, D) : 0.0;
+  h->species.push_back(s);
+  if (out_id) *out_id = (uint16_t)(h->species.size() - 1);
+  return PSC_OK;
+}
+
+psc_status psc_add_reaction(psc_lattice *h, const uint16_t *reactants, uint32_t n_r,
+                            const uint16_t *products, uint32_t n_p, double k, uint32_t *out_id) {
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (h->frozen) return fail(h, PSC_ESTATE, "model is frozen after the first step");
+  if (h->rx.size() >= (size_t)PSC_MAX_REACTIONS)
+    return fail(h, PSC_EINVAL, "at most %d reactions", PSC_MAX_REACTIONS);
+  if (!reactants || n_r < 1 || n_r > 2) return fail(h, PSC_EINVAL, "1 or 2 reactants");
+  if (n_p && !products) return fail(h, PSC_EINVAL, "products is NULL");
+  if (!(k >= 0.0) || !std::isfinite(k)) return fail(h, PSC_EINVAL, "k must be finite and >= 0");
+  const uint16_t S = (uint16_t)(h->species.size() - 1);
+  for (uint32_t a = 0; a < n_r; ++a)
+    if (reactants[a] < 1 || reactants[a] > S) return fail(h, PSC_EINVAL, "unknown reactant");
+  for (uint32_t a = 0; a < n_p; ++a)
+    if (products[a] < 1 || products[a] > S) return fail(h, PSC_EINVAL, "unknown product");
+  if (n_r == 1 && n_p > (uint32_t)PSC_MAX_PRODUCTS)
+    return fail(h, PSC_EINVAL, "first-order reactions take 0..%d products", PSC_MAX_PRODUCTS);
+  if (n_r == 2) {
+    if (n_p < 1 || n_p > 2)
+      return fail(h, PSC_EINVAL, "second-order reactions take 1 or 2 products");
+    const uint16_t A = reactants[0], B = reactants[1];
+    if (!(h->species[A].D + h->species[B].D > 0.0))
+      return fail(h, PSC_EINVAL, "two immobile reactants never collide");
+    for (auto &r : h->rx)
+      if (r.nr == 2 && ((r.r[0] == A && r.r[1] == B) || (r.r[0] == B && r.r[1] == A)))
+        return fail(h, PSC_EINVAL, "reactant pair already has a reaction");
+  }
+  ReactionDef d;
+  d.nr = n_r;
+  d.np = n_p;
+  for (uint32_t a = 0; a < n_r; ++a) d.r[a] = reactants[a];
+  for (uint32_t a = 0; a < n_p; ++a) d.p[a] = products[a];
+  d.k = k;
+  h->rx.push_back(d);
+  if (out_id) *out_id = (uint32_t)(h->rx.size() - 1);
+  return PSC_OK;
+}
+
+psc_status psc_place_uniform(psc_lattice *h, uint16_t species, uint64_t count) {
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (h->frozen) return fail(h, PSC_ESTATE, "placement only before the first step");
+  if (species < 1 || species >= h->species.size()) return fail(h, PSC_EINVAL, "unknown species");
+  const uint64_t have = h->mid.size();
+  if (count > h->nv - have) return fail(h, PSC_ECAPACITY, "too few vacant voxels");
+  if (have + count > h->desc.max_molecules)
+    return fail(h, PSC_ECAPACITY, "placement exceeds max_molecules");
+  if ((uint64_t)h->next_id + count >= 0xFFFFFFFFull) return fail(h, PSC_ECAPACITY, "ids exhausted");
+  const uint32_t call = (uint32_t)h->place_calls;
+  const uint32_t k0 = (uint32_t)h->desc.seed, k1 = (uint32_t)(h->desc.seed >> 32);
+  uint64_t attempt = 0;
+  const bool disp = (h->desc.flags & PSC_TRACK_DISPLACEMENT) != 0;
+  (void)disp;
+  for (uint64_t q = 0; q < count; ++q) {
+    for (;;) {
+      const U4 r = philox(call, (uint32_t)attempt, kPhasePlace, 0, k0, k1);
+      ++attempt;
+      const uint32_t v = (uint32_t)(((uint64_t)r.x * h->nv) >> 32);
+      if (h->occ[v] == 0) {
+        h->occ[v] = species;
+        h->mid.push_back(h->next_id++);
+        h->mvox.push_back(v);
+        h->mdx.push_back(0);
+        h->mdy.push_back(0);
+        h->mdz.push_back(0);
+        break;
+      }
+    }
+  }
+  h->place_calls++;
+  return PSC_OK;
+}
+
+psc_status psc_load_state(psc_lattice *h, const psc_state_view *st) {
+  if (!h || !st) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (h->frozen) return fail(h, PSC_ESTATE, "load_state only before the first step");
+  if (!st->occupancy || (st->n_molecules && (!st->id || !st->voxel)))
+    return fail(h, PSC_EINVAL, "occupancy, id and voxel arrays are required");
+  if (st->n_molecules > h->desc.max_molecules)
+    return fail(h, PSC_ECAPACITY, "state exceeds max_molecules");
+  const uint16_t S = (uint16_t)(h->species.size() - 1);
+  uint64_t occupied = 0;
+  for (uint64_t v = 0; v < h->nv; ++v) {
+    if (st->occupancy[v] > S) return fail(h, PSC_EINVAL, "occupancy holds an unknown species");
+    occupied += st->occupancy[v] != 0;
+  }
+  if (occupied != st->n_molecules)
+    return fail(h, PSC_EINVAL, "occupied voxels (%llu) != molecules (%llu)",
+                (unsigned long long)occupied, (unsigned long long)st->n_molecules);
+  std::vector<uint8_t> seen(h->nv, 0);
+  for (uint64_t q = 0; q < st->n_molecules; ++q) {
+    if (q && st->id[q] <= st->id[q - 1]) return fail(h, PSC_EINVAL, "ids must ascend");
+    if (st->id[q] >= st->next_id || st->next_id == 0xFFFFFFFFu)
+      return fail(h, PSC_EINVAL, "id >= next_id");
+    if (st->voxel[q] >= h->nv || st->occupancy[st->voxel[q]] == 0)
+      return fail(h, PSC_EINVAL, "molecule on an empty voxel");
+    if (st->species && st->species[q] != st->occupancy[st->voxel[q]])
+      return fail(h, PSC_EINVAL, "species disagrees with occupancy");
+    if (seen[st->voxel[q]]++) return fail(h, PSC_EINVAL, "two molecules on one voxel");
+  }
+  h->occ.assign(st->occupancy, st->occupancy + h->nv);
+  h->mid.assign(st->id, st->id + st->n_molecules);
+  h->mvox.assign(st->voxel, st->voxel + st->n_molecules);
+  const uint64_t n = st->n_molecules;
+  h->mdx.assign(n, 0);
+  h->mdy.assign(n, 0);
+  h->mdz.assign(n, 0);
+  if (st->dx) h->mdx.assign(st->dx, st->dx + n);
+  if (st->dy) h->mdy.assign(st->dy, st->dy + n);
+  if (st->dz) h->mdz.assign(st->dz, st->dz + n);
+  h->next_id = st->next_id;
+  h->event0 = st->event;
+  return PSC_OK;
+}
+
+psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!h->frozen) {
+    // the device is first touched here: creation, the model and the initial
+    // state are host-only
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || h->desc.device >= ndev)
+      return fail(h, PSC_EINVAL, "no HIP device %d", h->desc.device);
+  }
+  HIP_OK(h, hipSetDevice(h->desc.device));
+  if (!h->frozen) {
+    psc_status st = freeze(h, stream);
+    if (st) return st;
+  }
+  if (n_events == 0) return PSC_OK;
+  const uint64_t end = h->events_done + n_events;
+  if (end >= 0xFFFFFFFFull) return fail(h, PSC_EINVAL, "event index exceeds 2^32");
+  if (end > h->tape_end) {
+    extend_tape(h, std::max(end, h->tape_end * 2));
+    psc_status st = sync_tape(h, stream);
+    if (st) return st;
+  }
+  for (uint64_t e = 0; e < n_events; ++e)
+    HIP_OK(h, launch_event(h->dL, h->fire, h->grid, stream));
+  h->events_done = end;
+  h->last_stream = stream;
+  return PSC_OK;
+}
+
+psc_status psc_sync(psc_lattice *h) {
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (!h->frozen) return PSC_OK;
+  HIP_OK(h, hipSetDevice(h->desc.device));
+  HIP_OK(h, hipDeviceSynchronize());
+  return check_device_error(h);
+}
+
+psc_status psc_query_sizes(const psc_lattice *hc, uint64_t *n_voxels, uint64_t *n_molecules,
+                           uint32_t *n_species, uint32_t *n_reactions) {
+  psc_lattice *h = const_cast<psc_lattice *>(hc);
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (n_voxels) *n_voxels = h->nv;
+  if (n_species) *n_species = (uint32_t)(h->species.size() - 1);
+  if (n_reactions) *n_reactions = (uint32_t)h->rx.size();
+  if (n_molecules) {
+    if (!h->frozen) {
+      *n_molecules = h->mid.size();
+    } else {
+      HIP_OK(h, hipSetDevice(h->desc.device));
+      HIP_OK(h, hipDeviceSynchronize());
+      uint32_t counts[16];
+      HIP_OK(h, hipMemcpy(counts, h->L.bins[h->events_done & 1].count, sizeof counts,
+                          hipMemcpyDeviceToHost));
+      uint64_t n = h->st_id.size();
+      for (int c = 0; c < 16; ++c) n += counts[c];
+      *n_molecules = n;  // upper bound: dead entries are dropped by the walk
+    }
+  }
+  return PSC_OK;
+}
+
+psc_status psc_device_bytes(const psc_lattice *h, uint64_t *bytes) {
+  if (!h || !bytes) return PSC_EINVAL;
+  *bytes = h->device_bytes;
+  return PSC_OK;
+}
+
+psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
+  if (!h || !out) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  (void)stream_;
+  const bool want_mol = out->id || out->voxel || out->species || out->dx || out->dy || out->dz;
+  if (!h->frozen) {
+    const uint64_t n = h->mid.size();
+    std::vector<uint64_t> order(n);
+    for (uint64_t q = 0; q < n; ++q) order[q] = q;
+    std::sort(order.begin(), order.end(),
+              [&](uint64_t a, uint64_t b) { return h->mid[a] < h->mid[b]; });
+    if (want_mol && out->n_molecules < n) {
+      out->n_molecules = n;
+      return fail(h, PSC_ECAPACITY, "output arrays too small");
+    }
+    if (out->occupancy) std::memcpy(out->occupancy, h->occ.data(), h->nv * sizeof(uint16_t));
+    for (uint64_t z = 0; z < n; ++z) {
+      const uint64_t q = order[z];
+      if (out->id) out->id[z] = h->mid[q];
+      if (out->voxel) out->voxel[z] = h->mvox[q];
+      if (out->species) out->species[z] = h->occ[h->mvox[q]];
+      if (out->dx) out->dx[z] = h->mdx[q];
+      if (out->dy) out->dy[z] = h->mdy[q];
+      if (out->dz) out->dz[z] = h->mdz[q];
+    }
+    out->n_molecules = n;
+    out->event = h->event0;
+    out->next_id = h->next_id;
+    out->time = clock_time(h, h->event0);
+    out->counters = psc_counters{0, 0, 0, 0};
+    if (out->reactions_fired)
+      for (size_t r = 0; r < h->rx.size(); ++r) out->reactions_fired[r] = 0;
+    return PSC_OK;
+  }
+  HIP_OK(h, hipSetDevice(h->desc.device));
+  HIP_OK(h, hipDeviceSynchronize());
+  psc_status st = check_device_error(h);
+  if (st) return st;
+  const LatDev &L = h->L;
+  const int cur = (int)(h->events_done & 1);
+  uint32_t counts[16];
+  HIP_OK(h, hipMemcpy(counts, L.bins[cur].count, sizeof counts, hipMemcpyDeviceToHost));
+  const bool disp = L.bins[cur].disp != nullptr;
+  std::vector<uint32_t> vox, id;
+  std::vector<int32_t> d3[3];
+  for (int c = 0; c < 16; ++c) {
+    const uint32_t n = counts[c];
+    if (!n) continue;
+    const size_t at = vox.size();
+    vox.resize(at + n);
+    id.resize(at + n);
+    HIP_OK(h, hipMemcpy(vox.data() + at, L.bins[cur].vox + c * L.cap, n * 4, hipMemcpyDeviceToHost));
+    HIP_OK(h, hipMemcpy(id.data() + at, L.bins[cur].id + c * L.cap, n * 4, hipMemcpyDeviceToHost));
+    if (disp)
+      for (int a = 0; a < 3; ++a) {
+        d3[a].resize(at + n);
+        HIP_OK(h, hipMemcpy(d3[a].data() + at, L.bins[cur].disp + (a * 16 + c) * L.cap, n * 4,
+                            hipMemcpyDeviceToHost));
+      }
+  }
+  // gather live walkers and static molecules, ascending id
+  std::vector<uint64_t> order;
+  order.reserve(vox.size() + h->st_id.size());
+  for (uint64_t q = 0; q < vox.size(); ++q)
+    if (id[q] != kDeadId) order.push_back(q);
+  const uint64_t nwalk = vox.size();
+  for (uint64_t q = 0; q < h->st_id.size(); ++q) order.push_back(nwalk + q);
+  auto id_of = [&](uint64_t q) { return q < nwalk ? id[q] : h->st_id[q - nwalk]; };
+  auto vox_of = [&](uint64_t q) { return q < nwalk ? vox[q] : h->st_vox[q - nwalk]; };
+  std::sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) { return id_of(a) < id_of(b); });
+  const uint64_t n = order.size();
+  if (want_mol && out->n_molecules < n) {
+    out->n_molecules = n;
+    return fail(h, PSC_ECAPACITY, "output arrays too small");
+  }
+  std::vector<uint16_t> occ;
+  uint16_t *occp = out->occupancy;
+  if (!occp && out->species) {
+    occ.resize(h->nv);
+    occp = occ.data();
+  }
+  if (occp) {
+    HIP_OK(h, hipMemcpy(occp, L.occ, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
+    for (uint64_t v = 0; v < h->nv; ++v) occp[v] &= kSpeciesMask;
+  }
+  for (uint64_t z = 0; z < n; ++z) {
+    const uint64_t q = order[z];
+    const uint32_t v = vox_of(q);
+    if (out->id) out->id[z] = id_of(q);
+    if (out->voxel) out->voxel[z] = v;
+    if (out->species) out->species[z] = occp[v];
+    const bool w = q < nwalk && disp;
+    if (out->dx) out->dx[z] = w ? d3[0][q] : 0;
+    if (out->dy) out->dy[z] = w ? d3[1][q] : 0;
+    if (out->dz) out->dz[z] = w ? d3[2][q] : 0;
+  }
+  out->n_molecules = n;
+  out->event = h->events_done;
+  HIP_OK(h, hipMemcpy(&out->next_id, L.next_id, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  out->time = h->events_done ? h->tape_time[h->events_done - 1] : 0.0;
+  unsigned long long cnt[4];
+  HIP_OK(h, hipMemcpy(cnt, L.cnt, sizeof cnt, hipMemcpyDeviceToHost));
+  out->counters = psc_counters{cnt[0], cnt[1], cnt[2], cnt[3]};
+  if (out->reactions_fired && !h->rx.size()) {
+  } else if (out->reactions_fired) {
+    std::vector<unsigned long long> f(h->rx.size());
+    HIP_OK(h, hipMemcpy(f.data(), L.fired, f.size() * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost));
+    for (size_t r = 0; r < f.size(); ++r) out->reactions_fired[r] = f[r];
+  }
+  return PSC_OK;
+}
+
+}  // extern "C"

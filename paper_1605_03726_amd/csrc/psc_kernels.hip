@@ -1,0 +1,501 @@
+// psc_kernels.hip -- gfx950 kernels of the lattice walk.
+//
+// One diffusion event e of a lattice is four kinds of launch, in order:
+//   k_begin   one workgroup: the event's random stage order, the first-order
+//             reactions over the interval since the previous event (2.4.1),
+//             and id assignment + binning of their newborns;
+//   k_stage   16 launches, one per colour stage in the event's order: every
+//             molecule whose voxel has that colour attempts one hop (2.3) and
+//             fires a collision reaction with a registered partner (2.4.2);
+//             survivors are appended to the next event's colour bins;
+//   k_end     one workgroup: clears the reacted flags, advances the event.
+// Same-colour voxels are >= 3 hops apart, so the molecules of one stage touch
+// disjoint closed neighbourhoods: a stage needs no locks or atomics on the
+// lattice, and its result does not depend on the order of its molecules.
+//
+// The device path is integer only: every probability arrives as a 32-bit
+// threshold fixed on the host.
+#include "psc_core.h"
+
+namespace psc {
+
+namespace {
+
+constexpr int kStageThreads = 256;
+constexpr int kBeginThreads = 1024;
+
+__device__ inline uint32_t colour_of_voxel(const Geo &g, uint32_t v) {
+  return colour_of(coord_of(g, v));
+}
+
+__device__ inline void set_error(const LatDev &L, uint32_t bit) { atomicOr(L.error, bit); }
+
+// ---- stage order ---------------------------------------------------------------
+// Fisher-Yates over the 16 colours, slot i = 15..1 swapping with
+// floor(r (i+1) / 2^32), r in sequence from the words of
+// Philox(seed; e, 0xFFFFFFFF, phase 2, block 0..3).
+__device__ void stage_order(const LatDev &L, uint64_t e, uint32_t *perm) {
+  uint32_t w[16];
+  for (uint32_t b = 0; b < 4; ++b) {
+    const U4 r = philox((uint32_t)e, 0xFFFFFFFFu, kPhaseStage, b, L.key0, L.key1);
+    w[4 * b + 0] = r.x;
+    w[4 * b + 1] = r.y;
+    w[4 * b + 2] = r.z;
+    w[4 * b + 3] = r.w;
+  }
+  for (uint32_t c = 0; c < 16; ++c) perm[c] = c;
+  int idx = 0;
+  for (int i = 15; i >= 1; --i) {
+    const uint32_t j = scale32(w[idx++], (uint32_t)(i + 1));
+    const uint32_t t = perm[i];
+    perm[i] = perm[j];
+    perm[j] = t;
+  }
+}
+
+// first-order reaction fired by a molecule of species sp with first draw r0,
+// or -1: the slot whose cumulative threshold first exceeds r0
+__device__ inline int first_order_choice(const LatDev &L, uint64_t e, uint32_t sp, uint32_t r0) {
+  const uint32_t first = L.fo_first[sp], n = L.fo_n[sp];
+  const uint32_t *C = L.tape_thr + e * (uint64_t)L.n_fo + first;
+  for (uint32_t a = 0; a < n; ++a)
+    if (r0 < C[a]) return (int)L.fo_rx[first + a];
+  return -1;
+}
+
+// the words used to place extra first-order products: r.y, r.z, r.w of block
+// 0, then the four words of blocks 1, 2, 3
+__device__ inline uint32_t placement_word(const LatDev &L, uint64_t e, uint32_t id, const U4 &r0,
+                                          int q) {
+  if (q == 0) return r0.y;
+  if (q == 1) return r0.z;
+  if (q == 2) return r0.w;
+  const int b = 1 + (q - 3) / 4, w = (q - 3) % 4;
+  const U4 r = philox((uint32_t)e, id, kPhaseFirst, (uint32_t)b, L.key0, L.key1);
+  return w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
+}
+
+// ---- block-wide helpers ----------------------------------------------------------
+__device__ inline unsigned long long block_sum_u64(unsigned long long x,
+                                                   unsigned long long *s_tmp) {
+  // wavefront reduction, then one value per wave through LDS
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s_tmp[wave] = x;
+  __syncthreads();
+  unsigned long long total = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += s_tmp[w];
+  __syncthreads();
+  return total;
+}
+
+}  // namespace
+
+// =============================================================================
+// initial first-order candidate scan (before the first event after a load)
+// =============================================================================
+__global__ void __launch_bounds__(kStageThreads) k_scan_candidates(const LatDev *__restrict__ Lp) {
+  const LatDev &L = *Lp;
+  const uint64_t e = *L.ev;
+  if (L.n_fo == 0 || e >= L.tape_horizon) return;
+  const uint32_t cmax = L.tape_cmax[e];
+  if (cmax == 0) return;
+  const Bins &in = L.bins[e & 1];
+  const uint32_t cb = (uint32_t)(e & 1);
+  for (uint32_t c = 0; c < 16; ++c) {
+    const uint32_t n = min(in.count[c], (uint32_t)L.cap);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+      const uint32_t id = in.id[c * L.cap + i];
+      if (id == kDeadId) continue;
+      const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
+      if (r.x < cmax) {
+        const uint32_t slot = atomicAdd(&L.cand_count[cb], 1u);
+        if (slot < L.cand_cap) {
+          L.cand_pos[cb][slot] = (uint32_t)i;
+          L.cand_id[cb][slot] = id;
+          L.cand_col[cb][slot] = (uint8_t)c;
+        } else {
+          set_error(L, kErrCandOverflow);
+        }
+      }
+    }
+  }
+}
+
+// =============================================================================
+// k_begin: stage order, first-order pass, newborn ids
+// =============================================================================
+__global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restrict__ Lp,
+                                                          uint32_t *__restrict__ fire_pos,
+                                                          uint32_t *__restrict__ fire_id,
+                                                          uint8_t *__restrict__ fire_col,
+                                                          uint8_t *__restrict__ fire_rx) {
+  const LatDev &L = *Lp;
+  __shared__ uint32_t s_perm[16];
+  __shared__ uint32_t s_nfire, s_nb, s_next;
+  const uint64_t e = *L.ev;
+  const int tid = threadIdx.x;
+  if (e >= L.tape_horizon) {
+    if (tid == 0) set_error(L, kErrTape);
+    return;
+  }
+  const uint32_t buf = (uint32_t)(e & 1);
+  const Bins &in = L.bins[buf];
+  const Bins &out = L.bins[buf ^ 1];
+  if (tid == 0) {
+    stage_order(L, e, s_perm);
+    s_nfire = 0;
+    s_nb = 0;
+    s_next = *L.next_id;
+    *L.birth_count = 0;
+  }
+  if (tid < 16) out.count[tid] = 0;
+  if (tid == 16) L.cand_count[buf ^ 1] = 0;
+  __syncthreads();
+  if (tid < 16) L.perm[tid] = s_perm[tid];
+
+  // ---- first-order decisions (independent of order: species of a candidate
+  // cannot change before its own turn) ----
+  const uint32_t ncand = L.n_fo ? min(L.cand_count[buf], (uint32_t)L.cand_cap) : 0u;
+  for (uint32_t q = tid; q < ncand; q += blockDim.x) {
+    const uint32_t c = L.cand_col[buf][q], pos = L.cand_pos[buf][q], id = L.cand_id[buf][q];
+    const uint32_t v = in.vox[c * L.cap + pos];
+    const uint32_t sp = L.occ[v] & 63u;
+    if (!(L.sp_flags[sp] & kSpFirstOrder)) continue;
+    const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
+    const int rx = first_order_choice(L, e, sp, r.x);
+    if (rx < 0) continue;
+    const uint32_t slot = atomicAdd(&s_nfire, 1u);
+    fire_pos[slot] = pos;
+    fire_id[slot] = id;
+    fire_col[slot] = (uint8_t)c;
+    fire_rx[slot] = (uint8_t)rx;
+  }
+  __syncthreads();
+  const uint32_t nfire = s_nfire;
+
+  // ---- staged application: products go to neighbours, so molecules of
+  // different colours are applied stage by stage in the event's order ----
+  if (nfire > 0) {
+    for (int g = 0; g < 16; ++g) {
+      const uint32_t c = s_perm[g];
+      for (uint32_t q = tid; q < nfire; q += blockDim.x) {
+        if (fire_col[q] != c) continue;
+        const uint32_t pos = fire_pos[q], id = fire_id[q], rx = fire_rx[q];
+        const uint32_t v = in.vox[c * L.cap + pos];
+        const uint32_t m = L.rx_nprod[rx];
+        const uint16_t *prod = L.rx_prod + rx * 12;
+        if (m == 0) {
+          L.occ[v] = 0;
+          in.id[c * L.cap + pos] = kDeadId;
+          atomicAdd(&L.fired[rx], 1ull);
+          continue;
+        }
+        uint32_t dest[kMaxProducts];
+        if (m > 1) {
+          uint32_t vac[12];
+          int nv = 0;
+          const Coord cv = coord_of(L.geo, v);
+          for (uint32_t n = 0; n < 12; ++n) {
+            const uint32_t t = index_of(L.geo, step_coord(L.geo, cv, n));
+            if (L.occ[t] == 0) vac[nv++] = t;
+          }
+          if (nv < (int)(m - 1)) {
+            atomicAdd(&L.cnt[3], 1ull);
+            continue;
+          }
+          const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
+          for (uint32_t a = 0; a + 1 < m; ++a) {
+            const uint32_t x = scale32(placement_word(L, e, id, r, (int)a), (uint32_t)nv);
+            dest[a] = vac[x];
+            for (int y = (int)x; y + 1 < nv; ++y) vac[y] = vac[y + 1];
+            --nv;
+          }
+        }
+        L.occ[v] = prod[0];
+        for (uint32_t a = 0; a + 1 < m; ++a) {
+          L.occ[dest[a]] = prod[a + 1];
+          const uint32_t b = atomicAdd(&s_nb, 1u);
+          if (b < L.birth_cap) {
+            L.birth_key[b] = ((uint64_t)id << 31) | ((uint64_t)(a + 1) << 27) | b;
+            L.birth_vox[b] = dest[a];
+            L.birth_sp[b] = prod[a + 1];
+          } else {
+            set_error(L, kErrBirthOverflow);
+          }
+        }
+        atomicAdd(&L.fired[rx], 1ull);
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- newborn ids: ascending parent id, then product index ----
+  const uint32_t nb = min(s_nb, (uint32_t)L.birth_cap);
+  if (nb > 0) {
+    uint32_t n2 = 1;
+    while (n2 < nb) n2 <<= 1;
+    for (uint32_t q = nb + tid; q < n2; q += blockDim.x) L.birth_key[q] = ~0ull;
+    __syncthreads();
+    // bitonic sort of the keys in global memory by this workgroup
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t q = tid; q < n2; q += blockDim.x) {
+          const uint32_t p = q ^ j;
+          if (p > q) {
+            const uint64_t a = L.birth_key[q], b = L.birth_key[p];
+            const bool up = (q & k) == 0;
+            if ((a > b) == up) {
+              L.birth_key[q] = b;
+              L.birth_key[p] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    const uint32_t base_id = s_next;
+    if ((uint64_t)base_id + nb >= 0xFFFFFFFFull) {
+      if (tid == 0) set_error(L, kErrIds);
+    } else {
+      for (uint32_t q = tid; q < nb; q += blockDim.x) {
+        const uint32_t src = (uint32_t)(L.birth_key[q] & ((1u << 27) - 1u));
+        const uint32_t v = L.birth_vox[src];
+        const uint32_t c = colour_of_voxel(L.geo, v);
+        const uint32_t pos = atomicAdd(&in.count[c], 1u);
+        if (pos < L.cap) {
+          in.vox[c * L.cap + pos] = v;
+          in.id[c * L.cap + pos] = base_id + q;
+          if (in.disp) {
+            in.disp[(0 * 16 + c) * L.cap + pos] = 0;
+            in.disp[(1 * 16 + c) * L.cap + pos] = 0;
+            in.disp[(2 * 16 + c) * L.cap + pos] = 0;
+          }
+        } else {
+          set_error(L, kErrBinOverflow);
+        }
+      }
+      if (tid == 0) *L.next_id = base_id + nb;
+    }
+  }
+}
+
+// =============================================================================
+// k_stage: one colour stage of the walk
+// =============================================================================
+template <int ITEMS>
+__global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restrict__ Lp, uint32_t g) {
+  const LatDev &L = *Lp;
+  __shared__ uint32_t s_cnt[16], s_base[16];
+  __shared__ uint32_t s_ncand, s_cand_base, s_nflag, s_flag_base;
+  __shared__ unsigned long long s_red[kStageThreads / 64];
+
+  const uint64_t e = *L.ev;
+  if (e >= L.tape_horizon) return;  // k_begin has recorded the error
+  const uint32_t buf = (uint32_t)(e & 1);
+  const uint32_t c = L.perm[g];
+  const Bins &in = L.bins[buf];
+  const Bins &out = L.bins[buf ^ 1];
+  const uint32_t n = min(in.count[c], (uint32_t)L.cap);
+  const uint64_t due = L.tape_due[e];
+  const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
+  const uint32_t cnext = (uint32_t)((e + 1) & 1);
+  const uint64_t cap = L.cap;
+  const bool disp = in.disp != nullptr;
+
+  unsigned long long n_att = 0, n_hop = 0, n_col = 0;
+  const int tid = threadIdx.x;
+  const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
+
+  for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk) {
+    uint32_t vox[ITEMS], id[ITEMS], ocol[ITEMS], lpos[ITEMS];
+    int32_t d0[ITEMS], d1[ITEMS], d2[ITEMS];
+    bool cand[ITEMS], flag[ITEMS];
+    uint32_t ftgt[ITEMS];
+    if (tid < 16) s_cnt[tid] = 0;
+    if (tid == 16) s_ncand = 0;
+    if (tid == 17) s_nflag = 0;
+    __syncthreads();
+
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint64_t idx = base + (uint64_t)it * kStageThreads + tid;
+      ocol[it] = 0xFFu;
+      cand[it] = false;
+      flag[it] = false;
+      vox[it] = 0;
+      id[it] = kDeadId;
+      d0[it] = d1[it] = d2[it] = 0;
+      if (idx < n) {
+        vox[it] = in.vox[c * cap + idx];
+        id[it] = in.id[c * cap + idx];
+        if (disp) {
+          d0[it] = in.disp[(0 * 16 + c) * cap + idx];
+          d1[it] = in.disp[(1 * 16 + c) * cap + idx];
+          d2[it] = in.disp[(2 * 16 + c) * cap + idx];
+        }
+      }
+    }
+
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      if (id[it] == kDeadId) continue;
+      const uint32_t v = vox[it];
+      // the draw and the target do not depend on the occupancy, so both
+      // voxel words are requested together
+      const U4 r = philox((uint32_t)e, id[it], kPhaseWalk, 0, L.key0, L.key1);
+      const uint32_t dir = scale32(r.x, 12);
+      const Coord cv = coord_of(L.geo, v);
+      const Coord ct = step_coord(L.geo, cv, dir);
+      const uint32_t t = index_of(L.geo, ct);
+      const uint16_t w = L.occ[v];
+      const uint16_t wt = L.occ[t];
+      const uint32_t sp = w & 63u;  // species ids are < 64
+      ocol[it] = c;  // stays in place unless it hops or is consumed
+      if ((w & kReactedFlag) || !((due >> sp) & 1ull)) continue;
+      ++n_att;
+      if (wt == 0) {
+        L.occ[t] = (uint16_t)sp;
+        L.occ[v] = 0;
+        vox[it] = t;
+        ocol[it] = colour_of(ct);
+        int32_t X, Y, Z;
+        hop_vector(dir, cv.k & 1, X, Y, Z);
+        d0[it] += X;
+        d1[it] += Y;
+        d2[it] += Z;
+        ++n_hop;
+        continue;
+      }
+      ++n_col;
+      const uint32_t psp = wt & 63u;
+      const int rx = L.pair_rx[sp * 64 + psp];
+      if (rx < 0) continue;
+      if (!L.rx_always[rx] && !(r.y < L.rx_thr[rx])) continue;
+      // first product on the partner's voxel with the partner's identity;
+      // its own entry (wherever it is) stays valid and it is flagged so that
+      // it does not walk again in this event
+      const uint16_t *prod = L.rx_prod + rx * 12;
+      L.occ[t] = (uint16_t)(prod[0] | kReactedFlag);
+      flag[it] = true;
+      ftgt[it] = t;
+      if (L.rx_nprod[rx] == 2) {
+        L.occ[v] = prod[1];
+      } else {
+        L.occ[v] = 0;
+        ocol[it] = 0xFFu;  // the mover's identity ends here
+      }
+      atomicAdd(&L.fired[rx], 1ull);
+    }
+
+    // ---- append survivors to the next event's bins: block-local slots
+    // through LDS, one global reservation per colour per block ----
+    uint32_t fslot[ITEMS], cslot[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      if (ocol[it] != 0xFFu) lpos[it] = atomicAdd(&s_cnt[ocol[it]], 1u);
+      if (flag[it]) fslot[it] = atomicAdd(&s_nflag, 1u);
+    }
+    __syncthreads();
+    if (tid < 16 && s_cnt[tid]) s_base[tid] = atomicAdd(&out.count[tid], s_cnt[tid]);
+    if (tid == 17 && s_nflag) s_flag_base = atomicAdd(L.flag_count, s_nflag);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      if (flag[it]) {
+        const uint64_t f = (uint64_t)s_flag_base + fslot[it];
+        if (f < L.flag_cap) L.flag_vox[f] = ftgt[it];
+        else set_error(L, kErrFlagOverflow);
+      }
+      if (ocol[it] == 0xFFu) continue;
+      const uint32_t oc = ocol[it];
+      const uint64_t pos = (uint64_t)s_base[oc] + lpos[it];
+      if (pos >= cap) {
+        set_error(L, kErrBinOverflow);
+        continue;
+      }
+      lpos[it] = (uint32_t)pos;
+      out.vox[oc * cap + pos] = vox[it];
+      out.id[oc * cap + pos] = id[it];
+      if (disp) {
+        out.disp[(0 * 16 + oc) * cap + pos] = d0[it];
+        out.disp[(1 * 16 + oc) * cap + pos] = d1[it];
+        out.disp[(2 * 16 + oc) * cap + pos] = d2[it];
+      }
+      // can this molecule fire a first-order reaction in the next event?
+      if (cmax_next) {
+        const U4 r = philox((uint32_t)(e + 1), id[it], kPhaseFirst, 0, L.key0, L.key1);
+        cand[it] = r.x < cmax_next;
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it)
+      if (cand[it]) cslot[it] = atomicAdd(&s_ncand, 1u);
+    __syncthreads();
+    if (tid == 16 && s_ncand) s_cand_base = atomicAdd(&L.cand_count[cnext], s_ncand);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      if (!cand[it]) continue;
+      const uint64_t q = (uint64_t)s_cand_base + cslot[it];
+      if (q < L.cand_cap) {
+        L.cand_pos[cnext][q] = lpos[it];
+        L.cand_id[cnext][q] = id[it];
+        L.cand_col[cnext][q] = (uint8_t)ocol[it];
+      } else {
+        set_error(L, kErrCandOverflow);
+      }
+    }
+    __syncthreads();
+  }
+
+  const unsigned long long a = block_sum_u64(n_att, s_red);
+  const unsigned long long h = block_sum_u64(n_hop, s_red);
+  const unsigned long long k = block_sum_u64(n_col, s_red);
+  if (tid == 0) {
+    if (a) atomicAdd(&L.cnt[0], a);
+    if (h) atomicAdd(&L.cnt[1], h);
+    if (k) atomicAdd(&L.cnt[2], k);
+  }
+}
+
+// =============================================================================
+// k_end: clear reacted flags, advance the event counter
+// =============================================================================
+__global__ void __launch_bounds__(kBeginThreads) k_end(const LatDev *__restrict__ Lp) {
+  const LatDev &L = *Lp;
+  if (*L.ev >= L.tape_horizon) return;
+  const uint32_t nf = min(*L.flag_count, (uint32_t)L.flag_cap);
+  for (uint32_t q = threadIdx.x; q < nf; q += blockDim.x) {
+    const uint32_t v = L.flag_vox[q];
+    L.occ[v] = (uint16_t)(L.occ[v] & kSpeciesMask);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *L.flag_count = 0;
+    *L.ev = *L.ev + 1;
+  }
+}
+
+// =============================================================================
+// host-side launchers
+// =============================================================================
+hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_candidates, dim3(grid), dim3(kStageThreads), 0, s, dL);
+  return hipGetLastError();
+}
+
+hipError_t launch_event(const LatDev *dL, const FireScratch &f, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, f.pos, f.id, f.col, f.rx);
+  for (uint32_t g = 0; g < 16; ++g)
+    hipLaunchKernelGGL(k_stage<4>, dim3(grid), dim3(kStageThreads), 0, s, dL, g);
+  hipLaunchKernelGGL(k_end, dim3(1), dim3(kBeginThreads), 0, s, dL);
+  return hipGetLastError();
+}
+
+int stage_items() { return 4; }
+int stage_threads() { return kStageThreads; }
+
+}  // namespace psc

@@ -1,0 +1,264 @@
+"""ctypes binding of libpsc (include/psc.h): argument marshalling only.
+
+Every step of the walk runs in the HIP kernels of libpsc.so.  PyTorch provides
+device memory (through the caching allocator hooks) and streams.  If the
+library is not built, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpsc.so")
+
+PSC_OK, PSC_EINVAL, PSC_ESTATE, PSC_ENOMEM, PSC_ECAPACITY, PSC_EDEVICE = 0, -1, -2, -3, -4, -5
+TRACK_DISPLACEMENT = 1
+
+_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Desc(C.Structure):
+    _fields_ = [("ni", C.c_uint32), ("nj", C.c_uint32), ("nk", C.c_uint32),
+                ("voxel_radius", C.c_double), ("seed", C.c_uint64),
+                ("max_molecules", C.c_uint64), ("flags", C.c_uint32), ("device", C.c_int32),
+                ("alloc", _ALLOC), ("free", _FREE), ("alloc_user", C.c_void_p)]
+
+
+class Counters(C.Structure):
+    _fields_ = [("attempts", C.c_uint64), ("hops", C.c_uint64), ("collisions", C.c_uint64),
+                ("placement_failures", C.c_uint64)]
+
+
+class StateView(C.Structure):
+    _fields_ = [("occupancy", C.POINTER(C.c_uint16)), ("n_molecules", C.c_uint64),
+                ("id", C.POINTER(C.c_uint32)), ("voxel", C.POINTER(C.c_uint32)),
+                ("species", C.POINTER(C.c_uint16)), ("dx", C.POINTER(C.c_int32)),
+                ("dy", C.POINTER(C.c_int32)), ("dz", C.POINTER(C.c_int32)),
+                ("event", C.c_uint64), ("next_id", C.c_uint32), ("time", C.c_double),
+                ("counters", Counters), ("reactions_fired", C.POINTER(C.c_uint64))]
+
+
+class PscError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"psc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run paper_1605_03726_amd/build.py "
+                          "(or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.psc_create_lattice.argtypes = [C.POINTER(Desc), C.POINTER(vp)]
+    L.psc_create_lattice.restype = C.c_int32
+    L.psc_destroy.argtypes = [vp]
+    L.psc_destroy.restype = None
+    L.psc_last_error.argtypes = [vp]
+    L.psc_last_error.restype = C.c_char_p
+    L.psc_add_species.argtypes = [vp, C.c_char_p, C.c_double, C.POINTER(C.c_uint16)]
+    L.psc_add_species.restype = C.c_int32
+    L.psc_add_reaction.argtypes = [vp, C.POINTER(C.c_uint16), C.c_uint32, C.POINTER(C.c_uint16),
+                                   C.c_uint32, C.c_double, C.POINTER(C.c_uint32)]
+    L.psc_add_reaction.restype = C.c_int32
+    L.psc_place_uniform.argtypes = [vp, C.c_uint16, C.c_uint64]
+    L.psc_place_uniform.restype = C.c_int32
+    L.psc_load_state.argtypes = [vp, C.POINTER(StateView)]
+    L.psc_load_state.restype = C.c_int32
+    L.psc_step.argtypes = [vp, C.c_uint64, vp]
+    L.psc_step.restype = C.c_int32
+    L.psc_sync.argtypes = [vp]
+    L.psc_sync.restype = C.c_int32
+    L.psc_read_state.argtypes = [vp, C.POINTER(StateView), vp]
+    L.psc_read_state.restype = C.c_int32
+    L.psc_query_sizes.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                  C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+    L.psc_query_sizes.restype = C.c_int32
+    L.psc_device_bytes.argtypes = [vp, C.POINTER(C.c_uint64)]
+    L.psc_device_bytes.restype = C.c_int32
+    _lib = L
+    return L
+
+
+def _ptr(a, ct):
+    return None if a is None else a.ctypes.data_as(C.POINTER(ct))
+
+
+def _torch_hooks(device: int):
+    """allocator hooks backed by torch's caching allocator"""
+    import torch
+
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=device)
+        except Exception:
+            return None
+
+    def free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return _ALLOC(alloc), _FREE(free)
+
+
+def current_stream():
+    """torch's current HIP stream (None, the default stream, without a GPU)"""
+    import torch
+    if not torch.cuda.is_available():
+        return None
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Lattice:
+    """One HCP lattice on the GPU (see include/psc.h)."""
+
+    def __init__(self, dims, voxel_radius: float, seed: int, max_molecules: int,
+                 track_displacement: bool = False, device: int = 0,
+                 torch_allocator: bool = True):
+        self.L = lib()
+        self.dims = tuple(int(x) for x in dims)
+        self.nv = self.dims[0] * self.dims[1] * self.dims[2]
+        d = Desc()
+        d.ni, d.nj, d.nk = self.dims
+        d.voxel_radius = voxel_radius
+        d.seed = seed
+        d.max_molecules = max_molecules
+        d.flags = TRACK_DISPLACEMENT if track_displacement else 0
+        d.device = device
+        self._hooks = None
+        if torch_allocator:
+            self._hooks = _torch_hooks(device)
+            d.alloc, d.free = self._hooks
+        h = C.c_void_p()
+        rc = self.L.psc_create_lattice(C.byref(d), C.byref(h))
+        if rc != PSC_OK:
+            raise PscError(rc, self.L.psc_last_error(None).decode())
+        self.h = h
+        self.n_rx = 0
+        self.n_species = 0
+
+    def _check(self, rc):
+        if rc != PSC_OK:
+            raise PscError(rc, self.L.psc_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.psc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_species(self, name: str, D: float) -> int:
+        out = C.c_uint16()
+        self._check(self.L.psc_add_species(self.h, name.encode(), D, C.byref(out)))
+        self.n_species += 1
+        return out.value
+
+    def add_reaction(self, reactants, products, k: float) -> int:
+        r = np.array(reactants, np.uint16)
+        p = np.array(list(products) + [0], np.uint16)
+        out = C.c_uint32()
+        self._check(self.L.psc_add_reaction(self.h, _ptr(r, C.c_uint16), len(reactants),
+                                            _ptr(p, C.c_uint16), len(products), k, C.byref(out)))
+        self.n_rx += 1
+        return out.value
+
+    def place_uniform(self, species: int, count: int):
+        self._check(self.L.psc_place_uniform(self.h, species, count))
+
+    def load_state(self, st: dict):
+        occ = np.ascontiguousarray(st["occ"], np.uint16)
+        ids = np.ascontiguousarray(st["id"], np.uint32)
+        vox = np.ascontiguousarray(st["vox"], np.uint32)
+        sp = st.get("species")
+        sp = None if sp is None else np.ascontiguousarray(sp, np.uint16)
+        d = [None if st.get(k) is None else np.ascontiguousarray(st[k], np.int32)
+             for k in ("dx", "dy", "dz")]
+        v = StateView()
+        v.occupancy = _ptr(occ, C.c_uint16)
+        v.n_molecules = len(ids)
+        v.id = _ptr(ids, C.c_uint32)
+        v.voxel = _ptr(vox, C.c_uint32)
+        v.species = _ptr(sp, C.c_uint16)
+        v.dx, v.dy, v.dz = (_ptr(a, C.c_int32) for a in d)
+        v.event = int(st.get("event", 0))
+        v.next_id = int(st["next_id"])
+        self._check(self.L.psc_load_state(self.h, C.byref(v)))
+
+    def step(self, n_events: int, stream=None):
+        s = current_stream() if stream is None else stream
+        self._check(self.L.psc_step(self.h, n_events, s))
+
+    def sync(self):
+        self._check(self.L.psc_sync(self.h))
+
+    def n_molecules(self) -> int:
+        n = C.c_uint64()
+        self._check(self.L.psc_query_sizes(self.h, None, C.byref(n), None, None))
+        return n.value
+
+    def device_bytes(self) -> int:
+        b = C.c_uint64()
+        self._check(self.L.psc_device_bytes(self.h, C.byref(b)))
+        return b.value
+
+    def read_state(self, with_occ: bool = True, stream=None) -> dict:
+        cap = self.n_molecules()
+        occ = np.zeros(self.nv, np.uint16) if with_occ else None
+        arrays = {k: np.zeros(cap, t) for k, t in (("id", np.uint32), ("vox", np.uint32),
+                                                    ("species", np.uint16), ("dx", np.int32),
+                                                    ("dy", np.int32), ("dz", np.int32))}
+        fired = np.zeros(max(self.n_rx, 1), np.uint64)
+        v = StateView()
+        v.occupancy = _ptr(occ, C.c_uint16)
+        v.n_molecules = cap
+        v.id = _ptr(arrays["id"], C.c_uint32)
+        v.voxel = _ptr(arrays["vox"], C.c_uint32)
+        v.species = _ptr(arrays["species"], C.c_uint16)
+        v.dx = _ptr(arrays["dx"], C.c_int32)
+        v.dy = _ptr(arrays["dy"], C.c_int32)
+        v.dz = _ptr(arrays["dz"], C.c_int32)
+        v.reactions_fired = _ptr(fired, C.c_uint64)
+        s = None if stream is None else stream
+        self._check(self.L.psc_read_state(self.h, C.byref(v), s))
+        n = v.n_molecules
+        out = {k: a[:n].copy() for k, a in arrays.items()}
+        out.update(occ=occ, attempts=v.counters.attempts, hops=v.counters.hops,
+                   collisions=v.counters.collisions,
+                   place_fail=v.counters.placement_failures,
+                   fired=fired[: self.n_rx].copy(), event=v.event, time=v.time,
+                   next_id=v.next_id)
+        return out
+
+
+def lattice_from_workload(w: dict, max_molecules: int | None = None, device: int = 0,
+                          place: bool = True) -> Lattice:
+    """Builds a Lattice from a workload description (species, reactions,
+    uniform placements)."""
+    nv = int(np.prod(w["dims"]))
+    if max_molecules is None:
+        placed = sum(c for _, c in w["place"])
+        max_molecules = min(nv, max(1024, int(placed * 1.5) + 1024))
+    lat = Lattice(w["dims"], w["rv"], w["seed"], max_molecules,
+                  track_displacement=w.get("track_displacement", False), device=device)
+    for name, D in w["species"]:
+        lat.add_species(name, D)
+    for r, p, k in w["reactions"]:
+        lat.add_reaction(r, p, k)
+    if place:
+        for s, c in w["place"]:
+            lat.place_uniform(s, c)
+    return lat

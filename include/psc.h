@@ -176,6 +176,10 @@ psc_status psc_sync(psc_lattice *h);
  * the required count and nothing else is written). */
 psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream);
 
+/* Cumulative counters and events completed, without reading the state
+ * (waits for pending work). */
+psc_status psc_read_counters(psc_lattice *h, psc_counters *out, uint64_t *event);
+
 /* Sizes needed to read the state. */
 psc_status psc_query_sizes(const psc_lattice *h, uint64_t *n_voxels,
                            uint64_t *n_molecules, uint32_t *n_species,
@@ -183,6 +187,25 @@ psc_status psc_query_sizes(const psc_lattice *h, uint64_t *n_voxels,
 
 /* Device bytes held by the lattice (for admission control). */
 psc_status psc_device_bytes(const psc_lattice *h, uint64_t *bytes);
+
+/* ---- measurement ------------------------------------------------------------ */
+
+/* Per-kernel device time of the steps run while timing is on, measured with
+ * HIP events recorded on the step's stream around every launch:
+ * begin = stage order + first-order pass, stage = one colour stage of the
+ * walk, end = flag sweep. */
+typedef struct psc_kernel_times {
+  double begin_ms, stage_ms, end_ms;
+  uint64_t begin_launches, stage_launches, end_launches;
+} psc_kernel_times;
+
+/* Turns per-launch timing on (1) or off (0) and clears the totals.  Timing
+ * adds two event records per launch; leave it off for throughput runs. */
+psc_status psc_set_kernel_timing(psc_lattice *h, int enable);
+
+/* Waits for the timed work and returns the totals since timing was turned
+ * on. */
+psc_status psc_get_kernel_times(psc_lattice *h, psc_kernel_times *out);
 
 #ifdef __cplusplus
 }

@@ -253,6 +253,9 @@ struct FireScratch {
 
 hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
 hipError_t launch_event(const LatDev *dL, const FireScratch &f, int grid, hipStream_t s);
+hipError_t launch_begin(const LatDev *dL, const FireScratch &f, hipStream_t s);
+hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, hipStream_t s);
+hipError_t launch_end(const LatDev *dL, hipStream_t s);
 int stage_items();
 int stage_threads();
 

@@ -97,6 +97,7 @@ struct psc_lattice {
   // static molecules: immobile species that react with nothing never change,
   // so they stay out of the walk's bins
   std::vector<uint32_t> st_id, st_vox;
+  std::vector<int32_t> st_d[3];
 
   // event tape (absolute event index)
   std::vector<uint64_t> n_walks;
@@ -128,6 +129,15 @@ struct psc_lattice {
   uint64_t d_tape_rows = 0;
   int grid = 1;
   hipStream_t last_stream = nullptr;
+
+  // per-launch timing: kind (0 begin, 1 stage, 2 end) and its event pair
+  bool timing = false;
+  struct Timed {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> event_pool;
 };
 
 namespace {
@@ -323,6 +333,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   // split molecules into the walk's bins and the static list
   h->st_id.clear();
   h->st_vox.clear();
+  for (auto &d : h->st_d) d.clear();
   const uint64_t nmol = h->mid.size();
   std::vector<uint8_t> colour(nmol);
   uint64_t bin_count[16] = {0};
@@ -333,6 +344,9 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
     if (!mobile(h, s) && !reactant[s]) {
       h->st_id.push_back(h->mid[q]);
       h->st_vox.push_back(h->mvox[q]);
+      h->st_d[0].push_back(h->mdx[q]);
+      h->st_d[1].push_back(h->mdy[q]);
+      h->st_d[2].push_back(h->mdz[q]);
       continue;
     }
     colour[q] = (uint8_t)colour_of(coord_of(h->geo, h->mvox[q]));
@@ -575,6 +589,11 @@ void psc_destroy(psc_lattice *h) {
     (void)hipSetDevice(h->desc.device);
     (void)hipDeviceSynchronize();
   }
+  for (auto &t : h->timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (auto &e : h->event_pool) (void)hipEventDestroy(e);
   dev_free_all(h);
   delete h;
 }
@@ -723,8 +742,10 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
     // the device is first touched here: creation, the model and the initial
     // state are host-only
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || h->desc.device >= ndev)
-      return fail(h, PSC_EINVAL, "no HIP device %d", h->desc.device);
+    const hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || h->desc.device >= ndev)
+      return fail(h, PSC_EINVAL, "no HIP device %d (%d devices, %s)", h->desc.device, ndev,
+                  hipGetErrorString(e));
   }
   HIP_OK(h, hipSetDevice(h->desc.device));
   if (!h->frozen) {
@@ -739,8 +760,33 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
     psc_status st = sync_tape(h, stream);
     if (st) return st;
   }
-  for (uint64_t e = 0; e < n_events; ++e)
-    HIP_OK(h, launch_event(h->dL, h->fire, h->grid, stream));
+  if (!h->timing) {
+    for (uint64_t e = 0; e < n_events; ++e)
+      HIP_OK(h, launch_event(h->dL, h->fire, h->grid, stream));
+  } else {
+    auto ev = [&](hipEvent_t *out) -> hipError_t {
+      if (!h->event_pool.empty()) {
+        *out = h->event_pool.back();
+        h->event_pool.pop_back();
+        return hipSuccess;
+      }
+      return hipEventCreate(out);
+    };
+    for (uint64_t e = 0; e < n_events; ++e) {
+      for (int g = -1; g <= 16; ++g) {
+        psc_lattice::Timed t;
+        t.kind = g < 0 ? 0 : (g < 16 ? 1 : 2);
+        HIP_OK(h, ev(&t.a));
+        HIP_OK(h, ev(&t.b));
+        HIP_OK(h, hipEventRecord(t.a, stream));
+        if (g < 0) HIP_OK(h, launch_begin(h->dL, h->fire, stream));
+        else if (g < 16) HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, stream));
+        else HIP_OK(h, launch_end(h->dL, stream));
+        HIP_OK(h, hipEventRecord(t.b, stream));
+        h->timed.push_back(t);
+      }
+    }
+  }
   h->events_done = end;
   h->last_stream = stream;
   return PSC_OK;
@@ -775,6 +821,64 @@ psc_status psc_query_sizes(const psc_lattice *hc, uint64_t *n_voxels, uint64_t *
       uint64_t n = h->st_id.size();
       for (int c = 0; c < 16; ++c) n += counts[c];
       *n_molecules = n;  // upper bound: dead entries are dropped by the walk
+    }
+  }
+  return PSC_OK;
+}
+
+psc_status psc_read_counters(psc_lattice *h, psc_counters *out, uint64_t *event) {
+  if (!h || !out) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (event) *event = h->frozen ? h->events_done : h->event0;
+  if (!h->frozen) {
+    *out = psc_counters{0, 0, 0, 0};
+    return PSC_OK;
+  }
+  HIP_OK(h, hipSetDevice(h->desc.device));
+  HIP_OK(h, hipDeviceSynchronize());
+  psc_status st = check_device_error(h);
+  if (st) return st;
+  unsigned long long cnt[4];
+  HIP_OK(h, hipMemcpy(cnt, h->L.cnt, sizeof cnt, hipMemcpyDeviceToHost));
+  *out = psc_counters{cnt[0], cnt[1], cnt[2], cnt[3]};
+  return PSC_OK;
+}
+
+psc_status psc_set_kernel_timing(psc_lattice *h, int enable) {
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (!h->timed.empty()) {
+    HIP_OK(h, hipSetDevice(h->desc.device));
+    HIP_OK(h, hipDeviceSynchronize());
+    for (auto &t : h->timed) {
+      h->event_pool.push_back(t.a);
+      h->event_pool.push_back(t.b);
+    }
+    h->timed.clear();
+  }
+  h->timing = enable != 0;
+  return PSC_OK;
+}
+
+psc_status psc_get_kernel_times(psc_lattice *h, psc_kernel_times *out) {
+  if (!h || !out) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  *out = psc_kernel_times{0, 0, 0, 0, 0, 0};
+  if (h->timed.empty()) return PSC_OK;
+  HIP_OK(h, hipSetDevice(h->desc.device));
+  HIP_OK(h, hipEventSynchronize(h->timed.back().b));
+  for (auto &t : h->timed) {
+    float ms = 0.f;
+    HIP_OK(h, hipEventElapsedTime(&ms, t.a, t.b));
+    if (t.kind == 0) {
+      out->begin_ms += ms;
+      out->begin_launches++;
+    } else if (t.kind == 1) {
+      out->stage_ms += ms;
+      out->stage_launches++;
+    } else {
+      out->end_ms += ms;
+      out->end_launches++;
     }
   }
   return PSC_OK;
@@ -877,10 +981,12 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
     if (out->id) out->id[z] = id_of(q);
     if (out->voxel) out->voxel[z] = v;
     if (out->species) out->species[z] = occp[v];
-    const bool w = q < nwalk && disp;
-    if (out->dx) out->dx[z] = w ? d3[0][q] : 0;
-    if (out->dy) out->dy[z] = w ? d3[1][q] : 0;
-    if (out->dz) out->dz[z] = w ? d3[2][q] : 0;
+    for (int a = 0; a < 3; ++a) {
+      int32_t *dst = a == 0 ? out->dx : (a == 1 ? out->dy : out->dz);
+      if (!dst) continue;
+      if (q >= nwalk) dst[z] = h->st_d[a][q - nwalk];  // static molecules never move
+      else dst[z] = disp ? d3[a][q] : 0;
+    }
   }
   out->n_molecules = n;
   out->event = h->events_done;

@@ -487,6 +487,21 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_begin(const LatDev *dL, const FireScratch &f, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, f.pos, f.id, f.col, f.rx);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage<4>, dim3(grid), dim3(kStageThreads), 0, s, dL, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_end(const LatDev *dL, hipStream_t s) {
+  hipLaunchKernelGGL(k_end, dim3(1), dim3(kBeginThreads), 0, s, dL);
+  return hipGetLastError();
+}
+
 hipError_t launch_event(const LatDev *dL, const FireScratch &f, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, f.pos, f.id, f.col, f.rx);
   for (uint32_t g = 0; g < 16; ++g)

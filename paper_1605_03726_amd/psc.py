@@ -33,6 +33,12 @@ class Counters(C.Structure):
                 ("placement_failures", C.c_uint64)]
 
 
+class KernelTimes(C.Structure):
+    _fields_ = [("begin_ms", C.c_double), ("stage_ms", C.c_double), ("end_ms", C.c_double),
+                ("begin_launches", C.c_uint64), ("stage_launches", C.c_uint64),
+                ("end_launches", C.c_uint64)]
+
+
 class StateView(C.Structure):
     _fields_ = [("occupancy", C.POINTER(C.c_uint16)), ("n_molecules", C.c_uint64),
                 ("id", C.POINTER(C.c_uint32)), ("voxel", C.POINTER(C.c_uint32)),
@@ -51,6 +57,19 @@ class PscError(RuntimeError):
 _lib = None
 
 
+def _hip_runtimes() -> set:
+    """paths of every HIP runtime mapped into this process"""
+    out = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    out.add(line.split()[-1])
+    except OSError:
+        pass
+    return out
+
+
 def lib() -> C.CDLL:
     global _lib
     if _lib is not None:
@@ -58,7 +77,15 @@ def lib() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run paper_1605_03726_amd/build.py "
                           "(or __graft_entry__.build())")
+    # torch ships its own HIP runtime.  It is loaded first so that libpsc's
+    # dependency (same soname) binds to it: one runtime per process, which is
+    # what lets libpsc use torch's device memory and streams.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError("two HIP runtimes are loaded (%s); import torch before any other "
+                          "HIP library" % ", ".join(sorted(rts)))
     vp = C.c_void_p
     L.psc_create_lattice.argtypes = [C.POINTER(Desc), C.POINTER(vp)]
     L.psc_create_lattice.restype = C.c_int32
@@ -86,6 +113,12 @@ def lib() -> C.CDLL:
     L.psc_query_sizes.restype = C.c_int32
     L.psc_device_bytes.argtypes = [vp, C.POINTER(C.c_uint64)]
     L.psc_device_bytes.restype = C.c_int32
+    L.psc_read_counters.argtypes = [vp, C.POINTER(Counters), C.POINTER(C.c_uint64)]
+    L.psc_read_counters.restype = C.c_int32
+    L.psc_set_kernel_timing.argtypes = [vp, C.c_int]
+    L.psc_set_kernel_timing.restype = C.c_int32
+    L.psc_get_kernel_times.argtypes = [vp, C.POINTER(KernelTimes)]
+    L.psc_get_kernel_times.restype = C.c_int32
     _lib = L
     return L
 
@@ -209,6 +242,22 @@ class Lattice:
         n = C.c_uint64()
         self._check(self.L.psc_query_sizes(self.h, None, C.byref(n), None, None))
         return n.value
+
+    def counters(self) -> dict:
+        c = Counters()
+        e = C.c_uint64()
+        self._check(self.L.psc_read_counters(self.h, C.byref(c), C.byref(e)))
+        out = {f: getattr(c, f) for f, _ in Counters._fields_}
+        out["event"] = e.value
+        return out
+
+    def set_kernel_timing(self, on: bool):
+        self._check(self.L.psc_set_kernel_timing(self.h, 1 if on else 0))
+
+    def kernel_times(self) -> dict:
+        t = KernelTimes()
+        self._check(self.L.psc_get_kernel_times(self.h, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in KernelTimes._fields_}
 
     def device_bytes(self) -> int:
         b = C.c_uint64()

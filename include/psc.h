@@ -188,6 +188,21 @@ psc_status psc_query_sizes(const psc_lattice *h, uint64_t *n_voxels,
 /* Device bytes held by the lattice (for admission control). */
 psc_status psc_device_bytes(const psc_lattice *h, uint64_t *bytes);
 
+/* ---- launch shape (result-invariant) ---------------------------------------- */
+
+/* Launch shape of the walk-stage kernel: molecules per thread per pass
+ * (1, 2, 4, 8 or 16) and workgroups per launch (grid-striding beyond).  It
+ * changes only how the work is spread over the GPU, never the result (the
+ * molecules of one stage commute).  0 keeps the current value; the default is
+ * 4 items and enough workgroups for one pass over an average colour bin. */
+typedef struct psc_launch {
+  uint32_t items_per_thread;
+  uint32_t stage_blocks;
+} psc_launch;
+
+psc_status psc_set_launch(psc_lattice *h, const psc_launch *l);
+psc_status psc_get_launch(const psc_lattice *h, psc_launch *out);
+
 /* ---- measurement ------------------------------------------------------------ */
 
 /* Per-kernel device time of the steps run while timing is on, measured with

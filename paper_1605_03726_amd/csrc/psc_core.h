@@ -185,9 +185,22 @@ __host__ __device__ inline void hop_vector(uint32_t n, int32_t p, int32_t &X, in
 struct Bins {
   uint32_t *vox;    // [16 * cap]
   uint32_t *id;     // [16 * cap]
+  uint16_t *sp;     // [16 * cap] species when the entry was last written
   int32_t *disp;    // [3 * 16 * cap] (dx | dy | dz planes) or nullptr
   uint32_t *count;  // [16]
 };
+
+// Voxels where a collision put a product on the partner's voxel are marked
+// in a per-event hash bitmap.  Only there can a bin entry's cached species be
+// stale (the partner keeps its entry and its id but changes species), or
+// the molecule be one that must not walk again in this event; everywhere
+// else the walk trusts the cached species and never reads the lattice word
+// at the mover's voxel.  Event e sets hot[e & 1] and consults hot[e & 1] and
+// hot[(e + 1) & 1] (the previous event's); the end of event e clears the
+// latter for reuse by event e + 1.
+__host__ __device__ inline uint32_t hot_hash(uint32_t v, uint32_t bits) {
+  return (v * 0x9E3779B1u) >> (32u - bits);
+}
 
 struct LatDev {
   Geo geo;
@@ -216,6 +229,16 @@ struct LatDev {
   uint16_t *birth_sp;
   uint32_t *birth_count;
   uint64_t birth_cap;
+
+  // stale-entry filter (see hot_hash)
+  uint32_t *hot[2];
+  uint32_t hot_bits;      // log2 of the bitmap size in bits
+  uint32_t *end_done;     // completion counter of the multi-block k_end
+
+  // first-order conflict test: per hashed voxel, how many firing molecules
+  // have it in their closed neighbourhood (zero between events)
+  uint32_t *nbr_cnt;
+  uint32_t nbr_bits;
 
   // model
   uint32_t n_species, n_rx, n_fo;  // n_fo: first-order slots (see fo_rx)
@@ -252,9 +275,10 @@ struct FireScratch {
 };
 
 hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
-hipError_t launch_event(const LatDev *dL, const FireScratch &f, int grid, hipStream_t s);
+hipError_t launch_event(const LatDev *dL, const FireScratch &f, int grid, int items,
+                        hipStream_t s);
 hipError_t launch_begin(const LatDev *dL, const FireScratch &f, hipStream_t s);
-hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, hipStream_t s);
+hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, hipStream_t s);
 hipError_t launch_end(const LatDev *dL, hipStream_t s);
 int stage_items();
 int stage_threads();

@@ -128,6 +128,8 @@ struct psc_lattice {
   uint32_t *d_tape_thr = nullptr, *d_tape_cmax = nullptr;
   uint64_t d_tape_rows = 0;
   int grid = 1;
+  int items = 4;
+  bool grid_set = false;
   hipStream_t last_stream = nullptr;
 
   // per-launch timing: kind (0 begin, 1 stage, 2 end) and its event pair
@@ -367,12 +369,14 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   for (int b = 0; b < 2; ++b) {
     L.bins[b].vox = alloc_n<uint32_t>(h, 16 * cap);
     L.bins[b].id = alloc_n<uint32_t>(h, 16 * cap);
+    L.bins[b].sp = alloc_n<uint16_t>(h, 16 * cap);
     L.bins[b].disp = disp ? alloc_n<int32_t>(h, 3 * 16 * cap) : nullptr;
     L.bins[b].count = alloc_n<uint32_t>(h, 16);
     L.cand_pos[b] = alloc_n<uint32_t>(h, cap);
     L.cand_id[b] = alloc_n<uint32_t>(h, cap);
     L.cand_col[b] = alloc_n<uint8_t>(h, cap);
-    if (!L.bins[b].vox || !L.bins[b].id || (disp && !L.bins[b].disp) || !L.bins[b].count ||
+    if (!L.bins[b].vox || !L.bins[b].id || !L.bins[b].sp || (disp && !L.bins[b].disp) ||
+        !L.bins[b].count ||
         !L.cand_pos[b] || !L.cand_id[b] || !L.cand_col[b])
       return fail(h, PSC_ENOMEM, "device allocation of molecule bins failed");
   }
@@ -386,6 +390,16 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.birth_vox = alloc_n<uint32_t>(h, L.birth_cap);
   L.birth_sp = alloc_n<uint16_t>(h, L.birth_cap);
   L.birth_count = alloc_n<uint32_t>(h, 1);
+  {
+    uint32_t bits = 16;
+    while (bits < 24 && (1ull << bits) < cap / 4) ++bits;
+    L.hot_bits = bits;
+  }
+  L.hot[0] = alloc_n<uint32_t>(h, (1ull << L.hot_bits) / 32);
+  L.hot[1] = alloc_n<uint32_t>(h, (1ull << L.hot_bits) / 32);
+  L.end_done = alloc_n<uint32_t>(h, 1);
+  L.nbr_bits = 22;
+  L.nbr_cnt = alloc_n<uint32_t>(h, 1ull << L.nbr_bits);
   h->fire.pos = alloc_n<uint32_t>(h, cap);
   h->fire.id = alloc_n<uint32_t>(h, cap);
   h->fire.col = alloc_n<uint8_t>(h, cap);
@@ -413,7 +427,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
       !L.birth_sp || !L.birth_count || !h->fire.pos || !h->fire.id || !h->fire.col ||
       !h->fire.rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod ||
       !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.next_id || !L.cnt ||
-      !L.fired || !L.error || !h->dL)
+      !L.fired || !L.error || !h->dL || !L.hot[0] || !L.hot[1] || !L.end_done || !L.nbr_cnt)
     return fail(h, PSC_ENOMEM, "device allocation failed");
   L.sp_flags = d_flags;
   L.pair_rx = d_pair;
@@ -443,6 +457,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   const int cur = (int)(h->event0 & 1);
   {
     std::vector<uint32_t> vox(walkers.size()), id(walkers.size());
+    std::vector<uint16_t> spc(walkers.size());
     std::vector<int32_t> d3(disp ? 3 * walkers.size() : 0);
     uint64_t start[17] = {0};
     for (int c = 0; c < 16; ++c) start[c + 1] = start[c] + bin_count[c];
@@ -452,6 +467,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
       const uint64_t at = fill[colour[q]]++;
       vox[at] = h->mvox[q];
       id[at] = h->mid[q];
+      spc[at] = h->occ[h->mvox[q]];
       if (disp) {
         d3[3 * at + 0] = h->mdx[q];
         d3[3 * at + 1] = h->mdy[q];
@@ -465,6 +481,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
       if (!bin_count[c]) continue;
       HIP_OK(h, up(L.bins[cur].vox + c * cap, vox.data() + start[c], bin_count[c] * 4));
       HIP_OK(h, up(L.bins[cur].id + c * cap, id.data() + start[c], bin_count[c] * 4));
+      HIP_OK(h, up(L.bins[cur].sp + c * cap, spc.data() + start[c], bin_count[c] * 2));
       if (disp) {
         std::vector<int32_t> plane(bin_count[c]);
         for (int a = 0; a < 3; ++a) {
@@ -482,6 +499,10 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   HIP_OK(h, hipMemset(L.cnt, 0, 4 * sizeof(unsigned long long)));
   HIP_OK(h, hipMemset(L.fired, 0, std::max<uint32_t>(R, 1) * sizeof(unsigned long long)));
   HIP_OK(h, hipMemset(L.error, 0, sizeof(uint32_t)));
+  HIP_OK(h, hipMemset(L.end_done, 0, sizeof(uint32_t)));
+  HIP_OK(h, hipMemset(L.nbr_cnt, 0, (1ull << L.nbr_bits) * sizeof(uint32_t)));
+  HIP_OK(h, hipMemset(L.hot[0], 0, (1ull << L.hot_bits) / 8));
+  HIP_OK(h, hipMemset(L.hot[1], 0, (1ull << L.hot_bits) / 8));
   HIP_OK(h, up(L.ev, &h->event0, sizeof(uint64_t)));
   HIP_OK(h, up(L.next_id, &h->next_id, sizeof(uint32_t)));
 
@@ -494,10 +515,12 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
 
   // launch shape of the stage kernel: enough workgroups for the expected
   // bin size, grid-striding beyond
-  const uint64_t per_block = (uint64_t)stage_threads() * stage_items();
-  const uint64_t expect = std::max<uint64_t>(cap / 16, 1);
-  h->grid = (int)std::min<uint64_t>(std::max<uint64_t>((expect + per_block - 1) / per_block, 1),
-                                    4096);
+  if (!h->grid_set) {
+    const uint64_t per_block = (uint64_t)stage_threads() * (uint64_t)h->items;
+    const uint64_t expect = std::max<uint64_t>(cap / 16, 1);
+    h->grid = (int)std::min<uint64_t>(
+        std::max<uint64_t>((expect + per_block - 1) / per_block, 1), 4096);
+  }
   HIP_OK(h, launch_scan(h->dL, std::min(h->grid * 4, 4096), stream));
   h->frozen = true;
   // the host copy of the walkers is no longer authoritative
@@ -762,7 +785,7 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   }
   if (!h->timing) {
     for (uint64_t e = 0; e < n_events; ++e)
-      HIP_OK(h, launch_event(h->dL, h->fire, h->grid, stream));
+      HIP_OK(h, launch_event(h->dL, h->fire, h->grid, h->items, stream));
   } else {
     auto ev = [&](hipEvent_t *out) -> hipError_t {
       if (!h->event_pool.empty()) {
@@ -780,7 +803,7 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
         HIP_OK(h, ev(&t.b));
         HIP_OK(h, hipEventRecord(t.a, stream));
         if (g < 0) HIP_OK(h, launch_begin(h->dL, h->fire, stream));
-        else if (g < 16) HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, stream));
+        else if (g < 16) HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, h->items, stream));
         else HIP_OK(h, launch_end(h->dL, stream));
         HIP_OK(h, hipEventRecord(t.b, stream));
         h->timed.push_back(t);
@@ -841,6 +864,28 @@ psc_status psc_read_counters(psc_lattice *h, psc_counters *out, uint64_t *event)
   unsigned long long cnt[4];
   HIP_OK(h, hipMemcpy(cnt, h->L.cnt, sizeof cnt, hipMemcpyDeviceToHost));
   *out = psc_counters{cnt[0], cnt[1], cnt[2], cnt[3]};
+  return PSC_OK;
+}
+
+psc_status psc_set_launch(psc_lattice *h, const psc_launch *l) {
+  if (!h || !l) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  const int it = (int)l->items_per_thread;
+  if (it != 0 && it != 1 && it != 2 && it != 4 && it != 8 && it != 16)
+    return fail(h, PSC_EINVAL, "items_per_thread must be 1, 2, 4, 8 or 16");
+  if (l->stage_blocks > 65536) return fail(h, PSC_EINVAL, "stage_blocks must be <= 65536");
+  if (it) h->items = it;
+  if (l->stage_blocks) {
+    h->grid = (int)l->stage_blocks;
+    h->grid_set = true;
+  }
+  return PSC_OK;
+}
+
+psc_status psc_get_launch(const psc_lattice *h, psc_launch *out) {
+  if (!h || !out) return PSC_EINVAL;
+  out->items_per_thread = (uint32_t)h->items;
+  out->stage_blocks = (uint32_t)h->grid;
   return PSC_OK;
 }
 

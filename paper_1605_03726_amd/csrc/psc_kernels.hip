@@ -127,14 +127,88 @@ __global__ void __launch_bounds__(kStageThreads) k_scan_candidates(const LatDev 
 // =============================================================================
 // k_begin: stage order, first-order pass, newborn ids
 // =============================================================================
+constexpr uint32_t kSortLds = 2048;  // birth keys sorted in LDS up to this count
+
+__device__ void bitonic_sort_keys(uint64_t *keys, uint32_t n2, int tid, int nthreads) {
+  for (uint32_t k = 2; k <= n2; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t q = tid; q < n2; q += nthreads) {
+        const uint32_t p = q ^ j;
+        if (p > q) {
+          const uint64_t a = keys[q], b = keys[p];
+          const bool up = (q & k) == 0;
+          if ((a > b) == up) {
+            keys[q] = b;
+            keys[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// one first-order firing of the molecule at (colour c, position pos): the
+// first product stays in place, the others go to distinct vacant neighbours
+// chosen by the placement words; too few vacant neighbours: no change
+__device__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in, uint32_t c,
+                                  uint32_t pos, uint32_t id, uint32_t rx, uint32_t *s_nb) {
+  const uint64_t at = c * L.cap + pos;
+  const uint32_t v = in.vox[at];
+  const uint32_t m = L.rx_nprod[rx];
+  const uint16_t *prod = L.rx_prod + rx * 12;
+  if (m == 0) {
+    L.occ[v] = 0;
+    in.id[at] = kDeadId;
+    atomicAdd(&L.fired[rx], 1ull);
+    return;
+  }
+  uint32_t dest[kMaxProducts];
+  if (m > 1) {
+    uint32_t vac[12];
+    int nv = 0;
+    const Coord cv = coord_of(L.geo, v);
+    for (uint32_t n = 0; n < 12; ++n) {
+      const uint32_t t = index_of(L.geo, step_coord(L.geo, cv, n));
+      if (L.occ[t] == 0) vac[nv++] = t;
+    }
+    if (nv < (int)(m - 1)) {
+      atomicAdd(&L.cnt[3], 1ull);
+      return;
+    }
+    const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
+    for (uint32_t a = 0; a + 1 < m; ++a) {
+      const uint32_t x = scale32(placement_word(L, e, id, r, (int)a), (uint32_t)nv);
+      dest[a] = vac[x];
+      for (int y = (int)x; y + 1 < nv; ++y) vac[y] = vac[y + 1];
+      --nv;
+    }
+  }
+  L.occ[v] = prod[0];
+  in.sp[at] = prod[0];  // the entry stays; its cached species follows
+  for (uint32_t a = 0; a + 1 < m; ++a) {
+    L.occ[dest[a]] = prod[a + 1];
+    const uint32_t b = atomicAdd(s_nb, 1u);
+    if (b < L.birth_cap) {
+      L.birth_key[b] = ((uint64_t)id << 31) | ((uint64_t)(a + 1) << 27) | b;
+      L.birth_vox[b] = dest[a];
+      L.birth_sp[b] = prod[a + 1];
+    } else {
+      atomicOr(L.error, kErrBirthOverflow);
+    }
+  }
+  atomicAdd(&L.fired[rx], 1ull);
+}
+
 __global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restrict__ Lp,
                                                           uint32_t *__restrict__ fire_pos,
                                                           uint32_t *__restrict__ fire_id,
                                                           uint8_t *__restrict__ fire_col,
                                                           uint8_t *__restrict__ fire_rx) {
   const LatDev &L = *Lp;
-  __shared__ uint32_t s_perm[16];
+  __shared__ uint32_t s_perm[16], s_colcnt[16];
   __shared__ uint32_t s_nfire, s_nb, s_next;
+  __shared__ uint64_t s_keys[kSortLds];
   const uint64_t e = *L.ev;
   const int tid = threadIdx.x;
   if (e >= L.tape_horizon) {
@@ -149,9 +223,11 @@ __global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restric
     s_nfire = 0;
     s_nb = 0;
     s_next = *L.next_id;
-    *L.birth_count = 0;
   }
-  if (tid < 16) out.count[tid] = 0;
+  if (tid < 16) {
+    out.count[tid] = 0;
+    s_colcnt[tid] = 0;
+  }
   if (tid == 16) L.cand_count[buf ^ 1] = 0;
   __syncthreads();
   if (tid < 16) L.perm[tid] = s_perm[tid];
@@ -176,110 +252,100 @@ __global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restric
   __syncthreads();
   const uint32_t nfire = s_nfire;
 
-  // ---- staged application: products go to neighbours, so molecules of
-  // different colours are applied stage by stage in the event's order ----
+  // ---- application.  A firing molecule reads and writes only its closed
+  // neighbourhood N[v] (its voxel and the 12 neighbours).  Molecules whose
+  // N[v] meets no other firing molecule's commute with everything and are
+  // applied at once; the others (rare) are applied stage by stage in the
+  // event's order.  Overlaps are found by counting, per hashed voxel, the
+  // neighbourhoods that contain it (a hash collision only sends a molecule
+  // to the staged path, which is always correct). ----
   if (nfire > 0) {
+    const uint32_t nb_bits = L.nbr_bits;
+    for (uint32_t q = tid; q < nfire; q += blockDim.x) {
+      const uint32_t c = fire_col[q];
+      const uint32_t v = in.vox[c * L.cap + fire_pos[q]];
+      const Coord cv = coord_of(L.geo, v);
+      atomicAdd(&L.nbr_cnt[hot_hash(v, nb_bits)], 1u);
+      for (uint32_t n = 0; n < 12; ++n)
+        atomicAdd(&L.nbr_cnt[hot_hash(index_of(L.geo, step_coord(L.geo, cv, n)), nb_bits)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < nfire; q += blockDim.x) {
+      const uint32_t c = fire_col[q];
+      const uint32_t v = in.vox[c * L.cap + fire_pos[q]];
+      const Coord cv = coord_of(L.geo, v);
+      bool alone = atomicAdd(&L.nbr_cnt[hot_hash(v, nb_bits)], 0u) == 1u;
+      for (uint32_t n = 0; n < 12 && alone; ++n)
+        alone = atomicAdd(&L.nbr_cnt[hot_hash(index_of(L.geo, step_coord(L.geo, cv, n)), nb_bits)],
+                          0u) == 1u;
+      if (alone) {
+        apply_first_order(L, e, in, c, fire_pos[q], fire_id[q], fire_rx[q], &s_nb);
+      } else {
+        fire_col[q] = (uint8_t)(c | 0x80u);  // deferred to the staged pass
+        atomicAdd(&s_colcnt[c], 1u);
+      }
+    }
+    __syncthreads();
     for (int g = 0; g < 16; ++g) {
       const uint32_t c = s_perm[g];
-      for (uint32_t q = tid; q < nfire; q += blockDim.x) {
-        if (fire_col[q] != c) continue;
-        const uint32_t pos = fire_pos[q], id = fire_id[q], rx = fire_rx[q];
-        const uint32_t v = in.vox[c * L.cap + pos];
-        const uint32_t m = L.rx_nprod[rx];
-        const uint16_t *prod = L.rx_prod + rx * 12;
-        if (m == 0) {
-          L.occ[v] = 0;
-          in.id[c * L.cap + pos] = kDeadId;
-          atomicAdd(&L.fired[rx], 1ull);
-          continue;
-        }
-        uint32_t dest[kMaxProducts];
-        if (m > 1) {
-          uint32_t vac[12];
-          int nv = 0;
-          const Coord cv = coord_of(L.geo, v);
-          for (uint32_t n = 0; n < 12; ++n) {
-            const uint32_t t = index_of(L.geo, step_coord(L.geo, cv, n));
-            if (L.occ[t] == 0) vac[nv++] = t;
-          }
-          if (nv < (int)(m - 1)) {
-            atomicAdd(&L.cnt[3], 1ull);
-            continue;
-          }
-          const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
-          for (uint32_t a = 0; a + 1 < m; ++a) {
-            const uint32_t x = scale32(placement_word(L, e, id, r, (int)a), (uint32_t)nv);
-            dest[a] = vac[x];
-            for (int y = (int)x; y + 1 < nv; ++y) vac[y] = vac[y + 1];
-            --nv;
-          }
-        }
-        L.occ[v] = prod[0];
-        for (uint32_t a = 0; a + 1 < m; ++a) {
-          L.occ[dest[a]] = prod[a + 1];
-          const uint32_t b = atomicAdd(&s_nb, 1u);
-          if (b < L.birth_cap) {
-            L.birth_key[b] = ((uint64_t)id << 31) | ((uint64_t)(a + 1) << 27) | b;
-            L.birth_vox[b] = dest[a];
-            L.birth_sp[b] = prod[a + 1];
-          } else {
-            set_error(L, kErrBirthOverflow);
-          }
-        }
-        atomicAdd(&L.fired[rx], 1ull);
-      }
+      if (s_colcnt[c] == 0) continue;
+      for (uint32_t q = tid; q < nfire; q += blockDim.x)
+        if (fire_col[q] == (c | 0x80u))
+          apply_first_order(L, e, in, c, fire_pos[q], fire_id[q], fire_rx[q], &s_nb);
       __syncthreads();
     }
+    // leave the counts at zero for the next event
+    for (uint32_t q = tid; q < nfire; q += blockDim.x) {
+      const uint32_t c = fire_col[q] & 0x0Fu;
+      const uint32_t v = in.vox[c * L.cap + fire_pos[q]];
+      const Coord cv = coord_of(L.geo, v);
+      atomicSub(&L.nbr_cnt[hot_hash(v, nb_bits)], 1u);
+      for (uint32_t n = 0; n < 12; ++n)
+        atomicSub(&L.nbr_cnt[hot_hash(index_of(L.geo, step_coord(L.geo, cv, n)), nb_bits)], 1u);
+    }
+    __syncthreads();
   }
 
   // ---- newborn ids: ascending parent id, then product index ----
   const uint32_t nb = min(s_nb, (uint32_t)L.birth_cap);
-  if (nb > 0) {
-    uint32_t n2 = 1;
-    while (n2 < nb) n2 <<= 1;
+  if (nb == 0) return;
+  uint32_t n2 = 1;
+  while (n2 < nb) n2 <<= 1;
+  uint64_t *keys = L.birth_key;
+  if (n2 <= kSortLds) {
+    for (uint32_t q = tid; q < n2; q += blockDim.x) s_keys[q] = q < nb ? L.birth_key[q] : ~0ull;
+    __syncthreads();
+    keys = s_keys;
+  } else {
     for (uint32_t q = nb + tid; q < n2; q += blockDim.x) L.birth_key[q] = ~0ull;
     __syncthreads();
-    // bitonic sort of the keys in global memory by this workgroup
-    for (uint32_t k = 2; k <= n2; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t q = tid; q < n2; q += blockDim.x) {
-          const uint32_t p = q ^ j;
-          if (p > q) {
-            const uint64_t a = L.birth_key[q], b = L.birth_key[p];
-            const bool up = (q & k) == 0;
-            if ((a > b) == up) {
-              L.birth_key[q] = b;
-              L.birth_key[p] = a;
-            }
-          }
-        }
-        __syncthreads();
+  }
+  bitonic_sort_keys(keys, n2, tid, blockDim.x);
+  const uint32_t base_id = s_next;
+  if ((uint64_t)base_id + nb >= 0xFFFFFFFFull) {
+    if (tid == 0) set_error(L, kErrIds);
+    return;
+  }
+  for (uint32_t q = tid; q < nb; q += blockDim.x) {
+    const uint32_t src = (uint32_t)(keys[q] & ((1u << 27) - 1u));
+    const uint32_t v = L.birth_vox[src];
+    const uint32_t c = colour_of_voxel(L.geo, v);
+    const uint32_t pos = atomicAdd(&in.count[c], 1u);
+    if (pos < L.cap) {
+      const uint64_t at = c * L.cap + pos;
+      in.vox[at] = v;
+      in.id[at] = base_id + q;
+      in.sp[at] = L.birth_sp[src];
+      if (in.disp) {
+        in.disp[(0 * 16 + c) * L.cap + pos] = 0;
+        in.disp[(1 * 16 + c) * L.cap + pos] = 0;
+        in.disp[(2 * 16 + c) * L.cap + pos] = 0;
       }
-    }
-    const uint32_t base_id = s_next;
-    if ((uint64_t)base_id + nb >= 0xFFFFFFFFull) {
-      if (tid == 0) set_error(L, kErrIds);
     } else {
-      for (uint32_t q = tid; q < nb; q += blockDim.x) {
-        const uint32_t src = (uint32_t)(L.birth_key[q] & ((1u << 27) - 1u));
-        const uint32_t v = L.birth_vox[src];
-        const uint32_t c = colour_of_voxel(L.geo, v);
-        const uint32_t pos = atomicAdd(&in.count[c], 1u);
-        if (pos < L.cap) {
-          in.vox[c * L.cap + pos] = v;
-          in.id[c * L.cap + pos] = base_id + q;
-          if (in.disp) {
-            in.disp[(0 * 16 + c) * L.cap + pos] = 0;
-            in.disp[(1 * 16 + c) * L.cap + pos] = 0;
-            in.disp[(2 * 16 + c) * L.cap + pos] = 0;
-          }
-        } else {
-          set_error(L, kErrBinOverflow);
-        }
-      }
-      if (tid == 0) *L.next_id = base_id + nb;
+      set_error(L, kErrBinOverflow);
     }
   }
+  if (tid == 0) *L.next_id = base_id + nb;
 }
 
 // =============================================================================
@@ -304,13 +370,16 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
   const uint32_t cnext = (uint32_t)((e + 1) & 1);
   const uint64_t cap = L.cap;
   const bool disp = in.disp != nullptr;
+  uint32_t *hot_now = L.hot[buf];
+  const uint32_t *hot_prev = L.hot[buf ^ 1];
+  const uint32_t hbits = L.hot_bits;
 
   unsigned long long n_att = 0, n_hop = 0, n_col = 0;
   const int tid = threadIdx.x;
   const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
 
   for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk) {
-    uint32_t vox[ITEMS], id[ITEMS], ocol[ITEMS], lpos[ITEMS];
+    uint32_t vox[ITEMS], id[ITEMS], ocol[ITEMS], lpos[ITEMS], osp[ITEMS];
     int32_t d0[ITEMS], d1[ITEMS], d2[ITEMS];
     bool cand[ITEMS], flag[ITEMS];
     uint32_t ftgt[ITEMS];
@@ -327,10 +396,12 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
       flag[it] = false;
       vox[it] = 0;
       id[it] = kDeadId;
+      osp[it] = 0;
       d0[it] = d1[it] = d2[it] = 0;
       if (idx < n) {
         vox[it] = in.vox[c * cap + idx];
         id[it] = in.id[c * cap + idx];
+        osp[it] = in.sp[c * cap + idx];
         if (disp) {
           d0[it] = in.disp[(0 * 16 + c) * cap + idx];
           d1[it] = in.disp[(1 * 16 + c) * cap + idx];
@@ -343,18 +414,24 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
     for (int it = 0; it < ITEMS; ++it) {
       if (id[it] == kDeadId) continue;
       const uint32_t v = vox[it];
-      // the draw and the target do not depend on the occupancy, so both
-      // voxel words are requested together
       const U4 r = philox((uint32_t)e, id[it], kPhaseWalk, 0, L.key0, L.key1);
       const uint32_t dir = scale32(r.x, 12);
       const Coord cv = coord_of(L.geo, v);
       const Coord ct = step_coord(L.geo, cv, dir);
       const uint32_t t = index_of(L.geo, ct);
-      const uint16_t w = L.occ[v];
       const uint16_t wt = L.occ[t];
-      const uint32_t sp = w & 63u;  // species ids are < 64
+      uint32_t sp = osp[it] & 63u;
       ocol[it] = c;  // stays in place unless it hops or is consumed
-      if ((w & kReactedFlag) || !((due >> sp) & 1ull)) continue;
+      const uint32_t h = hot_hash(v, hbits);
+      if (((hot_now[h >> 5] | hot_prev[h >> 5]) >> (h & 31u)) & 1u) {
+        // the cached species may be stale, or the molecule may have reacted
+        // as a partner earlier in this walk: consult the lattice word
+        const uint16_t w = L.occ[v];
+        sp = w & 63u;
+        osp[it] = sp;
+        if (w & kReactedFlag) continue;
+      }
+      if (!((due >> sp) & 1ull)) continue;
       ++n_att;
       if (wt == 0) {
         L.occ[t] = (uint16_t)sp;
@@ -375,14 +452,18 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
       if (rx < 0) continue;
       if (!L.rx_always[rx] && !(r.y < L.rx_thr[rx])) continue;
       // first product on the partner's voxel with the partner's identity;
-      // its own entry (wherever it is) stays valid and it is flagged so that
-      // it does not walk again in this event
+      // its own entry (wherever it is) stays valid: it is flagged so that it
+      // does not walk again in this event, and its voxel is marked hot so
+      // that its cached species is refreshed
       const uint16_t *prod = L.rx_prod + rx * 12;
       L.occ[t] = (uint16_t)(prod[0] | kReactedFlag);
+      const uint32_t ht = hot_hash(t, hbits);
+      atomicOr(&hot_now[ht >> 5], 1u << (ht & 31u));
       flag[it] = true;
       ftgt[it] = t;
       if (L.rx_nprod[rx] == 2) {
         L.occ[v] = prod[1];
+        osp[it] = prod[1];
       } else {
         L.occ[v] = 0;
         ocol[it] = 0xFFu;  // the mover's identity ends here
@@ -419,6 +500,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
       lpos[it] = (uint32_t)pos;
       out.vox[oc * cap + pos] = vox[it];
       out.id[oc * cap + pos] = id[it];
+      out.sp[oc * cap + pos] = (uint16_t)osp[it];
       if (disp) {
         out.disp[(0 * 16 + oc) * cap + pos] = d0[it];
         out.disp[(1 * 16 + oc) * cap + pos] = d1[it];
@@ -462,20 +544,35 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
 }
 
 // =============================================================================
-// k_end: clear reacted flags, advance the event counter
+// k_end: clear reacted flags and the previous event's hot bitmap, advance the
+// event counter (the last workgroup to finish does the bookkeeping)
 // =============================================================================
-__global__ void __launch_bounds__(kBeginThreads) k_end(const LatDev *__restrict__ Lp) {
+constexpr int kEndBlocks = 32;
+
+__global__ void __launch_bounds__(kStageThreads) k_end(const LatDev *__restrict__ Lp) {
   const LatDev &L = *Lp;
-  if (*L.ev >= L.tape_horizon) return;
+  const uint64_t e = *L.ev;
+  if (e >= L.tape_horizon) return;
   const uint32_t nf = min(*L.flag_count, (uint32_t)L.flag_cap);
-  for (uint32_t q = threadIdx.x; q < nf; q += blockDim.x) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t me = blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint32_t q = me; q < nf; q += stride) {
     const uint32_t v = L.flag_vox[q];
     L.occ[v] = (uint16_t)(L.occ[v] & kSpeciesMask);
   }
+  uint32_t *prev = L.hot[(e + 1) & 1];
+  const uint32_t words = (1u << L.hot_bits) >> 5;
+  for (uint32_t q = me; q < words; q += stride) prev[q] = 0;
   __syncthreads();
   if (threadIdx.x == 0) {
-    *L.flag_count = 0;
-    *L.ev = *L.ev + 1;
+    __threadfence();
+    const uint32_t done = atomicAdd(L.end_done, 1u);
+    if (done == gridDim.x - 1) {
+      __threadfence();
+      *L.flag_count = 0;
+      *L.end_done = 0;
+      *L.ev = e + 1;
+    }
   }
 }
 
@@ -492,21 +589,30 @@ hipError_t launch_begin(const LatDev *dL, const FireScratch &f, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_stage<4>, dim3(grid), dim3(kStageThreads), 0, s, dL, g);
+hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, hipStream_t s) {
+  switch (items) {
+  case 1: hipLaunchKernelGGL(k_stage<1>, dim3(grid), dim3(kStageThreads), 0, s, dL, g); break;
+  case 2: hipLaunchKernelGGL(k_stage<2>, dim3(grid), dim3(kStageThreads), 0, s, dL, g); break;
+  case 8: hipLaunchKernelGGL(k_stage<8>, dim3(grid), dim3(kStageThreads), 0, s, dL, g); break;
+  case 16: hipLaunchKernelGGL(k_stage<16>, dim3(grid), dim3(kStageThreads), 0, s, dL, g); break;
+  default: hipLaunchKernelGGL(k_stage<4>, dim3(grid), dim3(kStageThreads), 0, s, dL, g); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_end(const LatDev *dL, hipStream_t s) {
-  hipLaunchKernelGGL(k_end, dim3(1), dim3(kBeginThreads), 0, s, dL);
+  hipLaunchKernelGGL(k_end, dim3(kEndBlocks), dim3(kStageThreads), 0, s, dL);
   return hipGetLastError();
 }
 
-hipError_t launch_event(const LatDev *dL, const FireScratch &f, int grid, hipStream_t s) {
+hipError_t launch_event(const LatDev *dL, const FireScratch &f, int grid, int items,
+                        hipStream_t s) {
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, f.pos, f.id, f.col, f.rx);
-  for (uint32_t g = 0; g < 16; ++g)
-    hipLaunchKernelGGL(k_stage<4>, dim3(grid), dim3(kStageThreads), 0, s, dL, g);
-  hipLaunchKernelGGL(k_end, dim3(1), dim3(kBeginThreads), 0, s, dL);
+  for (uint32_t g = 0; g < 16; ++g) {
+    const hipError_t err = launch_stage(dL, g, grid, items, s);
+    if (err != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(k_end, dim3(kEndBlocks), dim3(kStageThreads), 0, s, dL);
   return hipGetLastError();
 }
 

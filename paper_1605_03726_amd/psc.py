@@ -39,6 +39,10 @@ class KernelTimes(C.Structure):
                 ("end_launches", C.c_uint64)]
 
 
+class Launch(C.Structure):
+    _fields_ = [("items_per_thread", C.c_uint32), ("stage_blocks", C.c_uint32)]
+
+
 class StateView(C.Structure):
     _fields_ = [("occupancy", C.POINTER(C.c_uint16)), ("n_molecules", C.c_uint64),
                 ("id", C.POINTER(C.c_uint32)), ("voxel", C.POINTER(C.c_uint32)),
@@ -115,6 +119,10 @@ def lib() -> C.CDLL:
     L.psc_device_bytes.restype = C.c_int32
     L.psc_read_counters.argtypes = [vp, C.POINTER(Counters), C.POINTER(C.c_uint64)]
     L.psc_read_counters.restype = C.c_int32
+    L.psc_set_launch.argtypes = [vp, C.POINTER(Launch)]
+    L.psc_set_launch.restype = C.c_int32
+    L.psc_get_launch.argtypes = [vp, C.POINTER(Launch)]
+    L.psc_get_launch.restype = C.c_int32
     L.psc_set_kernel_timing.argtypes = [vp, C.c_int]
     L.psc_set_kernel_timing.restype = C.c_int32
     L.psc_get_kernel_times.argtypes = [vp, C.POINTER(KernelTimes)]
@@ -138,7 +146,10 @@ def _torch_hooks(device: int):
             return None
 
     def free(ptr, user):
-        torch.cuda.caching_allocator_delete(ptr)
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except (AttributeError, TypeError):
+            pass  # interpreter shutdown: torch's allocator is already gone
 
     return _ALLOC(alloc), _FREE(free)
 
@@ -250,6 +261,15 @@ class Lattice:
         out = {f: getattr(c, f) for f, _ in Counters._fields_}
         out["event"] = e.value
         return out
+
+    def set_launch(self, items_per_thread: int = 0, stage_blocks: int = 0):
+        l = Launch(items_per_thread, stage_blocks)
+        self._check(self.L.psc_set_launch(self.h, C.byref(l)))
+
+    def get_launch(self) -> dict:
+        l = Launch()
+        self._check(self.L.psc_get_launch(self.h, C.byref(l)))
+        return {"items_per_thread": l.items_per_thread, "stage_blocks": l.stage_blocks}
 
     def set_kernel_timing(self, on: bool):
         self._check(self.L.psc_set_kernel_timing(self.h, 1 if on else 0))

@@ -222,6 +222,48 @@ psc_status psc_set_kernel_timing(psc_lattice *h, int enable);
  * on. */
 psc_status psc_get_kernel_times(psc_lattice *h, psc_kernel_times *out);
 
+/* ---- ensembles ---------------------------------------------------------------
+ * Many independent lattices (replicates of one model, or different models of
+ * any sizes) advanced together: every event of every member is one batched
+ * launch sequence (first-order pass of all members, the 16 colour stages of
+ * all members as one work list each, event end), captured once as a HIP
+ * graph and replayed.  Each member's result is bit-identical to stepping it
+ * alone: the members share no state and every draw is keyed by the member's
+ * own seed, event and molecule ids. */
+typedef struct psc_ensemble psc_ensemble;
+
+/* Groups 1..4096 distinct lattices of one device.  Members are frozen (their
+ * state moves to the device) and, while grouped, may be read (psc_read_state,
+ * psc_read_counters) but not stepped alone (ESTATE).  The members must
+ * outlive the ensemble.  EINVAL on a bad member list. */
+psc_status psc_ensemble_create(psc_lattice *const *members, uint32_t n, psc_ensemble **out);
+
+/* Advances every member by n_events, asynchronously on `stream`. */
+psc_status psc_ensemble_step(psc_ensemble *e, uint64_t n_events, void *stream);
+
+/* Waits for the ensemble's work; reports device-side failures of members. */
+psc_status psc_ensemble_sync(psc_ensemble *e);
+
+/* Launch shape of the batched stage kernel (items per thread 1, 2, 4 or 8;
+ * workgroups per launch).  Result-invariant. */
+psc_status psc_ensemble_set_launch(psc_ensemble *e, const psc_launch *l);
+psc_status psc_ensemble_get_launch(const psc_ensemble *e, psc_launch *out);
+
+/* Autotuner: the next psc_ensemble_step times each candidate launch shape on
+ * trial_events of its own events (plus one untimed event per candidate) and
+ * runs the rest with the fastest.  The events count toward n_events and the
+ * results are the same as with any shape. */
+psc_status psc_ensemble_autotune(psc_ensemble *e, uint32_t trial_events);
+
+/* The shape the autotuner chose and its time per event (0 before tuning). */
+psc_status psc_ensemble_tuned(const psc_ensemble *e, psc_launch *chosen, double *ms_per_event);
+
+/* Releases the ensemble (members stay valid and can be stepped alone). */
+void psc_ensemble_destroy(psc_ensemble *e);
+
+/* Message for the last error on e; NULL: the last create failure. */
+const char *psc_ensemble_last_error(const psc_ensemble *e);
+
 #ifdef __cplusplus
 }
 #endif

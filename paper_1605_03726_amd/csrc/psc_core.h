@@ -235,6 +235,10 @@ struct LatDev {
   uint32_t hot_bits;      // log2 of the bitmap size in bits
   uint32_t *end_done;     // completion counter of the multi-block k_end
 
+  // scratch of the first-order pass: molecules firing this event
+  uint32_t *fire_pos, *fire_id;
+  uint8_t *fire_col, *fire_rx;
+
   // first-order conflict test: per hashed voxel, how many firing molecules
   // have it in their closed neighbourhood (zero between events)
   uint32_t *nbr_cnt;
@@ -268,17 +272,12 @@ struct LatDev {
   uint32_t *error;
 };
 
-// scratch of k_begin: molecules firing a first-order reaction this event
-struct FireScratch {
-  uint32_t *pos, *id;
-  uint8_t *col, *rx;
-};
-
 hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
-hipError_t launch_event(const LatDev *dL, const FireScratch &f, int grid, int items,
-                        hipStream_t s);
-hipError_t launch_begin(const LatDev *dL, const FireScratch &f, hipStream_t s);
+hipError_t launch_event(const LatDev *dL, int grid, int items, hipStream_t s);
+hipError_t launch_event_multi(const LatDev *lats, uint32_t R, int grid, int items, hipStream_t s);
+hipError_t launch_begin(const LatDev *dL, hipStream_t s);
 hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, hipStream_t s);
+uint32_t max_members();
 hipError_t launch_end(const LatDev *dL, hipStream_t s);
 int stage_items();
 int stage_threads();

@@ -123,13 +123,14 @@ struct psc_lattice {
   uint64_t device_bytes = 0;
   LatDev L{};
   LatDev *dL = nullptr;
-  FireScratch fire{};
   uint64_t *d_tape_due = nullptr;
   uint32_t *d_tape_thr = nullptr, *d_tape_cmax = nullptr;
   uint64_t d_tape_rows = 0;
   int grid = 1;
   int items = 4;
   bool grid_set = false;
+  uint64_t version = 0;   // bumped whenever the device record changes
+  bool in_ensemble = false;
   hipStream_t last_stream = nullptr;
 
   // per-launch timing: kind (0 begin, 1 stage, 2 end) and its event pair
@@ -282,6 +283,7 @@ psc_status sync_tape(psc_lattice *h, hipStream_t stream) {
   h->L.tape_cmax = cmax;
   h->L.tape_horizon = rows;
   HIP_OK(h, hipMemcpy(h->dL, &h->L, sizeof(LatDev), hipMemcpyHostToDevice));
+  h->version++;
   return PSC_OK;
 }
 
@@ -398,12 +400,13 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.hot[0] = alloc_n<uint32_t>(h, (1ull << L.hot_bits) / 32);
   L.hot[1] = alloc_n<uint32_t>(h, (1ull << L.hot_bits) / 32);
   L.end_done = alloc_n<uint32_t>(h, 1);
-  L.nbr_bits = 22;
+  L.nbr_bits = 12;
+  while (L.nbr_bits < 22 && (1ull << L.nbr_bits) < 8 * cap) ++L.nbr_bits;
   L.nbr_cnt = alloc_n<uint32_t>(h, 1ull << L.nbr_bits);
-  h->fire.pos = alloc_n<uint32_t>(h, cap);
-  h->fire.id = alloc_n<uint32_t>(h, cap);
-  h->fire.col = alloc_n<uint8_t>(h, cap);
-  h->fire.rx = alloc_n<uint8_t>(h, cap);
+  L.fire_pos = alloc_n<uint32_t>(h, cap);
+  L.fire_id = alloc_n<uint32_t>(h, cap);
+  L.fire_col = alloc_n<uint8_t>(h, cap);
+  L.fire_rx = alloc_n<uint8_t>(h, cap);
   L.n_species = (uint32_t)(S - 1);
   L.n_rx = R;
   L.n_fo = h->n_fo;
@@ -424,8 +427,8 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.error = alloc_n<uint32_t>(h, 1);
   h->dL = alloc_n<LatDev>(h, 1);
   if (!L.occ || !L.cand_count || !L.flag_vox || !L.flag_count || !L.birth_key || !L.birth_vox ||
-      !L.birth_sp || !L.birth_count || !h->fire.pos || !h->fire.id || !h->fire.col ||
-      !h->fire.rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod ||
+      !L.birth_sp || !L.birth_count || !L.fire_pos || !L.fire_id || !L.fire_col ||
+      !L.fire_rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod ||
       !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.next_id || !L.cnt ||
       !L.fired || !L.error || !h->dL || !L.hot[0] || !L.hot[1] || !L.end_done || !L.nbr_cnt)
     return fail(h, PSC_ENOMEM, "device allocation failed");
@@ -760,6 +763,8 @@ psc_status psc_load_state(psc_lattice *h, const psc_state_view *st) {
 psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   if (!h) return PSC_EINVAL;
   if (h->poisoned) return PSC_EDEVICE;
+  if (h->in_ensemble && n_events)
+    return fail(h, PSC_ESTATE, "the lattice is stepped by its ensemble");
   hipStream_t stream = (hipStream_t)stream_;
   if (!h->frozen) {
     // the device is first touched here: creation, the model and the initial
@@ -785,7 +790,7 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   }
   if (!h->timing) {
     for (uint64_t e = 0; e < n_events; ++e)
-      HIP_OK(h, launch_event(h->dL, h->fire, h->grid, h->items, stream));
+      HIP_OK(h, launch_event(h->dL, h->grid, h->items, stream));
   } else {
     auto ev = [&](hipEvent_t *out) -> hipError_t {
       if (!h->event_pool.empty()) {
@@ -802,7 +807,7 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
         HIP_OK(h, ev(&t.a));
         HIP_OK(h, ev(&t.b));
         HIP_OK(h, hipEventRecord(t.a, stream));
-        if (g < 0) HIP_OK(h, launch_begin(h->dL, h->fire, stream));
+        if (g < 0) HIP_OK(h, launch_begin(h->dL, stream));
         else if (g < 16) HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, h->items, stream));
         else HIP_OK(h, launch_end(h->dL, stream));
         HIP_OK(h, hipEventRecord(t.b, stream));
@@ -1046,6 +1051,285 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
     HIP_OK(h, hipMemcpy(f.data(), L.fired, f.size() * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost));
     for (size_t r = 0; r < f.size(); ++r) out->reactions_fired[r] = f[r];
+  }
+  return PSC_OK;
+}
+
+}  // extern "C"
+
+// =============================================================================
+// ensembles: many independent lattices advanced together
+// =============================================================================
+struct psc_ensemble {
+  std::vector<psc_lattice *> members;
+  int device = 0;
+  std::string err;
+  bool poisoned = false;
+  LatDev *d_lats = nullptr;                 // device array of member records
+  std::vector<uint64_t> versions;           // member record versions uploaded
+  int grid = 1024;
+  int items = 4;
+  // one captured event of the batched launches, replayed per event
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_grid = 0, graph_items = 0;
+  uint32_t autotune_events = 0;             // > 0: tune on the next step
+  psc_launch tuned{0, 0};
+  double tuned_ms_per_event = 0.0;
+};
+
+namespace {
+
+psc_status efail(psc_ensemble *E, psc_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  E->err = buf;
+  if (code == PSC_EDEVICE) E->poisoned = true;
+  return code;
+}
+
+#define EHIP_OK(E, call)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return efail((E), PSC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+psc_status ensure_member_records(psc_ensemble *E, hipStream_t stream, uint64_t n_events) {
+  // every member's tape must cover the coming events; records re-uploaded
+  // when a member's record changed
+  bool dirty = false;
+  for (size_t r = 0; r < E->members.size(); ++r) {
+    psc_lattice *h = E->members[r];
+    if (h->poisoned) return efail(E, PSC_EDEVICE, "member %zu is poisoned: %s", r, h->err.c_str());
+    const uint64_t end = h->events_done + n_events;
+    if (end >= 0xFFFFFFFFull) return efail(E, PSC_EINVAL, "event index exceeds 2^32");
+    if (end > h->tape_end) {
+      extend_tape(h, std::max(end, h->tape_end * 2));
+      psc_status st = sync_tape(h, stream);
+      if (st) return efail(E, st, "member %zu: %s", r, h->err.c_str());
+    }
+    if (E->versions[r] != h->version) dirty = true;
+  }
+  if (!dirty) return PSC_OK;
+  EHIP_OK(E, hipStreamSynchronize(stream));
+  std::vector<LatDev> recs(E->members.size());
+  for (size_t r = 0; r < E->members.size(); ++r) {
+    recs[r] = E->members[r]->L;
+    E->versions[r] = E->members[r]->version;
+  }
+  EHIP_OK(E, hipMemcpy(E->d_lats, recs.data(), recs.size() * sizeof(LatDev),
+                       hipMemcpyHostToDevice));
+  return PSC_OK;
+}
+
+psc_status ensure_graph(psc_ensemble *E) {
+  if (E->exec && E->graph_grid == E->grid && E->graph_items == E->items) return PSC_OK;
+  if (E->exec) {
+    EHIP_OK(E, hipGraphExecDestroy(E->exec));
+    E->exec = nullptr;
+  }
+  if (E->graph) {
+    EHIP_OK(E, hipGraphDestroy(E->graph));
+    E->graph = nullptr;
+  }
+  if (!E->cap_stream) EHIP_OK(E, hipStreamCreateWithFlags(&E->cap_stream, hipStreamNonBlocking));
+  EHIP_OK(E, hipStreamBeginCapture(E->cap_stream, hipStreamCaptureModeThreadLocal));
+  const hipError_t le =
+      launch_event_multi(E->d_lats, (uint32_t)E->members.size(), E->grid, E->items, E->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(E->cap_stream, &g);
+  if (le != hipSuccess || ce != hipSuccess)
+    return efail(E, PSC_EDEVICE, "capturing the ensemble event failed: %s / %s",
+                 hipGetErrorString(le), hipGetErrorString(ce));
+  E->graph = g;
+  EHIP_OK(E, hipGraphInstantiate(&E->exec, E->graph, nullptr, nullptr, 0));
+  E->graph_grid = E->grid;
+  E->graph_items = E->items;
+  return PSC_OK;
+}
+
+psc_status run_events(psc_ensemble *E, uint64_t n, hipStream_t stream) {
+  psc_status st = ensure_graph(E);
+  if (st) return st;
+  for (uint64_t e = 0; e < n; ++e) EHIP_OK(E, hipGraphLaunch(E->exec, stream));
+  for (psc_lattice *h : E->members) h->events_done += n;
+  return PSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+psc_status psc_ensemble_create(psc_lattice *const *members, uint32_t n, psc_ensemble **out) {
+  if (!out) return PSC_EINVAL;
+  *out = nullptr;
+  if (!members || n == 0 || n > max_members()) {
+    g_create_error = "an ensemble has 1.." + std::to_string(max_members()) + " members";
+    return PSC_EINVAL;
+  }
+  for (uint32_t a = 0; a < n; ++a) {
+    if (!members[a] || members[a]->poisoned || members[a]->in_ensemble) {
+      g_create_error = "member " + std::to_string(a) + " is missing, poisoned or in an ensemble";
+      return PSC_EINVAL;
+    }
+    for (uint32_t b = 0; b < a; ++b)
+      if (members[a] == members[b]) {
+        g_create_error = "a lattice appears twice";
+        return PSC_EINVAL;
+      }
+    if (members[a]->desc.device != members[0]->desc.device) {
+      g_create_error = "members must share one device";
+      return PSC_EINVAL;
+    }
+  }
+  psc_ensemble *E = new (std::nothrow) psc_ensemble();
+  if (!E) return PSC_ENOMEM;
+  E->members.assign(members, members + n);
+  E->device = members[0]->desc.device;
+  E->versions.assign(n, ~0ull);
+  // freeze every member (state moves to the device)
+  for (uint32_t a = 0; a < n; ++a) {
+    psc_status st = psc_step(members[a], 0, nullptr);
+    if (st) {
+      g_create_error = "member " + std::to_string(a) + ": " + members[a]->err;
+      delete E;
+      return st;
+    }
+  }
+  if (hipSetDevice(E->device) != hipSuccess ||
+      hipMalloc(&E->d_lats, (size_t)n * sizeof(LatDev)) != hipSuccess) {
+    g_create_error = "device allocation of the member records failed";
+    delete E;
+    return PSC_ENOMEM;
+  }
+  // default launch: about two passes' worth of chunks for the whole ensemble
+  uint64_t mol = 0;
+  for (auto *h : E->members) mol += h->desc.max_molecules;
+  const uint64_t chunks = std::max<uint64_t>(mol / 16 / (256ull * 4), 1);
+  E->grid = (int)std::min<uint64_t>(std::max<uint64_t>(chunks, 256), 4096);
+  for (auto *h : E->members) h->in_ensemble = true;
+  *out = E;
+  return PSC_OK;
+}
+
+void psc_ensemble_destroy(psc_ensemble *E) {
+  if (!E) return;
+  if (!E->poisoned) {
+    (void)hipSetDevice(E->device);
+    (void)hipDeviceSynchronize();
+  }
+  if (E->exec) (void)hipGraphExecDestroy(E->exec);
+  if (E->graph) (void)hipGraphDestroy(E->graph);
+  if (E->cap_stream) (void)hipStreamDestroy(E->cap_stream);
+  if (E->d_lats) (void)hipFree(E->d_lats);
+  for (auto *h : E->members) h->in_ensemble = false;
+  delete E;
+}
+
+const char *psc_ensemble_last_error(const psc_ensemble *E) {
+  return E ? E->err.c_str() : g_create_error.c_str();
+}
+
+psc_status psc_ensemble_set_launch(psc_ensemble *E, const psc_launch *l) {
+  if (!E || !l) return PSC_EINVAL;
+  const int it = (int)l->items_per_thread;
+  if (it != 0 && it != 1 && it != 2 && it != 4 && it != 8)
+    return efail(E, PSC_EINVAL, "items_per_thread must be 1, 2, 4 or 8");
+  if (l->stage_blocks > 65536) return efail(E, PSC_EINVAL, "stage_blocks must be <= 65536");
+  if (it) E->items = it;
+  if (l->stage_blocks) E->grid = (int)l->stage_blocks;
+  return PSC_OK;
+}
+
+psc_status psc_ensemble_get_launch(const psc_ensemble *E, psc_launch *out) {
+  if (!E || !out) return PSC_EINVAL;
+  out->items_per_thread = (uint32_t)E->items;
+  out->stage_blocks = (uint32_t)E->grid;
+  return PSC_OK;
+}
+
+psc_status psc_ensemble_autotune(psc_ensemble *E, uint32_t trial_events) {
+  if (!E) return PSC_EINVAL;
+  E->autotune_events = trial_events;
+  return PSC_OK;
+}
+
+psc_status psc_ensemble_tuned(const psc_ensemble *E, psc_launch *chosen, double *ms_per_event) {
+  if (!E) return PSC_EINVAL;
+  if (chosen) *chosen = E->tuned;
+  if (ms_per_event) *ms_per_event = E->tuned_ms_per_event;
+  return PSC_OK;
+}
+
+psc_status psc_ensemble_step(psc_ensemble *E, uint64_t n_events, void *stream_) {
+  if (!E) return PSC_EINVAL;
+  if (E->poisoned) return PSC_EDEVICE;
+  hipStream_t stream = (hipStream_t)stream_;
+  EHIP_OK(E, hipSetDevice(E->device));
+  psc_status st = ensure_member_records(E, stream, n_events);
+  if (st) return st;
+  uint64_t left = n_events;
+  if (E->autotune_events && left) {
+    // spend the first events timing candidate shapes (the shape never
+    // changes results, so these events are ordinary events of the run)
+    static const int kItems[] = {2, 4, 8};
+    static const int kGrids[] = {256, 512, 1024, 2048, 4096};
+    hipEvent_t a, b;
+    EHIP_OK(E, hipEventCreate(&a));
+    EHIP_OK(E, hipEventCreate(&b));
+    double best = 1e300;
+    int best_items = E->items, best_grid = E->grid;
+    for (int it : kItems)
+      for (int gr : kGrids) {
+        const uint64_t k = std::min<uint64_t>(E->autotune_events, left);
+        if (k == 0) break;
+        E->items = it;
+        E->grid = gr;
+        // one untimed event absorbs the graph rebuild
+        st = run_events(E, 1, stream);
+        if (st) return st;
+        left -= 1;
+        const uint64_t kt = std::min<uint64_t>(k, left);
+        if (kt == 0) break;
+        EHIP_OK(E, hipEventRecord(a, stream));
+        st = run_events(E, kt, stream);
+        if (st) return st;
+        EHIP_OK(E, hipEventRecord(b, stream));
+        EHIP_OK(E, hipEventSynchronize(b));
+        float ms = 0.f;
+        EHIP_OK(E, hipEventElapsedTime(&ms, a, b));
+        left -= kt;
+        const double per = ms / (double)kt;
+        if (per < best) {
+          best = per;
+          best_items = it;
+          best_grid = gr;
+        }
+      }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    E->items = best_items;
+    E->grid = best_grid;
+    E->tuned = psc_launch{(uint32_t)best_items, (uint32_t)best_grid};
+    E->tuned_ms_per_event = best;
+    E->autotune_events = 0;
+  }
+  return run_events(E, left, stream);
+}
+
+psc_status psc_ensemble_sync(psc_ensemble *E) {
+  if (!E) return PSC_EINVAL;
+  if (E->poisoned) return PSC_EDEVICE;
+  EHIP_OK(E, hipSetDevice(E->device));
+  EHIP_OK(E, hipDeviceSynchronize());
+  for (size_t r = 0; r < E->members.size(); ++r) {
+    psc_status st = check_device_error(E->members[r]);
+    if (st) return efail(E, st, "member %zu: %s", r, E->members[r]->err.c_str());
   }
   return PSC_OK;
 }

@@ -200,12 +200,12 @@ __device__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in, u
   atomicAdd(&L.fired[rx], 1ull);
 }
 
-__global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restrict__ Lp,
-                                                          uint32_t *__restrict__ fire_pos,
-                                                          uint32_t *__restrict__ fire_id,
-                                                          uint8_t *__restrict__ fire_col,
-                                                          uint8_t *__restrict__ fire_rx) {
-  const LatDev &L = *Lp;
+// the event's opening work for one lattice, by one workgroup
+__device__ void begin_body(const LatDev &L) {
+  uint32_t *__restrict__ fire_pos = L.fire_pos;
+  uint32_t *__restrict__ fire_id = L.fire_id;
+  uint8_t *__restrict__ fire_col = L.fire_col;
+  uint8_t *__restrict__ fire_rx = L.fire_rx;
   __shared__ uint32_t s_perm[16], s_colcnt[16];
   __shared__ uint32_t s_nfire, s_nb, s_next;
   __shared__ uint64_t s_keys[kSortLds];
@@ -348,23 +348,37 @@ __global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restric
   if (tid == 0) *L.next_id = base_id + nb;
 }
 
+__global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restrict__ Lp) {
+  begin_body(*Lp);
+}
+
+// one workgroup per member lattice of an ensemble
+__global__ void __launch_bounds__(kBeginThreads) k_begin_multi(const LatDev *__restrict__ lats) {
+  begin_body(lats[blockIdx.x]);
+}
+
 // =============================================================================
 // k_stage: one colour stage of the walk
 // =============================================================================
-template <int ITEMS>
-__global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restrict__ Lp, uint32_t g) {
-  const LatDev &L = *Lp;
-  __shared__ uint32_t s_cnt[16], s_base[16];
-  __shared__ uint32_t s_ncand, s_cand_base, s_nflag, s_flag_base;
-  __shared__ unsigned long long s_red[kStageThreads / 64];
+// shared scratch of one walk-stage workgroup
+struct StageShared {
+  uint32_t cnt[16], base[16];
+  uint32_t ncand, cand_base, nflag, flag_base;
+  unsigned long long att, hop, col;
+};
 
-  const uint64_t e = *L.ev;
-  if (e >= L.tape_horizon) return;  // k_begin has recorded the error
+// Molecules [base, base + kStageThreads * ITEMS) of colour bin c of lattice L
+// in event e: each attempts one hop; collisions with a registered partner
+// fire the second-order reaction; survivors are appended to the next event's
+// bins through block-local slots (LDS) and one global reservation per colour.
+template <int ITEMS>
+__device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t base, uint32_t n,
+                            StageShared &S) {
+  StageShared *sh = &S;
+  const int tid = threadIdx.x;
   const uint32_t buf = (uint32_t)(e & 1);
-  const uint32_t c = L.perm[g];
   const Bins &in = L.bins[buf];
   const Bins &out = L.bins[buf ^ 1];
-  const uint32_t n = min(in.count[c], (uint32_t)L.cap);
   const uint64_t due = L.tape_due[e];
   const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
   const uint32_t cnext = (uint32_t)((e + 1) & 1);
@@ -373,173 +387,251 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
   uint32_t *hot_now = L.hot[buf];
   const uint32_t *hot_prev = L.hot[buf ^ 1];
   const uint32_t hbits = L.hot_bits;
-
   unsigned long long n_att = 0, n_hop = 0, n_col = 0;
-  const int tid = threadIdx.x;
-  const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
+  uint32_t *s_cnt = sh->cnt, *s_base = sh->base;
+  uint32_t &s_ncand = sh->ncand, &s_cand_base = sh->cand_base;
+  uint32_t &s_nflag = sh->nflag, &s_flag_base = sh->flag_base;
+  if (tid < 16) s_cnt[tid] = 0;
+  if (tid == 16) s_ncand = 0;
+  if (tid == 17) s_nflag = 0;
+  if (tid == 18) {
+    sh->att = 0;
+    sh->hop = 0;
+    sh->col = 0;
+  }
+  __syncthreads();
 
-  for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk) {
-    uint32_t vox[ITEMS], id[ITEMS], ocol[ITEMS], lpos[ITEMS], osp[ITEMS];
-    int32_t d0[ITEMS], d1[ITEMS], d2[ITEMS];
-    bool cand[ITEMS], flag[ITEMS];
-    uint32_t ftgt[ITEMS];
-    if (tid < 16) s_cnt[tid] = 0;
-    if (tid == 16) s_ncand = 0;
-    if (tid == 17) s_nflag = 0;
-    __syncthreads();
-
-#pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const uint64_t idx = base + (uint64_t)it * kStageThreads + tid;
-      ocol[it] = 0xFFu;
-      cand[it] = false;
-      flag[it] = false;
-      vox[it] = 0;
-      id[it] = kDeadId;
-      osp[it] = 0;
-      d0[it] = d1[it] = d2[it] = 0;
-      if (idx < n) {
-        vox[it] = in.vox[c * cap + idx];
-        id[it] = in.id[c * cap + idx];
-        osp[it] = in.sp[c * cap + idx];
-        if (disp) {
-          d0[it] = in.disp[(0 * 16 + c) * cap + idx];
-          d1[it] = in.disp[(1 * 16 + c) * cap + idx];
-          d2[it] = in.disp[(2 * 16 + c) * cap + idx];
-        }
-      }
-    }
+  uint32_t vox[ITEMS], id[ITEMS], ocol[ITEMS], lpos[ITEMS], osp[ITEMS];
+  int32_t d0[ITEMS], d1[ITEMS], d2[ITEMS];
+  bool cand[ITEMS], flag[ITEMS];
+  uint32_t ftgt[ITEMS];
 
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      if (id[it] == kDeadId) continue;
-      const uint32_t v = vox[it];
-      const U4 r = philox((uint32_t)e, id[it], kPhaseWalk, 0, L.key0, L.key1);
-      const uint32_t dir = scale32(r.x, 12);
-      const Coord cv = coord_of(L.geo, v);
-      const Coord ct = step_coord(L.geo, cv, dir);
-      const uint32_t t = index_of(L.geo, ct);
-      const uint16_t wt = L.occ[t];
-      uint32_t sp = osp[it] & 63u;
-      ocol[it] = c;  // stays in place unless it hops or is consumed
-      const uint32_t h = hot_hash(v, hbits);
-      if (((hot_now[h >> 5] | hot_prev[h >> 5]) >> (h & 31u)) & 1u) {
-        // the cached species may be stale, or the molecule may have reacted
-        // as a partner earlier in this walk: consult the lattice word
-        const uint16_t w = L.occ[v];
-        sp = w & 63u;
-        osp[it] = sp;
-        if (w & kReactedFlag) continue;
-      }
-      if (!((due >> sp) & 1ull)) continue;
-      ++n_att;
-      if (wt == 0) {
-        L.occ[t] = (uint16_t)sp;
-        L.occ[v] = 0;
-        vox[it] = t;
-        ocol[it] = colour_of(ct);
-        int32_t X, Y, Z;
-        hop_vector(dir, cv.k & 1, X, Y, Z);
-        d0[it] += X;
-        d1[it] += Y;
-        d2[it] += Z;
-        ++n_hop;
-        continue;
-      }
-      ++n_col;
-      const uint32_t psp = wt & 63u;
-      const int rx = L.pair_rx[sp * 64 + psp];
-      if (rx < 0) continue;
-      if (!L.rx_always[rx] && !(r.y < L.rx_thr[rx])) continue;
-      // first product on the partner's voxel with the partner's identity;
-      // its own entry (wherever it is) stays valid: it is flagged so that it
-      // does not walk again in this event, and its voxel is marked hot so
-      // that its cached species is refreshed
-      const uint16_t *prod = L.rx_prod + rx * 12;
-      L.occ[t] = (uint16_t)(prod[0] | kReactedFlag);
-      const uint32_t ht = hot_hash(t, hbits);
-      atomicOr(&hot_now[ht >> 5], 1u << (ht & 31u));
-      flag[it] = true;
-      ftgt[it] = t;
-      if (L.rx_nprod[rx] == 2) {
-        L.occ[v] = prod[1];
-        osp[it] = prod[1];
-      } else {
-        L.occ[v] = 0;
-        ocol[it] = 0xFFu;  // the mover's identity ends here
-      }
-      atomicAdd(&L.fired[rx], 1ull);
-    }
-
-    // ---- append survivors to the next event's bins: block-local slots
-    // through LDS, one global reservation per colour per block ----
-    uint32_t fslot[ITEMS], cslot[ITEMS];
-#pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      if (ocol[it] != 0xFFu) lpos[it] = atomicAdd(&s_cnt[ocol[it]], 1u);
-      if (flag[it]) fslot[it] = atomicAdd(&s_nflag, 1u);
-    }
-    __syncthreads();
-    if (tid < 16 && s_cnt[tid]) s_base[tid] = atomicAdd(&out.count[tid], s_cnt[tid]);
-    if (tid == 17 && s_nflag) s_flag_base = atomicAdd(L.flag_count, s_nflag);
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      if (flag[it]) {
-        const uint64_t f = (uint64_t)s_flag_base + fslot[it];
-        if (f < L.flag_cap) L.flag_vox[f] = ftgt[it];
-        else set_error(L, kErrFlagOverflow);
-      }
-      if (ocol[it] == 0xFFu) continue;
-      const uint32_t oc = ocol[it];
-      const uint64_t pos = (uint64_t)s_base[oc] + lpos[it];
-      if (pos >= cap) {
-        set_error(L, kErrBinOverflow);
-        continue;
-      }
-      lpos[it] = (uint32_t)pos;
-      out.vox[oc * cap + pos] = vox[it];
-      out.id[oc * cap + pos] = id[it];
-      out.sp[oc * cap + pos] = (uint16_t)osp[it];
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t idx = base + (uint64_t)it * kStageThreads + tid;
+    ocol[it] = 0xFFu;
+    cand[it] = false;
+    flag[it] = false;
+    vox[it] = 0;
+    id[it] = kDeadId;
+    osp[it] = 0;
+    d0[it] = d1[it] = d2[it] = 0;
+    if (idx < n) {
+      vox[it] = in.vox[c * cap + idx];
+      id[it] = in.id[c * cap + idx];
+      osp[it] = in.sp[c * cap + idx];
       if (disp) {
-        out.disp[(0 * 16 + oc) * cap + pos] = d0[it];
-        out.disp[(1 * 16 + oc) * cap + pos] = d1[it];
-        out.disp[(2 * 16 + oc) * cap + pos] = d2[it];
-      }
-      // can this molecule fire a first-order reaction in the next event?
-      if (cmax_next) {
-        const U4 r = philox((uint32_t)(e + 1), id[it], kPhaseFirst, 0, L.key0, L.key1);
-        cand[it] = r.x < cmax_next;
+        d0[it] = in.disp[(0 * 16 + c) * cap + idx];
+        d1[it] = in.disp[(1 * 16 + c) * cap + idx];
+        d2[it] = in.disp[(2 * 16 + c) * cap + idx];
       }
     }
-#pragma unroll
-    for (int it = 0; it < ITEMS; ++it)
-      if (cand[it]) cslot[it] = atomicAdd(&s_ncand, 1u);
-    __syncthreads();
-    if (tid == 16 && s_ncand) s_cand_base = atomicAdd(&L.cand_count[cnext], s_ncand);
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      if (!cand[it]) continue;
-      const uint64_t q = (uint64_t)s_cand_base + cslot[it];
-      if (q < L.cand_cap) {
-        L.cand_pos[cnext][q] = lpos[it];
-        L.cand_id[cnext][q] = id[it];
-        L.cand_col[cnext][q] = (uint8_t)ocol[it];
-      } else {
-        set_error(L, kErrCandOverflow);
-      }
-    }
-    __syncthreads();
   }
 
-  const unsigned long long a = block_sum_u64(n_att, s_red);
-  const unsigned long long h = block_sum_u64(n_hop, s_red);
-  const unsigned long long k = block_sum_u64(n_col, s_red);
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (id[it] == kDeadId) continue;
+    const uint32_t v = vox[it];
+    const U4 r = philox((uint32_t)e, id[it], kPhaseWalk, 0, L.key0, L.key1);
+    const uint32_t dir = scale32(r.x, 12);
+    const Coord cv = coord_of(L.geo, v);
+    const Coord ct = step_coord(L.geo, cv, dir);
+    const uint32_t t = index_of(L.geo, ct);
+    const uint16_t wt = L.occ[t];
+    uint32_t sp = osp[it] & 63u;
+    ocol[it] = c;  // stays in place unless it hops or is consumed
+    const uint32_t h = hot_hash(v, hbits);
+    if (((hot_now[h >> 5] | hot_prev[h >> 5]) >> (h & 31u)) & 1u) {
+      // the cached species may be stale, or the molecule may have reacted
+      // as a partner earlier in this walk: consult the lattice word
+      const uint16_t w = L.occ[v];
+      sp = w & 63u;
+      osp[it] = sp;
+      if (w & kReactedFlag) continue;
+    }
+    if (!((due >> sp) & 1ull)) continue;
+    ++n_att;
+    if (wt == 0) {
+      L.occ[t] = (uint16_t)sp;
+      L.occ[v] = 0;
+      vox[it] = t;
+      ocol[it] = colour_of(ct);
+      int32_t X, Y, Z;
+      hop_vector(dir, cv.k & 1, X, Y, Z);
+      d0[it] += X;
+      d1[it] += Y;
+      d2[it] += Z;
+      ++n_hop;
+      continue;
+    }
+    ++n_col;
+    const uint32_t psp = wt & 63u;
+    const int rx = L.pair_rx[sp * 64 + psp];
+    if (rx < 0) continue;
+    if (!L.rx_always[rx] && !(r.y < L.rx_thr[rx])) continue;
+    // first product on the partner's voxel with the partner's identity;
+    // its own entry (wherever it is) stays valid: it is flagged so that it
+    // does not walk again in this event, and its voxel is marked hot so
+    // that its cached species is refreshed
+    const uint16_t *prod = L.rx_prod + rx * 12;
+    L.occ[t] = (uint16_t)(prod[0] | kReactedFlag);
+    const uint32_t ht = hot_hash(t, hbits);
+    atomicOr(&hot_now[ht >> 5], 1u << (ht & 31u));
+    flag[it] = true;
+    ftgt[it] = t;
+    if (L.rx_nprod[rx] == 2) {
+      L.occ[v] = prod[1];
+      osp[it] = prod[1];
+    } else {
+      L.occ[v] = 0;
+      ocol[it] = 0xFFu;  // the mover's identity ends here
+    }
+    atomicAdd(&L.fired[rx], 1ull);
+  }
+
+  // ---- append survivors to the next event's bins: block-local slots
+  // through LDS, one global reservation per colour per block ----
+  uint32_t fslot[ITEMS], cslot[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (ocol[it] != 0xFFu) lpos[it] = atomicAdd(&s_cnt[ocol[it]], 1u);
+    if (flag[it]) fslot[it] = atomicAdd(&s_nflag, 1u);
+  }
+  __syncthreads();
+  if (tid < 16 && s_cnt[tid]) s_base[tid] = atomicAdd(&out.count[tid], s_cnt[tid]);
+  if (tid == 17 && s_nflag) s_flag_base = atomicAdd(L.flag_count, s_nflag);
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (flag[it]) {
+      const uint64_t f = (uint64_t)s_flag_base + fslot[it];
+      if (f < L.flag_cap) L.flag_vox[f] = ftgt[it];
+      else set_error(L, kErrFlagOverflow);
+    }
+    if (ocol[it] == 0xFFu) continue;
+    const uint32_t oc = ocol[it];
+    const uint64_t pos = (uint64_t)s_base[oc] + lpos[it];
+    if (pos >= cap) {
+      set_error(L, kErrBinOverflow);
+      continue;
+    }
+    lpos[it] = (uint32_t)pos;
+    out.vox[oc * cap + pos] = vox[it];
+    out.id[oc * cap + pos] = id[it];
+    out.sp[oc * cap + pos] = (uint16_t)osp[it];
+    if (disp) {
+      out.disp[(0 * 16 + oc) * cap + pos] = d0[it];
+      out.disp[(1 * 16 + oc) * cap + pos] = d1[it];
+      out.disp[(2 * 16 + oc) * cap + pos] = d2[it];
+    }
+    // can this molecule fire a first-order reaction in the next event?
+    if (cmax_next) {
+      const U4 r = philox((uint32_t)(e + 1), id[it], kPhaseFirst, 0, L.key0, L.key1);
+      cand[it] = r.x < cmax_next;
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it)
+    if (cand[it]) cslot[it] = atomicAdd(&s_ncand, 1u);
+  __syncthreads();
+  if (tid == 16 && s_ncand) s_cand_base = atomicAdd(&L.cand_count[cnext], s_ncand);
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (!cand[it]) continue;
+    const uint64_t q = (uint64_t)s_cand_base + cslot[it];
+    if (q < L.cand_cap) {
+      L.cand_pos[cnext][q] = lpos[it];
+      L.cand_id[cnext][q] = id[it];
+      L.cand_col[cnext][q] = (uint8_t)ocol[it];
+    } else {
+      set_error(L, kErrCandOverflow);
+    }
+  }
+  __syncthreads();
+  // counters of this chunk
+  if (n_att) atomicAdd(&sh->att, n_att);
+  if (n_hop) atomicAdd(&sh->hop, n_hop);
+  if (n_col) atomicAdd(&sh->col, n_col);
+  __syncthreads();
   if (tid == 0) {
-    if (a) atomicAdd(&L.cnt[0], a);
-    if (h) atomicAdd(&L.cnt[1], h);
-    if (k) atomicAdd(&L.cnt[2], k);
+    if (sh->att) atomicAdd(&L.cnt[0], sh->att);
+    if (sh->hop) atomicAdd(&L.cnt[1], sh->hop);
+    if (sh->col) atomicAdd(&L.cnt[2], sh->col);
+  }
+  __syncthreads();
+}
+
+template <int ITEMS>
+__global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restrict__ Lp, uint32_t g) {
+  __shared__ StageShared S;
+  const LatDev &L = *Lp;
+  const uint64_t e = *L.ev;
+  if (e >= L.tape_horizon) return;  // k_begin has recorded the error
+  const uint32_t c = L.perm[g];
+  const uint32_t n = min(L.bins[e & 1].count[c], (uint32_t)L.cap);
+  const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
+  for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk)
+    stage_chunk<ITEMS>(L, e, c, base, n, S);
+}
+
+// Stage g of every member lattice of an ensemble in one launch: the chunks of
+// all members' stage bins form one work list (prefix over members, built in
+// LDS by every workgroup), so lattices of any size share the GPU evenly.
+constexpr uint32_t kMaxMembers = 4096;
+
+template <int ITEMS>
+__global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__restrict__ lats,
+                                                               uint32_t R, uint32_t g) {
+  __shared__ StageShared S;
+  __shared__ uint32_t s_pre[kMaxMembers + 1];
+  __shared__ uint32_t s_part[kStageThreads];
+  const int tid = threadIdx.x;
+  const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
+  // chunks per member (contiguous slices of members per thread), then an
+  // exclusive scan over the slices
+  const uint32_t per = (R + kStageThreads - 1) / kStageThreads;
+  const uint32_t lo = min((uint32_t)tid * per, R), hi = min(lo + per, R);
+  uint32_t run = 0;
+  for (uint32_t r = lo; r < hi; ++r) {
+    const LatDev &L = lats[r];
+    const uint64_t e = *L.ev;
+    uint32_t k = 0;
+    if (e < L.tape_horizon) {
+      const uint32_t n = min(L.bins[e & 1].count[L.perm[g]], (uint32_t)L.cap);
+      k = (uint32_t)((n + chunk - 1) / chunk);
+    }
+    s_pre[r] = run;
+    run += k;
+  }
+  s_part[tid] = run;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int t = 0; t < kStageThreads; ++t) {
+      const uint32_t x = s_part[t];
+      s_part[t] = acc;
+      acc += x;
+    }
+    s_pre[R] = acc;
+  }
+  __syncthreads();
+  for (uint32_t r = lo; r < hi; ++r) s_pre[r] += s_part[tid];
+  __syncthreads();
+  const uint32_t total = s_pre[R];
+  for (uint32_t q = blockIdx.x; q < total; q += gridDim.x) {
+    // member owning chunk q: last r with s_pre[r] <= q
+    uint32_t a = 0, b = R;
+    while (b - a > 1) {
+      const uint32_t m = (a + b) >> 1;
+      if (s_pre[m] <= q) a = m;
+      else b = m;
+    }
+    const LatDev &L = lats[a];
+    const uint64_t e = *L.ev;
+    const uint32_t c = L.perm[g];
+    const uint32_t n = min(L.bins[e & 1].count[c], (uint32_t)L.cap);
+    stage_chunk<ITEMS>(L, e, c, (uint64_t)(q - s_pre[a]) * chunk, n, S);
   }
 }
 
@@ -548,14 +640,16 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
 // event counter (the last workgroup to finish does the bookkeeping)
 // =============================================================================
 constexpr int kEndBlocks = 32;
+constexpr int kEndBlocksMulti = 4;
 
-__global__ void __launch_bounds__(kStageThreads) k_end(const LatDev *__restrict__ Lp) {
-  const LatDev &L = *Lp;
+// workgroup bid of nblk: sweep flags and the previous hot bitmap; the last
+// workgroup to finish advances the lattice's event counter
+__device__ void end_body(const LatDev &L, uint32_t bid, uint32_t nblk) {
   const uint64_t e = *L.ev;
   if (e >= L.tape_horizon) return;
   const uint32_t nf = min(*L.flag_count, (uint32_t)L.flag_cap);
-  const uint32_t stride = gridDim.x * blockDim.x;
-  const uint32_t me = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t stride = nblk * blockDim.x;
+  const uint32_t me = bid * blockDim.x + threadIdx.x;
   for (uint32_t q = me; q < nf; q += stride) {
     const uint32_t v = L.flag_vox[q];
     L.occ[v] = (uint16_t)(L.occ[v] & kSpeciesMask);
@@ -567,13 +661,21 @@ __global__ void __launch_bounds__(kStageThreads) k_end(const LatDev *__restrict_
   if (threadIdx.x == 0) {
     __threadfence();
     const uint32_t done = atomicAdd(L.end_done, 1u);
-    if (done == gridDim.x - 1) {
+    if (done == nblk - 1) {
       __threadfence();
       *L.flag_count = 0;
       *L.end_done = 0;
       *L.ev = e + 1;
     }
   }
+}
+
+__global__ void __launch_bounds__(kStageThreads) k_end(const LatDev *__restrict__ Lp) {
+  end_body(*Lp, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kStageThreads) k_end_multi(const LatDev *__restrict__ lats) {
+  end_body(lats[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // =============================================================================
@@ -584,8 +686,8 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_begin(const LatDev *dL, const FireScratch &f, hipStream_t s) {
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, f.pos, f.id, f.col, f.rx);
+hipError_t launch_begin(const LatDev *dL, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL);
   return hipGetLastError();
 }
 
@@ -605,16 +707,29 @@ hipError_t launch_end(const LatDev *dL, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_event(const LatDev *dL, const FireScratch &f, int grid, int items,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, f.pos, f.id, f.col, f.rx);
+hipError_t launch_event(const LatDev *dL, int grid, int items, hipStream_t s) {
+  hipError_t err = launch_begin(dL, s);
+  for (uint32_t g = 0; g < 16 && err == hipSuccess; ++g) err = launch_stage(dL, g, grid, items, s);
+  if (err == hipSuccess) err = launch_end(dL, s);
+  return err;
+}
+
+hipError_t launch_event_multi(const LatDev *lats, uint32_t R, int grid, int items, hipStream_t s) {
+  if (R == 0 || R > kMaxMembers) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_begin_multi, dim3(R), dim3(kBeginThreads), 0, s, lats);
   for (uint32_t g = 0; g < 16; ++g) {
-    const hipError_t err = launch_stage(dL, g, grid, items, s);
-    if (err != hipSuccess) return err;
+    switch (items) {
+    case 1: hipLaunchKernelGGL(k_stage_multi<1>, dim3(grid), dim3(kStageThreads), 0, s, lats, R, g); break;
+    case 2: hipLaunchKernelGGL(k_stage_multi<2>, dim3(grid), dim3(kStageThreads), 0, s, lats, R, g); break;
+    case 8: hipLaunchKernelGGL(k_stage_multi<8>, dim3(grid), dim3(kStageThreads), 0, s, lats, R, g); break;
+    default: hipLaunchKernelGGL(k_stage_multi<4>, dim3(grid), dim3(kStageThreads), 0, s, lats, R, g); break;
+    }
   }
-  hipLaunchKernelGGL(k_end, dim3(kEndBlocks), dim3(kStageThreads), 0, s, dL);
+  hipLaunchKernelGGL(k_end_multi, dim3(kEndBlocksMulti, R), dim3(kStageThreads), 0, s, lats);
   return hipGetLastError();
 }
+
+uint32_t max_members() { return kMaxMembers; }
 
 int stage_items() { return 4; }
 int stage_threads() { return kStageThreads; }

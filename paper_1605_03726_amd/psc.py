@@ -127,6 +127,24 @@ def lib() -> C.CDLL:
     L.psc_set_kernel_timing.restype = C.c_int32
     L.psc_get_kernel_times.argtypes = [vp, C.POINTER(KernelTimes)]
     L.psc_get_kernel_times.restype = C.c_int32
+    L.psc_ensemble_create.argtypes = [C.POINTER(vp), C.c_uint32, C.POINTER(vp)]
+    L.psc_ensemble_create.restype = C.c_int32
+    L.psc_ensemble_step.argtypes = [vp, C.c_uint64, vp]
+    L.psc_ensemble_step.restype = C.c_int32
+    L.psc_ensemble_sync.argtypes = [vp]
+    L.psc_ensemble_sync.restype = C.c_int32
+    L.psc_ensemble_set_launch.argtypes = [vp, C.POINTER(Launch)]
+    L.psc_ensemble_set_launch.restype = C.c_int32
+    L.psc_ensemble_get_launch.argtypes = [vp, C.POINTER(Launch)]
+    L.psc_ensemble_get_launch.restype = C.c_int32
+    L.psc_ensemble_autotune.argtypes = [vp, C.c_uint32]
+    L.psc_ensemble_autotune.restype = C.c_int32
+    L.psc_ensemble_tuned.argtypes = [vp, C.POINTER(Launch), C.POINTER(C.c_double)]
+    L.psc_ensemble_tuned.restype = C.c_int32
+    L.psc_ensemble_destroy.argtypes = [vp]
+    L.psc_ensemble_destroy.restype = None
+    L.psc_ensemble_last_error.argtypes = [vp]
+    L.psc_ensemble_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -331,3 +349,59 @@ def lattice_from_workload(w: dict, max_molecules: int | None = None, device: int
         for s, c in w["place"]:
             lat.place_uniform(s, c)
     return lat
+
+
+class Ensemble:
+    """Independent lattices advanced together in batched launches (see
+    psc_ensemble_* in include/psc.h)."""
+
+    def __init__(self, members):
+        self.L = lib()
+        self.members = list(members)
+        arr = (C.c_void_p * len(self.members))(*[m.h for m in self.members])
+        h = C.c_void_p()
+        rc = self.L.psc_ensemble_create(arr, len(self.members), C.byref(h))
+        if rc != PSC_OK:
+            raise PscError(rc, self.L.psc_ensemble_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != PSC_OK:
+            raise PscError(rc, self.L.psc_ensemble_last_error(self.h).decode())
+
+    def step(self, n_events: int, stream=None):
+        s = current_stream() if stream is None else stream
+        self._check(self.L.psc_ensemble_step(self.h, n_events, s))
+
+    def sync(self):
+        self._check(self.L.psc_ensemble_sync(self.h))
+
+    def set_launch(self, items_per_thread: int = 0, stage_blocks: int = 0):
+        l = Launch(items_per_thread, stage_blocks)
+        self._check(self.L.psc_ensemble_set_launch(self.h, C.byref(l)))
+
+    def get_launch(self) -> dict:
+        l = Launch()
+        self._check(self.L.psc_ensemble_get_launch(self.h, C.byref(l)))
+        return {"items_per_thread": l.items_per_thread, "stage_blocks": l.stage_blocks}
+
+    def autotune(self, trial_events: int):
+        self._check(self.L.psc_ensemble_autotune(self.h, trial_events))
+
+    def tuned(self) -> dict:
+        l = Launch()
+        ms = C.c_double()
+        self._check(self.L.psc_ensemble_tuned(self.h, C.byref(l), C.byref(ms)))
+        return {"items_per_thread": l.items_per_thread, "stage_blocks": l.stage_blocks,
+                "ms_per_event": ms.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.psc_ensemble_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -85,6 +85,109 @@ def cpu_baseline(w: dict, events: int) -> dict:
             "sample": "first %d events of %s (%d attempts, %.1f s)" % (events, w["name"], att, dt)}
 
 
+def ensemble_bench(n_members: int, events: int, plain_sample: int, plain_events: int,
+                   trial_events: int) -> dict:
+    """Replicate ensemble: all members in batched launches (autotuned shape)
+    against the plain form, one lattice per launch sequence, timed on a
+    sample of members and extrapolated with a per-event cost that is linear
+    in the member's molecule count."""
+    import numpy as np
+    import torch
+    from paper_1605_03726_amd import psc
+    from psc_inputs import ensemble_members
+
+    ws = ensemble_members(n=n_members, events=events)
+    t0 = time.perf_counter()
+    lats = [psc.lattice_from_workload(w) for w in ws]
+    ens = psc.Ensemble(lats)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    c0 = sum(l.counters()["attempts"] for l in lats)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ens.autotune(trial_events)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    ens.step(events)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    batched_s = ev0.elapsed_time(ev1) / 1e3
+    ens.sync()
+    attempts = sum(l.counters()["attempts"] for l in lats) - c0
+    tuned = ens.tuned()
+    ens.close()
+    for l in lats:
+        l.close()
+    del lats
+
+    # plain form on a sample spread over the member sizes
+    mol = np.array([sum(c for _, c in w["place"]) for w in ws], dtype=float)
+    order = np.argsort(mol)
+    pick = order[np.linspace(0, len(ws) - 1, plain_sample).round().astype(int)]
+    per_event = []
+    for r in pick:
+        lat = psc.lattice_from_workload(ws[r])
+        lat.step(2)
+        lat.sync()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        lat.step(plain_events)
+        b.record(stream)
+        torch.cuda.synchronize()
+        per_event.append(a.elapsed_time(b) / 1e3 / plain_events)
+        lat.close()
+    A = np.vstack([np.ones(len(pick)), mol[pick]]).T
+    coef = np.linalg.lstsq(A, np.array(per_event), rcond=None)[0]
+    plain_s = float(sum(max(coef[0] + coef[1] * m, min(per_event)) for m in mol) * events)
+    return {"members": n_members, "events": events, "edges": [32, 48, 64, 96, 128],
+            "batched_s": batched_s, "attempts": attempts,
+            "batched_attempts_per_s": attempts / batched_s,
+            "plain_estimate_s": plain_s, "speedup": plain_s / batched_s,
+            "tuned_launch": tuned, "setup_s": setup_s,
+            "plain_sample": "%d members spread over the sizes, %d events each, per-event time "
+                            "fitted linear in molecule count" % (plain_sample, plain_events),
+            "equal_accuracy": "members are bit-identical in both forms (tests)"}
+
+
+def serving_bench(duration: float, rate: float, budget_gb: float, quantum: int) -> dict:
+    """Poisson arrivals submitted in real time to the continuous-batching
+    server; latency = completion - submission."""
+    import numpy as np
+    from paper_1605_03726_amd import psc
+    from psc_inputs import serving_jobs
+
+    jobs = serving_jobs(rate=rate, duration=duration)
+    srv = psc.Server(budget_bytes=int(budget_gb * (1 << 30)), quantum_events=quantum)
+    t0 = time.perf_counter()
+    ids = []
+    for w in jobs:
+        dt = w["arrival"] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        ids.append(srv.submit(w))
+    sts = [srv.wait(j) for j in ids]
+    stats = srv.stats()
+    srv.close()
+    done = [s for s in sts if s["state"] == psc.JOB_DONE]
+    lat = np.array([s["done_s"] - s["submit_s"] for s in done])
+    t_first = min(s["submit_s"] for s in sts)
+    t_last = max(s["done_s"] for s in sts)
+    wall = t_last - t_first
+    attempts = sum(s["attempts"] for s in done)
+    offered = sum(sum(c for _, c in w["place"]) * w["events"] for w in jobs) / duration
+    return {"arrival_rate": rate, "arrival_window_s": duration, "jobs": len(jobs),
+            "done": len(done), "failed": len(sts) - len(done),
+            "jobs_per_s": len(done) / wall, "attempts_per_s": attempts / wall,
+            "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)),
+            "wall_s": wall, "offered_attempts_per_s_upper": offered,
+            "budget_gb": budget_gb, "quantum_events": quantum,
+            "peak_resident_jobs": stats["peak_active"], "batched_steps": stats["quanta"],
+            "note": "offered load exceeds one GPU: latency includes queueing"}
+
+
 def calibrate_copy(nbytes: int, reps: int):
     """plain device-to-device copies of a known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters"""
@@ -108,6 +211,13 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=40)
     ap.add_argument("--cpu-events", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-only", action="store_true")
+    ap.add_argument("--ensemble-members", type=int, default=512)
+    ap.add_argument("--ensemble-events", type=int, default=5000)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--serving-window", type=float, default=1.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run N-byte device copies (counter calibration)")
     args = ap.parse_args()
@@ -122,6 +232,13 @@ def main():
 
     import torch
     from paper_1605_03726_amd import psc
+
+    if args.serving_only:
+        print(json.dumps(serving_bench(args.serving_window, 200.0, 200.0, 64)))
+        return
+    if args.ensemble_only:
+        print(json.dumps(ensemble_bench(args.ensemble_members, args.ensemble_events, 12, 300, 3)))
+        return
 
     w = pick_workload(args.workload)
     nv = int(w["dims"][0]) * int(w["dims"][1]) * int(w["dims"][2])
@@ -188,6 +305,16 @@ def main():
                      "avg_launch_ms": stage_avg_ms,
                      "algorithmic_bytes_per_launch": alg_bytes_per_launch},
     }
+    if not args.no_ensemble:
+        result["ensemble"] = ensemble_bench(args.ensemble_members, args.ensemble_events, 12, 300, 3)
+        print("ensemble: %.2f s batched, %.1fx over plain" % (
+            result["ensemble"]["batched_s"], result["ensemble"]["speedup"]), file=sys.stderr,
+            flush=True)
+    if not args.no_serving:
+        result["serving"] = serving_bench(args.serving_window, 200.0, 200.0, 64)
+        print("serving: %d jobs, p50 %.2f s, p99 %.2f s" % (
+            result["serving"]["done"], result["serving"]["latency_p50_s"],
+            result["serving"]["latency_p99_s"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_events)
     print(json.dumps(result))

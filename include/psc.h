@@ -264,6 +264,107 @@ void psc_ensemble_destroy(psc_ensemble *e);
 /* Message for the last error on e; NULL: the last create failure. */
 const char *psc_ensemble_last_error(const psc_ensemble *e);
 
+/* ---- serving loop ---------------------------------------------------------------
+ * Continuous batching of simulation jobs.  Jobs are submitted from any thread
+ * and copied.  A worker thread owns the GPU: at every step boundary it admits
+ * queued jobs (first come, first served) while their device memory fits the
+ * budget, advances all resident jobs together as one batched ensemble by
+ * `quantum_events` events (a job that reaches its last event idles for the
+ * rest of the quantum), and retires finished jobs, which frees their memory
+ * for the queue.  A job's result is bit-identical to running it alone. */
+typedef struct psc_server psc_server;
+
+typedef struct psc_server_options {
+  int32_t device;           /* HIP device ordinal */
+  uint64_t budget_bytes;    /* device memory the resident jobs may hold */
+  uint32_t quantum_events;  /* events per step between admissions (>= 1) */
+  uint32_t max_active;      /* resident jobs at most (1..4096) */
+} psc_server_options;
+
+typedef struct psc_reaction_desc {
+  uint32_t n_r, n_p;        /* as psc_add_reaction */
+  uint16_t reactants[2];
+  uint16_t products[PSC_MAX_PRODUCTS];
+  double k;
+} psc_reaction_desc;
+
+typedef struct psc_place_desc {
+  uint16_t species;         /* uniform placement, as psc_place_uniform */
+  uint64_t count;
+} psc_place_desc;
+
+/* One job: a lattice (desc fields as psc_lattice_desc; allocator hooks and
+ * device come from the server), species D[0..n_species) = ids 1..n,
+ * reactions, placements in order, and the number of events to run. */
+typedef struct psc_job_desc {
+  uint32_t ni, nj, nk;
+  double voxel_radius;
+  uint64_t seed;
+  uint64_t max_molecules;
+  uint32_t flags;
+  uint32_t n_species;
+  const double *D;
+  uint32_t n_reactions;
+  const psc_reaction_desc *reactions;
+  uint32_t n_place;
+  const psc_place_desc *place;
+  uint64_t n_events;
+  uint32_t keep_state;      /* keep the final state until psc_server_release */
+} psc_job_desc;
+
+#define PSC_JOB_QUEUED 0
+#define PSC_JOB_RUNNING 1
+#define PSC_JOB_DONE 2
+#define PSC_JOB_FAILED 3
+
+typedef struct psc_job_status {
+  int32_t state;            /* PSC_JOB_* */
+  psc_status error;         /* why a job failed (EINVAL: bad job; ENOMEM: does
+                               not fit the budget; ECAPACITY; EDEVICE) */
+  double submit_s, admit_s, done_s;  /* seconds since the server started */
+  uint64_t events_done;
+  psc_counters counters;
+} psc_job_status;
+
+typedef struct psc_server_stats {
+  uint64_t submitted, admitted, done, failed, active, queued;
+  uint64_t device_bytes_in_use;
+  uint64_t attempts;        /* hop attempts of finished jobs */
+  uint64_t quanta;          /* batched steps run */
+  double busy_s;            /* time spent in batched steps */
+  uint64_t peak_active;     /* most jobs resident at once */
+} psc_server_stats;
+
+/* Device bytes the server reserves for a job (its admission cost). */
+psc_status psc_server_job_bytes(const psc_job_desc *job, uint64_t *bytes);
+
+/* Starts the worker.  EINVAL on bad options or device. */
+psc_status psc_server_create(const psc_server_options *opt, psc_server **out);
+
+/* Queues a copy of the job; *job_id identifies it.  A job that can never fit
+ * the budget fails at once (ENOMEM); one the lattice rejects fails with that
+ * status when it is admitted; other jobs are unaffected.  ESTATE once the
+ * server is being destroyed. */
+psc_status psc_server_submit(psc_server *s, const psc_job_desc *job, uint64_t *job_id);
+
+/* Current status of a job (non-blocking) / wait until it is done or failed. */
+psc_status psc_server_poll(psc_server *s, uint64_t job_id, psc_job_status *out);
+psc_status psc_server_wait(psc_server *s, uint64_t job_id, psc_job_status *out);
+
+/* Final state of a finished job submitted with keep_state (ESTATE otherwise),
+ * as psc_read_state. */
+psc_status psc_server_read_state(psc_server *s, uint64_t job_id, psc_state_view *out);
+
+/* Frees a finished job's kept state. */
+psc_status psc_server_release(psc_server *s, uint64_t job_id);
+
+psc_status psc_server_stats_get(psc_server *s, psc_server_stats *out);
+const char *psc_server_last_error(const psc_server *s);
+
+/* Runs every submitted job to completion, then stops the worker and frees
+ * everything (kept states included). */
+void psc_server_destroy(psc_server *s);
+
 #ifdef __cplusplus
 }
 #endif

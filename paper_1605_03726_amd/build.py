@@ -8,7 +8,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpsc.so")
-SOURCES = [os.path.join(CSRC, "psc_kernels.hip"), os.path.join(CSRC, "psc_host.cpp")]
+SOURCES = [os.path.join(CSRC, "psc_kernels.hip"), os.path.join(CSRC, "psc_host.cpp"),
+           os.path.join(CSRC, "psc_server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -17,7 +18,7 @@ FLAGS = [
     # packed FP32 instructions stay off in all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
-    "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+    "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-pthread",
 ]
 
 

@@ -264,6 +264,7 @@ struct LatDev {
   uint64_t tape_horizon;
 
   // event state
+  uint64_t stop_event;             // the lattice idles once ev reaches it
   uint64_t *ev;                    // events completed
   uint32_t *perm;                  // [16] stage order of the running event
   uint32_t *next_id;

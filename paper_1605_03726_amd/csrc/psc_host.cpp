@@ -13,27 +13,15 @@
 #include <string>
 #include <vector>
 
-#include "psc.h"
-#include "psc_core.h"
+#include "psc_internal.h"
 
 using namespace psc;
+using namespace psc_detail;
 
 namespace {
 
 thread_local std::string g_create_error;
 
-struct SpeciesDef {
-  std::string name;
-  double D = 0.0;
-  double tau = 0.0;  // 2 r^2 / (3 D), eq. (2) of 2.3; 0 if immobile
-};
-
-struct ReactionDef {
-  uint32_t nr = 0, np = 0;
-  uint16_t r[2] = {0, 0};
-  uint16_t p[kMaxProducts] = {};
-  double k = 0.0;
-};
 
 // interval between diffusion events of a species, tau = 2 r^2 / (3 D) (2.3)
 double diffusion_interval(double rv, double D) {
@@ -76,74 +64,8 @@ uint64_t pow2_at_least(uint64_t x) {
 
 }  // namespace
 
-struct psc_lattice {
-  psc_lattice_desc desc{};
-  uint64_t nv = 0;
-  Geo geo{};
-  std::vector<SpeciesDef> species{1};  // index 0 = vacant
-  std::vector<ReactionDef> rx;
-  bool frozen = false;
-  bool poisoned = false;
-  std::string err;
 
-  // state before the freeze (host)
-  std::vector<uint16_t> occ;
-  std::vector<uint32_t> mid, mvox;
-  std::vector<int32_t> mdx, mdy, mdz;
-  uint32_t next_id = 0;
-  uint64_t event0 = 0;
-  uint64_t place_calls = 0;
-
-  // static molecules: immobile species that react with nothing never change,
-  // so they stay out of the walk's bins
-  std::vector<uint32_t> st_id, st_vox;
-  std::vector<int32_t> st_d[3];
-
-  // event tape (absolute event index)
-  std::vector<uint64_t> n_walks;
-  uint64_t tape_end = 0;
-  double t_prev = 0.0;
-  std::vector<double> tape_time;
-  std::vector<uint64_t> tape_due;
-  std::vector<uint32_t> tape_thr, tape_cmax;
-  uint64_t events_done = 0;  // events enqueued on the device
-
-  // first-order slots: for each species, its first-order reactions in
-  // registration order
-  std::vector<uint16_t> fo_first, fo_rx;
-  std::vector<uint8_t> fo_n;
-  uint32_t n_fo = 0;
-
-  // device
-  struct Block {
-    void *p;
-    size_t bytes;
-  };
-  std::vector<Block> blocks;
-  uint64_t device_bytes = 0;
-  LatDev L{};
-  LatDev *dL = nullptr;
-  uint64_t *d_tape_due = nullptr;
-  uint32_t *d_tape_thr = nullptr, *d_tape_cmax = nullptr;
-  uint64_t d_tape_rows = 0;
-  int grid = 1;
-  int items = 4;
-  bool grid_set = false;
-  uint64_t version = 0;   // bumped whenever the device record changes
-  bool in_ensemble = false;
-  hipStream_t last_stream = nullptr;
-
-  // per-launch timing: kind (0 begin, 1 stage, 2 end) and its event pair
-  bool timing = false;
-  struct Timed {
-    int kind;
-    hipEvent_t a, b;
-  };
-  std::vector<Timed> timed;
-  std::vector<hipEvent_t> event_pool;
-};
-
-namespace {
+namespace psc_detail {
 
 psc_status fail(psc_lattice *h, psc_status code, const char *fmt, ...) {
   char buf[512];
@@ -362,6 +284,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   const uint64_t cap = std::max<uint64_t>(h->desc.max_molecules, 1);
   const bool disp = (h->desc.flags & PSC_TRACK_DISPLACEMENT) != 0;
   LatDev &L = h->L;
+  L.stop_event = ~0ull;
   L.geo = h->geo;
   L.nv = h->nv;
   L.key0 = (uint32_t)h->desc.seed;
@@ -536,6 +459,32 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   return PSC_OK;
 }
 
+uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool displacement,
+                               uint32_t n_reactions) {
+  auto r = [](uint64_t b) { return (std::max<uint64_t>(b, 16) + 255) & ~uint64_t(255); };
+  const uint64_t cap = std::max<uint64_t>(max_molecules, 1);
+  uint64_t t = r(voxels * 2);
+  for (int b = 0; b < 2; ++b) {
+    t += r(16 * cap * 4) * 2 + r(16 * cap * 2) + r(64);
+    if (displacement) t += r(3 * 16 * cap * 4);
+    t += r(cap * 4) * 2 + r(cap);
+  }
+  t += r(8) + r(cap * 4) + r(4);
+  const uint64_t bcap = std::min<uint64_t>(pow2_at_least(cap), 1ull << 27);
+  t += r(bcap * 8) + r(bcap * 4) + r(bcap * 2) + r(4);
+  uint32_t hb = 16;
+  while (hb < 24 && (1ull << hb) < cap / 4) ++hb;
+  t += 2 * r((1ull << hb) / 8) + r(4);
+  uint32_t nb = 12;
+  while (nb < 22 && (1ull << nb) < 8 * cap) ++nb;
+  t += r((1ull << nb) * 4);
+  t += r(cap * 4) * 2 + r(cap) * 2;
+  const uint64_t R = std::max<uint32_t>(n_reactions, 1);
+  t += r(64) + r(64 * 64 * 2) + r(R * 4) + r(R) * 2 + r(R * 24) + r(128) + r(64) + r(512);
+  t += r(8) + r(64) + r(4) + r(32) + r(R * 8) + r(4) + r(sizeof(LatDev));
+  return t;
+}
+
 psc_status check_device_error(psc_lattice *h) {
   uint32_t e = 0;
   HIP_OK(h, hipMemcpy(&e, h->L.error, sizeof e, hipMemcpyDeviceToHost));
@@ -545,7 +494,7 @@ psc_status check_device_error(psc_lattice *h) {
   return fail(h, PSC_EDEVICE, "device error bits 0x%x", e);
 }
 
-}  // namespace
+}  // namespace psc_detail
 
 // =============================================================================
 // C ABI
@@ -1060,26 +1009,8 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
 // =============================================================================
 // ensembles: many independent lattices advanced together
 // =============================================================================
-struct psc_ensemble {
-  std::vector<psc_lattice *> members;
-  int device = 0;
-  std::string err;
-  bool poisoned = false;
-  LatDev *d_lats = nullptr;                 // device array of member records
-  std::vector<uint64_t> versions;           // member record versions uploaded
-  int grid = 1024;
-  int items = 4;
-  // one captured event of the batched launches, replayed per event
-  hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int graph_grid = 0, graph_items = 0;
-  uint32_t autotune_events = 0;             // > 0: tune on the next step
-  psc_launch tuned{0, 0};
-  double tuned_ms_per_event = 0.0;
-};
 
-namespace {
+namespace psc_detail {
 
 psc_status efail(psc_ensemble *E, psc_status code, const char *fmt, ...) {
   char buf[512];
@@ -1154,14 +1085,20 @@ psc_status ensure_graph(psc_ensemble *E) {
 }
 
 psc_status run_events(psc_ensemble *E, uint64_t n, hipStream_t stream) {
-  psc_status st = ensure_graph(E);
-  if (st) return st;
-  for (uint64_t e = 0; e < n; ++e) EHIP_OK(E, hipGraphLaunch(E->exec, stream));
+  if (E->use_graph) {
+    psc_status st = ensure_graph(E);
+    if (st) return st;
+    for (uint64_t e = 0; e < n; ++e) EHIP_OK(E, hipGraphLaunch(E->exec, stream));
+  } else {
+    for (uint64_t e = 0; e < n; ++e)
+      EHIP_OK(E, launch_event_multi(E->d_lats, (uint32_t)E->members.size(), E->grid, E->items,
+                                    stream));
+  }
   for (psc_lattice *h : E->members) h->events_done += n;
   return PSC_OK;
 }
 
-}  // namespace
+}  // namespace psc_detail
 
 extern "C" {
 

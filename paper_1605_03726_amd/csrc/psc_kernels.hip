@@ -211,6 +211,7 @@ __device__ void begin_body(const LatDev &L) {
   __shared__ uint64_t s_keys[kSortLds];
   const uint64_t e = *L.ev;
   const int tid = threadIdx.x;
+  if (e >= L.stop_event) return;  // an idle member of an ensemble
   if (e >= L.tape_horizon) {
     if (tid == 0) set_error(L, kErrTape);
     return;
@@ -567,7 +568,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
   __shared__ StageShared S;
   const LatDev &L = *Lp;
   const uint64_t e = *L.ev;
-  if (e >= L.tape_horizon) return;  // k_begin has recorded the error
+  if (e >= L.tape_horizon || e >= L.stop_event) return;  // error recorded / idle
   const uint32_t c = L.perm[g];
   const uint32_t n = min(L.bins[e & 1].count[c], (uint32_t)L.cap);
   const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
@@ -597,7 +598,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
     const LatDev &L = lats[r];
     const uint64_t e = *L.ev;
     uint32_t k = 0;
-    if (e < L.tape_horizon) {
+    if (e < L.tape_horizon && e < L.stop_event) {
       const uint32_t n = min(L.bins[e & 1].count[L.perm[g]], (uint32_t)L.cap);
       k = (uint32_t)((n + chunk - 1) / chunk);
     }
@@ -646,7 +647,7 @@ constexpr int kEndBlocksMulti = 4;
 // workgroup to finish advances the lattice's event counter
 __device__ void end_body(const LatDev &L, uint32_t bid, uint32_t nblk) {
   const uint64_t e = *L.ev;
-  if (e >= L.tape_horizon) return;
+  if (e >= L.tape_horizon || e >= L.stop_event) return;
   const uint32_t nf = min(*L.flag_count, (uint32_t)L.flag_cap);
   const uint32_t stride = nblk * blockDim.x;
   const uint32_t me = bid * blockDim.x + threadIdx.x;

@@ -1,0 +1,376 @@
+// psc_server.cpp -- continuous-batching serving loop of libpsc.
+//
+// Jobs (one lattice + model + initial state + a number of diffusion events
+// each) are submitted from any thread.  One worker thread owns the GPU work:
+// at every step boundary it admits queued jobs while their estimated device
+// memory fits the budget, advances all resident jobs together as one batched
+// ensemble by a quantum of events (a job that reaches its last event idles
+// for the rest of the quantum), and retires finished jobs, freeing their
+// memory for the queue.  A job's result does not depend on what it ran with:
+// every draw is keyed by the job's own seed, event and molecule ids.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+#include "psc_internal.h"
+
+using namespace psc;
+using namespace psc_detail;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Job {
+  uint64_t id = 0;
+  psc_lattice_desc desc{};
+  std::vector<double> D;
+  std::vector<psc_reaction_desc> rx;
+  std::vector<psc_place_desc> place;
+  uint64_t n_events = 0;
+  bool keep_state = false;
+  psc_job_status st{};
+  psc_lattice *lat = nullptr;
+  uint64_t est_bytes = 0;
+};
+
+}  // namespace
+
+struct psc_server {
+  psc_server_options opt{};
+  Clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Job *> queue;
+  std::map<uint64_t, Job *> jobs;   // every job ever submitted, by id
+  std::vector<Job *> active;
+  uint64_t next_job = 1;
+  uint64_t used_bytes = 0;
+  bool stopping = false;
+  psc_server_stats stats{};
+  std::thread worker;
+  hipStream_t stream = nullptr;
+  psc_ensemble ens;                  // the resident jobs, rebuilt on change
+  uint64_t ens_capacity = 0;
+  bool ens_dirty = true;
+  std::string err;
+};
+
+namespace {
+
+double seconds(const psc_server *S) {
+  return std::chrono::duration<double>(Clock::now() - S->t0).count();
+}
+
+// builds the job's lattice on the host (model, placement), freezes it on the
+// device; returns a status for the job
+psc_status build_job(psc_server *S, Job *j) {
+  psc_lattice *h = nullptr;
+  psc_status st = psc_create_lattice(&j->desc, &h);
+  if (st) return st;
+  j->lat = h;
+  for (size_t s = 0; s < j->D.size(); ++s) {
+    st = psc_add_species(h, "", j->D[s], nullptr);
+    if (st) return st;
+  }
+  for (auto &r : j->rx) {
+    st = psc_add_reaction(h, r.reactants, r.n_r, r.products, r.n_p, r.k, nullptr);
+    if (st) return st;
+  }
+  for (auto &p : j->place) {
+    st = psc_place_uniform(h, p.species, p.count);
+    if (st) return st;
+  }
+  st = psc_step(h, 0, S->stream);  // freeze: the state moves to the device
+  if (st) return st;
+  h->L.stop_event = h->events_done + j->n_events;
+  if (hipMemcpy(h->dL, &h->L, sizeof(LatDev), hipMemcpyHostToDevice) != hipSuccess)
+    return PSC_EDEVICE;
+  h->version++;
+  return PSC_OK;
+}
+
+void finish_job(psc_server *S, Job *j, int state, psc_status code) {
+  // called with the lock held
+  j->st.state = state;
+  j->st.error = code;
+  j->st.done_s = seconds(S);
+  if (state == PSC_JOB_DONE) S->stats.done++;
+  else S->stats.failed++;
+  S->cv_done.notify_all();
+}
+
+void release_lattice(psc_server *S, Job *j) {
+  if (!j->lat) return;
+  psc_destroy(j->lat);
+  j->lat = nullptr;
+  S->used_bytes -= std::min(S->used_bytes, j->est_bytes);
+}
+
+void worker_main(psc_server *S) {
+  (void)hipSetDevice(S->opt.device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    // ---- admission at the step boundary ----
+    while (!S->queue.empty() && S->active.size() < S->opt.max_active) {
+      Job *j = S->queue.front();
+      if (S->used_bytes + j->est_bytes > S->opt.budget_bytes && !S->active.empty()) break;
+      S->queue.pop_front();
+      S->used_bytes += j->est_bytes;
+      lk.unlock();
+      const psc_status st = build_job(S, j);
+      lk.lock();
+      if (st) {
+        if (j->lat && j->lat->poisoned) S->err = j->lat->err;
+        release_lattice(S, j);
+        finish_job(S, j, PSC_JOB_FAILED, st);
+        continue;
+      }
+      j->st.state = PSC_JOB_RUNNING;
+      j->st.admit_s = seconds(S);
+      S->stats.admitted++;
+      S->active.push_back(j);
+      S->stats.peak_active = std::max<uint64_t>(S->stats.peak_active, S->active.size());
+      S->ens_dirty = true;
+    }
+    S->stats.active = S->active.size();
+    S->stats.queued = S->queue.size();
+    S->stats.device_bytes_in_use = S->used_bytes;
+    if (S->active.empty()) {
+      if (S->stopping && S->queue.empty()) break;
+      S->cv_work.wait(lk);
+      continue;
+    }
+    // ---- one quantum of events for every resident job ----
+    if (S->ens_dirty) {
+      psc_ensemble &E = S->ens;
+      E.members.clear();
+      for (Job *j : S->active) E.members.push_back(j->lat);
+      E.versions.assign(E.members.size(), ~0ull);
+      if (E.members.size() > S->ens_capacity) {
+        if (E.d_lats) (void)hipFree(E.d_lats);
+        E.d_lats = nullptr;
+        S->ens_capacity = std::max<uint64_t>(E.members.size(), 2 * S->ens_capacity);
+        if (hipMalloc(&E.d_lats, S->ens_capacity * sizeof(LatDev)) != hipSuccess) {
+          S->err = "device allocation of the member records failed";
+          for (Job *j : S->active) {
+            release_lattice(S, j);
+            finish_job(S, j, PSC_JOB_FAILED, PSC_ENOMEM);
+          }
+          S->active.clear();
+          S->ens_capacity = 0;
+          continue;
+        }
+      }
+      uint64_t mol = 0;
+      for (auto *h : E.members) mol += h->desc.max_molecules;
+      E.grid = (int)std::min<uint64_t>(std::max<uint64_t>(mol / 16 / 1024, 64), 2048);
+      E.items = 4;
+      S->ens_dirty = false;
+    }
+    uint64_t q = S->opt.quantum_events;
+    lk.unlock();
+    psc_ensemble &E = S->ens;
+    psc_status st = ensure_member_records(&E, S->stream, q);
+    const double tb = seconds(S);
+    // direct launches: a server shares its process with other threads, and
+    // capturing a graph would forbid their legacy-stream work meanwhile
+    for (uint64_t e = 0; e < q && !st; ++e)
+      if (launch_event_multi(E.d_lats, (uint32_t)E.members.size(), E.grid, E.items, S->stream) !=
+          hipSuccess)
+        st = PSC_EDEVICE;
+    if (!st && hipStreamSynchronize(S->stream) != hipSuccess) st = PSC_EDEVICE;
+    const double te = seconds(S);
+    lk.lock();
+    S->stats.quanta++;
+    S->stats.busy_s += te - tb;
+    // ---- retire finished jobs ----
+    std::vector<Job *> still;
+    for (Job *j : S->active) {
+      psc_lattice *h = j->lat;
+      h->events_done = std::min(h->events_done + q, h->L.stop_event);
+      psc_status js = st;
+      if (!js) js = check_device_error(h);
+      if (js) {
+        release_lattice(S, j);
+        finish_job(S, j, PSC_JOB_FAILED, js);
+        S->ens_dirty = true;
+        continue;
+      }
+      if (h->events_done < h->L.stop_event) {
+        still.push_back(j);
+        continue;
+      }
+      psc_counters c{};
+      uint64_t ev = 0;
+      psc_read_counters(h, &c, &ev);
+      j->st.counters = c;
+      j->st.events_done = ev;
+      S->stats.attempts += c.attempts;
+      if (!j->keep_state) release_lattice(S, j);
+      finish_job(S, j, PSC_JOB_DONE, PSC_OK);
+      S->ens_dirty = true;
+    }
+    S->active.swap(still);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+psc_status psc_server_create(const psc_server_options *opt, psc_server **out) {
+  if (!opt || !out) return PSC_EINVAL;
+  *out = nullptr;
+  if (opt->device < 0 || opt->budget_bytes == 0 || opt->quantum_events == 0 ||
+      opt->max_active == 0 || opt->max_active > max_members())
+    return PSC_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device >= ndev) return PSC_EINVAL;
+  psc_server *S = new (std::nothrow) psc_server();
+  if (!S) return PSC_ENOMEM;
+  S->opt = *opt;
+  S->t0 = Clock::now();
+  if (hipSetDevice(opt->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete S;
+    return PSC_EDEVICE;
+  }
+  S->ens.device = opt->device;
+  S->ens.use_graph = false;
+  S->worker = std::thread(worker_main, S);
+  *out = S;
+  return PSC_OK;
+}
+
+psc_status psc_server_job_bytes(const psc_job_desc *d, uint64_t *bytes) {
+  if (!d || !bytes) return PSC_EINVAL;
+  const uint64_t nv = (uint64_t)d->ni * d->nj * d->nk;
+  *bytes = estimate_device_bytes(nv, d->max_molecules, (d->flags & PSC_TRACK_DISPLACEMENT) != 0,
+                                 d->n_reactions) +
+           (d->n_events + 2048) * 64;  // event tape, grown geometrically
+  return PSC_OK;
+}
+
+psc_status psc_server_submit(psc_server *S, const psc_job_desc *d, uint64_t *job_id) {
+  if (!S || !d || !job_id) return PSC_EINVAL;
+  Job *j = new (std::nothrow) Job();
+  if (!j) return PSC_ENOMEM;
+  j->desc.ni = d->ni;
+  j->desc.nj = d->nj;
+  j->desc.nk = d->nk;
+  j->desc.voxel_radius = d->voxel_radius;
+  j->desc.seed = d->seed;
+  j->desc.max_molecules = d->max_molecules;
+  j->desc.flags = d->flags;
+  j->desc.device = S->opt.device;
+  if (d->n_species && d->D) j->D.assign(d->D, d->D + d->n_species);
+  if (d->n_reactions && d->reactions) j->rx.assign(d->reactions, d->reactions + d->n_reactions);
+  if (d->n_place && d->place) j->place.assign(d->place, d->place + d->n_place);
+  j->n_events = d->n_events;
+  j->keep_state = d->keep_state != 0;
+  psc_server_job_bytes(d, &j->est_bytes);
+  std::lock_guard<std::mutex> g(S->mu);
+  if (S->stopping) {
+    delete j;
+    return PSC_ESTATE;
+  }
+  j->id = S->next_job++;
+  j->st.state = PSC_JOB_QUEUED;
+  j->st.submit_s = seconds(S);
+  S->jobs[j->id] = j;
+  S->stats.submitted++;
+  if (j->est_bytes > S->opt.budget_bytes) {
+    // can never fit: rejected at once, the others are unaffected
+    finish_job(S, j, PSC_JOB_FAILED, PSC_ENOMEM);
+  } else {
+    S->queue.push_back(j);
+    S->cv_work.notify_one();
+  }
+  *job_id = j->id;
+  return PSC_OK;
+}
+
+psc_status psc_server_poll(psc_server *S, uint64_t job_id, psc_job_status *out) {
+  if (!S || !out) return PSC_EINVAL;
+  std::lock_guard<std::mutex> g(S->mu);
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return PSC_EINVAL;
+  *out = it->second->st;
+  return PSC_OK;
+}
+
+psc_status psc_server_wait(psc_server *S, uint64_t job_id, psc_job_status *out) {
+  if (!S) return PSC_EINVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return PSC_EINVAL;
+  Job *j = it->second;
+  S->cv_done.wait(lk, [&] { return j->st.state == PSC_JOB_DONE || j->st.state == PSC_JOB_FAILED; });
+  if (out) *out = j->st;
+  return PSC_OK;
+}
+
+psc_status psc_server_read_state(psc_server *S, uint64_t job_id, psc_state_view *out) {
+  if (!S || !out) return PSC_EINVAL;
+  psc_lattice *h = nullptr;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->jobs.find(job_id);
+    if (it == S->jobs.end()) return PSC_EINVAL;
+    if (it->second->st.state != PSC_JOB_DONE || !it->second->lat) return PSC_ESTATE;
+    h = it->second->lat;
+  }
+  return psc_read_state(h, out, nullptr);
+}
+
+psc_status psc_server_release(psc_server *S, uint64_t job_id) {
+  if (!S) return PSC_EINVAL;
+  std::lock_guard<std::mutex> g(S->mu);
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return PSC_EINVAL;
+  if (it->second->st.state != PSC_JOB_DONE && it->second->st.state != PSC_JOB_FAILED)
+    return PSC_ESTATE;
+  release_lattice(S, it->second);
+  S->cv_work.notify_one();
+  return PSC_OK;
+}
+
+psc_status psc_server_stats_get(psc_server *S, psc_server_stats *out) {
+  if (!S || !out) return PSC_EINVAL;
+  std::lock_guard<std::mutex> g(S->mu);
+  *out = S->stats;
+  return PSC_OK;
+}
+
+const char *psc_server_last_error(const psc_server *S) { return S ? S->err.c_str() : ""; }
+
+void psc_server_destroy(psc_server *S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->stopping = true;
+    S->cv_work.notify_all();
+  }
+  if (S->worker.joinable()) S->worker.join();
+  (void)hipSetDevice(S->opt.device);
+  if (S->ens.exec) (void)hipGraphExecDestroy(S->ens.exec);
+  if (S->ens.graph) (void)hipGraphDestroy(S->ens.graph);
+  if (S->ens.cap_stream) (void)hipStreamDestroy(S->ens.cap_stream);
+  if (S->ens.d_lats) (void)hipFree(S->ens.d_lats);
+  S->ens.members.clear();
+  for (auto &kv : S->jobs) {
+    if (kv.second->lat) psc_destroy(kv.second->lat);
+    delete kv.second;
+  }
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  delete S;
+}
+
+}  // extern "C"

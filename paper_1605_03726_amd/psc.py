@@ -405,3 +405,198 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+class ServerOptions(C.Structure):
+    _fields_ = [("device", C.c_int32), ("budget_bytes", C.c_uint64),
+                ("quantum_events", C.c_uint32), ("max_active", C.c_uint32)]
+
+
+class ReactionDesc(C.Structure):
+    _fields_ = [("n_r", C.c_uint32), ("n_p", C.c_uint32), ("reactants", C.c_uint16 * 2),
+                ("products", C.c_uint16 * 11), ("k", C.c_double)]
+
+
+class PlaceDesc(C.Structure):
+    _fields_ = [("species", C.c_uint16), ("count", C.c_uint64)]
+
+
+class JobDesc(C.Structure):
+    _fields_ = [("ni", C.c_uint32), ("nj", C.c_uint32), ("nk", C.c_uint32),
+                ("voxel_radius", C.c_double), ("seed", C.c_uint64),
+                ("max_molecules", C.c_uint64), ("flags", C.c_uint32),
+                ("n_species", C.c_uint32), ("D", C.POINTER(C.c_double)),
+                ("n_reactions", C.c_uint32), ("reactions", C.POINTER(ReactionDesc)),
+                ("n_place", C.c_uint32), ("place", C.POINTER(PlaceDesc)),
+                ("n_events", C.c_uint64), ("keep_state", C.c_uint32)]
+
+
+class JobStatus(C.Structure):
+    _fields_ = [("state", C.c_int32), ("error", C.c_int32), ("submit_s", C.c_double),
+                ("admit_s", C.c_double), ("done_s", C.c_double), ("events_done", C.c_uint64),
+                ("counters", Counters)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("done", C.c_uint64),
+                ("failed", C.c_uint64), ("active", C.c_uint64), ("queued", C.c_uint64),
+                ("device_bytes_in_use", C.c_uint64), ("attempts", C.c_uint64),
+                ("quanta", C.c_uint64), ("busy_s", C.c_double), ("peak_active", C.c_uint64)]
+
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
+
+def _server_lib():
+    L = lib()
+    if getattr(L, "_server_bound", False):
+        return L
+    vp = C.c_void_p
+    L.psc_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(vp)]
+    L.psc_server_create.restype = C.c_int32
+    L.psc_server_submit.argtypes = [vp, C.POINTER(JobDesc), C.POINTER(C.c_uint64)]
+    L.psc_server_submit.restype = C.c_int32
+    L.psc_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(JobStatus)]
+    L.psc_server_poll.restype = C.c_int32
+    L.psc_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(JobStatus)]
+    L.psc_server_wait.restype = C.c_int32
+    L.psc_server_read_state.argtypes = [vp, C.c_uint64, C.POINTER(StateView)]
+    L.psc_server_read_state.restype = C.c_int32
+    L.psc_server_release.argtypes = [vp, C.c_uint64]
+    L.psc_server_release.restype = C.c_int32
+    L.psc_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
+    L.psc_server_stats_get.restype = C.c_int32
+    L.psc_server_last_error.argtypes = [vp]
+    L.psc_server_last_error.restype = C.c_char_p
+    L.psc_server_job_bytes.argtypes = [C.POINTER(JobDesc), C.POINTER(C.c_uint64)]
+    L.psc_server_job_bytes.restype = C.c_int32
+    L.psc_server_destroy.argtypes = [vp]
+    L.psc_server_destroy.restype = None
+    L._server_bound = True
+    return L
+
+
+def _status(st: JobStatus) -> dict:
+    return {"state": st.state, "error": st.error, "submit_s": st.submit_s,
+            "admit_s": st.admit_s, "done_s": st.done_s, "events_done": st.events_done,
+            "attempts": st.counters.attempts, "hops": st.counters.hops,
+            "collisions": st.counters.collisions,
+            "place_fail": st.counters.placement_failures}
+
+
+class Server:
+    """Continuous-batching serving loop (psc_server_* in include/psc.h)."""
+
+    def __init__(self, budget_bytes: int, quantum_events: int = 64, max_active: int = 4096,
+                 device: int = 0):
+        self.L = _server_lib()
+        o = ServerOptions(device, budget_bytes, quantum_events, max_active)
+        h = C.c_void_p()
+        rc = self.L.psc_server_create(C.byref(o), C.byref(h))
+        if rc != PSC_OK:
+            raise PscError(rc, "server create failed")
+        self.h = h
+        self._meta = {}
+
+    def _check(self, rc):
+        if rc != PSC_OK:
+            raise PscError(rc, self.L.psc_server_last_error(self.h).decode())
+
+    def submit(self, w: dict, keep_state: bool = False, max_molecules: int | None = None) -> int:
+        d, keep = job_desc(w, keep_state, max_molecules)
+        jid = C.c_uint64()
+        self._check(self.L.psc_server_submit(self.h, C.byref(d), C.byref(jid)))
+        nv = int(w["dims"][0]) * int(w["dims"][1]) * int(w["dims"][2])
+        self._meta[jid.value] = (nv, len(w["reactions"]))
+        return jid.value
+
+    @staticmethod
+    def job_bytes(w: dict, max_molecules: int | None = None) -> int:
+        d, keep = job_desc(w, False, max_molecules)
+        b = C.c_uint64()
+        rc = _server_lib().psc_server_job_bytes(C.byref(d), C.byref(b))
+        if rc != PSC_OK:
+            raise PscError(rc, "job_bytes")
+        return b.value
+
+    def poll(self, job_id: int) -> dict:
+        st = JobStatus()
+        self._check(self.L.psc_server_poll(self.h, job_id, C.byref(st)))
+        return _status(st)
+
+    def wait(self, job_id: int) -> dict:
+        st = JobStatus()
+        self._check(self.L.psc_server_wait(self.h, job_id, C.byref(st)))
+        return _status(st)
+
+    def read_state(self, job_id: int, max_molecules: int) -> dict:
+        nv, n_rx = self._meta[job_id]
+        occ = np.zeros(nv, np.uint16)
+        arrays = {k: np.zeros(max_molecules, t) for k, t in (
+            ("id", np.uint32), ("vox", np.uint32), ("species", np.uint16), ("dx", np.int32),
+            ("dy", np.int32), ("dz", np.int32))}
+        fired = np.zeros(max(n_rx, 1), np.uint64)
+        v = StateView()
+        v.occupancy = _ptr(occ, C.c_uint16)
+        v.n_molecules = max_molecules
+        v.id = _ptr(arrays["id"], C.c_uint32)
+        v.voxel = _ptr(arrays["vox"], C.c_uint32)
+        v.species = _ptr(arrays["species"], C.c_uint16)
+        v.dx, v.dy, v.dz = (_ptr(arrays[k], C.c_int32) for k in ("dx", "dy", "dz"))
+        v.reactions_fired = _ptr(fired, C.c_uint64)
+        self._check(self.L.psc_server_read_state(self.h, job_id, C.byref(v)))
+        n = v.n_molecules
+        out = {k: a[:n].copy() for k, a in arrays.items()}
+        out.update(occ=occ, attempts=v.counters.attempts, hops=v.counters.hops,
+                   collisions=v.counters.collisions, place_fail=v.counters.placement_failures,
+                   fired=fired[:n_rx].copy(), event=v.event, time=v.time, next_id=v.next_id)
+        return out
+
+    def release(self, job_id: int):
+        self._check(self.L.psc_server_release(self.h, job_id))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        self._check(self.L.psc_server_stats_get(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.psc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def job_desc(w: dict, keep_state: bool = False, max_molecules: int | None = None):
+    """psc_job_desc for a workload dict; the second value keeps the arrays
+    the descriptor points to alive"""
+    nv = int(w["dims"][0]) * int(w["dims"][1]) * int(w["dims"][2])
+    placed = sum(c for _, c in w["place"])
+    if max_molecules is None:
+        max_molecules = min(nv, max(1024, int(placed * 1.5) + 1024))
+    D = (C.c_double * max(len(w["species"]), 1))(*[d for _, d in w["species"]])
+    rxs = (ReactionDesc * max(len(w["reactions"]), 1))()
+    for i, (r, p, k) in enumerate(w["reactions"]):
+        rxs[i].n_r, rxs[i].n_p, rxs[i].k = len(r), len(p), k
+        for a, x in enumerate(r):
+            rxs[i].reactants[a] = x
+        for a, x in enumerate(p):
+            rxs[i].products[a] = x
+    pl = (PlaceDesc * max(len(w["place"]), 1))(*[PlaceDesc(s, c) for s, c in w["place"]])
+    d = JobDesc()
+    d.ni, d.nj, d.nk = (int(x) for x in w["dims"])
+    d.voxel_radius = w["rv"]
+    d.seed = w["seed"]
+    d.max_molecules = max_molecules
+    d.flags = TRACK_DISPLACEMENT if w.get("track_displacement") else 0
+    d.n_species, d.D = len(w["species"]), D
+    d.n_reactions, d.reactions = len(w["reactions"]), rxs
+    d.n_place, d.place = len(w["place"]), pl
+    d.n_events = w["events"]
+    d.keep_state = 1 if keep_state else 0
+    return d, (D, rxs, pl)

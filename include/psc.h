@@ -180,6 +180,16 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream);
  * (waits for pending work). */
 psc_status psc_read_counters(psc_lattice *h, psc_counters *out, uint64_t *event);
 
+/* Statistics without reading the state (waits for pending work):
+ * species_count[s] for s = 0..n_species (index 0 unused) = live molecules of
+ * each species, kept exact on the device through every reaction;
+ * disp_sum = sum over molecules of 3 dx^2 + dy^2 + 8 dz^2, i.e. 3 |d|^2 / r^2
+ * for the unwrapped displacements (zero unless PSC_TRACK_DISPLACEMENT), so the
+ * mean squared displacement is r^2 disp_sum / (3 n) (3.1, eq. 7);
+ * n_walkers = molecules that can move.  Any pointer may be NULL. */
+psc_status psc_read_stats(psc_lattice *h, uint64_t *species_count, uint64_t *disp_sum,
+                          uint64_t *n_walkers);
+
 /* Sizes needed to read the state. */
 psc_status psc_query_sizes(const psc_lattice *h, uint64_t *n_voxels,
                            uint64_t *n_molecules, uint32_t *n_species,

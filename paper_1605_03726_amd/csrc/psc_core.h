@@ -269,6 +269,7 @@ struct LatDev {
   uint32_t *perm;                  // [16] stage order of the running event
   uint32_t *next_id;
   unsigned long long *cnt;         // attempts, hops, collisions, placement failures
+  unsigned long long *sp_count;    // [64] live molecules per species (two's complement deltas)
   unsigned long long *fired;       // [n_rx]
   uint32_t *error;
 };
@@ -279,6 +280,7 @@ hipError_t launch_event_multi(const LatDev *lats, uint32_t R, int grid, int item
 hipError_t launch_begin(const LatDev *dL, hipStream_t s);
 hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, hipStream_t s);
 uint32_t max_members();
+hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t s);
 hipError_t launch_end(const LatDev *dL, hipStream_t s);
 int stage_items();
 int stage_threads();

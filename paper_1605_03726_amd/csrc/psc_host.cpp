@@ -346,13 +346,14 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.perm = alloc_n<uint32_t>(h, 16);
   L.next_id = alloc_n<uint32_t>(h, 1);
   L.cnt = alloc_n<unsigned long long>(h, 4);
+  L.sp_count = alloc_n<unsigned long long>(h, 64);
   L.fired = alloc_n<unsigned long long>(h, std::max<uint32_t>(R, 1));
   L.error = alloc_n<uint32_t>(h, 1);
   h->dL = alloc_n<LatDev>(h, 1);
   if (!L.occ || !L.cand_count || !L.flag_vox || !L.flag_count || !L.birth_key || !L.birth_vox ||
       !L.birth_sp || !L.birth_count || !L.fire_pos || !L.fire_id || !L.fire_col ||
       !L.fire_rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod ||
-      !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.next_id || !L.cnt ||
+      !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.next_id || !L.cnt || !L.sp_count ||
       !L.fired || !L.error || !h->dL || !L.hot[0] || !L.hot[1] || !L.end_done || !L.nbr_cnt)
     return fail(h, PSC_ENOMEM, "device allocation failed");
   L.sp_flags = d_flags;
@@ -423,6 +424,11 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   HIP_OK(h, hipMemset(L.flag_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.birth_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.cnt, 0, 4 * sizeof(unsigned long long)));
+  {
+    std::vector<unsigned long long> counts(64, 0);
+    for (uint64_t q = 0; q < nmol; ++q) counts[h->occ[h->mvox[q]] & 63u]++;
+    HIP_OK(h, up(L.sp_count, counts.data(), 64 * sizeof(unsigned long long)));
+  }
   HIP_OK(h, hipMemset(L.fired, 0, std::max<uint32_t>(R, 1) * sizeof(unsigned long long)));
   HIP_OK(h, hipMemset(L.error, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.end_done, 0, sizeof(uint32_t)));
@@ -818,6 +824,52 @@ psc_status psc_read_counters(psc_lattice *h, psc_counters *out, uint64_t *event)
   unsigned long long cnt[4];
   HIP_OK(h, hipMemcpy(cnt, h->L.cnt, sizeof cnt, hipMemcpyDeviceToHost));
   *out = psc_counters{cnt[0], cnt[1], cnt[2], cnt[3]};
+  return PSC_OK;
+}
+
+psc_status psc_read_stats(psc_lattice *h, uint64_t *species_count, uint64_t *disp_sum,
+                          uint64_t *n_walkers) {
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (!h->frozen) {
+    if (species_count) {
+      for (size_t s = 0; s < h->species.size(); ++s) species_count[s] = 0;
+      for (uint64_t q = 0; q < h->mid.size(); ++q) species_count[h->occ[h->mvox[q]]]++;
+    }
+    uint64_t acc = 0;
+    for (uint64_t q = 0; q < h->mid.size(); ++q) {
+      const int64_t X = h->mdx[q], Y = h->mdy[q], Z = h->mdz[q];
+      acc += (uint64_t)(3 * X * X + Y * Y + 8 * Z * Z);
+    }
+    if (disp_sum) *disp_sum = acc;
+    if (n_walkers) *n_walkers = h->mid.size();
+    return PSC_OK;
+  }
+  HIP_OK(h, hipSetDevice(h->desc.device));
+  HIP_OK(h, hipDeviceSynchronize());
+  psc_status st = check_device_error(h);
+  if (st) return st;
+  if (species_count) {
+    unsigned long long c[64];
+    HIP_OK(h, hipMemcpy(c, h->L.sp_count, sizeof c, hipMemcpyDeviceToHost));
+    for (size_t s = 0; s < h->species.size(); ++s) species_count[s] = c[s];
+  }
+  if (disp_sum || n_walkers) {
+    unsigned long long *d = nullptr, out[2] = {0, 0};
+    HIP_OK(h, hipMalloc(&d, sizeof out));
+    HIP_OK(h, hipMemset(d, 0, sizeof out));
+    HIP_OK(h, launch_msd(h->dL, d, nullptr));
+    HIP_OK(h, hipMemcpy(out, d, sizeof out, hipMemcpyDeviceToHost));
+    HIP_OK(h, hipFree(d));
+    // static molecules never move, but a loaded state may give them a
+    // displacement
+    for (size_t q = 0; q < h->st_id.size(); ++q) {
+      const int64_t X = h->st_d[0][q], Y = h->st_d[1][q], Z = h->st_d[2][q];
+      out[0] += (uint64_t)(3 * X * X + Y * Y + 8 * Z * Z);
+    }
+    if (disp_sum) *disp_sum = out[0];
+    if (n_walkers) *n_walkers = out[1];
+  }
   return PSC_OK;
 }
 

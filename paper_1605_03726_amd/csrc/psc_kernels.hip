@@ -157,9 +157,11 @@ __device__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in, u
   const uint32_t v = in.vox[at];
   const uint32_t m = L.rx_nprod[rx];
   const uint16_t *prod = L.rx_prod + rx * 12;
+  const uint32_t sp0 = L.occ[v] & 63u;
   if (m == 0) {
     L.occ[v] = 0;
     in.id[at] = kDeadId;
+    atomicAdd(&L.sp_count[sp0], ~0ull);  // -1
     atomicAdd(&L.fired[rx], 1ull);
     return;
   }
@@ -186,8 +188,11 @@ __device__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in, u
   }
   L.occ[v] = prod[0];
   in.sp[at] = prod[0];  // the entry stays; its cached species follows
+  atomicAdd(&L.sp_count[sp0], ~0ull);
+  atomicAdd(&L.sp_count[prod[0] & 63u], 1ull);
   for (uint32_t a = 0; a + 1 < m; ++a) {
     L.occ[dest[a]] = prod[a + 1];
+    atomicAdd(&L.sp_count[prod[a + 1] & 63u], 1ull);
     const uint32_t b = atomicAdd(s_nb, 1u);
     if (b < L.birth_cap) {
       L.birth_key[b] = ((uint64_t)id << 31) | ((uint64_t)(a + 1) << 27) | b;
@@ -366,6 +371,8 @@ struct StageShared {
   uint32_t cnt[16], base[16];
   uint32_t ncand, cand_base, nflag, flag_base;
   unsigned long long att, hop, col;
+  int32_t dsp[64];   // species count changes of this chunk
+  uint32_t any_rx;
 };
 
 // Molecules [base, base + kStageThreads * ITEMS) of colour bin c of lattice L
@@ -399,7 +406,9 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
     sh->att = 0;
     sh->hop = 0;
     sh->col = 0;
+    sh->any_rx = 0;
   }
+  if (tid < 64) sh->dsp[tid] = 0;
   __syncthreads();
 
   uint32_t vox[ITEMS], id[ITEMS], ocol[ITEMS], lpos[ITEMS], osp[ITEMS];
@@ -480,9 +489,14 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
     atomicOr(&hot_now[ht >> 5], 1u << (ht & 31u));
     flag[it] = true;
     ftgt[it] = t;
+    atomicSub(&sh->dsp[sp], 1);
+    atomicSub(&sh->dsp[psp], 1);
+    atomicAdd(&sh->dsp[prod[0] & 63u], 1);
+    sh->any_rx = 1;
     if (L.rx_nprod[rx] == 2) {
       L.occ[v] = prod[1];
       osp[it] = prod[1];
+      atomicAdd(&sh->dsp[prod[1] & 63u], 1);
     } else {
       L.occ[v] = 0;
       ocol[it] = 0xFFu;  // the mover's identity ends here
@@ -560,6 +574,8 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
     if (sh->hop) atomicAdd(&L.cnt[1], sh->hop);
     if (sh->col) atomicAdd(&L.cnt[2], sh->col);
   }
+  if (sh->any_rx && tid < 64 && sh->dsp[tid])
+    atomicAdd(&L.sp_count[tid], (unsigned long long)(long long)sh->dsp[tid]);
   __syncthreads();
 }
 
@@ -677,6 +693,42 @@ __global__ void __launch_bounds__(kStageThreads) k_end(const LatDev *__restrict_
 
 __global__ void __launch_bounds__(kStageThreads) k_end_multi(const LatDev *__restrict__ lats) {
   end_body(lats[blockIdx.y], blockIdx.x, gridDim.x);
+}
+
+// =============================================================================
+// k_msd: sum over the walkers of 3 X^2 + Y^2 + 8 Z^2 (= 3 |displacement|^2 / r^2)
+// =============================================================================
+__global__ void __launch_bounds__(kStageThreads) k_msd(const LatDev *__restrict__ Lp,
+                                                       unsigned long long *out) {
+  __shared__ unsigned long long s_red[kStageThreads / 64];
+  const LatDev &L = *Lp;
+  const Bins &in = L.bins[*L.ev & 1];
+  unsigned long long acc = 0, n = 0;
+  if (in.disp) {
+    for (uint32_t c = 0; c < 16; ++c) {
+      const uint32_t cnt = min(in.count[c], (uint32_t)L.cap);
+      for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cnt;
+           i += (uint64_t)gridDim.x * blockDim.x) {
+        if (in.id[c * L.cap + i] == kDeadId) continue;
+        const long long X = in.disp[(0 * 16 + c) * L.cap + i];
+        const long long Y = in.disp[(1 * 16 + c) * L.cap + i];
+        const long long Z = in.disp[(2 * 16 + c) * L.cap + i];
+        acc += (unsigned long long)(3 * X * X + Y * Y + 8 * Z * Z);
+        ++n;
+      }
+    }
+  }
+  acc = block_sum_u64(acc, s_red);
+  n = block_sum_u64(n, s_red);
+  if (threadIdx.x == 0) {
+    atomicAdd(&out[0], acc);
+    atomicAdd(&out[1], n);
+  }
+}
+
+hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_msd, dim3(256), dim3(kStageThreads), 0, s, dL, out);
+  return hipGetLastError();
 }
 
 // =============================================================================

@@ -123,6 +123,9 @@ def lib() -> C.CDLL:
     L.psc_set_launch.restype = C.c_int32
     L.psc_get_launch.argtypes = [vp, C.POINTER(Launch)]
     L.psc_get_launch.restype = C.c_int32
+    L.psc_read_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                 C.POINTER(C.c_uint64)]
+    L.psc_read_stats.restype = C.c_int32
     L.psc_set_kernel_timing.argtypes = [vp, C.c_int]
     L.psc_set_kernel_timing.restype = C.c_int32
     L.psc_get_kernel_times.argtypes = [vp, C.POINTER(KernelTimes)]
@@ -288,6 +291,14 @@ class Lattice:
         l = Launch()
         self._check(self.L.psc_get_launch(self.h, C.byref(l)))
         return {"items_per_thread": l.items_per_thread, "stage_blocks": l.stage_blocks}
+
+    def stats(self) -> dict:
+        counts = np.zeros(self.n_species + 1, np.uint64)
+        dsum = C.c_uint64()
+        nw = C.c_uint64()
+        self._check(self.L.psc_read_stats(self.h, _ptr(counts, C.c_uint64), C.byref(dsum),
+                                          C.byref(nw)))
+        return {"species_count": counts, "disp_sum": dsum.value, "n_walkers": nw.value}
 
     def set_kernel_timing(self, on: bool):
         self._check(self.L.psc_set_kernel_timing(self.h, 1 if on else 0))

@@ -161,3 +161,12 @@ def test_load_state_rejects_inconsistent_states():
         with pytest.raises(psc.PscError) as e:
             lat.load_state(s)
         assert e.value.code == psc.PSC_EINVAL
+
+
+def test_statistics_before_the_first_step():
+    w = workload("small_reactive")
+    lat = psc.lattice_from_workload(w, device=0)
+    st = lat.stats()
+    for sp, c in w["place"]:
+        assert st["species_count"][sp] == c
+    assert st["disp_sum"] == 0

@@ -190,3 +190,24 @@ def test_mapk_full_size_prefix():
     s = o.state()
     o.close()
     assert_same(g, s, disp=False)
+
+
+@pytest.mark.parametrize("name,kw,events", [("small_reactive", {"seed": 4}, 40),
+                                            ("cfg2", {"dims": (32, 32, 32)}, 60)])
+def test_device_statistics(name, kw, events):
+    # per-species counts kept on the device through every reaction, and the
+    # displacement sum behind the mean squared displacement
+    w = workload(name, **kw)
+    lat = build_gpu(w)
+    lat.step(events)
+    st = lat.stats()
+    g = lat.read_state()
+    o = build_oracle(w)
+    o.run(events, oracle.MODE_C)
+    s = o.state()
+    for sp in range(1, len(w["species"]) + 1):
+        assert st["species_count"][sp] == int((s["species"] == sp).sum()) == o.species_count(sp)
+    if w.get("track_displacement"):
+        X, Y, Z = (s[k].astype(np.int64) for k in ("dx", "dy", "dz"))
+        assert st["disp_sum"] == int((3 * X * X + Y * Y + 8 * Z * Z).sum())
+    assert np.array_equal(g["species"], s["species"])

@@ -62,6 +62,8 @@ def pick_workload(name: str):
         return workload("cfg2")
     if name == "cfg1":
         return workload("cfg1")
+    if name == "mapk_paper":
+        return workload("mapk_paper")
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -207,7 +209,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "mapk_paper"])
     ap.add_argument("--timing-steps", type=int, default=40)
     ap.add_argument("--cpu-events", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -56,6 +56,9 @@ typedef int32_t psc_status;
 
 /* lattice flags */
 #define PSC_TRACK_DISPLACEMENT 1u /* keep unwrapped per-molecule displacement */
+#define PSC_LAYOUT_LINEAR 2u      /* keep the occupancy in linear order on the
+                                     device instead of 4x4x4 bricks (a 128-byte
+                                     line each); results are identical */
 
 /* Device memory allocator hooks.  alloc returns a device pointer of at least
  * `bytes` bytes usable on `stream` (or NULL on failure); free releases it.

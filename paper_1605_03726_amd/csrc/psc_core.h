@@ -106,9 +106,19 @@ __host__ __device__ inline uint32_t divu(uint32_t n, const DivU32 &q) {
 //   Y = 0,0,3,3,-3,-3,c,c,d,c,c,d  with c = 1-2p, d = 4p-2.
 // Tables are bit-packed so that lanes taking different directions do not
 // diverge.
+// Memory layout of the occupancy words.  Linear: v = i + ni (j + nj k).
+// Brick: the lattice is cut into 4 x 4 x 4 bricks of 64 words (one 128-byte
+// cache line each), bricks in linear order, voxels inside a brick in linear
+// order: u = 64 ((kb nbj + jb) nbi + ib) + 16 (k & 3) + 4 (j & 3) + (i & 3)
+// with ib = i / 4 etc.  Two thirds of the hops then stay inside the mover's
+// line (one sixth in the linear layout).  The layout changes addresses only;
+// the ABI always speaks linear indices.
 struct Geo {
   uint32_t ni, nj, nk;
   DivU32 dni, dnj;
+  uint32_t brick;       // 1: brick layout
+  uint32_t nbi, nbj;    // bricks along i and j
+  DivU32 dnbi, dnbj;
 };
 
 struct Coord {
@@ -116,13 +126,27 @@ struct Coord {
 };
 
 __host__ __device__ inline Coord coord_of(const Geo &g, uint32_t v) {
+  Coord c;
+  if (g.brick) {
+    const uint32_t b = v >> 6;
+    const uint32_t a = divu(b, g.dnbi);
+    const uint32_t kb = divu(a, g.dnbj);
+    c.i = (int32_t)(((b - a * g.nbi) << 2) | (v & 3u));
+    c.j = (int32_t)(((a - kb * g.nbj) << 2) | ((v >> 2) & 3u));
+    c.k = (int32_t)((kb << 2) | ((v >> 4) & 3u));
+    return c;
+  }
   const uint32_t a = divu(v, g.dni);
   const uint32_t k = divu(a, g.dnj);
-  Coord c;
   c.i = (int32_t)(v - a * g.ni);
   c.j = (int32_t)(a - k * g.nj);
   c.k = (int32_t)k;
   return c;
+}
+
+// linear index of a coordinate (the ABI's voxel index)
+__host__ __device__ inline uint32_t linear_of(const Geo &g, const Coord &c) {
+  return (uint32_t)c.i + g.ni * ((uint32_t)c.j + g.nj * (uint32_t)c.k);
 }
 
 __host__ __device__ inline uint32_t colour_of(const Coord &c) {
@@ -131,7 +155,28 @@ __host__ __device__ inline uint32_t colour_of(const Coord &c) {
 }
 
 __host__ __device__ inline uint32_t index_of(const Geo &g, const Coord &c) {
+  if (g.brick) {
+    const uint32_t ib = (uint32_t)c.i >> 2, jb = (uint32_t)c.j >> 2, kb = (uint32_t)c.k >> 2;
+    return (((kb * g.nbj + jb) * g.nbi + ib) << 6) | (((uint32_t)c.k & 3u) << 4) |
+           (((uint32_t)c.j & 3u) << 2) | ((uint32_t)c.i & 3u);
+  }
   return (uint32_t)c.i + g.ni * ((uint32_t)c.j + g.nj * (uint32_t)c.k);
+}
+
+// layout index <-> linear index
+__host__ __device__ inline uint32_t to_layout(const Geo &g, uint32_t lin) {
+  if (!g.brick) return lin;
+  const uint32_t a = divu(lin, g.dni);
+  const uint32_t k = divu(a, g.dnj);
+  Coord c;
+  c.i = (int32_t)(lin - a * g.ni);
+  c.j = (int32_t)(a - k * g.nj);
+  c.k = (int32_t)k;
+  return index_of(g, c);
+}
+
+__host__ __device__ inline uint32_t to_linear(const Geo &g, uint32_t u) {
+  return g.brick ? linear_of(g, coord_of(g, u)) : u;
 }
 
 // target coordinate of hop n from c (periodic)
@@ -191,13 +236,14 @@ struct Bins {
 };
 
 // Voxels where a collision put a product on the partner's voxel are marked
-// in a per-event hash bitmap.  Only there can a bin entry's cached species be
-// stale (the partner keeps its entry and its id but changes species), or
-// the molecule be one that must not walk again in this event; everywhere
-// else the walk trusts the cached species and never reads the lattice word
-// at the mover's voxel.  Event e sets hot[e & 1] and consults hot[e & 1] and
-// hot[(e + 1) & 1] (the previous event's); the end of event e clears the
-// latter for reuse by event e + 1.
+// in a hash bitmap.  Only there can a bin entry's cached species be stale
+// (the partner keeps its entry and its id but changes species), or the
+// molecule be one that must not walk again in this event; everywhere else the
+// walk trusts the cached species and never reads the lattice word at the
+// mover's voxel.  Each 32-bit word holds 16 hash slots with one bit per event
+// parity (bit 2 slot + parity), so one load answers "marked in this or the
+// previous event"; event e sets parity e & 1 and the end of event e clears
+// parity (e + 1) & 1 for reuse by event e + 1.
 __host__ __device__ inline uint32_t hot_hash(uint32_t v, uint32_t bits) {
   return (v * 0x9E3779B1u) >> (32u - bits);
 }
@@ -218,9 +264,11 @@ struct LatDev {
   uint32_t *cand_count;   // [2]
   uint64_t cand_cap;
 
-  // voxels carrying the reacted flag in this walk
-  uint32_t *flag_vox;
-  uint32_t *flag_count;
+  // voxels where a collision put a product on the partner's voxel, by event
+  // parity: the walk of event e appends to list e & 1; its end clears their
+  // reacted flags and the hot marks of the previous event's list
+  uint32_t *flag_vox[2];
+  uint32_t *flag_count;   // [2]
   uint64_t flag_cap;
 
   // first-order newborns of one event: key = parent id << 4 | product index
@@ -231,8 +279,8 @@ struct LatDev {
   uint64_t birth_cap;
 
   // stale-entry filter (see hot_hash)
-  uint32_t *hot[2];
-  uint32_t hot_bits;      // log2 of the bitmap size in bits
+  uint32_t *hot;          // [2^hot_bits / 16] words
+  uint32_t hot_bits;      // log2 of the number of hash slots
   uint32_t *end_done;     // completion counter of the multi-block k_end
 
   // scratch of the first-order pass: molecules firing this event
@@ -281,6 +329,9 @@ hipError_t launch_begin(const LatDev *dL, hipStream_t s);
 hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, hipStream_t s);
 uint32_t max_members();
 hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t s);
+// occupancy between the linear (ABI) order and the lattice's layout
+hipError_t launch_relayout(const Geo &g, uint64_t nv, const uint16_t *src, uint16_t *dst,
+                           bool to_layout_order, hipStream_t s);
 hipError_t launch_end(const LatDev *dL, hipStream_t s);
 int stage_items();
 int stage_threads();

@@ -257,6 +257,8 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   }
 
   // split molecules into the walk's bins and the static list
+  Geo lin_geo = h->geo;  // decodes the ABI's linear indices
+  lin_geo.brick = 0;
   h->st_id.clear();
   h->st_vox.clear();
   for (auto &d : h->st_d) d.clear();
@@ -275,7 +277,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
       h->st_d[2].push_back(h->mdz[q]);
       continue;
     }
-    colour[q] = (uint8_t)colour_of(coord_of(h->geo, h->mvox[q]));
+    colour[q] = (uint8_t)colour_of(coord_of(lin_geo, h->mvox[q]));
     bin_count[colour[q]]++;
     walkers.push_back(q);
   }
@@ -307,8 +309,9 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   }
   L.cand_count = alloc_n<uint32_t>(h, 2);
   L.cand_cap = cap;
-  L.flag_vox = alloc_n<uint32_t>(h, cap);
-  L.flag_count = alloc_n<uint32_t>(h, 1);
+  L.flag_vox[0] = alloc_n<uint32_t>(h, cap);
+  L.flag_vox[1] = alloc_n<uint32_t>(h, cap);
+  L.flag_count = alloc_n<uint32_t>(h, 2);
   L.flag_cap = cap;
   L.birth_cap = std::min<uint64_t>(pow2_at_least(cap), 1ull << 27);
   L.birth_key = alloc_n<uint64_t>(h, L.birth_cap);
@@ -320,8 +323,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
     while (bits < 24 && (1ull << bits) < cap / 4) ++bits;
     L.hot_bits = bits;
   }
-  L.hot[0] = alloc_n<uint32_t>(h, (1ull << L.hot_bits) / 32);
-  L.hot[1] = alloc_n<uint32_t>(h, (1ull << L.hot_bits) / 32);
+  L.hot = alloc_n<uint32_t>(h, (1ull << L.hot_bits) / 16);
   L.end_done = alloc_n<uint32_t>(h, 1);
   L.nbr_bits = 12;
   while (L.nbr_bits < 22 && (1ull << L.nbr_bits) < 8 * cap) ++L.nbr_bits;
@@ -350,11 +352,11 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.fired = alloc_n<unsigned long long>(h, std::max<uint32_t>(R, 1));
   L.error = alloc_n<uint32_t>(h, 1);
   h->dL = alloc_n<LatDev>(h, 1);
-  if (!L.occ || !L.cand_count || !L.flag_vox || !L.flag_count || !L.birth_key || !L.birth_vox ||
+  if (!L.occ || !L.cand_count || !L.flag_vox[0] || !L.flag_vox[1] || !L.flag_count || !L.birth_key || !L.birth_vox ||
       !L.birth_sp || !L.birth_count || !L.fire_pos || !L.fire_id || !L.fire_col ||
       !L.fire_rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod ||
       !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.next_id || !L.cnt || !L.sp_count ||
-      !L.fired || !L.error || !h->dL || !L.hot[0] || !L.hot[1] || !L.end_done || !L.nbr_cnt)
+      !L.fired || !L.error || !h->dL || !L.hot || !L.end_done || !L.nbr_cnt)
     return fail(h, PSC_ENOMEM, "device allocation failed");
   L.sp_flags = d_flags;
   L.pair_rx = d_pair;
@@ -378,7 +380,17 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   HIP_OK(h, up(d_fo_first, h->fo_first.data(), 64 * sizeof(uint16_t)));
   HIP_OK(h, up(d_fo_n, h->fo_n.data(), 64));
   if (!h->fo_rx.empty()) HIP_OK(h, up(d_fo_rx, h->fo_rx.data(), h->fo_rx.size() * sizeof(uint16_t)));
-  HIP_OK(h, up(L.occ, h->occ.data(), h->nv * sizeof(uint16_t)));
+  if (h->geo.brick) {
+    uint16_t *tmp = nullptr;
+    if (hipMalloc(&tmp, h->nv * sizeof(uint16_t)) != hipSuccess)
+      return fail(h, PSC_ENOMEM, "transient device buffer for the layout change failed");
+    HIP_OK(h, up(tmp, h->occ.data(), h->nv * sizeof(uint16_t)));
+    HIP_OK(h, launch_relayout(h->geo, h->nv, tmp, L.occ, true, stream));
+    HIP_OK(h, hipStreamSynchronize(stream));
+    HIP_OK(h, hipFree(tmp));
+  } else {
+    HIP_OK(h, up(L.occ, h->occ.data(), h->nv * sizeof(uint16_t)));
+  }
 
   // bins of the current event parity, by colour (counting sort)
   const int cur = (int)(h->event0 & 1);
@@ -392,7 +404,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
     for (int c = 0; c < 16; ++c) fill[c] = start[c];
     for (uint64_t q : walkers) {
       const uint64_t at = fill[colour[q]]++;
-      vox[at] = h->mvox[q];
+      vox[at] = to_layout(h->geo, h->mvox[q]);
       id[at] = h->mid[q];
       spc[at] = h->occ[h->mvox[q]];
       if (disp) {
@@ -421,7 +433,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
     HIP_OK(h, hipMemset(L.bins[cur ^ 1].count, 0, 16 * sizeof(uint32_t)));
   }
   HIP_OK(h, hipMemset(L.cand_count, 0, 2 * sizeof(uint32_t)));
-  HIP_OK(h, hipMemset(L.flag_count, 0, sizeof(uint32_t)));
+  HIP_OK(h, hipMemset(L.flag_count, 0, 2 * sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.birth_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.cnt, 0, 4 * sizeof(unsigned long long)));
   {
@@ -433,8 +445,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   HIP_OK(h, hipMemset(L.error, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.end_done, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.nbr_cnt, 0, (1ull << L.nbr_bits) * sizeof(uint32_t)));
-  HIP_OK(h, hipMemset(L.hot[0], 0, (1ull << L.hot_bits) / 8));
-  HIP_OK(h, hipMemset(L.hot[1], 0, (1ull << L.hot_bits) / 8));
+  HIP_OK(h, hipMemset(L.hot, 0, (1ull << L.hot_bits) / 4));
   HIP_OK(h, up(L.ev, &h->event0, sizeof(uint64_t)));
   HIP_OK(h, up(L.next_id, &h->next_id, sizeof(uint32_t)));
 
@@ -448,10 +459,11 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   // launch shape of the stage kernel: enough workgroups for the expected
   // bin size, grid-striding beyond
   if (!h->grid_set) {
+    // about two passes over an average colour bin per workgroup
     const uint64_t per_block = (uint64_t)stage_threads() * (uint64_t)h->items;
     const uint64_t expect = std::max<uint64_t>(cap / 16, 1);
     h->grid = (int)std::min<uint64_t>(
-        std::max<uint64_t>((expect + per_block - 1) / per_block, 1), 4096);
+        std::max<uint64_t>((expect + 2 * per_block - 1) / (2 * per_block), 1), 4096);
   }
   HIP_OK(h, launch_scan(h->dL, std::min(h->grid * 4, 4096), stream));
   h->frozen = true;
@@ -475,12 +487,12 @@ uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool dis
     if (displacement) t += r(3 * 16 * cap * 4);
     t += r(cap * 4) * 2 + r(cap);
   }
-  t += r(8) + r(cap * 4) + r(4);
+  t += r(8) + 2 * r(cap * 4) + r(8);
   const uint64_t bcap = std::min<uint64_t>(pow2_at_least(cap), 1ull << 27);
   t += r(bcap * 8) + r(bcap * 4) + r(bcap * 2) + r(4);
   uint32_t hb = 16;
   while (hb < 24 && (1ull << hb) < cap / 4) ++hb;
-  t += 2 * r((1ull << hb) / 8) + r(4);
+  t += r((1ull << hb) / 4) + r(4);
   uint32_t nb = 12;
   while (nb < 22 && (1ull << nb) < 8 * cap) ++nb;
   t += r((1ull << nb) * 4);
@@ -536,7 +548,7 @@ psc_status psc_create_lattice(const psc_lattice_desc *desc, psc_lattice **out) {
     g_create_error = "alloc and free hooks come together";
     return PSC_EINVAL;
   }
-  if (desc->flags & ~PSC_TRACK_DISPLACEMENT) {
+  if (desc->flags & ~(PSC_TRACK_DISPLACEMENT | PSC_LAYOUT_LINEAR)) {
     g_create_error = "unknown flags";
     return PSC_EINVAL;
   }
@@ -553,6 +565,11 @@ psc_status psc_create_lattice(const psc_lattice_desc *desc, psc_lattice **out) {
   h->geo.nk = nk;
   h->geo.dni = make_div(ni);
   h->geo.dnj = make_div(nj);
+  h->geo.brick = (desc->flags & PSC_LAYOUT_LINEAR) ? 0u : 1u;
+  h->geo.nbi = ni / 4;
+  h->geo.nbj = nj / 4;
+  h->geo.dnbi = make_div(ni / 4);
+  h->geo.dnbj = make_div(nj / 4);
   try {
     h->occ.assign(nv, 0);
   } catch (...) {
@@ -1009,6 +1026,7 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
   const uint64_t nwalk = vox.size();
   for (uint64_t q = 0; q < h->st_id.size(); ++q) order.push_back(nwalk + q);
   auto id_of = [&](uint64_t q) { return q < nwalk ? id[q] : h->st_id[q - nwalk]; };
+  for (uint64_t q = 0; q < nwalk; ++q) vox[q] = to_linear(h->geo, vox[q]);
   auto vox_of = [&](uint64_t q) { return q < nwalk ? vox[q] : h->st_vox[q - nwalk]; };
   std::sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) { return id_of(a) < id_of(b); });
   const uint64_t n = order.size();
@@ -1023,7 +1041,16 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
     occp = occ.data();
   }
   if (occp) {
-    HIP_OK(h, hipMemcpy(occp, L.occ, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
+    if (h->geo.brick) {
+      uint16_t *tmp = nullptr;
+      if (hipMalloc(&tmp, h->nv * sizeof(uint16_t)) != hipSuccess)
+        return fail(h, PSC_ENOMEM, "transient device buffer for the layout change failed");
+      HIP_OK(h, launch_relayout(h->geo, h->nv, L.occ, tmp, false, nullptr));
+      HIP_OK(h, hipMemcpy(occp, tmp, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
+      HIP_OK(h, hipFree(tmp));
+    } else {
+      HIP_OK(h, hipMemcpy(occp, L.occ, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
+    }
     for (uint64_t v = 0; v < h->nv; ++v) occp[v] &= kSpeciesMask;
   }
   for (uint64_t z = 0; z < n; ++z) {

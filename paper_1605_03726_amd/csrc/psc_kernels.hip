@@ -392,8 +392,7 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
   const uint32_t cnext = (uint32_t)((e + 1) & 1);
   const uint64_t cap = L.cap;
   const bool disp = in.disp != nullptr;
-  uint32_t *hot_now = L.hot[buf];
-  const uint32_t *hot_prev = L.hot[buf ^ 1];
+  uint32_t *hot = L.hot;
   const uint32_t hbits = L.hot_bits;
   unsigned long long n_att = 0, n_hop = 0, n_col = 0;
   uint32_t *s_cnt = sh->cnt, *s_base = sh->base;
@@ -451,7 +450,7 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
     uint32_t sp = osp[it] & 63u;
     ocol[it] = c;  // stays in place unless it hops or is consumed
     const uint32_t h = hot_hash(v, hbits);
-    if (((hot_now[h >> 5] | hot_prev[h >> 5]) >> (h & 31u)) & 1u) {
+    if ((hot[h >> 4] >> ((h & 15u) << 1)) & 3u) {
       // the cached species may be stale, or the molecule may have reacted
       // as a partner earlier in this walk: consult the lattice word
       const uint16_t w = L.occ[v];
@@ -486,7 +485,7 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
     const uint16_t *prod = L.rx_prod + rx * 12;
     L.occ[t] = (uint16_t)(prod[0] | kReactedFlag);
     const uint32_t ht = hot_hash(t, hbits);
-    atomicOr(&hot_now[ht >> 5], 1u << (ht & 31u));
+    atomicOr(&hot[ht >> 4], 1u << (((ht & 15u) << 1) | buf));
     flag[it] = true;
     ftgt[it] = t;
     atomicSub(&sh->dsp[sp], 1);
@@ -514,13 +513,13 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
   }
   __syncthreads();
   if (tid < 16 && s_cnt[tid]) s_base[tid] = atomicAdd(&out.count[tid], s_cnt[tid]);
-  if (tid == 17 && s_nflag) s_flag_base = atomicAdd(L.flag_count, s_nflag);
+  if (tid == 17 && s_nflag) s_flag_base = atomicAdd(&L.flag_count[buf], s_nflag);
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     if (flag[it]) {
       const uint64_t f = (uint64_t)s_flag_base + fslot[it];
-      if (f < L.flag_cap) L.flag_vox[f] = ftgt[it];
+      if (f < L.flag_cap) L.flag_vox[buf][f] = ftgt[it];
       else set_error(L, kErrFlagOverflow);
     }
     if (ocol[it] == 0xFFu) continue;
@@ -664,23 +663,28 @@ constexpr int kEndBlocksMulti = 4;
 __device__ void end_body(const LatDev &L, uint32_t bid, uint32_t nblk) {
   const uint64_t e = *L.ev;
   if (e >= L.tape_horizon || e >= L.stop_event) return;
-  const uint32_t nf = min(*L.flag_count, (uint32_t)L.flag_cap);
+  const uint32_t cur = (uint32_t)(e & 1), prv = cur ^ 1u;
   const uint32_t stride = nblk * blockDim.x;
   const uint32_t me = bid * blockDim.x + threadIdx.x;
+  // this walk's partners may walk again from the next event on
+  const uint32_t nf = min(L.flag_count[cur], (uint32_t)L.flag_cap);
   for (uint32_t q = me; q < nf; q += stride) {
-    const uint32_t v = L.flag_vox[q];
+    const uint32_t v = L.flag_vox[cur][q];
     L.occ[v] = (uint16_t)(L.occ[v] & kSpeciesMask);
   }
-  uint32_t *prev = L.hot[(e + 1) & 1];
-  const uint32_t words = (1u << L.hot_bits) >> 5;
-  for (uint32_t q = me; q < words; q += stride) prev[q] = 0;
+  // the previous walk's hot marks have served both of their events
+  const uint32_t np = min(L.flag_count[prv], (uint32_t)L.flag_cap);
+  for (uint32_t q = me; q < np; q += stride) {
+    const uint32_t h = hot_hash(L.flag_vox[prv][q], L.hot_bits);
+    atomicAnd(&L.hot[h >> 4], ~(1u << (((h & 15u) << 1) | prv)));
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
     const uint32_t done = atomicAdd(L.end_done, 1u);
     if (done == nblk - 1) {
       __threadfence();
-      *L.flag_count = 0;
+      L.flag_count[prv] = 0;  // the next walk fills this list
       *L.end_done = 0;
       *L.ev = e + 1;
     }
@@ -724,6 +728,26 @@ __global__ void __launch_bounds__(kStageThreads) k_msd(const LatDev *__restrict_
     atomicAdd(&out[0], acc);
     atomicAdd(&out[1], n);
   }
+}
+
+// dst[u] = src[linear(u)] (linear -> layout) or dst[linear(u)] = src[u]
+__global__ void __launch_bounds__(kStageThreads) k_relayout(Geo g, uint64_t nv,
+                                                            const uint16_t *__restrict__ src,
+                                                            uint16_t *__restrict__ dst,
+                                                            int to_layout_order) {
+  for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < nv;
+       u += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t lin = linear_of(g, coord_of(g, (uint32_t)u));
+    if (to_layout_order) dst[u] = src[lin];
+    else dst[lin] = src[u];
+  }
+}
+
+hipError_t launch_relayout(const Geo &g, uint64_t nv, const uint16_t *src, uint16_t *dst,
+                           bool to_layout_order, hipStream_t s) {
+  hipLaunchKernelGGL(k_relayout, dim3(8192), dim3(kStageThreads), 0, s, g, nv, src, dst,
+                     to_layout_order ? 1 : 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t s) {

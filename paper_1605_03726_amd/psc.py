@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(PKG, "libpsc.so")
 
 PSC_OK, PSC_EINVAL, PSC_ESTATE, PSC_ENOMEM, PSC_ECAPACITY, PSC_EDEVICE = 0, -1, -2, -3, -4, -5
 TRACK_DISPLACEMENT = 1
+LAYOUT_LINEAR = 2
 
 _ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -188,7 +189,7 @@ class Lattice:
 
     def __init__(self, dims, voxel_radius: float, seed: int, max_molecules: int,
                  track_displacement: bool = False, device: int = 0,
-                 torch_allocator: bool = True):
+                 torch_allocator: bool = True, linear_layout: bool = False):
         self.L = lib()
         self.dims = tuple(int(x) for x in dims)
         self.nv = self.dims[0] * self.dims[1] * self.dims[2]
@@ -197,7 +198,8 @@ class Lattice:
         d.voxel_radius = voxel_radius
         d.seed = seed
         d.max_molecules = max_molecules
-        d.flags = TRACK_DISPLACEMENT if track_displacement else 0
+        d.flags = (TRACK_DISPLACEMENT if track_displacement else 0) | (
+            LAYOUT_LINEAR if linear_layout else 0)
         d.device = device
         self._hooks = None
         if torch_allocator:
@@ -343,7 +345,7 @@ class Lattice:
 
 
 def lattice_from_workload(w: dict, max_molecules: int | None = None, device: int = 0,
-                          place: bool = True) -> Lattice:
+                          place: bool = True, linear_layout: bool = False) -> Lattice:
     """Builds a Lattice from a workload description (species, reactions,
     uniform placements)."""
     nv = int(np.prod(w["dims"]))
@@ -351,7 +353,8 @@ def lattice_from_workload(w: dict, max_molecules: int | None = None, device: int
         placed = sum(c for _, c in w["place"])
         max_molecules = min(nv, max(1024, int(placed * 1.5) + 1024))
     lat = Lattice(w["dims"], w["rv"], w["seed"], max_molecules,
-                  track_displacement=w.get("track_displacement", False), device=device)
+                  track_displacement=w.get("track_displacement", False), device=device,
+                  linear_layout=linear_layout)
     for name, D in w["species"]:
         lat.add_species(name, D)
     for r, p, k in w["reactions"]:

@@ -134,11 +134,53 @@ def small_reactive(dims=(16, 12, 8), seed: int = 7, events: int = 40) -> dict:
                 events=events, track_displacement=True)
 
 
+AVOGADRO = 6.02214076e23
+
+
+def per_nM_s(k: float) -> float:
+    """second-order rate constant in 1/(nM s) -> m^3/s per molecule pair"""
+    return k * 1e9 * 1e-3 / AVOGADRO
+
+
+def mapk_paper(events: int = 450000, dims=(480, 480, 480), seed: int = 6,
+               mapkk_nM: float = 50.0) -> dict:
+    """The paper's MAPK model (its section 3.4): MAPK doubly phosphorylated by
+    MAPKK and dephosphorylated by a phosphatase, 9 species, 12 reactions,
+    D = 1 um^2/s, r_v = 10 nm, 480^3 voxels, MAPK 200 nM, MAPKK 50 nM, Pase
+    50 nM.  Counts come from those concentrations over the simulated
+    lattice's own volume (n_v 4 sqrt2 r^3 = 0.626 pL for 480^3; the paper's
+    0.443 pL does not match its lattice).  30 s simulated = 450,000 events."""
+    rv = 10e-9
+    D = 1e-12
+    nv = dims[0] * dims[1] * dims[2]
+    volume_l = nv * 4.0 * math.sqrt(2.0) * rv ** 3 * 1e3
+    def count(nM):
+        return int(nM * 1e-9 * volume_l * AVOGADRO)
+    k1, k2, k3 = per_nM_s(0.027), 1.3, 1.5
+    k4, k5, k6 = per_nM_s(0.026), 1.73, 15.0
+    names = ["MAPK", "pMAPK", "ppMAPK", "MAPKK", "Pase",
+             "MAPK/MAPKK", "pMAPK/MAPKK", "ppMAPK/Pase", "pMAPK/Pase"]
+    K, Kp, Kpp, KK, P, C1, C2, C3, C4 = range(1, 10)
+    reactions = [
+        ((K, KK), (C1,), k1), ((C1,), (K, KK), k2),
+        ((Kp, KK), (C2,), k4), ((C2,), (Kp, KK), k5),
+        ((Kpp, P), (C3,), k1), ((C3,), (Kpp, P), k2),
+        ((Kp, P), (C4,), k4), ((C4,), (Kp, P), k5),
+        ((C1,), (Kp, KK), k3), ((C2,), (Kpp, KK), k6),
+        ((C3,), (Kp, P), k3), ((C4,), (K, P), k6),
+    ]
+    return dict(name="mapk_paper_%dx%dx%d" % dims, dims=tuple(dims), rv=rv, seed=seed,
+                species=[(n, D) for n in names], reactions=reactions,
+                place=[(K, count(200.0)), (KK, count(mapkk_nM)), (P, count(50.0))],
+                events=events, track_displacement=False)
+
+
 WORKLOADS = {
     "cfg1": cfg1,
     "cfg2": cfg2,
     "cfg3": cfg3,
     "small_reactive": small_reactive,
+    "mapk_paper": mapk_paper,
 }
 
 

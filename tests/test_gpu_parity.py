@@ -211,3 +211,25 @@ def test_device_statistics(name, kw, events):
         X, Y, Z = (s[k].astype(np.int64) for k in ("dx", "dy", "dz"))
         assert st["disp_sum"] == int((3 * X * X + Y * Y + 8 * Z * Z).sum())
     assert np.array_equal(g["species"], s["species"])
+
+
+def test_paper_mapk_model_prefix():
+    # the paper's own MAPK model (9 species, 12 reactions, 480^3, r_v 10 nm)
+    w = workload("mapk_paper", events=40)
+    g, s = run_pair(w, 40, chunks=2)
+    assert s["collisions"] > 0
+
+
+@pytest.mark.parametrize("name,kw,events", [("small_reactive", {"seed": 12}, 40),
+                                            ("cfg2", {"dims": (64, 64, 64)}, 80),
+                                            ("cfg3", {"dims": (128, 128, 64)}, 40)])
+def test_linear_layout_gives_the_same_result(name, kw, events):
+    # the occupancy layout (4x4x4 bricks by default, or linear) changes
+    # addresses only
+    w = workload(name, **kw)
+    lat = psc.lattice_from_workload(w, linear_layout=True)
+    lat.step(events)
+    g = lat.read_state()
+    o = build_oracle(w)
+    o.run(events, oracle.MODE_C)
+    assert_same(g, o.state(), disp=w.get("track_displacement", False))

@@ -305,7 +305,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_stage (one colour stage of the walk)",
                      "avg_launch_ms": stage_avg_ms,
-                     "algorithmic_bytes_per_launch": alg_bytes_per_launch},
+                     "algorithmic_bytes_per_launch": alg_bytes_per_launch,
+                     # measured HBM bytes over the live launch time, and the share
+                     # of them the method needs
+                     "traffic_gbs": (traffic / (stage_avg_ms * 1e-3) / 1e9
+                                     if traffic else None),
+                     "useful_byte_fraction": (alg_bytes_per_launch / traffic
+                                              if traffic else None)},
     }
     if not args.no_ensemble:
         result["ensemble"] = ensemble_bench(args.ensemble_members, args.ensemble_events, 12, 300, 3)

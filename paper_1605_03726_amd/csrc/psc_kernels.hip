@@ -24,17 +24,17 @@ namespace {
 constexpr int kStageThreads = 256;
 constexpr int kBeginThreads = 1024;
 
-__device__ inline uint32_t colour_of_voxel(const Geo &g, uint32_t v) {
+__device__ __forceinline__ uint32_t colour_of_voxel(const Geo &g, uint32_t v) {
   return colour_of(coord_of(g, v));
 }
 
-__device__ inline void set_error(const LatDev &L, uint32_t bit) { atomicOr(L.error, bit); }
+__device__ __forceinline__ void set_error(const LatDev &L, uint32_t bit) { atomicOr(L.error, bit); }
 
 // ---- stage order ---------------------------------------------------------------
 // Fisher-Yates over the 16 colours, slot i = 15..1 swapping with
 // floor(r (i+1) / 2^32), r in sequence from the words of
 // Philox(seed; e, 0xFFFFFFFF, phase 2, block 0..3).
-__device__ void stage_order(const LatDev &L, uint64_t e, uint32_t *perm) {
+__device__ __forceinline__ void stage_order(const LatDev &L, uint64_t e, uint32_t *perm) {
   uint32_t w[16];
   for (uint32_t b = 0; b < 4; ++b) {
     const U4 r = philox((uint32_t)e, 0xFFFFFFFFu, kPhaseStage, b, L.key0, L.key1);
@@ -55,7 +55,7 @@ __device__ void stage_order(const LatDev &L, uint64_t e, uint32_t *perm) {
 
 // first-order reaction fired by a molecule of species sp with first draw r0,
 // or -1: the slot whose cumulative threshold first exceeds r0
-__device__ inline int first_order_choice(const LatDev &L, uint64_t e, uint32_t sp, uint32_t r0) {
+__device__ __forceinline__ int first_order_choice(const LatDev &L, uint64_t e, uint32_t sp, uint32_t r0) {
   const uint32_t first = L.fo_first[sp], n = L.fo_n[sp];
   const uint32_t *C = L.tape_thr + e * (uint64_t)L.n_fo + first;
   for (uint32_t a = 0; a < n; ++a)
@@ -65,7 +65,7 @@ __device__ inline int first_order_choice(const LatDev &L, uint64_t e, uint32_t s
 
 // the words used to place extra first-order products: r.y, r.z, r.w of block
 // 0, then the four words of blocks 1, 2, 3
-__device__ inline uint32_t placement_word(const LatDev &L, uint64_t e, uint32_t id, const U4 &r0,
+__device__ __forceinline__ uint32_t placement_word(const LatDev &L, uint64_t e, uint32_t id, const U4 &r0,
                                           int q) {
   if (q == 0) return r0.y;
   if (q == 1) return r0.z;
@@ -76,7 +76,7 @@ __device__ inline uint32_t placement_word(const LatDev &L, uint64_t e, uint32_t 
 }
 
 // ---- block-wide helpers ----------------------------------------------------------
-__device__ inline unsigned long long block_sum_u64(unsigned long long x,
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x,
                                                    unsigned long long *s_tmp) {
   // wavefront reduction, then one value per wave through LDS
   for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(kStageThreads) k_scan_candidates(const LatDev 
 // =============================================================================
 constexpr uint32_t kSortLds = 2048;  // birth keys sorted in LDS up to this count
 
-__device__ void bitonic_sort_keys(uint64_t *keys, uint32_t n2, int tid, int nthreads) {
+__device__ __forceinline__ void bitonic_sort_keys(uint64_t *keys, uint32_t n2, int tid, int nthreads) {
   for (uint32_t k = 2; k <= n2; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
       for (uint32_t q = tid; q < n2; q += nthreads) {
@@ -151,7 +151,7 @@ __device__ void bitonic_sort_keys(uint64_t *keys, uint32_t n2, int tid, int nthr
 // one first-order firing of the molecule at (colour c, position pos): the
 // first product stays in place, the others go to distinct vacant neighbours
 // chosen by the placement words; too few vacant neighbours: no change
-__device__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in, uint32_t c,
+__device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in, uint32_t c,
                                   uint32_t pos, uint32_t id, uint32_t rx, uint32_t *s_nb) {
   const uint64_t at = c * L.cap + pos;
   const uint32_t v = in.vox[at];
@@ -206,7 +206,7 @@ __device__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in, u
 }
 
 // the event's opening work for one lattice, by one workgroup
-__device__ void begin_body(const LatDev &L) {
+__device__ __forceinline__ void begin_body(const LatDev &L) {
   uint32_t *__restrict__ fire_pos = L.fire_pos;
   uint32_t *__restrict__ fire_id = L.fire_id;
   uint8_t *__restrict__ fire_col = L.fire_col;
@@ -368,20 +368,39 @@ __global__ void __launch_bounds__(kBeginThreads) k_begin_multi(const LatDev *__r
 // =============================================================================
 // shared scratch of one walk-stage workgroup
 struct StageShared {
-  uint32_t cnt[16], base[16];
-  uint32_t ncand, cand_base, nflag, flag_base;
+  uint32_t cnt[16], base[16], loff[16];
+  uint32_t ncand, cand_base, nflag, flag_base, total;
   unsigned long long att, hop, col;
   int32_t dsp[64];   // species count changes of this chunk
   uint32_t any_rx;
+};
+
+// a chunk's surviving entries in LDS, colour-major, so that they leave for
+// the bins in contiguous runs (coalesced stores)
+template <int ITEMS>
+struct StageStaging {
+  uint32_t vox[kStageThreads * ITEMS];
+  uint32_t id[kStageThreads * ITEMS];
+  uint32_t spc[kStageThreads * ITEMS];  // species | colour << 16
 };
 
 // Molecules [base, base + kStageThreads * ITEMS) of colour bin c of lattice L
 // in event e: each attempts one hop; collisions with a registered partner
 // fire the second-order reaction; survivors are appended to the next event's
 // bins through block-local slots (LDS) and one global reservation per colour.
+// The kernels' buffers all live in device memory: a view in the global
+// address space makes loads and stores through it global instructions
+// instead of flat ones.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> global(T *p) {
+  return (gptr<T>)p;
+}
+
 template <int ITEMS>
-__device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t base, uint32_t n,
-                            StageShared &S) {
+__device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t base, uint32_t n,
+                            StageShared &S, StageStaging<ITEMS> &stg) {
   StageShared *sh = &S;
   const int tid = threadIdx.x;
   const uint32_t buf = (uint32_t)(e & 1);
@@ -392,7 +411,11 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
   const uint32_t cnext = (uint32_t)((e + 1) & 1);
   const uint64_t cap = L.cap;
   const bool disp = in.disp != nullptr;
-  uint32_t *hot = L.hot;
+  const auto hot = global(L.hot);
+  const auto occ = global(L.occ);
+  const auto ivox = global(in.vox), iid = global(in.id), ovox = global(out.vox), oid = global(out.id);
+  const auto isp = global(in.sp), osp_ = global(out.sp);
+  const auto idsp = global(in.disp), odsp = global(out.disp);
   const uint32_t hbits = L.hot_bits;
   unsigned long long n_att = 0, n_hop = 0, n_col = 0;
   uint32_t *s_cnt = sh->cnt, *s_base = sh->base;
@@ -415,58 +438,85 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
   bool cand[ITEMS], flag[ITEMS];
   uint32_t ftgt[ITEMS];
 
+  // bin entries: lanes past the end read the last entry (base < n) and are
+  // then marked dead, so no load sits behind a branch
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
-    const uint64_t idx = base + (uint64_t)it * kStageThreads + tid;
+    const uint64_t idx = min(base + (uint64_t)it * kStageThreads + tid, (uint64_t)n - 1);
+    vox[it] = ivox[c * cap + idx];
+    id[it] = iid[c * cap + idx];
+    osp[it] = isp[c * cap + idx];
+    d0[it] = d1[it] = d2[it] = 0;
+  }
+  if (disp) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint64_t idx = min(base + (uint64_t)it * kStageThreads + tid, (uint64_t)n - 1);
+      d0[it] = idsp[(0 * 16 + c) * cap + idx];
+      d1[it] = idsp[(1 * 16 + c) * cap + idx];
+      d2[it] = idsp[(2 * 16 + c) * cap + idx];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
     ocol[it] = 0xFFu;
     cand[it] = false;
     flag[it] = false;
-    vox[it] = 0;
-    id[it] = kDeadId;
-    osp[it] = 0;
-    d0[it] = d1[it] = d2[it] = 0;
-    if (idx < n) {
-      vox[it] = in.vox[c * cap + idx];
-      id[it] = in.id[c * cap + idx];
-      osp[it] = in.sp[c * cap + idx];
-      if (disp) {
-        d0[it] = in.disp[(0 * 16 + c) * cap + idx];
-        d1[it] = in.disp[(1 * 16 + c) * cap + idx];
-        d2[it] = in.disp[(2 * 16 + c) * cap + idx];
-      }
-    }
+    if (base + (uint64_t)it * kStageThreads + tid >= n) id[it] = kDeadId;
   }
 
+  // Load phase: every item's draw, target and target word before any store.
+  // Same-stage molecules have disjoint closed neighbourhoods, so no store of
+  // this stage changes a word loaded here; issuing all loads first keeps
+  // 2 x ITEMS reads in flight per thread.  The phase has no branch: dead
+  // entries and tail lanes hold valid voxels (their results are dropped
+  // below), and a molecule whose cached species is not due reads voxel 0
+  // instead of its target.
+  uint32_t tgt[ITEMS], wt[ITEMS], hw[ITEMS], hs[ITEMS], ry[ITEMS], mv[ITEMS];
+  bool loaded[ITEMS];
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
-    if (id[it] == kDeadId) continue;
     const uint32_t v = vox[it];
     const U4 r = philox((uint32_t)e, id[it], kPhaseWalk, 0, L.key0, L.key1);
     const uint32_t dir = scale32(r.x, 12);
     const Coord cv = coord_of(L.geo, v);
     const Coord ct = step_coord(L.geo, cv, dir);
-    const uint32_t t = index_of(L.geo, ct);
-    const uint16_t wt = L.occ[t];
+    tgt[it] = index_of(L.geo, ct);
+    ry[it] = r.y;
+    mv[it] = dir | ((cv.k & 1u) << 4) | (colour_of(ct) << 8);
+    const uint32_t h = hot_hash(v, hbits);
+    hw[it] = hot[h >> 4];
+    hs[it] = (h & 15u) << 1;
+    loaded[it] = ((due >> (osp[it] & 63u)) & 1ull) != 0;
+    wt[it] = occ[loaded[it] ? tgt[it] : 0u];
+  }
+
+  // Commit phase.
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (id[it] == kDeadId) continue;
+    const uint32_t v = vox[it];
+    const uint32_t t = tgt[it];
     uint32_t sp = osp[it] & 63u;
     ocol[it] = c;  // stays in place unless it hops or is consumed
-    const uint32_t h = hot_hash(v, hbits);
-    if ((hot[h >> 4] >> ((h & 15u) << 1)) & 3u) {
+    if ((hw[it] >> hs[it]) & 3u) {
       // the cached species may be stale, or the molecule may have reacted
       // as a partner earlier in this walk: consult the lattice word
-      const uint16_t w = L.occ[v];
+      const uint16_t w = occ[v];
       sp = w & 63u;
       osp[it] = sp;
       if (w & kReactedFlag) continue;
     }
     if (!((due >> sp) & 1ull)) continue;
     ++n_att;
-    if (wt == 0) {
-      L.occ[t] = (uint16_t)sp;
-      L.occ[v] = 0;
+    const uint32_t w_t = loaded[it] ? wt[it] : (uint32_t)occ[t];
+    if (w_t == 0) {
+      occ[t] = (uint16_t)sp;
+      occ[v] = 0;
       vox[it] = t;
-      ocol[it] = colour_of(ct);
+      ocol[it] = mv[it] >> 8;
       int32_t X, Y, Z;
-      hop_vector(dir, cv.k & 1, X, Y, Z);
+      hop_vector(mv[it] & 15u, (mv[it] >> 4) & 1u, X, Y, Z);
       d0[it] += X;
       d1[it] += Y;
       d2[it] += Z;
@@ -474,18 +524,18 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
       continue;
     }
     ++n_col;
-    const uint32_t psp = wt & 63u;
+    const uint32_t psp = w_t & 63u;
     const int rx = L.pair_rx[sp * 64 + psp];
     if (rx < 0) continue;
-    if (!L.rx_always[rx] && !(r.y < L.rx_thr[rx])) continue;
+    if (!L.rx_always[rx] && !(ry[it] < L.rx_thr[rx])) continue;
     // first product on the partner's voxel with the partner's identity;
     // its own entry (wherever it is) stays valid: it is flagged so that it
     // does not walk again in this event, and its voxel is marked hot so
     // that its cached species is refreshed
     const uint16_t *prod = L.rx_prod + rx * 12;
-    L.occ[t] = (uint16_t)(prod[0] | kReactedFlag);
+    occ[t] = (uint16_t)(prod[0] | kReactedFlag);
     const uint32_t ht = hot_hash(t, hbits);
-    atomicOr(&hot[ht >> 4], 1u << (((ht & 15u) << 1) | buf));
+    atomicOr((uint32_t *)&hot[ht >> 4], 1u << (((ht & 15u) << 1) | buf));
     flag[it] = true;
     ftgt[it] = t;
     atomicSub(&sh->dsp[sp], 1);
@@ -493,27 +543,62 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
     atomicAdd(&sh->dsp[prod[0] & 63u], 1);
     sh->any_rx = 1;
     if (L.rx_nprod[rx] == 2) {
-      L.occ[v] = prod[1];
+      occ[v] = prod[1];
       osp[it] = prod[1];
       atomicAdd(&sh->dsp[prod[1] & 63u], 1);
     } else {
-      L.occ[v] = 0;
+      occ[v] = 0;
       ocol[it] = 0xFFu;  // the mover's identity ends here
     }
     atomicAdd(&L.fired[rx], 1ull);
   }
 
-  // ---- append survivors to the next event's bins: block-local slots
-  // through LDS, one global reservation per colour per block ----
+  // ---- survivors: block-local slots per colour (LDS atomics), one global
+  // reservation per colour per chunk, entries staged colour-major in LDS and
+  // written out in contiguous runs.  Flags and first-order candidates of the
+  // next event are reserved in the same round. ----
   uint32_t fslot[ITEMS], cslot[ITEMS];
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
-    if (ocol[it] != 0xFFu) lpos[it] = atomicAdd(&s_cnt[ocol[it]], 1u);
+    if (ocol[it] != 0xFFu) {
+      lpos[it] = atomicAdd(&s_cnt[ocol[it]], 1u);
+      // can this molecule fire a first-order reaction in the next event?
+      if (cmax_next) {
+        const U4 r = philox((uint32_t)(e + 1), id[it], kPhaseFirst, 0, L.key0, L.key1);
+        cand[it] = r.x < cmax_next;
+      }
+      if (cand[it]) cslot[it] = atomicAdd(&s_ncand, 1u);
+    }
     if (flag[it]) fslot[it] = atomicAdd(&s_nflag, 1u);
   }
+  if (n_att) atomicAdd(&sh->att, n_att);
+  if (n_hop) atomicAdd(&sh->hop, n_hop);
+  if (n_col) atomicAdd(&sh->col, n_col);
   __syncthreads();
-  if (tid < 16 && s_cnt[tid]) s_base[tid] = atomicAdd(&out.count[tid], s_cnt[tid]);
-  if (tid == 17 && s_nflag) s_flag_base = atomicAdd(&L.flag_count[buf], s_nflag);
+  // one wave per job: bin reservations; flag and candidate reservations;
+  // local colour offsets and the chunk's counters; species count changes
+  if (tid < 16) {
+    s_base[tid] = s_cnt[tid] ? atomicAdd(&out.count[tid], s_cnt[tid]) : 0u;
+  } else if (tid == 64) {
+    if (s_ncand) s_cand_base = atomicAdd(&L.cand_count[cnext], s_ncand);
+  } else if (tid == 65) {
+    if (s_nflag) s_flag_base = atomicAdd(&L.flag_count[buf], s_nflag);
+  } else if (tid == 128) {
+    uint32_t acc = 0;
+    for (int k = 0; k < 16; ++k) {
+      sh->loff[k] = acc;
+      acc += s_cnt[k];
+    }
+    sh->total = acc;
+  } else if (tid == 129) {
+    if (sh->att) atomicAdd(&L.cnt[0], sh->att);
+    if (sh->hop) atomicAdd(&L.cnt[1], sh->hop);
+    if (sh->col) atomicAdd(&L.cnt[2], sh->col);
+  } else if (tid >= 192) {
+    const int k = tid - 192;
+    if (sh->any_rx && sh->dsp[k])
+      atomicAdd(&L.sp_count[k], (unsigned long long)(long long)sh->dsp[k]);
+  }
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
@@ -524,63 +609,50 @@ __device__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t ba
     }
     if (ocol[it] == 0xFFu) continue;
     const uint32_t oc = ocol[it];
+    const uint32_t q = sh->loff[oc] + lpos[it];
+    stg.vox[q] = vox[it];
+    stg.id[q] = id[it];
+    stg.spc[q] = osp[it] | (oc << 16);
     const uint64_t pos = (uint64_t)s_base[oc] + lpos[it];
+    if (pos >= cap) continue;  // reported by the copy below
+    if (disp) {
+      odsp[(0 * 16 + oc) * cap + pos] = d0[it];
+      odsp[(1 * 16 + oc) * cap + pos] = d1[it];
+      odsp[(2 * 16 + oc) * cap + pos] = d2[it];
+    }
+    if (cand[it]) {
+      const uint64_t r = (uint64_t)s_cand_base + cslot[it];
+      if (r < L.cand_cap) {
+        L.cand_pos[cnext][r] = (uint32_t)pos;
+        L.cand_id[cnext][r] = id[it];
+        L.cand_col[cnext][r] = (uint8_t)oc;
+      } else {
+        set_error(L, kErrCandOverflow);
+      }
+    }
+  }
+  __syncthreads();
+  // The next chunk rewrites this LDS only after two more barriers, which
+  // every thread reaches after finishing this copy.
+  const uint32_t total = sh->total;
+  for (uint32_t q = tid; q < total; q += kStageThreads) {
+    const uint32_t w = stg.spc[q];
+    const uint32_t oc = w >> 16;
+    const uint64_t pos = (uint64_t)s_base[oc] + (q - sh->loff[oc]);
     if (pos >= cap) {
       set_error(L, kErrBinOverflow);
       continue;
     }
-    lpos[it] = (uint32_t)pos;
-    out.vox[oc * cap + pos] = vox[it];
-    out.id[oc * cap + pos] = id[it];
-    out.sp[oc * cap + pos] = (uint16_t)osp[it];
-    if (disp) {
-      out.disp[(0 * 16 + oc) * cap + pos] = d0[it];
-      out.disp[(1 * 16 + oc) * cap + pos] = d1[it];
-      out.disp[(2 * 16 + oc) * cap + pos] = d2[it];
-    }
-    // can this molecule fire a first-order reaction in the next event?
-    if (cmax_next) {
-      const U4 r = philox((uint32_t)(e + 1), id[it], kPhaseFirst, 0, L.key0, L.key1);
-      cand[it] = r.x < cmax_next;
-    }
+    ovox[oc * cap + pos] = stg.vox[q];
+    oid[oc * cap + pos] = stg.id[q];
+    osp_[oc * cap + pos] = (uint16_t)(w & 0xFFFFu);
   }
-#pragma unroll
-  for (int it = 0; it < ITEMS; ++it)
-    if (cand[it]) cslot[it] = atomicAdd(&s_ncand, 1u);
-  __syncthreads();
-  if (tid == 16 && s_ncand) s_cand_base = atomicAdd(&L.cand_count[cnext], s_ncand);
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
-    if (!cand[it]) continue;
-    const uint64_t q = (uint64_t)s_cand_base + cslot[it];
-    if (q < L.cand_cap) {
-      L.cand_pos[cnext][q] = lpos[it];
-      L.cand_id[cnext][q] = id[it];
-      L.cand_col[cnext][q] = (uint8_t)ocol[it];
-    } else {
-      set_error(L, kErrCandOverflow);
-    }
-  }
-  __syncthreads();
-  // counters of this chunk
-  if (n_att) atomicAdd(&sh->att, n_att);
-  if (n_hop) atomicAdd(&sh->hop, n_hop);
-  if (n_col) atomicAdd(&sh->col, n_col);
-  __syncthreads();
-  if (tid == 0) {
-    if (sh->att) atomicAdd(&L.cnt[0], sh->att);
-    if (sh->hop) atomicAdd(&L.cnt[1], sh->hop);
-    if (sh->col) atomicAdd(&L.cnt[2], sh->col);
-  }
-  if (sh->any_rx && tid < 64 && sh->dsp[tid])
-    atomicAdd(&L.sp_count[tid], (unsigned long long)(long long)sh->dsp[tid]);
-  __syncthreads();
 }
 
 template <int ITEMS>
 __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restrict__ Lp, uint32_t g) {
   __shared__ StageShared S;
+  __shared__ StageStaging<ITEMS> T;
   const LatDev &L = *Lp;
   const uint64_t e = *L.ev;
   if (e >= L.tape_horizon || e >= L.stop_event) return;  // error recorded / idle
@@ -588,7 +660,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
   const uint32_t n = min(L.bins[e & 1].count[c], (uint32_t)L.cap);
   const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
   for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk)
-    stage_chunk<ITEMS>(L, e, c, base, n, S);
+    stage_chunk<ITEMS>(L, e, c, base, n, S, T);
 }
 
 // Stage g of every member lattice of an ensemble in one launch: the chunks of
@@ -600,6 +672,7 @@ template <int ITEMS>
 __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__restrict__ lats,
                                                                uint32_t R, uint32_t g) {
   __shared__ StageShared S;
+  __shared__ StageStaging<ITEMS> T;
   __shared__ uint32_t s_pre[kMaxMembers + 1];
   __shared__ uint32_t s_part[kStageThreads];
   const int tid = threadIdx.x;
@@ -647,7 +720,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
     const uint64_t e = *L.ev;
     const uint32_t c = L.perm[g];
     const uint32_t n = min(L.bins[e & 1].count[c], (uint32_t)L.cap);
-    stage_chunk<ITEMS>(L, e, c, (uint64_t)(q - s_pre[a]) * chunk, n, S);
+    stage_chunk<ITEMS>(L, e, c, (uint64_t)(q - s_pre[a]) * chunk, n, S, T);
   }
 }
 
@@ -660,7 +733,7 @@ constexpr int kEndBlocksMulti = 4;
 
 // workgroup bid of nblk: sweep flags and the previous hot bitmap; the last
 // workgroup to finish advances the lattice's event counter
-__device__ void end_body(const LatDev &L, uint32_t bid, uint32_t nblk) {
+__device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t nblk) {
   const uint64_t e = *L.ev;
   if (e >= L.tape_horizon || e >= L.stop_event) return;
   const uint32_t cur = (uint32_t)(e & 1), prv = cur ^ 1u;

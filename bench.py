@@ -207,7 +207,7 @@ def calibrate_copy(nbytes: int, reps: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "mapk_paper"])
     ap.add_argument("--timing-steps", type=int, default=40)

@@ -323,10 +323,12 @@ struct LatDev {
 };
 
 hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
-hipError_t launch_event(const LatDev *dL, int grid, int items, hipStream_t s);
+// disp: the lattice tracks displacements (its bins carry the planes)
+hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, hipStream_t s);
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, int grid, int items, hipStream_t s);
 hipError_t launch_begin(const LatDev *dL, hipStream_t s);
-hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, hipStream_t s);
+hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp,
+                        hipStream_t s);
 uint32_t max_members();
 hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t s);
 // occupancy between the linear (ABI) order and the lattice's layout

@@ -762,7 +762,7 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   }
   if (!h->timing) {
     for (uint64_t e = 0; e < n_events; ++e)
-      HIP_OK(h, launch_event(h->dL, h->grid, h->items, stream));
+      HIP_OK(h, launch_event(h->dL, h->grid, h->items, h->L.bins[0].disp != nullptr, stream));
   } else {
     auto ev = [&](hipEvent_t *out) -> hipError_t {
       if (!h->event_pool.empty()) {
@@ -780,7 +780,9 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
         HIP_OK(h, ev(&t.b));
         HIP_OK(h, hipEventRecord(t.a, stream));
         if (g < 0) HIP_OK(h, launch_begin(h->dL, stream));
-        else if (g < 16) HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, h->items, stream));
+        else if (g < 16)
+          HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, h->items,
+                                 h->L.bins[0].disp != nullptr, stream));
         else HIP_OK(h, launch_end(h->dL, stream));
         HIP_OK(h, hipEventRecord(t.b, stream));
         h->timed.push_back(t);

@@ -398,7 +398,8 @@ __device__ __forceinline__ gptr<T> global(T *p) {
   return (gptr<T>)p;
 }
 
-template <int ITEMS>
+// DM: displacement planes never (0), always (1), or as the lattice says (2)
+template <int ITEMS, int DM>
 __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t base, uint32_t n,
                             StageShared &S, StageStaging<ITEMS> &stg) {
   StageShared *sh = &S;
@@ -410,7 +411,7 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
   const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
   const uint32_t cnext = (uint32_t)((e + 1) & 1);
   const uint64_t cap = L.cap;
-  const bool disp = in.disp != nullptr;
+  const bool disp = DM == 2 ? in.disp != nullptr : DM == 1;
   const auto hot = global(L.hot);
   const auto occ = global(L.occ);
   const auto ivox = global(in.vox), iid = global(in.id), ovox = global(out.vox), oid = global(out.id);
@@ -649,7 +650,7 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
   }
 }
 
-template <int ITEMS>
+template <int ITEMS, int DM>
 __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restrict__ Lp, uint32_t g) {
   __shared__ StageShared S;
   __shared__ StageStaging<ITEMS> T;
@@ -660,7 +661,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
   const uint32_t n = min(L.bins[e & 1].count[c], (uint32_t)L.cap);
   const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
   for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk)
-    stage_chunk<ITEMS>(L, e, c, base, n, S, T);
+    stage_chunk<ITEMS, DM>(L, e, c, base, n, S, T);
 }
 
 // Stage g of every member lattice of an ensemble in one launch: the chunks of
@@ -720,7 +721,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
     const uint64_t e = *L.ev;
     const uint32_t c = L.perm[g];
     const uint32_t n = min(L.bins[e & 1].count[c], (uint32_t)L.cap);
-    stage_chunk<ITEMS>(L, e, c, (uint64_t)(q - s_pre[a]) * chunk, n, S, T);
+    stage_chunk<ITEMS, 2>(L, e, c, (uint64_t)(q - s_pre[a]) * chunk, n, S, T);
   }
 }
 
@@ -841,14 +842,22 @@ hipError_t launch_begin(const LatDev *dL, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, hipStream_t s) {
+template <int DM>
+static void launch_stage_dm(const LatDev *dL, uint32_t g, int grid, int items, hipStream_t s) {
+  const dim3 G(grid), B(kStageThreads);
   switch (items) {
-  case 1: hipLaunchKernelGGL(k_stage<1>, dim3(grid), dim3(kStageThreads), 0, s, dL, g); break;
-  case 2: hipLaunchKernelGGL(k_stage<2>, dim3(grid), dim3(kStageThreads), 0, s, dL, g); break;
-  case 8: hipLaunchKernelGGL(k_stage<8>, dim3(grid), dim3(kStageThreads), 0, s, dL, g); break;
-  case 16: hipLaunchKernelGGL(k_stage<16>, dim3(grid), dim3(kStageThreads), 0, s, dL, g); break;
-  default: hipLaunchKernelGGL(k_stage<4>, dim3(grid), dim3(kStageThreads), 0, s, dL, g); break;
+  case 1: hipLaunchKernelGGL((k_stage<1, DM>), G, B, 0, s, dL, g); break;
+  case 2: hipLaunchKernelGGL((k_stage<2, DM>), G, B, 0, s, dL, g); break;
+  case 8: hipLaunchKernelGGL((k_stage<8, DM>), G, B, 0, s, dL, g); break;
+  case 16: hipLaunchKernelGGL((k_stage<16, DM>), G, B, 0, s, dL, g); break;
+  default: hipLaunchKernelGGL((k_stage<4, DM>), G, B, 0, s, dL, g); break;
   }
+}
+
+hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp,
+                        hipStream_t s) {
+  if (disp) launch_stage_dm<1>(dL, g, grid, items, s);
+  else launch_stage_dm<0>(dL, g, grid, items, s);
   return hipGetLastError();
 }
 
@@ -857,9 +866,10 @@ hipError_t launch_end(const LatDev *dL, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_event(const LatDev *dL, int grid, int items, hipStream_t s) {
+hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, hipStream_t s) {
   hipError_t err = launch_begin(dL, s);
-  for (uint32_t g = 0; g < 16 && err == hipSuccess; ++g) err = launch_stage(dL, g, grid, items, s);
+  for (uint32_t g = 0; g < 16 && err == hipSuccess; ++g)
+    err = launch_stage(dL, g, grid, items, disp, s);
   if (err == hipSuccess) err = launch_end(dL, s);
   return err;
 }

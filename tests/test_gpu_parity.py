@@ -233,3 +233,19 @@ def test_linear_layout_gives_the_same_result(name, kw, events):
     o = build_oracle(w)
     o.run(events, oracle.MODE_C)
     assert_same(g, o.state(), disp=w.get("track_displacement", False))
+
+
+@pytest.mark.parametrize("items", [1, 4, 16])
+def test_launch_shapes_on_a_reactive_lattice(items):
+    """Items per thread select different kernel instances (16 items per
+    thread exceed the register file and spill); every shape must equal the
+    oracle over many reactive events."""
+    w = workload("cfg2", dims=(128, 128, 128))
+    lat = build_gpu(w, max_molecules=1 << 20)
+    lat.set_launch(items, 64)
+    o = build_oracle(w)
+    lat.step(60)
+    o.run(60, oracle.MODE_C)
+    s = o.state()
+    assert_same(lat.read_state(), s, disp=False)
+    assert s["fired"][0] > 1000

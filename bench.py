@@ -35,8 +35,9 @@ def kernel_source_sha() -> str:
 
 
 def read_traffic(workload_name: str):
-    """HBM bytes per walk-stage launch from the committed rocprofv3 counter
-    summary, or None if absent or taken from a different kernel source."""
+    """HBM bytes per walk-stage launch and per attempt from the committed
+    rocprofv3 counter summary (averages over the timed events of the default
+    command), or None if absent or taken from a different kernel source."""
     path = os.path.join(PROFILE_DIR, "walk_stage_traffic_%s.txt" % workload_name)
     if not os.path.exists(path):
         return None
@@ -49,7 +50,8 @@ def read_traffic(workload_name: str):
     if kv.get("source_sha") != kernel_source_sha():
         return None
     try:
-        return float(kv["traffic_bytes_per_dispatch"])
+        return {"per_dispatch": float(kv["traffic_bytes_per_dispatch"]),
+                "per_attempt": float(kv["traffic_bytes_per_attempt"])}
     except (KeyError, ValueError):
         return None
 
@@ -302,16 +304,20 @@ def main():
                    "species": len(w["species"]), "reactions": len(w["reactions"]),
                    "step": "one diffusion event", "hop_fraction": hops / max(attempts, 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["per_dispatch"] if traffic else None,
                      "kernel": "k_stage (one colour stage of the walk)",
                      "avg_launch_ms": stage_avg_ms,
                      "algorithmic_bytes_per_launch": alg_bytes_per_launch,
-                     # measured HBM bytes over the live launch time, and the share
-                     # of them the method needs
-                     "traffic_gbs": (traffic / (stage_avg_ms * 1e-3) / 1e9
-                                     if traffic else None),
-                     "useful_byte_fraction": (alg_bytes_per_launch / traffic
-                                              if traffic else None)},
+                     "attempts_per_launch": t_att / stage_launches,
+                     # measured HBM bytes per attempt (profile), the rate they
+                     # imply at the live launch time, and the share of them the
+                     # method needs
+                     "traffic_per_attempt": traffic["per_attempt"] if traffic else None,
+                     "traffic_gbs": (traffic["per_attempt"] * t_att / stage_launches
+                                     / (stage_avg_ms * 1e-3) / 1e9 if traffic else None),
+                     "useful_byte_fraction": (alg_bytes_per_launch * stage_launches / t_att
+                                              / traffic["per_attempt"] if traffic else None)},
     }
     if not args.no_ensemble:
         result["ensemble"] = ensemble_bench(args.ensemble_members, args.ensemble_events, 12, 300, 3)

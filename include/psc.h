@@ -147,6 +147,22 @@ psc_status psc_add_reaction(psc_lattice *h, const uint16_t *reactants,
                             uint32_t n_r, const uint16_t *products, uint32_t n_p,
                             double k, uint32_t *out_id);
 
+/* How a registered reaction is applied.  Second order (2.4.2, eq. 6):
+ * p = k / (6 sqrt2 (D_A + D_B) r); a collision with a registered partner fires
+ * iff the draw r1 < threshold, or always once p >= 1 (clamped = 1, threshold
+ * = 2^32).  First order (2.4.1): p = k in 1/s, threshold 0, clamped 0 (its
+ * per-event probability depends on the event's interval).  Valid before and
+ * after the first step; EINVAL for an unknown reaction id or out == NULL. */
+typedef struct psc_reaction_info {
+  uint32_t order;      /* 1 or 2 */
+  uint32_t clamped;    /* 1: p > 1 was clamped to 1 */
+  double p;            /* per-collision probability before clamping; k for order 1 */
+  uint64_t threshold;  /* on a uniform 32-bit draw; 2^32 = always */
+} psc_reaction_info;
+
+psc_status psc_get_reaction_info(const psc_lattice *h, uint32_t reaction_id,
+                                 psc_reaction_info *out);
+
 /* ---- initial state -------------------------------------------------------- */
 
 /* Places `count` molecules of `species` at uniformly random vacant voxels

@@ -654,6 +654,29 @@ psc_status psc_add_reaction(psc_lattice *h, const uint16_t *reactants, uint32_t 
   return PSC_OK;
 }
 
+psc_status psc_get_reaction_info(const psc_lattice *h, uint32_t reaction_id,
+                                 psc_reaction_info *out) {
+  if (!h || !out || reaction_id >= h->rx.size()) return PSC_EINVAL;
+  const ReactionDef &d = h->rx[reaction_id];
+  *out = psc_reaction_info{};
+  out->order = d.nr;
+  if (d.nr == 1) {
+    out->p = d.k;
+    return PSC_OK;
+  }
+  double den = 6.0 * std::sqrt(2.0);
+  den = den * (h->species[d.r[0]].D + h->species[d.r[1]].D);
+  den = den * h->desc.voxel_radius;
+  out->p = d.k / den;
+  uint32_t thr = 0;
+  uint8_t always = 0;
+  second_order_threshold(d.k, h->species[d.r[0]].D, h->species[d.r[1]].D,
+                         h->desc.voxel_radius, &thr, &always);
+  out->clamped = out->p > 1.0 ? 1u : 0u;
+  out->threshold = always ? (1ull << 32) : (uint64_t)thr;
+  return PSC_OK;
+}
+
 psc_status psc_place_uniform(psc_lattice *h, uint16_t species, uint64_t count) {
   if (!h) return PSC_EINVAL;
   if (h->poisoned) return PSC_EDEVICE;

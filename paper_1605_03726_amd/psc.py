@@ -34,6 +34,11 @@ class Counters(C.Structure):
                 ("placement_failures", C.c_uint64)]
 
 
+class ReactionInfo(C.Structure):
+    _fields_ = [("order", C.c_uint32), ("clamped", C.c_uint32), ("p", C.c_double),
+                ("threshold", C.c_uint64)]
+
+
 class KernelTimes(C.Structure):
     _fields_ = [("begin_ms", C.c_double), ("stage_ms", C.c_double), ("end_ms", C.c_double),
                 ("begin_launches", C.c_uint64), ("stage_launches", C.c_uint64),
@@ -103,6 +108,8 @@ def lib() -> C.CDLL:
     L.psc_add_reaction.argtypes = [vp, C.POINTER(C.c_uint16), C.c_uint32, C.POINTER(C.c_uint16),
                                    C.c_uint32, C.c_double, C.POINTER(C.c_uint32)]
     L.psc_add_reaction.restype = C.c_int32
+    L.psc_get_reaction_info.argtypes = [vp, C.c_uint32, C.POINTER(ReactionInfo)]
+    L.psc_get_reaction_info.restype = C.c_int32
     L.psc_place_uniform.argtypes = [vp, C.c_uint16, C.c_uint64]
     L.psc_place_uniform.restype = C.c_int32
     L.psc_load_state.argtypes = [vp, C.POINTER(StateView)]
@@ -242,6 +249,11 @@ class Lattice:
                                             _ptr(p, C.c_uint16), len(products), k, C.byref(out)))
         self.n_rx += 1
         return out.value
+
+    def reaction_info(self, reaction_id: int) -> dict:
+        ri = ReactionInfo()
+        self._check(self.L.psc_get_reaction_info(self.h, reaction_id, C.byref(ri)))
+        return {f: getattr(ri, f) for f, _ in ReactionInfo._fields_}
 
     def place_uniform(self, species: int, count: int):
         self._check(self.L.psc_place_uniform(self.h, species, count))

@@ -170,3 +170,35 @@ def test_statistics_before_the_first_step():
     for sp, c in w["place"]:
         assert st["species_count"][sp] == c
     assert st["disp_sum"] == 0
+
+
+def test_reaction_info_reports_probability_and_clamping():
+    """Eq. 6: p = k / (6 sqrt2 (D_A + D_B) r).  The paper's reaction-limited
+    check (k_f = 0.027 /nM/s, D = 10 um^2/s, r = 5 nm) gives p = 0.053; the
+    crowded workload's A + B -> C (k = 1e-18 m^3/s, D 1 and 0.5 um^2/s,
+    r = 4.4 nm) gives p = 17.86, clamped to 1.  Thresholds equal the
+    oracle's."""
+    from psc_inputs.workloads import per_nM_s
+    lat = psc.Lattice((8, 8, 8), 5e-9, 1, 64, torch_allocator=False)
+    a = lat.add_species("A", 10e-12)
+    b = lat.add_species("B", 10e-12)
+    c = lat.add_species("C", 10e-12)
+    r0 = lat.add_reaction((a, b), (c,), per_nM_s(0.027))
+    r1 = lat.add_reaction((c,), (a, b), 13.5)
+    i0 = lat.reaction_info(r0)
+    assert i0["order"] == 2 and i0["clamped"] == 0 and abs(i0["p"] - 0.053) < 5e-4
+    assert i0["threshold"] == oracle.second_order_threshold(per_nM_s(0.027), 10e-12, 10e-12, 5e-9)
+    i1 = lat.reaction_info(r1)
+    assert i1 == {"order": 1, "clamped": 0, "p": 13.5, "threshold": 0}
+    with pytest.raises(psc.PscError):
+        lat.reaction_info(2)
+    lat.close()
+    w = workload("cfg2", dims=(8, 8, 8))
+    lat = psc.Lattice(w["dims"], w["rv"], 1, 64, torch_allocator=False)
+    for name, D in w["species"]:
+        lat.add_species(name, D)
+    rid = lat.add_reaction(*w["reactions"][0])
+    info = lat.reaction_info(rid)
+    assert info["clamped"] == 1 and info["threshold"] == 1 << 32 and abs(info["p"] - 17.86) < 0.01
+    assert oracle.second_order_threshold(w["reactions"][0][2], 1e-12, 0.5e-12, w["rv"]) == 1 << 32
+    lat.close()

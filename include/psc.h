@@ -222,8 +222,11 @@ psc_status psc_device_bytes(const psc_lattice *h, uint64_t *bytes);
 /* Launch shape of the walk-stage kernel: molecules per thread per pass
  * (1, 2, 4, 8 or 16) and workgroups per launch (grid-striding beyond).  It
  * changes only how the work is spread over the GPU, never the result (the
- * molecules of one stage commute).  0 keeps the current value; the default is
- * 4 items and enough workgroups for one pass over an average colour bin. */
+ * molecules of one stage commute).  0 keeps the current value.  Unless set,
+ * both are chosen at the first step from the molecules in the colour bins:
+ * 4 items and about 1.5 passes over an average bin per workgroup when a stage
+ * fills the GPU (512 workgroups), else 2 or 1 items and one chunk per
+ * workgroup. */
 typedef struct psc_launch {
   uint32_t items_per_thread;
   uint32_t stage_blocks;

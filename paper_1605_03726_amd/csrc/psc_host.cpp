@@ -456,14 +456,18 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   psc_status st = sync_tape(h, stream);
   if (st) return st;
 
-  // launch shape of the stage kernel: enough workgroups for the expected
-  // bin size, grid-striding beyond
+  // launch shape of the stage kernel from the molecules binned now (an
+  // average colour bin holds 1/16 of them): a stage that cannot fill the GPU
+  // with 4-item chunks (two workgroups per CU) takes one-item chunks, one
+  // per workgroup, to shorten its chain of dependent accesses; a large one
+  // takes 4 items and about 1.5 passes per workgroup
   if (!h->grid_set) {
-    // about two passes over an average colour bin per workgroup
-    const uint64_t per_block = (uint64_t)stage_threads() * (uint64_t)h->items;
-    const uint64_t expect = std::max<uint64_t>(cap / 16, 1);
+    const uint64_t expect = std::max<uint64_t>(walkers.size() / 16, 1);
+    const uint64_t T = (uint64_t)stage_threads();
+    if (!h->items_set) h->items = expect >= 512 * 4 * T ? 4 : (expect >= 512 * 2 * T ? 2 : 1);
+    const uint64_t per_block = T * (uint64_t)h->items * (h->items >= 4 ? 3 : 2);
     h->grid = (int)std::min<uint64_t>(
-        std::max<uint64_t>((expect + 2 * per_block - 1) / (2 * per_block), 1), 4096);
+        std::max<uint64_t>((2 * expect + per_block - 1) / per_block, 1), 4096);
   }
   HIP_OK(h, launch_scan(h->dL, std::min(h->grid * 4, 4096), stream));
   h->frozen = true;
@@ -922,7 +926,10 @@ psc_status psc_set_launch(psc_lattice *h, const psc_launch *l) {
   if (it != 0 && it != 1 && it != 2 && it != 4 && it != 8 && it != 16)
     return fail(h, PSC_EINVAL, "items_per_thread must be 1, 2, 4, 8 or 16");
   if (l->stage_blocks > 65536) return fail(h, PSC_EINVAL, "stage_blocks must be <= 65536");
-  if (it) h->items = it;
+  if (it) {
+    h->items = it;
+    h->items_set = true;
+  }
   if (l->stage_blocks) {
     h->grid = (int)l->stage_blocks;
     h->grid_set = true;

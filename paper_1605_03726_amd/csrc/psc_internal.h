@@ -79,6 +79,7 @@ struct psc_lattice {
   uint64_t d_tape_rows = 0;
   int grid = 1;
   int items = 4;
+  bool items_set = false;
   bool grid_set = false;
   uint64_t version = 0;   // bumped whenever the device record changes
   bool in_ensemble = false;

@@ -17,6 +17,8 @@ LIB = os.path.join(HERE, "libpsc_oracle.so")
 SRC = os.path.join(HERE, "psc_oracle.c")
 
 MODE_C, MODE_S, MODE_C_REV = 0, 1, 2
+PERIODIC, REFLECT = 0, 1
+OUTSIDE = 0xFFFFFFFF
 CNT_ATTEMPTS, CNT_HOPS, CNT_COLLISIONS, CNT_PLACE_FAIL, CNT_N = range(5)
 
 
@@ -45,6 +47,10 @@ def lib() -> C.CDLL:
     L.orc_philox4x64.argtypes = [u64p, u64p, u64p]
     L.orc_neighbour.argtypes = [C.c_uint32] * 4 + [C.c_int]
     L.orc_neighbour.restype = C.c_uint32
+    L.orc_neighbour_b.argtypes = [C.c_uint32] * 4 + [C.c_int, C.c_int]
+    L.orc_neighbour_b.restype = C.c_uint32
+    L.orc_set_boundary.argtypes = [C.c_void_p, C.c_int]
+    L.orc_set_boundary.restype = C.c_int
     L.orc_neighbour_table.argtypes = [C.c_uint32] * 3 + [u32p]
     L.orc_hop_vector.argtypes = [C.c_uint32] * 4 + [C.c_int, C.POINTER(C.c_int32)]
     L.orc_position.argtypes = [C.c_uint32] * 4 + [C.c_double, C.POINTER(C.c_double)]
@@ -121,6 +127,11 @@ def neighbour(dims, v: int, n: int) -> int:
     return lib().orc_neighbour(dims[0], dims[1], dims[2], v, n)
 
 
+def neighbour_b(dims, v: int, n: int, boundary: int) -> int:
+    """neighbour n of v; OUTSIDE beyond a wall of a closed box"""
+    return lib().orc_neighbour_b(dims[0], dims[1], dims[2], v, n, boundary)
+
+
 def neighbour_table(dims) -> np.ndarray:
     nv = int(dims[0]) * int(dims[1]) * int(dims[2])
     out = np.zeros(nv * 12, np.uint32)
@@ -166,7 +177,7 @@ def tau(rv: float, D: float) -> float:
 class Oracle:
     """One lattice simulated by the CPU oracle."""
 
-    def __init__(self, dims, rv: float, seed: int):
+    def __init__(self, dims, rv: float, seed: int, boundary: int = 0):
         self.L = lib()
         self.dims = tuple(int(x) for x in dims)
         h = self.L.orc_create(self.dims[0], self.dims[1], self.dims[2], rv, seed)
@@ -174,6 +185,8 @@ class Oracle:
             raise ValueError(f"oracle: bad lattice {dims}")
         self.h = h
         self.n_rx = 0
+        if self.L.orc_set_boundary(self.h, boundary) != 0:
+            raise ValueError(f"oracle: bad boundary {boundary}")
 
     def close(self):
         if self.h:

@@ -152,6 +152,22 @@ uint32_t orc_neighbour(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n)
               wrap((int64_t)k + dk, nk));
 }
 
+/* Neighbour n of v in a box with the given boundary: periodic (wrapping, as
+ * orc_neighbour) or reflecting, where a neighbour beyond a face does not
+ * exist (ORC_OUTSIDE) -- the box is closed by walls. */
+uint32_t orc_neighbour_b(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
+                         int boundary) {
+  if (boundary == ORC_BOUNDARY_PERIODIC) return orc_neighbour(ni, nj, nk, v, n);
+  uint32_t i, j, k;
+  int di, dj, dk;
+  ijk_of(ni, nj, v, &i, &j, &k);
+  int s = (int)((j + k) & 1u), p = (int)(k & 1u);
+  stencil(n, s, p, &di, &dj, &dk);
+  int64_t a = (int64_t)i + di, b = (int64_t)j + dj, c = (int64_t)k + dk;
+  if (a < 0 || b < 0 || c < 0 || a >= ni || b >= nj || c >= nk) return ORC_OUTSIDE;
+  return v_of(ni, nj, (uint32_t)a, (uint32_t)b, (uint32_t)c);
+}
+
 void orc_neighbour_table(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t *out) {
   uint64_t nv = (uint64_t)ni * nj * nk;
   for (uint64_t v = 0; v < nv; v++)
@@ -251,6 +267,7 @@ typedef struct {
 struct orc_sim {
   uint32_t ni, nj, nk;
   uint64_t nv;
+  int boundary;       /* ORC_BOUNDARY_PERIODIC or ORC_BOUNDARY_REFLECT */
   double rv;
   uint64_t seed;
 
@@ -391,6 +408,12 @@ void orc_destroy(orc_sim *s) {
   free(s);
 }
 
+int orc_set_boundary(orc_sim *s, int boundary) {
+  if (boundary != ORC_BOUNDARY_PERIODIC && boundary != ORC_BOUNDARY_REFLECT) return -1;
+  s->boundary = boundary;
+  return 0;
+}
+
 int orc_add_species(orc_sim *s, double D) {
   if (s->frozen || !(D >= 0.0) || s->n_species + 1 >= MAX_SPECIES) return -1;
   int id = ++s->n_species;
@@ -528,8 +551,8 @@ static int pick_vacant(const orc_sim *s, uint32_t v, int n_extra,
   uint32_t cand[12];
   int nc = 0;
   for (int n = 0; n < 12; n++) {
-    uint32_t t = orc_neighbour(s->ni, s->nj, s->nk, v, n);
-    if (s->occ[t] == 0) cand[nc++] = t;
+    uint32_t t = orc_neighbour_b(s->ni, s->nj, s->nk, v, n, s->boundary);
+    if (t != ORC_OUTSIDE && s->occ[t] == 0) cand[nc++] = t;
   }
   if (nc < n_extra) return -1;
   for (int q = 0; q < n_extra; q++) {
@@ -742,7 +765,8 @@ static void attempt(orc_sim *s, uint32_t slot, int dir, int fire_forced,
   uint32_t a = s->vox[slot];
   uint16_t A = s->sp[slot];
   s->cnt[ORC_CNT_ATTEMPTS]++;
-  uint32_t t = orc_neighbour(s->ni, s->nj, s->nk, a, dir);
+  uint32_t t = orc_neighbour_b(s->ni, s->nj, s->nk, a, dir, s->boundary);
+  if (t == ORC_OUTSIDE) return;  /* a wall: the molecule stays, no collision */
   if (s->occ[t] == 0) {
     /* vacant: the molecule hops and carries its unwrapped displacement */
     int32_t hv[3];

@@ -17,6 +17,9 @@
  *     propensity                              [2.4.1 First-Order, eqs. 3-5]
  *   - second-order reactions on collision with probability
  *     p = k / (6 sqrt2 (DA+DB) r)              [2.4.2 Second-Order, eq. 6]
+ *   - periodic boxes, or boxes closed by walls: a move into another
+ *     compartment fails like a move into an occupied voxel (2.3); the space
+ *     beyond a face of a closed box is read as such a compartment
  *
  * Two processing orders are provided:
  *   ORC_MODE_C     coloured stages: each event's molecules are processed by the
@@ -46,6 +49,12 @@ extern "C" {
 
 enum { ORC_MODE_C = 0, ORC_MODE_S = 1, ORC_MODE_C_REV = 2 };
 
+/* box boundary: periodic (the default) or reflecting walls on all six faces;
+ * with walls a hop towards a neighbour beyond a face is blocked (the attempt
+ * counts, nothing moves, no collision) and such neighbours take no products */
+enum { ORC_BOUNDARY_PERIODIC = 0, ORC_BOUNDARY_REFLECT = 1 };
+#define ORC_OUTSIDE 0xFFFFFFFFu
+
 /* Philox counter "phase" word values */
 enum { ORC_PHASE_WALK = 0, ORC_PHASE_FIRST = 1, ORC_PHASE_STAGE = 2,
        ORC_PHASE_PLACE = 3, ORC_PHASE_SSA = 4 };
@@ -60,6 +69,9 @@ typedef struct orc_sim orc_sim;
 void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 uint32_t orc_neighbour(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n);
+/* as orc_neighbour for either boundary; ORC_OUTSIDE beyond a wall */
+uint32_t orc_neighbour_b(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
+                         int boundary);
 /* out[12 v + n] = orc_neighbour(v, n) for every voxel */
 void orc_neighbour_table(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t *out);
 void orc_hop_vector(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
@@ -76,6 +88,8 @@ double orc_tau(double rv, double D);
 orc_sim *orc_create(uint32_t ni, uint32_t nj, uint32_t nk, double rv,
                     uint64_t seed);
 void orc_destroy(orc_sim *s);
+/* ORC_BOUNDARY_PERIODIC (default) or ORC_BOUNDARY_REFLECT; 0 on success */
+int orc_set_boundary(orc_sim *s, int boundary);
 /* returns the new species id (1, 2, ...) or -1 */
 int orc_add_species(orc_sim *s, double D);
 /* returns the new reaction id (0, 1, ...) or -1 */

@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "mapk_paper"])
     ap.add_argument("--timing-steps", type=int, default=40)
+    ap.add_argument("--walls", action="store_true",
+                    help="close the workload's box by walls instead of wrapping it")
     ap.add_argument("--cpu-events", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
@@ -245,6 +247,8 @@ def main():
         return
 
     w = pick_workload(args.workload)
+    if args.walls:
+        w = dict(w, boundary="walls", name=w["name"] + "_walls")
     nv = int(w["dims"][0]) * int(w["dims"][1]) * int(w["dims"][2])
     placed = sum(c for _, c in w["place"])
     t_setup = time.perf_counter()
@@ -301,6 +305,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": w["name"], "voxels": nv, "molecules": placed,
+                   "boundary": w.get("boundary", "periodic"),
                    "species": len(w["species"]), "reactions": len(w["reactions"]),
                    "step": "one diffusion event", "hop_fraction": hops / max(attempts, 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -56,6 +56,14 @@ typedef int32_t psc_status;
 
 /* lattice flags */
 #define PSC_TRACK_DISPLACEMENT 1u /* keep unwrapped per-molecule displacement */
+#define PSC_BOUNDARY_WALLS 4u     /* close the box by walls on its six faces instead
+                                     of wrapping it periodically: a move into
+                                     another compartment fails like a move into an
+                                     occupied voxel (2.3), and the space beyond a
+                                     face is such a compartment.  A hop towards it
+                                     counts as an attempt and is neither a hop nor
+                                     a collision; first-order products are never
+                                     placed there. */
 #define PSC_LAYOUT_LINEAR 2u      /* keep the occupancy in linear order on the
                                      device instead of 4x4x4 bricks (a 128-byte
                                      line each); results are identical */
@@ -74,7 +82,8 @@ typedef struct psc_lattice_desc {
   double voxel_radius;     /* r, metres, > 0 */
   uint64_t seed;           /* key of every random draw of this lattice */
   uint64_t max_molecules;  /* capacity: live molecules at any time */
-  uint32_t flags;          /* PSC_TRACK_DISPLACEMENT */
+  uint32_t flags;          /* PSC_TRACK_DISPLACEMENT | PSC_LAYOUT_LINEAR |
+                              PSC_BOUNDARY_WALLS */
   int32_t device;          /* HIP device ordinal */
   psc_alloc_fn alloc;      /* optional allocator hooks (both or neither) */
   psc_free_fn free;

@@ -117,6 +117,7 @@ struct Geo {
   uint32_t ni, nj, nk;
   DivU32 dni, dnj;
   uint32_t brick;       // 1: brick layout
+  uint32_t walls;       // 1: the box is closed by walls (no periodic wrap)
   uint32_t nbi, nbj;    // bricks along i and j
   DivU32 dnbi, dnbj;
 };
@@ -206,6 +207,16 @@ __host__ __device__ inline Coord step_coord(const Geo &g, const Coord &c, uint32
   if (t.k < 0) t.k += (int32_t)g.nk;
   else if (t.k >= (int32_t)g.nk) t.k -= (int32_t)g.nk;
   return t;
+}
+
+// target of hop n from c in the lattice's box: false if a wall closes the box
+// there (t is then the periodic image, a valid voxel that must not be used)
+__host__ __device__ inline bool step_target(const Geo &g, const Coord &c, uint32_t n, Coord &t) {
+  t = step_coord(g, c, n);
+  if (!g.walls) return true;
+  // wrapping moved exactly the coordinates that left the box
+  const int32_t di = t.i - c.i, dj = t.j - c.j, dk = t.k - c.k;
+  return di >= -1 && di <= 1 && dj >= -1 && dj <= 1 && dk >= -1 && dk <= 1;
 }
 
 __host__ __device__ inline void hop_vector(uint32_t n, int32_t p, int32_t &X, int32_t &Y,

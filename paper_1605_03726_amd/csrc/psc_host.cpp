@@ -552,7 +552,7 @@ psc_status psc_create_lattice(const psc_lattice_desc *desc, psc_lattice **out) {
     g_create_error = "alloc and free hooks come together";
     return PSC_EINVAL;
   }
-  if (desc->flags & ~(PSC_TRACK_DISPLACEMENT | PSC_LAYOUT_LINEAR)) {
+  if (desc->flags & ~(PSC_TRACK_DISPLACEMENT | PSC_LAYOUT_LINEAR | PSC_BOUNDARY_WALLS)) {
     g_create_error = "unknown flags";
     return PSC_EINVAL;
   }
@@ -570,6 +570,7 @@ psc_status psc_create_lattice(const psc_lattice_desc *desc, psc_lattice **out) {
   h->geo.dni = make_div(ni);
   h->geo.dnj = make_div(nj);
   h->geo.brick = (desc->flags & PSC_LAYOUT_LINEAR) ? 0u : 1u;
+  h->geo.walls = (desc->flags & PSC_BOUNDARY_WALLS) ? 1u : 0u;
   h->geo.nbi = ni / 4;
   h->geo.nbj = nj / 4;
   h->geo.dnbi = make_div(ni / 4);

@@ -171,7 +171,9 @@ __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, c
     int nv = 0;
     const Coord cv = coord_of(L.geo, v);
     for (uint32_t n = 0; n < 12; ++n) {
-      const uint32_t t = index_of(L.geo, step_coord(L.geo, cv, n));
+      Coord ct;
+      if (!step_target(L.geo, cv, n, ct)) continue;  // beyond a wall
+      const uint32_t t = index_of(L.geo, ct);
       if (L.occ[t] == 0) vac[nv++] = t;
     }
     if (nv < (int)(m - 1)) {
@@ -466,6 +468,7 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     if (base + (uint64_t)it * kStageThreads + tid >= n) id[it] = kDeadId;
   }
 
+  constexpr uint32_t kWallBit = 1u << 16;  // in mv: the target lies beyond a wall
   // Load phase: every item's draw, target and target word before any store.
   // Same-stage molecules have disjoint closed neighbourhoods, so no store of
   // this stage changes a word loaded here; issuing all loads first keeps
@@ -481,10 +484,11 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     const U4 r = philox((uint32_t)e, id[it], kPhaseWalk, 0, L.key0, L.key1);
     const uint32_t dir = scale32(r.x, 12);
     const Coord cv = coord_of(L.geo, v);
-    const Coord ct = step_coord(L.geo, cv, dir);
+    Coord ct;
+    const bool open = step_target(L.geo, cv, dir, ct);
     tgt[it] = index_of(L.geo, ct);
     ry[it] = r.y;
-    mv[it] = dir | ((cv.k & 1u) << 4) | (colour_of(ct) << 8);
+    mv[it] = dir | ((cv.k & 1u) << 4) | (colour_of(ct) << 8) | (open ? 0u : kWallBit);
     const uint32_t h = hot_hash(v, hbits);
     hw[it] = hot[h >> 4];
     hs[it] = (h & 15u) << 1;
@@ -510,12 +514,13 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     }
     if (!((due >> sp) & 1ull)) continue;
     ++n_att;
+    if (mv[it] & kWallBit) continue;  // a wall: the molecule stays, no collision
     const uint32_t w_t = loaded[it] ? wt[it] : (uint32_t)occ[t];
     if (w_t == 0) {
       occ[t] = (uint16_t)sp;
       occ[v] = 0;
       vox[it] = t;
-      ocol[it] = mv[it] >> 8;
+      ocol[it] = (mv[it] >> 8) & 15u;
       int32_t X, Y, Z;
       hop_vector(mv[it] & 15u, (mv[it] >> 4) & 1u, X, Y, Z);
       d0[it] += X;

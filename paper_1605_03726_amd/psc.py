@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(PKG, "libpsc.so")
 PSC_OK, PSC_EINVAL, PSC_ESTATE, PSC_ENOMEM, PSC_ECAPACITY, PSC_EDEVICE = 0, -1, -2, -3, -4, -5
 TRACK_DISPLACEMENT = 1
 LAYOUT_LINEAR = 2
+BOUNDARY_WALLS = 4
 
 _ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -196,7 +197,8 @@ class Lattice:
 
     def __init__(self, dims, voxel_radius: float, seed: int, max_molecules: int,
                  track_displacement: bool = False, device: int = 0,
-                 torch_allocator: bool = True, linear_layout: bool = False):
+                 torch_allocator: bool = True, linear_layout: bool = False,
+                 walls: bool = False):
         self.L = lib()
         self.dims = tuple(int(x) for x in dims)
         self.nv = self.dims[0] * self.dims[1] * self.dims[2]
@@ -206,7 +208,7 @@ class Lattice:
         d.seed = seed
         d.max_molecules = max_molecules
         d.flags = (TRACK_DISPLACEMENT if track_displacement else 0) | (
-            LAYOUT_LINEAR if linear_layout else 0)
+            LAYOUT_LINEAR if linear_layout else 0) | (BOUNDARY_WALLS if walls else 0)
         d.device = device
         self._hooks = None
         if torch_allocator:
@@ -366,7 +368,7 @@ def lattice_from_workload(w: dict, max_molecules: int | None = None, device: int
         max_molecules = min(nv, max(1024, int(placed * 1.5) + 1024))
     lat = Lattice(w["dims"], w["rv"], w["seed"], max_molecules,
                   track_displacement=w.get("track_displacement", False), device=device,
-                  linear_layout=linear_layout)
+                  linear_layout=linear_layout, walls=w.get("boundary") == "walls")
     for name, D in w["species"]:
         lat.add_species(name, D)
     for r, p, k in w["reactions"]:
@@ -619,7 +621,8 @@ def job_desc(w: dict, keep_state: bool = False, max_molecules: int | None = None
     d.voxel_radius = w["rv"]
     d.seed = w["seed"]
     d.max_molecules = max_molecules
-    d.flags = TRACK_DISPLACEMENT if w.get("track_displacement") else 0
+    d.flags = (TRACK_DISPLACEMENT if w.get("track_displacement") else 0) | (
+        BOUNDARY_WALLS if w.get("boundary") == "walls" else 0)
     d.n_species, d.D = len(w["species"]), D
     d.n_reactions, d.reactions = len(w["reactions"]), rxs
     d.n_place, d.place = len(w["place"]), pl

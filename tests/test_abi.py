@@ -202,3 +202,17 @@ def test_reaction_info_reports_probability_and_clamping():
     assert info["clamped"] == 1 and info["threshold"] == 1 << 32 and abs(info["p"] - 17.86) < 0.01
     assert oracle.second_order_threshold(w["reactions"][0][2], 1e-12, 0.5e-12, w["rv"]) == 1 << 32
     lat.close()
+
+
+def test_walls_flag_is_accepted_and_unknown_flags_rejected():
+    lat = psc.Lattice((8, 8, 8), 4.4e-9, 1, 64, walls=True, torch_allocator=False)
+    lat.add_species("A", 1e-12)
+    lat.close()
+    d = psc.Desc()
+    d.ni = d.nj = d.nk = 8
+    d.voxel_radius = 4.4e-9
+    d.seed = 1
+    d.max_molecules = 64
+    d.flags = 8
+    h = psc.C.c_void_p()
+    assert psc.lib().psc_create_lattice(psc.C.byref(d), psc.C.byref(h)) == psc.PSC_EINVAL

@@ -12,7 +12,8 @@ pytestmark = pytest.mark.gpu
 
 
 def oracle_run(w, events):
-    o = oracle.Oracle(w["dims"], w["rv"], w["seed"])
+    o = oracle.Oracle(w["dims"], w["rv"], w["seed"],
+                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC)
     for _, D in w["species"]:
         o.add_species(D)
     for r, p, k in w["reactions"]:
@@ -38,6 +39,9 @@ def mixed_members(n_rep=10, events=40):
     ws.append(workload("small_reactive", seed=5, events=events))
     ws.append(workload("cfg2", dims=(32, 32, 32), events=events))
     ws.append(dict(workload("cfg1"), dims=(24, 16, 8), events=events, place=[(1, 60)]))
+    # members closed by walls beside periodic ones
+    ws.append(dict(workload("small_reactive", seed=6, events=events), boundary="walls"))
+    ws.append(dict(ws[0], boundary="walls"))
     return ws
 
 

@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 
 def build_oracle(w, state=None):
-    o = oracle.Oracle(w["dims"], w["rv"], w["seed"])
+    o = oracle.Oracle(w["dims"], w["rv"], w["seed"],
+                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC)
     for _, D in w["species"]:
         o.add_species(D)
     for r, p, k in w["reactions"]:
@@ -249,3 +250,44 @@ def test_launch_shapes_on_a_reactive_lattice(items):
     s = o.state()
     assert_same(lat.read_state(), s, disp=False)
     assert s["fired"][0] > 1000
+
+
+# ---- boxes closed by walls (PSC_BOUNDARY_WALLS) --------------------------------
+
+@pytest.mark.parametrize("seed", [7, 8, 9])
+def test_walls_small_reactive_all_rules(seed):
+    """Every rule next to walls: a 16 x 12 x 8 box has most voxels on or near a
+    face, so hops, collisions and first-order product placement all meet them."""
+    w = dict(workload("small_reactive", seed=seed), boundary="walls")
+    g, s = run_pair(w, 40)
+    assert s["hops"] > 0 and s["collisions"] > 0 and np.all(s["fired"] > 0), s["fired"]
+    # the walls change the run
+    gp = build_gpu(dict(w, boundary=None))
+    gp.step(40)
+    assert not np.array_equal(gp.read_state()["occ"], g["occ"])
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4), (20, 4, 8)])
+def test_walls_shapes(dims):
+    w = dict(workload("small_reactive", dims=dims, seed=11), boundary="walls")
+    run_pair(w, 30)
+
+
+def test_walls_displacement_and_crowding():
+    w = dict(workload("cfg1", events=200), dims=(32, 32, 32), place=[(1, 3000)],
+             boundary="walls")
+    g, s = run_pair(w, 200)
+    assert s["hops"] > 100000
+    w = dict(workload("cfg2", dims=(64, 64, 64)), boundary="walls")
+    run_pair(w, 120)
+
+
+@pytest.mark.parametrize("items", [1, 4])
+def test_walls_launch_shapes(items):
+    w = dict(workload("cfg2", dims=(64, 64, 64)), boundary="walls")
+    lat = build_gpu(w)
+    lat.set_launch(items, 16)
+    o = build_oracle(w)
+    lat.step(60)
+    o.run(60, oracle.MODE_C)
+    assert_same(lat.read_state(), o.state(), disp=False)

@@ -29,7 +29,8 @@ def alone(w):
 
 
 def oracle_state(w):
-    o = oracle.Oracle(w["dims"], w["rv"], w["seed"])
+    o = oracle.Oracle(w["dims"], w["rv"], w["seed"],
+                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC)
     for _, D in w["species"]:
         o.add_species(D)
     for r, p, k in w["reactions"]:
@@ -56,6 +57,8 @@ def cap_of(w):
 
 def test_results_same_alone_and_in_the_mix():
     jobs = small_jobs(24)
+    # every third job is closed by walls
+    jobs = [dict(w, boundary="walls") if i % 3 == 1 else w for i, w in enumerate(jobs)]
     srv = psc.Server(budget_bytes=8 << 30, quantum_events=16)
     ids = []
     for i, w in enumerate(jobs):

@@ -229,8 +229,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (got --gpus %d); the walk of a "
-              "single lattice is measured on one MI355X" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU (got --gpus %d): one lattice's walk runs on one "
+              "MI355X; replicates and jobs shard over GPUs without exchange" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, 10)

@@ -326,6 +326,7 @@ struct LatDev {
   uint64_t stop_event;             // the lattice idles once ev reaches it
   uint64_t *ev;                    // events completed
   uint32_t *perm;                  // [16] stage order of the running event
+  uint4 *sdesc;                    // [16] per stage: colour, count, event (lo, hi)
   uint32_t *next_id;
   unsigned long long *cnt;         // attempts, hops, collisions, placement failures
   unsigned long long *sp_count;    // [64] live molecules per species (two's complement deltas)

@@ -346,6 +346,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   auto *d_fo_rx = alloc_n<uint16_t>(h, std::max<size_t>(h->fo_rx.size(), 1));
   L.ev = alloc_n<uint64_t>(h, 1);
   L.perm = alloc_n<uint32_t>(h, 16);
+  L.sdesc = alloc_n<uint4>(h, 16);
   L.next_id = alloc_n<uint32_t>(h, 1);
   L.cnt = alloc_n<unsigned long long>(h, 4);
   L.sp_count = alloc_n<unsigned long long>(h, 64);
@@ -355,7 +356,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   if (!L.occ || !L.cand_count || !L.flag_vox[0] || !L.flag_vox[1] || !L.flag_count || !L.birth_key || !L.birth_vox ||
       !L.birth_sp || !L.birth_count || !L.fire_pos || !L.fire_id || !L.fire_col ||
       !L.fire_rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod ||
-      !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.next_id || !L.cnt || !L.sp_count ||
+      !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.sdesc || !L.next_id || !L.cnt || !L.sp_count ||
       !L.fired || !L.error || !h->dL || !L.hot || !L.end_done || !L.nbr_cnt)
     return fail(h, PSC_ENOMEM, "device allocation failed");
   L.sp_flags = d_flags;
@@ -434,6 +435,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   }
   HIP_OK(h, hipMemset(L.cand_count, 0, 2 * sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.flag_count, 0, 2 * sizeof(uint32_t)));
+  HIP_OK(h, hipMemset(L.sdesc, 0, 16 * sizeof(uint4)));  // empty until a first-order pass
   HIP_OK(h, hipMemset(L.birth_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.cnt, 0, 4 * sizeof(unsigned long long)));
   {
@@ -491,7 +493,7 @@ uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool dis
     if (displacement) t += r(3 * 16 * cap * 4);
     t += r(cap * 4) * 2 + r(cap);
   }
-  t += r(8) + 2 * r(cap * 4) + r(8);
+  t += r(8) + 2 * r(cap * 4) + r(8) + r(256);
   const uint64_t bcap = std::min<uint64_t>(pow2_at_least(cap), 1ull << 27);
   t += r(bcap * 8) + r(bcap * 4) + r(bcap * 2) + r(4);
   uint32_t hb = 16;

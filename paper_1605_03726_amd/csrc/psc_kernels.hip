@@ -208,7 +208,7 @@ __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, c
 }
 
 // the event's opening work for one lattice, by one workgroup
-__device__ __forceinline__ void begin_body(const LatDev &L) {
+__device__ __forceinline__ void begin_work(const LatDev &L) {
   uint32_t *__restrict__ fire_pos = L.fire_pos;
   uint32_t *__restrict__ fire_id = L.fire_id;
   uint8_t *__restrict__ fire_col = L.fire_col;
@@ -354,6 +354,25 @@ __device__ __forceinline__ void begin_body(const LatDev &L) {
     }
   }
   if (tid == 0) *L.next_id = base_id + nb;
+}
+
+// The first-order pass, then each stage's descriptor for the walk: its colour,
+// its molecule count (final now: the walk appends only to the next event's
+// bins) and the event, so that a stage launch starts with one load instead of
+// a chain of three.  A lattice that does not run this event (idle or out of
+// tape) gets empty stages.
+__device__ __forceinline__ void begin_body(const LatDev &L) {
+  begin_work(L);
+  __syncthreads();  // every return of begin_work is taken by the whole block
+  const uint32_t tid = threadIdx.x;
+  if (tid < 16) {
+    const uint64_t e = *L.ev;
+    const bool run = e < L.tape_horizon && e < L.stop_event;
+    const uint32_t c = L.perm[tid];
+    // births were counted with atomics by other threads: read through L2
+    const uint32_t n = run ? min(atomicOr(&L.bins[e & 1].count[c], 0u), (uint32_t)L.cap) : 0u;
+    L.sdesc[tid] = make_uint4(c, n, (uint32_t)e, (uint32_t)(e >> 32));
+  }
 }
 
 __global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restrict__ Lp) {
@@ -660,10 +679,9 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
   __shared__ StageShared S;
   __shared__ StageStaging<ITEMS> T;
   const LatDev &L = *Lp;
-  const uint64_t e = *L.ev;
-  if (e >= L.tape_horizon || e >= L.stop_event) return;  // error recorded / idle
-  const uint32_t c = L.perm[g];
-  const uint32_t n = min(L.bins[e & 1].count[c], (uint32_t)L.cap);
+  const uint4 d = L.sdesc[g];  // empty when the lattice does not run this event
+  const uint64_t e = d.z | ((uint64_t)d.w << 32);
+  const uint32_t c = d.x, n = d.y;
   const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
   for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk)
     stage_chunk<ITEMS, DM>(L, e, c, base, n, S, T);
@@ -689,15 +707,9 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
   const uint32_t lo = min((uint32_t)tid * per, R), hi = min(lo + per, R);
   uint32_t run = 0;
   for (uint32_t r = lo; r < hi; ++r) {
-    const LatDev &L = lats[r];
-    const uint64_t e = *L.ev;
-    uint32_t k = 0;
-    if (e < L.tape_horizon && e < L.stop_event) {
-      const uint32_t n = min(L.bins[e & 1].count[L.perm[g]], (uint32_t)L.cap);
-      k = (uint32_t)((n + chunk - 1) / chunk);
-    }
+    const uint32_t n = lats[r].sdesc[g].y;
     s_pre[r] = run;
-    run += k;
+    run += (uint32_t)((n + chunk - 1) / chunk);
   }
   s_part[tid] = run;
   __syncthreads();
@@ -723,10 +735,9 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
       else b = m;
     }
     const LatDev &L = lats[a];
-    const uint64_t e = *L.ev;
-    const uint32_t c = L.perm[g];
-    const uint32_t n = min(L.bins[e & 1].count[c], (uint32_t)L.cap);
-    stage_chunk<ITEMS, 2>(L, e, c, (uint64_t)(q - s_pre[a]) * chunk, n, S, T);
+    const uint4 d = L.sdesc[g];
+    const uint64_t e = d.z | ((uint64_t)d.w << 32);
+    stage_chunk<ITEMS, 2>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, S, T);
   }
 }
 

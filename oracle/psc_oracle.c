@@ -303,6 +303,14 @@ struct orc_sim {
 
   uint64_t cnt[ORC_CNT_N];
   uint64_t fired[MAX_RX];
+
+  /* products beyond the second of collision reactions in the running walk:
+   * their slots sit at the end of the table from walk_slot0 on, with ids
+   * assigned when the walk ends; pend_key[q] orders slot walk_slot0 + q */
+  uint64_t walk_slot0;
+  uint64_t *pend_key;
+  uint64_t pend_cap;
+  int oom;            /* an allocation failed during a walk */
 };
 
 static int grow_slots(orc_sim *s, uint64_t need) {
@@ -402,6 +410,7 @@ orc_sim *orc_create(uint32_t ni, uint32_t nj, uint32_t nk, double rv, uint64_t s
 
 void orc_destroy(orc_sim *s) {
   if (!s) return;
+  free(s->pend_key);
   free(s->occ); free(s->slot_at);
   free(s->id); free(s->vox); free(s->sp); free(s->alive);
   free(s->dx); free(s->dy); free(s->dz);
@@ -431,7 +440,7 @@ int orc_add_reaction(orc_sim *s, int n_reac, const uint16_t *reac, int n_prod,
   for (int a = 0; a < n_prod; a++)
     if (prod[a] < 1 || prod[a] > s->n_species) return -1;
   if (n_reac == 1 && (n_prod < 0 || n_prod > MAX_PROD)) return -1;
-  if (n_reac == 2 && (n_prod < 1 || n_prod > 2)) return -1;
+  if (n_reac == 2 && (n_prod < 1 || n_prod > MAX_PROD)) return -1;
   orc_rx *r = &s->rx[s->n_rx];
   r->n_reac = n_reac;
   r->n_prod = n_prod;
@@ -759,6 +768,55 @@ static int first_order_ssa(orc_sim *s, double dt) {
   return 0;
 }
 
+/* words for placing collision products: r2, r3 of the walk draw of molecule
+ * id, then blocks 1, 2, ... of the same counter */
+static void walk_words(const orc_sim *s, uint32_t id, int n, uint32_t *out) {
+  uint32_t r[4];
+  draw4(s->seed, (uint32_t)s->event, id, ORC_PHASE_WALK, 0, r);
+  int k = 0;
+  out[k++] = r[2];
+  if (k < n) out[k++] = r[3];
+  for (uint32_t blk = 1; k < n; blk++) {
+    draw4(s->seed, (uint32_t)s->event, id, ORC_PHASE_WALK, blk, r);
+    for (int j = 0; j < 4 && k < n; j++) out[k++] = r[j];
+  }
+}
+
+static int pend_push(orc_sim *s, uint64_t key) {
+  uint64_t q = s->n_slots - s->walk_slot0;
+  if (q + 1 > s->pend_cap) {
+    uint64_t c = s->pend_cap ? 2 * s->pend_cap : 64;
+    uint64_t *k = realloc(s->pend_key, c * sizeof *k);
+    if (!k) return -1;
+    s->pend_key = k;
+    s->pend_cap = c;
+  }
+  s->pend_key[q] = key;
+  return 0;
+}
+
+/* End of a walk: the newborns of collision reactions get their ids in
+ * ascending (mover id, product index) order, the same whatever order the
+ * walk took; their slots are put in that order so that the table stays in
+ * ascending id. */
+static void finish_births(orc_sim *s) {
+  uint64_t n = s->n_slots - s->walk_slot0;
+  for (uint64_t z = 1; z < n; z++) {  /* insertion sort: newborns are few */
+    for (uint64_t y = z; y > 0 && s->pend_key[y - 1] > s->pend_key[y]; y--) {
+      uint64_t a = s->walk_slot0 + y - 1, b = a + 1;
+      uint64_t tk = s->pend_key[y - 1]; s->pend_key[y - 1] = s->pend_key[y]; s->pend_key[y] = tk;
+      uint32_t tv = s->vox[a]; s->vox[a] = s->vox[b]; s->vox[b] = tv;
+      uint16_t ts = s->sp[a]; s->sp[a] = s->sp[b]; s->sp[b] = ts;
+      uint8_t ta = s->alive[a]; s->alive[a] = s->alive[b]; s->alive[b] = ta;
+    }
+  }
+  for (uint64_t z = 0; z < n; z++) {
+    uint64_t q = s->walk_slot0 + z;
+    s->id[q] = s->next_id++;
+    s->slot_at[s->vox[q]] = (uint32_t)q;
+  }
+}
+
 /* ---- one molecule's diffusion attempt (2.3) with collision (2.4.2) ------- */
 static void attempt(orc_sim *s, uint32_t slot, int dir, int fire_forced,
                     uint32_t r1, uint8_t *reacted) {
@@ -789,18 +847,39 @@ static void attempt(orc_sim *s, uint32_t slot, int dir, int fire_forced,
   int fires = fire_forced >= 0 ? fire_forced : ((uint64_t)r1 < s->rx[r].thr2);
   if (!fires) return;
   const orc_rx *x = &s->rx[r];
+  /* products beyond the second go to distinct vacant neighbours of the
+   * mover's voxel (chosen as first-order products are, from the walk draw's
+   * words r2, r3 and further blocks); too few vacant: the reaction fails
+   * with no change */
+  const int n_extra = x->n_prod > 2 ? x->n_prod - 2 : 0;
+  uint32_t extra_vox[MAX_PROD];
+  if (n_extra > 0) {
+    uint32_t words[MAX_PROD];
+    walk_words(s, s->id[slot], n_extra, words);
+    if (pick_vacant(s, a, n_extra, words, extra_vox)) {
+      s->cnt[ORC_CNT_PLACE_FAIL]++;
+      return;
+    }
+  }
   uint32_t q = s->slot_at[t];
   /* first product in the partner's voxel, keeping the partner's identity */
   s->occ[t] = x->prod[0];
   mol_set_species(s, q, x->prod[0]);
-  if (reacted) reacted[q] = 1;
-  if (x->n_prod == 2) {
+  if (reacted && q < s->walk_slot0) reacted[q] = 1;  /* newborns do not walk anyway */
+  if (x->n_prod >= 2) {
     /* second product in the mover's voxel, keeping the mover's identity */
     s->occ[a] = x->prod[1];
     mol_set_species(s, slot, x->prod[1]);
   } else {
     s->occ[a] = 0;
     mol_kill(s, slot);
+  }
+  for (int e = 0; e < n_extra; e++) {
+    uint32_t v = extra_vox[e];
+    s->occ[v] = x->prod[2 + e];
+    if (pend_push(s, ((uint64_t)s->id[slot] << 8) | (uint64_t)(2 + e)) ||
+        mol_new(s, 0xFFFFFFFFu, v, x->prod[2 + e]))
+      s->oom = 1;
   }
   s->fired[r]++;
 }
@@ -811,6 +890,7 @@ static int walk(orc_sim *s, const uint8_t due[MAX_SPECIES], const uint8_t order[
   uint8_t *reacted = calloc(s->n_slots + 1, 1);
   if (!reacted) return -1;
   uint64_t n_slots0 = s->n_slots;
+  s->walk_slot0 = n_slots0;
   if (mode == ORC_MODE_S) {
     /* the paper's order: species ascending, molecules in dictionary order */
     uint32_t *list = malloc((n_slots0 + 1) * sizeof *list);
@@ -846,7 +926,8 @@ static int walk(orc_sim *s, const uint8_t due[MAX_SPECIES], const uint8_t order[
     free(b.slots);
   }
   free(reacted);
-  return 0;
+  finish_births(s);
+  return s->oom ? -1 : 0;
 }
 
 int orc_run(orc_sim *s, uint64_t n_events, int mode) {
@@ -878,6 +959,7 @@ int orc_walk_forced(orc_sim *s, uint64_t n_order, const uint32_t *order_ids,
   s->frozen = 1;
   uint8_t *reacted = calloc(s->n_slots + 1, 1);
   if (!reacted) return -1;
+  s->walk_slot0 = s->n_slots;
   for (uint64_t z = 0; z < n_order; z++) {
     uint32_t want = order_ids[z];
     uint64_t slot = s->n_slots;
@@ -889,7 +971,8 @@ int orc_walk_forced(orc_sim *s, uint64_t n_order, const uint32_t *order_ids,
     attempt(s, (uint32_t)slot, dirs[want] % 12, fire[want] ? 1 : 0, 0, reacted);
   }
   free(reacted);
-  return 0;
+  finish_births(s);
+  return s->oom ? -1 : 0;
 }
 
 uint64_t orc_n_molecules(const orc_sim *s) { return s->n_alive; }

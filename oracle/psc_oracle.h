@@ -17,6 +17,8 @@
  *     propensity                              [2.4.1 First-Order, eqs. 3-5]
  *   - second-order reactions on collision with probability
  *     p = k / (6 sqrt2 (DA+DB) r)              [2.4.2 Second-Order, eq. 6]
+ *     and one to eleven products (2.4: two reactants may coalesce or decay
+ *     into several molecules; at most eleven, the neighbours left)
  *   - periodic boxes, or boxes closed by walls: a move into another
  *     compartment fails like a move into an occupied voxel (2.3); the space
  *     beyond a face of a closed box is read as such a compartment
@@ -92,7 +94,13 @@ void orc_destroy(orc_sim *s);
 int orc_set_boundary(orc_sim *s, int boundary);
 /* returns the new species id (1, 2, ...) or -1 */
 int orc_add_species(orc_sim *s, double D);
-/* returns the new reaction id (0, 1, ...) or -1 */
+/* returns the new reaction id (0, 1, ...) or -1.  First order: 0..11
+ * products, the first in place, the others on vacant neighbours.  Second
+ * order: 1..11 products, the first on the partner's voxel (partner's id),
+ * the second on the mover's voxel (mover's id), the others on vacant
+ * neighbours of the mover's voxel with ids assigned at the end of the walk in
+ * ascending (mover id, product index) order; too few vacant neighbours: the
+ * reaction fails with no change (a placement failure). */
 int orc_add_reaction(orc_sim *s, int n_reac, const uint16_t *reac, int n_prod,
                      const uint16_t *prod, double k);
 /* places `count` molecules of `species` uniformly at random; 0 on success */

@@ -66,6 +66,10 @@ def pick_workload(name: str):
         return workload("cfg1")
     if name == "mapk_paper":
         return workload("mapk_paper")
+    if name == "multiproduct":
+        return dict(workload("multiproduct", dims=(256, 256, 256), seed=3, n_a=400000,
+                             events=2000), track_displacement=False,
+                    name="multiproduct_256x256x256")
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -211,7 +215,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "mapk_paper"])
+    ap.add_argument("--workload", default="cfg3",
+                    choices=["cfg1", "cfg2", "cfg3", "mapk_paper", "multiproduct"])
     ap.add_argument("--timing-steps", type=int, default=40)
     ap.add_argument("--walls", action="store_true",
                     help="close the workload's box by walls instead of wrapping it")

@@ -95,7 +95,8 @@ typedef struct psc_counters {
                                   molecule per diffusion event) */
   uint64_t hops;               /* attempts that moved */
   uint64_t collisions;         /* attempts whose target voxel was occupied */
-  uint64_t placement_failures; /* first-order reactions that found too few
+  uint64_t placement_failures; /* reactions (first order, or collisions with
+                                  more than two products) that found too few
                                   vacant neighbours for their products */
 } psc_counters;
 
@@ -147,9 +148,13 @@ psc_status psc_add_species(psc_lattice *h, const char *name, double D,
  * products: the first stays in the reactant's voxel (keeping its id), the
  * others go to distinct vacant neighbours (new ids), and the reaction fails
  * with no change if too few are vacant (2.4.1).  n_r == 2: second-order,
- * k in m^3/s, 1 or 2 products: on collision the first product takes the
+ * k in m^3/s, 1..PSC_MAX_PRODUCTS products (2.4: two reactants may coalesce
+ * or decay into several molecules): on collision the first product takes the
  * partner's voxel and id, the second the mover's voxel and id (with one
- * product the mover's voxel is vacated) (2.4.2).  EINVAL for a second pair
+ * product the mover's voxel is vacated), the others distinct vacant
+ * neighbours of the mover's voxel with new ids, numbered at the end of the
+ * event in ascending (mover id, product index) order; too few vacant
+ * neighbours: no reaction and one placement failure (2.4.2).  EINVAL for a second pair
  * on the same unordered reactant pair, two immobile reactants, unknown
  * species, or k < 0; ESTATE after the first psc_step. */
 psc_status psc_add_reaction(psc_lattice *h, const uint16_t *reactants,

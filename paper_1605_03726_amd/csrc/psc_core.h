@@ -289,6 +289,15 @@ struct LatDev {
   uint32_t *birth_count;
   uint64_t birth_cap;
 
+  // newborns of collision reactions with more than two products in the
+  // running walk (null when no such reaction is registered): voxel, and key
+  // (mover id << 32 | product index << 28 | slot); numbered and binned by
+  // the end of the event in key order
+  uint32_t *wb_vox;
+  uint64_t *wb_key;
+  uint32_t *wb_count;
+  uint64_t wb_cap;
+
   // stale-entry filter (see hot_hash)
   uint32_t *hot;          // [2^hot_bits / 16] words
   uint32_t hot_bits;      // log2 of the number of hash slots

@@ -318,6 +318,14 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.birth_vox = alloc_n<uint32_t>(h, L.birth_cap);
   L.birth_sp = alloc_n<uint16_t>(h, L.birth_cap);
   L.birth_count = alloc_n<uint32_t>(h, 1);
+  bool collision_births = false;
+  for (const auto &d : h->rx) collision_births |= d.nr == 2 && d.np > 2;
+  if (collision_births) {
+    L.wb_cap = L.birth_cap;
+    L.wb_vox = alloc_n<uint32_t>(h, L.wb_cap);
+    L.wb_key = alloc_n<uint64_t>(h, L.wb_cap);
+    L.wb_count = alloc_n<uint32_t>(h, 1);
+  }
   {
     uint32_t bits = 16;
     while (bits < 24 && (1ull << bits) < cap / 4) ++bits;
@@ -357,7 +365,8 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
       !L.birth_sp || !L.birth_count || !L.fire_pos || !L.fire_id || !L.fire_col ||
       !L.fire_rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod ||
       !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.sdesc || !L.next_id || !L.cnt || !L.sp_count ||
-      !L.fired || !L.error || !h->dL || !L.hot || !L.end_done || !L.nbr_cnt)
+      !L.fired || !L.error || !h->dL || !L.hot || !L.end_done || !L.nbr_cnt ||
+      (collision_births && (!L.wb_vox || !L.wb_key || !L.wb_count)))
     return fail(h, PSC_ENOMEM, "device allocation failed");
   L.sp_flags = d_flags;
   L.pair_rx = d_pair;
@@ -436,6 +445,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   HIP_OK(h, hipMemset(L.cand_count, 0, 2 * sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.flag_count, 0, 2 * sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.sdesc, 0, 16 * sizeof(uint4)));  // empty until a first-order pass
+  if (L.wb_count) HIP_OK(h, hipMemset(L.wb_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.birth_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.cnt, 0, 4 * sizeof(unsigned long long)));
   {
@@ -484,7 +494,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
 }
 
 uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool displacement,
-                               uint32_t n_reactions) {
+                               uint32_t n_reactions, bool collision_births) {
   auto r = [](uint64_t b) { return (std::max<uint64_t>(b, 16) + 255) & ~uint64_t(255); };
   const uint64_t cap = std::max<uint64_t>(max_molecules, 1);
   uint64_t t = r(voxels * 2);
@@ -496,6 +506,7 @@ uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool dis
   t += r(8) + 2 * r(cap * 4) + r(8) + r(256);
   const uint64_t bcap = std::min<uint64_t>(pow2_at_least(cap), 1ull << 27);
   t += r(bcap * 8) + r(bcap * 4) + r(bcap * 2) + r(4);
+  if (collision_births) t += r(bcap * 4) + r(bcap * 8) + r(4);
   uint32_t hb = 16;
   while (hb < 24 && (1ull << hb) < cap / 4) ++hb;
   t += r((1ull << hb) / 4) + r(4);
@@ -641,8 +652,8 @@ psc_status psc_add_reaction(psc_lattice *h, const uint16_t *reactants, uint32_t 
   if (n_r == 1 && n_p > (uint32_t)PSC_MAX_PRODUCTS)
     return fail(h, PSC_EINVAL, "first-order reactions take 0..%d products", PSC_MAX_PRODUCTS);
   if (n_r == 2) {
-    if (n_p < 1 || n_p > 2)
-      return fail(h, PSC_EINVAL, "second-order reactions take 1 or 2 products");
+    if (n_p < 1 || n_p > (uint32_t)PSC_MAX_PRODUCTS)
+      return fail(h, PSC_EINVAL, "second-order reactions take 1..%d products", PSC_MAX_PRODUCTS);
     const uint16_t A = reactants[0], B = reactants[1];
     if (!(h->species[A].D + h->species[B].D > 0.0))
       return fail(h, PSC_EINVAL, "two immobile reactants never collide");

@@ -126,6 +126,6 @@ psc_status ensure_member_records(psc_ensemble *E, hipStream_t stream, uint64_t n
 psc_status ensure_graph(psc_ensemble *E);
 // device bytes a lattice with this capacity and size will hold once frozen
 uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool displacement,
-                               uint32_t n_reactions);
+                               uint32_t n_reactions, bool collision_births);
 
 }  // namespace psc_detail

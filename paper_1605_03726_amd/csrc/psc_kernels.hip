@@ -553,6 +553,22 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     const int rx = L.pair_rx[sp * 64 + psp];
     if (rx < 0) continue;
     if (!L.rx_always[rx] && !(ry[it] < L.rx_thr[rx])) continue;
+    const uint32_t m = L.rx_nprod[rx];
+    // products beyond the second need as many distinct vacant neighbours of
+    // the mover's voxel (a mask in stencil order), else nothing happens
+    uint32_t vmask = 0;
+    Coord cv;
+    if (m > 2) {
+      cv = coord_of(L.geo, v);
+      for (uint32_t n = 0; n < 12; ++n) {
+        Coord cn;
+        if (step_target(L.geo, cv, n, cn) && occ[index_of(L.geo, cn)] == 0) vmask |= 1u << n;
+      }
+      if (__popc(vmask) < (int)(m - 2)) {
+        atomicAdd(&L.cnt[3], 1ull);
+        continue;
+      }
+    }
     // first product on the partner's voxel with the partner's identity;
     // its own entry (wherever it is) stays valid: it is flagged so that it
     // does not walk again in this event, and its voxel is marked hot so
@@ -567,13 +583,47 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     atomicSub(&sh->dsp[psp], 1);
     atomicAdd(&sh->dsp[prod[0] & 63u], 1);
     sh->any_rx = 1;
-    if (L.rx_nprod[rx] == 2) {
+    if (m >= 2) {
       occ[v] = prod[1];
       osp[it] = prod[1];
       atomicAdd(&sh->dsp[prod[1] & 63u], 1);
     } else {
       occ[v] = 0;
       ocol[it] = 0xFFu;  // the mover's identity ends here
+    }
+    // the others: each takes entry floor(w k / 2^32) of the k vacant
+    // neighbours left, w = r2, r3 of the walk draw, then further blocks;
+    // they are numbered at the end of the event
+    for (uint32_t q = 0; q + 2 < m; ++q) {
+      uint32_t w;
+      if (q < 2) {
+        const U4 r0 = philox((uint32_t)e, id[it], kPhaseWalk, 0, L.key0, L.key1);
+        w = q == 0 ? r0.z : r0.w;
+      } else {
+        const U4 rb = philox((uint32_t)e, id[it], kPhaseWalk, 1 + (q - 2) / 4, L.key0, L.key1);
+        const uint32_t k = (q - 2) & 3u;
+        w = k == 0 ? rb.x : (k == 1 ? rb.y : (k == 2 ? rb.z : rb.w));
+      }
+      uint32_t x = scale32(w, (uint32_t)__popc(vmask)), n = 0;
+      for (;; ++n) {
+        if (!((vmask >> n) & 1u)) continue;
+        if (x == 0) break;
+        --x;
+      }
+      vmask &= ~(1u << n);
+      Coord cn;
+      step_target(L.geo, cv, n, cn);
+      const uint32_t u = index_of(L.geo, cn);
+      const uint16_t ps = prod[2 + q];
+      occ[u] = ps;
+      atomicAdd(&sh->dsp[ps & 63u], 1);
+      const uint32_t slot = atomicAdd(L.wb_count, 1u);
+      if (slot < L.wb_cap) {
+        L.wb_vox[slot] = u;
+        L.wb_key[slot] = ((uint64_t)id[it] << 32) | ((uint64_t)(2 + q) << 28) | slot;
+      } else {
+        set_error(L, kErrBirthOverflow);
+      }
     }
     atomicAdd(&L.fired[rx], 1ull);
   }
@@ -750,6 +800,74 @@ constexpr int kEndBlocksMulti = 4;
 
 // workgroup bid of nblk: sweep flags and the previous hot bitmap; the last
 // workgroup to finish advances the lattice's event counter
+// Newborns of this walk's many-product collisions get ids next_id, ... in
+// ascending (mover id, product index) order and join the next event's bins
+// with their current species (one may have changed as a later partner);
+// they are also tested as first-order candidates of the next event, which a
+// walk does for every other molecule.  Run by one whole workgroup.
+__device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
+  __shared__ uint64_t s_wkeys[kSortLds];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nb = min(*L.wb_count, (uint32_t)L.wb_cap);
+  if (nb == 0) return;
+  uint32_t n2 = 1;
+  while (n2 < nb) n2 <<= 1;  // <= wb_cap, a power of two
+  uint64_t *keys = L.wb_key;
+  if (n2 <= kSortLds) {
+    for (uint32_t q = tid; q < n2; q += blockDim.x) s_wkeys[q] = q < nb ? L.wb_key[q] : ~0ull;
+    keys = s_wkeys;
+  } else {
+    for (uint32_t q = nb + tid; q < n2; q += blockDim.x) L.wb_key[q] = ~0ull;
+  }
+  __syncthreads();
+  bitonic_sort_keys(keys, n2, tid, blockDim.x);
+  const uint32_t base_id = *L.next_id;
+  if ((uint64_t)base_id + nb >= 0xFFFFFFFFull) {
+    if (tid == 0) set_error(L, kErrIds);
+    return;
+  }
+  const Bins &out = L.bins[(e + 1) & 1];
+  const uint32_t cnext = (uint32_t)((e + 1) & 1);
+  const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
+  for (uint32_t q = tid; q < nb; q += blockDim.x) {
+    const uint32_t u = L.wb_vox[keys[q] & ((1u << 28) - 1u)];
+    const uint32_t id = base_id + q;
+    const uint32_t c = colour_of_voxel(L.geo, u);
+    const uint32_t pos = atomicAdd(&out.count[c], 1u);
+    if (pos >= L.cap) {
+      set_error(L, kErrBinOverflow);
+      continue;
+    }
+    const uint64_t at = c * L.cap + pos;
+    out.vox[at] = u;
+    out.id[at] = id;
+    out.sp[at] = (uint16_t)(L.occ[u] & kSpeciesMask);
+    if (out.disp) {
+      out.disp[(0 * 16 + c) * L.cap + pos] = 0;
+      out.disp[(1 * 16 + c) * L.cap + pos] = 0;
+      out.disp[(2 * 16 + c) * L.cap + pos] = 0;
+    }
+    if (cmax_next) {
+      const U4 r = philox((uint32_t)(e + 1), id, kPhaseFirst, 0, L.key0, L.key1);
+      if (r.x < cmax_next) {
+        const uint32_t k = atomicAdd(&L.cand_count[cnext], 1u);
+        if (k < L.cand_cap) {
+          L.cand_pos[cnext][k] = pos;
+          L.cand_id[cnext][k] = id;
+          L.cand_col[cnext][k] = (uint8_t)c;
+        } else {
+          set_error(L, kErrCandOverflow);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    *L.next_id = base_id + nb;
+    *L.wb_count = 0;
+  }
+}
+
 __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t nblk) {
   const uint64_t e = *L.ev;
   if (e >= L.tape_horizon || e >= L.stop_event) return;
@@ -768,16 +886,22 @@ __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t
     const uint32_t h = hot_hash(L.flag_vox[prv][q], L.hot_bits);
     atomicAnd(&L.hot[h >> 4], ~(1u << (((h & 15u) << 1) | prv)));
   }
+  __shared__ uint32_t s_last;
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
-    const uint32_t done = atomicAdd(L.end_done, 1u);
-    if (done == nblk - 1) {
-      __threadfence();
-      L.flag_count[prv] = 0;  // the next walk fills this list
-      *L.end_done = 0;
-      *L.ev = e + 1;
-    }
+    s_last = atomicAdd(L.end_done, 1u) == nblk - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // the last workgroup: every other one has finished its sweeps
+  __threadfence();
+  if (L.wb_count) number_births(L, e);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    L.flag_count[prv] = 0;  // the next walk fills this list
+    *L.end_done = 0;
+    *L.ev = e + 1;
   }
 }
 

@@ -252,8 +252,11 @@ psc_status psc_server_create(const psc_server_options *opt, psc_server **out) {
 psc_status psc_server_job_bytes(const psc_job_desc *d, uint64_t *bytes) {
   if (!d || !bytes) return PSC_EINVAL;
   const uint64_t nv = (uint64_t)d->ni * d->nj * d->nk;
+  bool collision_births = false;
+  for (uint32_t r = 0; d->reactions && r < d->n_reactions; ++r)
+    collision_births |= d->reactions[r].n_r == 2 && d->reactions[r].n_p > 2;
   *bytes = estimate_device_bytes(nv, d->max_molecules, (d->flags & PSC_TRACK_DISPLACEMENT) != 0,
-                                 d->n_reactions) +
+                                 d->n_reactions, collision_births) +
            (d->n_events + 2048) * 64;  // event tape, grown geometrically
   return PSC_OK;
 }

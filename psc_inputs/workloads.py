@@ -134,6 +134,25 @@ def small_reactive(dims=(16, 12, 8), seed: int = 7, events: int = 40) -> dict:
                 events=events, track_displacement=True)
 
 
+def multiproduct(dims=(16, 12, 8), seed: int = 3, n_a: int = 0, events: int = 40,
+                 boundary=None) -> dict:
+    """Collisions with more than two products next to first-order decays:
+    A + B -> B + A + 2 C (p clamps to 1), C + A -> D + A + 3 C (p < 1),
+    C -> 0, D -> 2 C; A and B at n_a each (default 1/12 of the voxels)."""
+    nv = dims[0] * dims[1] * dims[2]
+    n_a = n_a or nv // 12
+    w = dict(name="multiproduct", dims=tuple(dims), rv=RV, seed=seed,
+             species=[("A", D1), ("B", D05), ("C", 2 * D1), ("D", 0.0)],
+             reactions=[((1, 2), (2, 1, 3, 3), 1e-15),
+                        ((3, 1), (4, 1, 3, 3, 3), 1e-19),
+                        ((3,), (), 4000.0),
+                        ((4,), (3, 3), 800.0)],
+             place=[(1, n_a), (2, n_a)], events=events, track_displacement=True)
+    if boundary:
+        w["boundary"] = boundary
+    return w
+
+
 AVOGADRO = 6.02214076e23
 
 
@@ -181,6 +200,7 @@ WORKLOADS = {
     "cfg3": cfg3,
     "small_reactive": small_reactive,
     "mapk_paper": mapk_paper,
+    "multiproduct": multiproduct,
 }
 
 

@@ -42,6 +42,8 @@ def mixed_members(n_rep=10, events=40):
     # members closed by walls beside periodic ones
     ws.append(dict(workload("small_reactive", seed=6, events=events), boundary="walls"))
     ws.append(dict(ws[0], boundary="walls"))
+    # collisions with more than two products
+    ws.append(workload("multiproduct", seed=8, events=events))
     return ws
 
 

@@ -420,6 +420,89 @@ __device__ __forceinline__ gptr<T> global(T *p) {
 }
 
 // DM: displacement planes never (0), always (1), or as the lattice says (2)
+// A collision of the mover (id, species sp, voxel v) with the partner at t
+// (species psp) fires reaction rx (2.4.2).  The first product takes the
+// partner's voxel and identity: the partner's entry (wherever it is) stays
+// valid, flagged so that it does not walk again in this event, its voxel
+// marked hot so that its cached species is refreshed.  The second takes the
+// mover's voxel and identity; with one product the mover's identity ends.
+// Further products need as many distinct vacant neighbours of v, else
+// nothing happens (a placement failure): each takes entry floor(w k / 2^32)
+// of the k vacant neighbours left in stencil order, w = r2, r3 of the walk
+// draw, then further blocks; they are numbered at the end of the event.
+// EXTRA: the reaction may have more than two products
+template <bool EXTRA, class OccP, class HotP>
+__device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh, uint64_t e,
+                                               uint32_t buf, uint32_t hbits, OccP occ, HotP hot,
+                                               int rx, uint32_t v, uint32_t t, uint32_t sp,
+                                               uint32_t psp, uint32_t id, uint32_t &osp,
+                                               uint32_t &ocol, bool &flag, uint32_t &ftgt) {
+  const uint32_t m = EXTRA ? L.rx_nprod[rx] : min(L.rx_nprod[rx], 2u);
+  uint32_t vmask = 0;
+  Coord cv;
+  if (EXTRA && m > 2) {
+    cv = coord_of(L.geo, v);
+    for (uint32_t n = 0; n < 12; ++n) {
+      Coord cn;
+      if (step_target(L.geo, cv, n, cn) && occ[index_of(L.geo, cn)] == 0) vmask |= 1u << n;
+    }
+    if (__popc(vmask) < (int)(m - 2)) {
+      atomicAdd(&L.cnt[3], 1ull);
+      return;
+    }
+  }
+  const uint16_t *prod = L.rx_prod + rx * 12;
+  occ[t] = (uint16_t)(prod[0] | kReactedFlag);
+  const uint32_t ht = hot_hash(t, hbits);
+  atomicOr((uint32_t *)&hot[ht >> 4], 1u << (((ht & 15u) << 1) | buf));
+  flag = true;
+  ftgt = t;
+  atomicSub(&sh.dsp[sp], 1);
+  atomicSub(&sh.dsp[psp], 1);
+  atomicAdd(&sh.dsp[prod[0] & 63u], 1);
+  sh.any_rx = 1;
+  if (m >= 2) {
+    occ[v] = prod[1];
+    osp = prod[1];
+    atomicAdd(&sh.dsp[prod[1] & 63u], 1);
+  } else {
+    occ[v] = 0;
+    ocol = 0xFFu;
+  }
+  for (uint32_t q = 0; EXTRA && q + 2 < m; ++q) {
+    uint32_t w;
+    if (q < 2) {
+      const U4 r0 = philox((uint32_t)e, id, kPhaseWalk, 0, L.key0, L.key1);
+      w = q == 0 ? r0.z : r0.w;
+    } else {
+      const U4 rb = philox((uint32_t)e, id, kPhaseWalk, 1 + (q - 2) / 4, L.key0, L.key1);
+      const uint32_t k = (q - 2) & 3u;
+      w = k == 0 ? rb.x : (k == 1 ? rb.y : (k == 2 ? rb.z : rb.w));
+    }
+    uint32_t x = scale32(w, (uint32_t)__popc(vmask)), n = 0;
+    for (;; ++n) {
+      if (!((vmask >> n) & 1u)) continue;
+      if (x == 0) break;
+      --x;
+    }
+    vmask &= ~(1u << n);
+    Coord cn;
+    step_target(L.geo, cv, n, cn);
+    const uint32_t u = index_of(L.geo, cn);
+    const uint16_t ps = prod[2 + q];
+    occ[u] = ps;
+    atomicAdd(&sh.dsp[ps & 63u], 1);
+    const uint32_t slot = atomicAdd(L.wb_count, 1u);
+    if (slot < L.wb_cap) {
+      L.wb_vox[slot] = u;
+      L.wb_key[slot] = ((uint64_t)id << 32) | ((uint64_t)(2 + q) << 28) | slot;
+    } else {
+      set_error(L, kErrBirthOverflow);
+    }
+  }
+  atomicAdd(&L.fired[rx], 1ull);
+}
+
 template <int ITEMS, int DM>
 __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t base, uint32_t n,
                             StageShared &S, StageStaging<ITEMS> &stg) {
@@ -497,8 +580,10 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
   // instead of its target.
   uint32_t tgt[ITEMS], wt[ITEMS], hw[ITEMS], hs[ITEMS], ry[ITEMS], mv[ITEMS];
   bool loaded[ITEMS];
+  int drx[ITEMS];  // reaction | partner species << 8 of a deferred collision, or -1
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
+    drx[it] = -1;
     const uint32_t v = vox[it];
     const U4 r = philox((uint32_t)e, id[it], kPhaseWalk, 0, L.key0, L.key1);
     const uint32_t dir = scale32(r.x, 12);
@@ -553,80 +638,21 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     const int rx = L.pair_rx[sp * 64 + psp];
     if (rx < 0) continue;
     if (!L.rx_always[rx] && !(ry[it] < L.rx_thr[rx])) continue;
-    const uint32_t m = L.rx_nprod[rx];
-    // products beyond the second need as many distinct vacant neighbours of
-    // the mover's voxel (a mask in stencil order), else nothing happens
-    uint32_t vmask = 0;
-    Coord cv;
-    if (m > 2) {
-      cv = coord_of(L.geo, v);
-      for (uint32_t n = 0; n < 12; ++n) {
-        Coord cn;
-        if (step_target(L.geo, cv, n, cn) && occ[index_of(L.geo, cn)] == 0) vmask |= 1u << n;
-      }
-      if (__popc(vmask) < (int)(m - 2)) {
-        atomicAdd(&L.cnt[3], 1ull);
-        continue;
-      }
+    if (L.rx_nprod[rx] > 2) {
+      // more than two products: applied after this loop (rare), where fewer
+      // of the items' values are live
+      drx[it] = rx | (int)(psp << 8);
+      continue;
     }
-    // first product on the partner's voxel with the partner's identity;
-    // its own entry (wherever it is) stays valid: it is flagged so that it
-    // does not walk again in this event, and its voxel is marked hot so
-    // that its cached species is refreshed
-    const uint16_t *prod = L.rx_prod + rx * 12;
-    occ[t] = (uint16_t)(prod[0] | kReactedFlag);
-    const uint32_t ht = hot_hash(t, hbits);
-    atomicOr((uint32_t *)&hot[ht >> 4], 1u << (((ht & 15u) << 1) | buf));
-    flag[it] = true;
-    ftgt[it] = t;
-    atomicSub(&sh->dsp[sp], 1);
-    atomicSub(&sh->dsp[psp], 1);
-    atomicAdd(&sh->dsp[prod[0] & 63u], 1);
-    sh->any_rx = 1;
-    if (m >= 2) {
-      occ[v] = prod[1];
-      osp[it] = prod[1];
-      atomicAdd(&sh->dsp[prod[1] & 63u], 1);
-    } else {
-      occ[v] = 0;
-      ocol[it] = 0xFFu;  // the mover's identity ends here
-    }
-    // the others: each takes entry floor(w k / 2^32) of the k vacant
-    // neighbours left, w = r2, r3 of the walk draw, then further blocks;
-    // they are numbered at the end of the event
-    for (uint32_t q = 0; q + 2 < m; ++q) {
-      uint32_t w;
-      if (q < 2) {
-        const U4 r0 = philox((uint32_t)e, id[it], kPhaseWalk, 0, L.key0, L.key1);
-        w = q == 0 ? r0.z : r0.w;
-      } else {
-        const U4 rb = philox((uint32_t)e, id[it], kPhaseWalk, 1 + (q - 2) / 4, L.key0, L.key1);
-        const uint32_t k = (q - 2) & 3u;
-        w = k == 0 ? rb.x : (k == 1 ? rb.y : (k == 2 ? rb.z : rb.w));
-      }
-      uint32_t x = scale32(w, (uint32_t)__popc(vmask)), n = 0;
-      for (;; ++n) {
-        if (!((vmask >> n) & 1u)) continue;
-        if (x == 0) break;
-        --x;
-      }
-      vmask &= ~(1u << n);
-      Coord cn;
-      step_target(L.geo, cv, n, cn);
-      const uint32_t u = index_of(L.geo, cn);
-      const uint16_t ps = prod[2 + q];
-      occ[u] = ps;
-      atomicAdd(&sh->dsp[ps & 63u], 1);
-      const uint32_t slot = atomicAdd(L.wb_count, 1u);
-      if (slot < L.wb_cap) {
-        L.wb_vox[slot] = u;
-        L.wb_key[slot] = ((uint64_t)id[it] << 32) | ((uint64_t)(2 + q) << 28) | slot;
-      } else {
-        set_error(L, kErrBirthOverflow);
-      }
-    }
-    atomicAdd(&L.fired[rx], 1ull);
+    fire_collision<false>(L, *sh, e, buf, hbits, occ, hot, rx, v, t, sp, psp, id[it], osp[it],
+                          ocol[it], flag[it], ftgt[it]);
   }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it)
+    if (drx[it] >= 0)
+      fire_collision<true>(L, *sh, e, buf, hbits, occ, hot, drx[it] & 0xFF, vox[it], tgt[it],
+                           osp[it] & 63u, (uint32_t)drx[it] >> 8, id[it], osp[it], ocol[it],
+                           flag[it], ftgt[it]);
 
   // ---- survivors: block-local slots per colour (LDS atomics), one global
   // reservation per colour per chunk, entries staged colour-major in LDS and

@@ -67,7 +67,7 @@ def pick_workload(name: str):
     if name == "mapk_paper":
         return workload("mapk_paper")
     if name == "multiproduct":
-        return dict(workload("multiproduct", dims=(256, 256, 256), seed=3, n_a=400000,
+        return dict(workload("multiproduct", dims=(256, 256, 256), seed=3, n_a=100000,
                              events=2000), track_displacement=False,
                     name="multiproduct_256x256x256")
     raise SystemExit("unknown workload %s" % name)

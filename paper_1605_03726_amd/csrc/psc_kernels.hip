@@ -821,6 +821,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
 // k_end: clear reacted flags and the previous event's hot bitmap, advance the
 // event counter (the last workgroup to finish does the bookkeeping)
 // =============================================================================
+constexpr int kEndThreads = kStageThreads;
 constexpr int kEndBlocks = 32;
 constexpr int kEndBlocksMulti = 4;
 
@@ -931,11 +932,11 @@ __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t
   }
 }
 
-__global__ void __launch_bounds__(kStageThreads) k_end(const LatDev *__restrict__ Lp) {
+__global__ void __launch_bounds__(kEndThreads) k_end(const LatDev *__restrict__ Lp) {
   end_body(*Lp, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kStageThreads) k_end_multi(const LatDev *__restrict__ lats) {
+__global__ void __launch_bounds__(kEndThreads) k_end_multi(const LatDev *__restrict__ lats) {
   end_body(lats[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
@@ -1028,7 +1029,7 @@ hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool 
 }
 
 hipError_t launch_end(const LatDev *dL, hipStream_t s) {
-  hipLaunchKernelGGL(k_end, dim3(kEndBlocks), dim3(kStageThreads), 0, s, dL);
+  hipLaunchKernelGGL(k_end, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL);
   return hipGetLastError();
 }
 
@@ -1051,7 +1052,7 @@ hipError_t launch_event_multi(const LatDev *lats, uint32_t R, int grid, int item
     default: hipLaunchKernelGGL(k_stage_multi<4>, dim3(grid), dim3(kStageThreads), 0, s, lats, R, g); break;
     }
   }
-  hipLaunchKernelGGL(k_end_multi, dim3(kEndBlocksMulti, R), dim3(kStageThreads), 0, s, lats);
+  hipLaunchKernelGGL(k_end_multi, dim3(kEndBlocksMulti, R), dim3(kEndThreads), 0, s, lats);
   return hipGetLastError();
 }
 

@@ -136,17 +136,19 @@ def small_reactive(dims=(16, 12, 8), seed: int = 7, events: int = 40) -> dict:
 
 def multiproduct(dims=(16, 12, 8), seed: int = 3, n_a: int = 0, events: int = 40,
                  boundary=None) -> dict:
-    """Collisions with more than two products next to first-order decays:
-    A + B -> B + A + 2 C (p clamps to 1), C + A -> D + A + 3 C (p < 1),
-    C -> 0, D -> 2 C; A and B at n_a each (default 1/12 of the voxels)."""
+    """Collisions with more than two products next to first-order decays, with
+    a bounded population: A + B -> B + A + 2 C (p about 0.36),
+    C + B -> D + B + E (p about 0.54), C -> 0, D -> 2 C, E -> 0; A and B at
+    n_a each (default 1/12 of the voxels)."""
     nv = dims[0] * dims[1] * dims[2]
     n_a = n_a or nv // 12
     w = dict(name="multiproduct", dims=tuple(dims), rv=RV, seed=seed,
-             species=[("A", D1), ("B", D05), ("C", 2 * D1), ("D", 0.0)],
-             reactions=[((1, 2), (2, 1, 3, 3), 1e-15),
-                        ((3, 1), (4, 1, 3, 3, 3), 1e-19),
-                        ((3,), (), 4000.0),
-                        ((4,), (3, 3), 800.0)],
+             species=[("A", D1), ("B", D05), ("C", 2 * D1), ("D", 0.0), ("E", D1)],
+             reactions=[((1, 2), (2, 1, 3, 3), 2e-20),
+                        ((3, 2), (4, 2, 5), 5e-20),
+                        ((3,), (), 20000.0),
+                        ((4,), (3, 3), 800.0),
+                        ((5,), (), 800.0)],
              place=[(1, n_a), (2, n_a)], events=events, track_displacement=True)
     if boundary:
         w["boundary"] = boundary

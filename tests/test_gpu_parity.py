@@ -297,20 +297,21 @@ def test_walls_launch_shapes(items):
 
 @pytest.mark.parametrize("seed,boundary", [(3, None), (4, "walls"), (5, None)])
 def test_multiproduct_collisions(seed, boundary):
-    w = workload("multiproduct", seed=seed, boundary=boundary)
+    w = workload("multiproduct", seed=seed, boundary=boundary, n_a=16 * 12 * 8 // 5)
     g, s = run_pair(w, 40)
     assert s["fired"][0] > 0 and s["fired"][1] > 0 and s["place_fail"] > 0, (s["fired"], s["place_fail"])
 
 
 def test_multiproduct_collisions_many_events_and_shapes():
-    w = workload("multiproduct", dims=(48, 48, 32), seed=6, n_a=4000)
-    lat = build_gpu(w)
+    w = workload("multiproduct", dims=(48, 48, 32), seed=6, n_a=6000)
+    nv = 48 * 48 * 32
+    lat = build_gpu(w, max_molecules=nv)
     o = build_oracle(w)
     for n in (1, 30, 90):
         lat.step(n)
         o.run(n, oracle.MODE_C)
         assert_same(lat.read_state(), o.state())
-    staged = build_gpu(w)
+    staged = build_gpu(w, max_molecules=nv)
     staged.set_launch(1, 7)
     staged.step(121)
     assert_same(staged.read_state(), o.state())

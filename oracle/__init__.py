@@ -18,6 +18,7 @@ SRC = os.path.join(HERE, "psc_oracle.c")
 
 MODE_C, MODE_S, MODE_C_REV = 0, 1, 2
 PERIODIC, REFLECT = 0, 1
+HCP, FCC = 0, 1
 OUTSIDE = 0xFFFFFFFF
 CNT_ATTEMPTS, CNT_HOPS, CNT_COLLISIONS, CNT_PLACE_FAIL, CNT_N = range(5)
 
@@ -51,6 +52,18 @@ def lib() -> C.CDLL:
     L.orc_neighbour_b.restype = C.c_uint32
     L.orc_set_boundary.argtypes = [C.c_void_p, C.c_int]
     L.orc_set_boundary.restype = C.c_int
+    L.orc_set_lattice.argtypes = [C.c_void_p, C.c_int]
+    L.orc_set_lattice.restype = C.c_int
+    L.orc_neighbour_l.argtypes = [C.c_uint32] * 4 + [C.c_int, C.c_int, C.c_int]
+    L.orc_neighbour_l.restype = C.c_uint32
+    L.orc_hop_vector_l.argtypes = [C.c_uint32] * 4 + [C.c_int, C.c_int, C.POINTER(C.c_int32)]
+    L.orc_position_l.argtypes = [C.c_uint32] * 4 + [C.c_double, C.c_int,
+                                                    C.POINTER(C.c_double)]
+    L.orc_colour_l.argtypes = [C.c_uint32] * 4 + [C.c_int]
+    L.orc_colour_l.restype = C.c_int
+    L.orc_n_colours.argtypes = [C.c_int]
+    L.orc_n_colours.restype = C.c_int
+    L.orc_stage_order_n.argtypes = [C.c_uint64, C.c_uint64, C.c_int, C.POINTER(C.c_uint8)]
     L.orc_neighbour_table.argtypes = [C.c_uint32] * 3 + [u32p]
     L.orc_hop_vector.argtypes = [C.c_uint32] * 4 + [C.c_int, C.POINTER(C.c_int32)]
     L.orc_position.argtypes = [C.c_uint32] * 4 + [C.c_double, C.POINTER(C.c_double)]
@@ -161,6 +174,37 @@ def stage_order(seed: int, event: int) -> list:
     return list(out)
 
 
+# either lattice (HCP or FCC)
+def neighbour_l(dims, v: int, n: int, lattice: int, boundary: int = PERIODIC) -> int:
+    return lib().orc_neighbour_l(dims[0], dims[1], dims[2], v, n, lattice, boundary)
+
+
+def hop_vector_l(dims, v: int, n: int, lattice: int):
+    out = (C.c_int32 * 3)()
+    lib().orc_hop_vector_l(dims[0], dims[1], dims[2], v, n, lattice, out)
+    return tuple(out)
+
+
+def position_l(dims, v: int, rv: float, lattice: int):
+    out = (C.c_double * 3)()
+    lib().orc_position_l(dims[0], dims[1], dims[2], v, rv, lattice, out)
+    return tuple(out)
+
+
+def colour_l(dims, v: int, lattice: int) -> int:
+    return lib().orc_colour_l(dims[0], dims[1], dims[2], v, lattice)
+
+
+def n_colours(lattice: int) -> int:
+    return lib().orc_n_colours(lattice)
+
+
+def stage_order_n(seed: int, event: int, n: int) -> list:
+    out = (C.c_uint8 * 24)()
+    lib().orc_stage_order_n(seed, event, n, out)
+    return list(out)[:n]
+
+
 def second_order_threshold(k, DA, DB, rv) -> int:
     return lib().orc_second_order_threshold(k, DA, DB, rv)
 
@@ -177,7 +221,7 @@ def tau(rv: float, D: float) -> float:
 class Oracle:
     """One lattice simulated by the CPU oracle."""
 
-    def __init__(self, dims, rv: float, seed: int, boundary: int = 0):
+    def __init__(self, dims, rv: float, seed: int, boundary: int = 0, lattice: int = 0):
         self.L = lib()
         self.dims = tuple(int(x) for x in dims)
         h = self.L.orc_create(self.dims[0], self.dims[1], self.dims[2], rv, seed)
@@ -187,6 +231,8 @@ class Oracle:
         self.n_rx = 0
         if self.L.orc_set_boundary(self.h, boundary) != 0:
             raise ValueError(f"oracle: bad boundary {boundary}")
+        if self.L.orc_set_lattice(self.h, lattice) != 0:
+            raise ValueError(f"oracle: bad lattice kind {lattice} for {dims}")
 
     def close(self):
         if self.h:

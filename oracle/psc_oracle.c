@@ -103,6 +103,32 @@ static uint32_t v_of(uint32_t ni, uint32_t nj, uint32_t i, uint32_t j, uint32_t 
 /* The 12 neighbours, written as (di, dj, dk) in index space for parities s, p.
  * Row n of the table; derived from the voxel centres above so that every
  * neighbour lies at distance exactly 2r. */
+/* FCC (ABC stacking, layer phase q = k mod 3, in-row offset s = (j+q)&1):
+ * rows 0..5 as HCP; above: (s, a, +1), (s-1, a, +1), (0, c, +1) with
+ * a = 0, c = -1 for q < 2 and a = +1, c = 0 for q = 2; below:
+ * (s, b, -1), (s-1, b, -1), (0, d, -1) with b = 0, d = +1 for q > 0 and
+ * b = -1, d = 0 for q = 0.  Derived from the positions below (the layer
+ * above is shifted by t = (r, r/sqrt3) in the plane, the one below by -t). */
+static void stencil_fcc(int n, uint32_t j, uint32_t k, int *di, int *dj, int *dk) {
+  int q = (int)(k % 3u), s = (int)((j + (uint32_t)q) & 1u);
+  int a = q < 2 ? 0 : 1, c = q < 2 ? -1 : 0;
+  int b = q > 0 ? 0 : -1, d = q > 0 ? 1 : 0;
+  switch (n) {
+  case 0: *di = 1;     *dj = 0;  *dk = 0;  break;
+  case 1: *di = -1;    *dj = 0;  *dk = 0;  break;
+  case 2: *di = s;     *dj = 1;  *dk = 0;  break;
+  case 3: *di = s - 1; *dj = 1;  *dk = 0;  break;
+  case 4: *di = s;     *dj = -1; *dk = 0;  break;
+  case 5: *di = s - 1; *dj = -1; *dk = 0;  break;
+  case 6: *di = s;     *dj = a;  *dk = 1;  break;
+  case 7: *di = s - 1; *dj = a;  *dk = 1;  break;
+  case 8: *di = 0;     *dj = c;  *dk = 1;  break;
+  case 9: *di = s;     *dj = b;  *dk = -1; break;
+  case 10: *di = s - 1; *dj = b; *dk = -1; break;
+  default: *di = 0;    *dj = d;  *dk = -1; break;
+  }
+}
+
 static void stencil(int n, int s, int p, int *di, int *dj, int *dk) {
   switch (n) {
   case 0: *di = 1;     *dj = 0;         *dk = 0;  break;
@@ -142,30 +168,31 @@ static uint32_t wrap(int64_t x, uint32_t n) {
   return (uint32_t)m;
 }
 
-uint32_t orc_neighbour(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n) {
+/* Neighbour n of v for either lattice and boundary: periodic boxes wrap, a
+ * box closed by walls has no neighbour beyond a face (ORC_OUTSIDE) -- the
+ * space there is another compartment. */
+uint32_t orc_neighbour_l(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
+                         int lattice, int boundary) {
   uint32_t i, j, k;
   int di, dj, dk;
   ijk_of(ni, nj, v, &i, &j, &k);
-  int s = (int)((j + k) & 1u), p = (int)(k & 1u);
-  stencil(n, s, p, &di, &dj, &dk);
-  return v_of(ni, nj, wrap((int64_t)i + di, ni), wrap((int64_t)j + dj, nj),
-              wrap((int64_t)k + dk, nk));
+  if (lattice == ORC_LATTICE_FCC) stencil_fcc(n, j, k, &di, &dj, &dk);
+  else stencil(n, (int)((j + k) & 1u), (int)(k & 1u), &di, &dj, &dk);
+  int64_t a = (int64_t)i + di, b = (int64_t)j + dj, c = (int64_t)k + dk;
+  if (boundary == ORC_BOUNDARY_REFLECT) {
+    if (a < 0 || b < 0 || c < 0 || a >= ni || b >= nj || c >= nk) return ORC_OUTSIDE;
+    return v_of(ni, nj, (uint32_t)a, (uint32_t)b, (uint32_t)c);
+  }
+  return v_of(ni, nj, wrap(a, ni), wrap(b, nj), wrap(c, nk));
 }
 
-/* Neighbour n of v in a box with the given boundary: periodic (wrapping, as
- * orc_neighbour) or reflecting, where a neighbour beyond a face does not
- * exist (ORC_OUTSIDE) -- the box is closed by walls. */
+uint32_t orc_neighbour(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n) {
+  return orc_neighbour_l(ni, nj, nk, v, n, ORC_LATTICE_HCP, ORC_BOUNDARY_PERIODIC);
+}
+
 uint32_t orc_neighbour_b(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
                          int boundary) {
-  if (boundary == ORC_BOUNDARY_PERIODIC) return orc_neighbour(ni, nj, nk, v, n);
-  uint32_t i, j, k;
-  int di, dj, dk;
-  ijk_of(ni, nj, v, &i, &j, &k);
-  int s = (int)((j + k) & 1u), p = (int)(k & 1u);
-  stencil(n, s, p, &di, &dj, &dk);
-  int64_t a = (int64_t)i + di, b = (int64_t)j + dj, c = (int64_t)k + dk;
-  if (a < 0 || b < 0 || c < 0 || a >= ni || b >= nj || c >= nk) return ORC_OUTSIDE;
-  return v_of(ni, nj, (uint32_t)a, (uint32_t)b, (uint32_t)c);
+  return orc_neighbour_l(ni, nj, nk, v, n, ORC_LATTICE_HCP, boundary);
 }
 
 void orc_neighbour_table(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t *out) {
@@ -174,53 +201,91 @@ void orc_neighbour_table(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t *out) {
     for (int n = 0; n < 12; n++) out[12 * v + n] = orc_neighbour(ni, nj, nk, (uint32_t)v, n);
 }
 
-void orc_hop_vector(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
-                    int32_t out[3]) {
+/* FCC hop n in the same units (r, r/sqrt3, 2 sqrt(2/3) r); the layer phase
+ * does not enter: FCC is a Bravais lattice */
+static void hopvec_fcc(int n, int32_t *X, int32_t *Y, int32_t *Z) {
+  static const int32_t tx[12] = {2, -2, 1, -1, 1, -1, 1, -1, 0, 1, -1, 0};
+  static const int32_t ty[12] = {0, 0, 3, 3, -3, -3, 1, 1, -2, -1, -1, 2};
+  static const int32_t tz[12] = {0, 0, 0, 0, 0, 0, 1, 1, 1, -1, -1, -1};
+  *X = tx[n];
+  *Y = ty[n];
+  *Z = tz[n];
+}
+
+void orc_hop_vector_l(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n, int lattice,
+                      int32_t out[3]) {
   uint32_t i, j, k;
   (void)nk;
   ijk_of(ni, nj, v, &i, &j, &k);
-  hopvec(n, (int)(k & 1u), &out[0], &out[1], &out[2]);
+  if (lattice == ORC_LATTICE_FCC) hopvec_fcc(n, &out[0], &out[1], &out[2]);
+  else hopvec(n, (int)(k & 1u), &out[0], &out[1], &out[2]);
+}
+
+void orc_hop_vector(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
+                    int32_t out[3]) {
+  orc_hop_vector_l(ni, nj, nk, v, n, ORC_LATTICE_HCP, out);
+}
+
+/* HCP: x = r(2i + s), y = (r/sqrt3)(3j + p), z = 2 sqrt(2/3) r k with
+ * s = (j+k)&1, p = k&1 (ABAB).  FCC: the same with p -> q = k mod 3 and
+ * s = (j+q)&1 (ABC: layer q shifted by q (r, r/sqrt3), reduced into the box). */
+void orc_position_l(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, double rv, int lattice,
+                    double out[3]) {
+  uint32_t i, j, k;
+  (void)nk;
+  ijk_of(ni, nj, v, &i, &j, &k);
+  uint32_t p = lattice == ORC_LATTICE_FCC ? k % 3u : (k & 1u);
+  double s = (double)((j + p) & 1u);
+  out[0] = rv * (2.0 * i + s);
+  out[1] = rv / sqrt(3.0) * (3.0 * j + (double)p);
+  out[2] = 2.0 * sqrt(2.0 / 3.0) * rv * k;
 }
 
 void orc_position(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, double rv,
                   double out[3]) {
-  uint32_t i, j, k;
-  (void)nk;
-  ijk_of(ni, nj, v, &i, &j, &k);
-  double s = (double)((j + k) & 1u), p = (double)(k & 1u);
-  out[0] = rv * (2.0 * i + s);
-  out[1] = rv / sqrt(3.0) * (3.0 * j + p);
-  out[2] = 2.0 * sqrt(2.0 / 3.0) * rv * k;
+  orc_position_l(ni, nj, nk, v, rv, ORC_LATTICE_HCP, out);
 }
 
-/* Colour classes for the coloured stage schedule: c = 8(k&1) + 4(j&1) +
- * ((i - j + k) mod 4).  Same-colour voxels are >= 3 hops apart when every
- * dimension is a multiple of 4, so their closed neighbourhoods are disjoint. */
-int orc_colour(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v) {
+/* stage colour: voxels of one colour are >= 3 hops apart.  HCP (16):
+ * 8(k&1) + 4(j&1) + ((i - j + k) mod 4).  FCC (24):
+ * 4(2(k mod 3) + (j&1)) + ((i + j) mod 4) (found by search, checked by the
+ * tests on the neighbour graph). */
+int orc_colour_l(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int lattice) {
   uint32_t i, j, k;
   (void)nk;
   ijk_of(ni, nj, v, &i, &j, &k);
+  if (lattice == ORC_LATTICE_FCC)
+    return (int)(4u * (2u * (k % 3u) + (j & 1u)) + ((i + j) & 3u));
   int64_t m = ((int64_t)i - (int64_t)j + (int64_t)k) % 4;
   if (m < 0) m += 4;
   return (int)(8 * (k & 1u) + 4 * (j & 1u) + (uint32_t)m);
 }
 
-/* Per-event random order of the 16 colour stages (the paper visits its
- * sub-volumes in random order, 2.5): Fisher-Yates, slot i (15 down to 1)
- * swaps with floor(r * (i+1) / 2^32), r taken in sequence from the words of
- * Philox(seed; event, 0xFFFFFFFF, PHASE_STAGE, block 0..3). */
-void orc_stage_order(uint64_t seed, uint64_t event, uint8_t out[16]) {
-  uint32_t words[16];
-  for (uint32_t b = 0; b < 4; b++)
-    draw4(seed, (uint32_t)event, 0xFFFFFFFFu, ORC_PHASE_STAGE, b, &words[4 * b]);
-  for (int c = 0; c < 16; c++) out[c] = (uint8_t)c;
+int orc_colour(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v) {
+  return orc_colour_l(ni, nj, nk, v, ORC_LATTICE_HCP);
+}
+
+int orc_n_colours(int lattice) { return lattice == ORC_LATTICE_FCC ? 24 : 16; }
+
+/* stage order of an event: Fisher-Yates over n colours, slot i = n-1..1
+ * swapping with j = floor(w (i + 1) / 2^32), words from blocks 0, 1, ... of
+ * Philox(seed; event, 0xFFFFFFFF, PHASE_STAGE) */
+void orc_stage_order_n(uint64_t seed, uint64_t event, int n, uint8_t *out) {
+  uint32_t words[ORC_MAX_COLOURS];
+  for (int b = 0; 4 * b < n; b++)
+    draw4(seed, (uint32_t)event, 0xFFFFFFFFu, ORC_PHASE_STAGE, (uint32_t)b, &words[4 * b]);
+  for (int c = 0; c < n; c++) out[c] = (uint8_t)c;
   int w = 0;
-  for (int i = 15; i >= 1; i--) {
+  for (int i = n - 1; i >= 1; i--) {
     uint32_t j = scale32(words[w++], (uint32_t)(i + 1));
     uint8_t t = out[i];
     out[i] = out[j];
     out[j] = t;
   }
+}
+
+void orc_stage_order(uint64_t seed, uint64_t event, uint8_t out[16]) {
+  orc_stage_order_n(seed, event, 16, out);
 }
 
 /* probability -> 32-bit threshold: an event of probability p happens iff a
@@ -268,6 +333,8 @@ struct orc_sim {
   uint32_t ni, nj, nk;
   uint64_t nv;
   int boundary;       /* ORC_BOUNDARY_PERIODIC or ORC_BOUNDARY_REFLECT */
+  int lattice;        /* ORC_LATTICE_HCP or ORC_LATTICE_FCC */
+  int n_col;          /* stage colours: 16 (HCP) or 24 (FCC) */
   double rv;
   uint64_t seed;
 
@@ -405,6 +472,7 @@ orc_sim *orc_create(uint32_t ni, uint32_t nj, uint32_t nk, double rv, uint64_t s
   }
   for (int a = 0; a < MAX_SPECIES; a++)
     for (int b = 0; b < MAX_SPECIES; b++) s->pair_rx[a][b] = -1;
+  s->n_col = 16;
   return s;
 }
 
@@ -415,6 +483,14 @@ void orc_destroy(orc_sim *s) {
   free(s->id); free(s->vox); free(s->sp); free(s->alive);
   free(s->dx); free(s->dy); free(s->dz);
   free(s);
+}
+
+int orc_set_lattice(orc_sim *s, int lattice) {
+  if (lattice != ORC_LATTICE_HCP && lattice != ORC_LATTICE_FCC) return -1;
+  if (lattice == ORC_LATTICE_FCC && s->nk % 12) return -1;  /* stacking x colour period */
+  s->lattice = lattice;
+  s->n_col = orc_n_colours(lattice);
+  return 0;
 }
 
 int orc_set_boundary(orc_sim *s, int boundary) {
@@ -560,7 +636,7 @@ static int pick_vacant(const orc_sim *s, uint32_t v, int n_extra,
   uint32_t cand[12];
   int nc = 0;
   for (int n = 0; n < 12; n++) {
-    uint32_t t = orc_neighbour_b(s->ni, s->nj, s->nk, v, n, s->boundary);
+    uint32_t t = orc_neighbour_l(s->ni, s->nj, s->nk, v, n, s->lattice, s->boundary);
     if (t != ORC_OUTSIDE && s->occ[t] == 0) cand[nc++] = t;
   }
   if (nc < n_extra) return -1;
@@ -649,28 +725,29 @@ static void placement_words(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t ph
  * inside each bucket; `want` selects species */
 typedef struct {
   uint32_t *slots;
-  uint64_t start[17];
+  uint64_t start[ORC_MAX_COLOURS + 1];
 } buckets;
 
 static int bucket_by_colour(const orc_sim *s, const uint8_t *want, buckets *b) {
-  uint64_t count[16] = {0};
+  uint64_t count[ORC_MAX_COLOURS] = {0};
+  const int nc = s->n_col;
   for (uint64_t q = 0; q < s->n_slots; q++)
     if (s->alive[q] && want[s->sp[q]])
-      count[orc_colour(s->ni, s->nj, s->nk, s->vox[q])]++;
+      count[orc_colour_l(s->ni, s->nj, s->nk, s->vox[q], s->lattice)]++;
   b->start[0] = 0;
-  for (int c = 0; c < 16; c++) b->start[c + 1] = b->start[c] + count[c];
-  b->slots = malloc((b->start[16] + 1) * sizeof *b->slots);
+  for (int c = 0; c < nc; c++) b->start[c + 1] = b->start[c] + count[c];
+  b->slots = malloc((b->start[nc] + 1) * sizeof *b->slots);
   if (!b->slots) return -1;
-  uint64_t fill[16];
-  for (int c = 0; c < 16; c++) fill[c] = b->start[c];
+  uint64_t fill[ORC_MAX_COLOURS];
+  for (int c = 0; c < nc; c++) fill[c] = b->start[c];
   for (uint64_t q = 0; q < s->n_slots; q++)
     if (s->alive[q] && want[s->sp[q]])
-      b->slots[fill[orc_colour(s->ni, s->nj, s->nk, s->vox[q])]++] = (uint32_t)q;
+      b->slots[fill[orc_colour_l(s->ni, s->nj, s->nk, s->vox[q], s->lattice)]++] = (uint32_t)q;
   return 0;
 }
 
 /* ---- first-order pass, per-molecule law in stage order (mode C) ---------- */
-static int first_order_coloured(orc_sim *s, double dt, const uint8_t order[16],
+static int first_order_coloured(orc_sim *s, double dt, const uint8_t *order,
                                 int reverse) {
   uint8_t want[MAX_SPECIES] = {0};
   int any = 0;
@@ -682,11 +759,11 @@ static int first_order_coloured(orc_sim *s, double dt, const uint8_t order[16],
     if (s->n_first[a]) first_thresholds(s, a, dt, C[a]);
   buckets b;
   if (bucket_by_colour(s, want, &b)) return -1;
-  uint64_t n_part = b.start[16];
+  uint64_t n_part = b.start[s->n_col];
   birth *births = malloc((n_part * MAX_PROD + 1) * sizeof *births);
   if (!births) { free(b.slots); return -1; }
   uint64_t n_births = 0;
-  for (int g = 0; g < 16; g++) {
+  for (int g = 0; g < s->n_col; g++) {
     int c = order[g];
     uint64_t lo = b.start[c], hi = b.start[c + 1];
     for (uint64_t z = 0; z < hi - lo; z++) {
@@ -823,12 +900,12 @@ static void attempt(orc_sim *s, uint32_t slot, int dir, int fire_forced,
   uint32_t a = s->vox[slot];
   uint16_t A = s->sp[slot];
   s->cnt[ORC_CNT_ATTEMPTS]++;
-  uint32_t t = orc_neighbour_b(s->ni, s->nj, s->nk, a, dir, s->boundary);
+  uint32_t t = orc_neighbour_l(s->ni, s->nj, s->nk, a, dir, s->lattice, s->boundary);
   if (t == ORC_OUTSIDE) return;  /* a wall: the molecule stays, no collision */
   if (s->occ[t] == 0) {
     /* vacant: the molecule hops and carries its unwrapped displacement */
     int32_t hv[3];
-    orc_hop_vector(s->ni, s->nj, s->nk, a, dir, hv);
+    orc_hop_vector_l(s->ni, s->nj, s->nk, a, dir, s->lattice, hv);
     s->occ[t] = A;
     s->occ[a] = 0;
     s->vox[slot] = t;
@@ -885,7 +962,7 @@ static void attempt(orc_sim *s, uint32_t slot, int dir, int fire_forced,
 }
 
 /* ---- one walk ------------------------------------------------------------ */
-static int walk(orc_sim *s, const uint8_t due[MAX_SPECIES], const uint8_t order[16],
+static int walk(orc_sim *s, const uint8_t due[MAX_SPECIES], const uint8_t *order,
                 int mode) {
   uint8_t *reacted = calloc(s->n_slots + 1, 1);
   if (!reacted) return -1;
@@ -912,7 +989,7 @@ static int walk(orc_sim *s, const uint8_t due[MAX_SPECIES], const uint8_t order[
   } else {
     buckets b;
     if (bucket_by_colour(s, due, &b)) { free(reacted); return -1; }
-    for (int g = 0; g < 16; g++) {
+    for (int g = 0; g < s->n_col; g++) {
       int c = order[g];
       uint64_t lo = b.start[c], hi = b.start[c + 1];
       for (uint64_t z = 0; z < hi - lo; z++) {
@@ -938,8 +1015,8 @@ int orc_run(orc_sim *s, uint64_t n_events, int mode) {
     uint8_t due[MAX_SPECIES];
     if (next_event(s, &te, due)) return -1;
     double dt = te - s->t;
-    uint8_t order[16];
-    orc_stage_order(s->seed, s->event, order);
+    uint8_t order[ORC_MAX_COLOURS];
+    orc_stage_order_n(s->seed, s->event, s->n_col, order);
     int rc;
     if (mode == ORC_MODE_S) rc = first_order_ssa(s, dt);
     else rc = first_order_coloured(s, dt, order, mode == ORC_MODE_C_REV);

@@ -22,6 +22,8 @@
  *   - periodic boxes, or boxes closed by walls: a move into another
  *     compartment fails like a move into an occupied voxel (2.3); the space
  *     beyond a face of a closed box is read as such a compartment
+ *   - the face-centred cubic lattice (ABC stacking of the same close-packed
+ *     layers; 2.1 names both close packings)
  *
  * Two processing orders are provided:
  *   ORC_MODE_C     coloured stages: each event's molecules are processed by the
@@ -57,6 +59,12 @@ enum { ORC_MODE_C = 0, ORC_MODE_S = 1, ORC_MODE_C_REV = 2 };
 enum { ORC_BOUNDARY_PERIODIC = 0, ORC_BOUNDARY_REFLECT = 1 };
 #define ORC_OUTSIDE 0xFFFFFFFFu
 
+/* lattice: hexagonal close packed (ABAB stacking, the default, 16 stage
+ * colours) or face-centred cubic (ABC stacking in the same twisted
+ * coordinates, 24 stage colours; the k edge a multiple of 12) */
+enum { ORC_LATTICE_HCP = 0, ORC_LATTICE_FCC = 1 };
+#define ORC_MAX_COLOURS 24
+
 /* Philox counter "phase" word values */
 enum { ORC_PHASE_WALK = 0, ORC_PHASE_FIRST = 1, ORC_PHASE_STAGE = 2,
        ORC_PHASE_PLACE = 3, ORC_PHASE_SSA = 4 };
@@ -74,6 +82,17 @@ uint32_t orc_neighbour(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n)
 /* as orc_neighbour for either boundary; ORC_OUTSIDE beyond a wall */
 uint32_t orc_neighbour_b(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
                          int boundary);
+/* the general forms, for either lattice */
+uint32_t orc_neighbour_l(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
+                         int lattice, int boundary);
+void orc_hop_vector_l(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n, int lattice,
+                      int32_t out[3]);
+void orc_position_l(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, double rv, int lattice,
+                    double out[3]);
+int orc_colour_l(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int lattice);
+int orc_n_colours(int lattice);
+/* a uniform permutation of 0..n-1 (n <= ORC_MAX_COLOURS) for an event */
+void orc_stage_order_n(uint64_t seed, uint64_t event, int n, uint8_t *out);
 /* out[12 v + n] = orc_neighbour(v, n) for every voxel */
 void orc_neighbour_table(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t *out);
 void orc_hop_vector(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
@@ -92,6 +111,8 @@ orc_sim *orc_create(uint32_t ni, uint32_t nj, uint32_t nk, double rv,
 void orc_destroy(orc_sim *s);
 /* ORC_BOUNDARY_PERIODIC (default) or ORC_BOUNDARY_REFLECT; 0 on success */
 int orc_set_boundary(orc_sim *s, int boundary);
+/* ORC_LATTICE_HCP (default) or ORC_LATTICE_FCC (nk % 12 == 0); 0 on success */
+int orc_set_lattice(orc_sim *s, int lattice);
 /* returns the new species id (1, 2, ...) or -1 */
 int orc_add_species(orc_sim *s, double D);
 /* returns the new reaction id (0, 1, ...) or -1.  First order: 0..11

@@ -1,7 +1,8 @@
 """Benchmark of the lattice walk on one MI355X.
 
 One step = one diffusion event of the whole hot path (first-order pass, the 16
-colour stages of the walk with collision reactions, re-binning, flag sweep)
+colour stages of the walk -- 24 on the FCC lattice -- with collision reactions,
+re-binning, flag sweep)
 over the workload's lattice.  Default workload: the 2^32-voxel MAPK-style
 lattice (2048 x 2048 x 1024, 0.3 % occupancy, 10 species, 8 second-order and
 10 first-order reactions), inputs resident in HBM before timing starts.
@@ -77,7 +78,9 @@ def cpu_baseline(w: dict, events: int) -> dict:
     """the oracle (coloured-stage mode, single thread) on the first events of
     the same workload; setup excluded from the timing"""
     import oracle
-    o = oracle.Oracle(w["dims"], w["rv"], w["seed"])
+    o = oracle.Oracle(w["dims"], w["rv"], w["seed"],
+                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC,
+                      lattice=oracle.FCC if w.get("lattice") == "fcc" else oracle.HCP)
     for _, D in w["species"]:
         o.add_species(D)
     for r, p, k in w["reactions"]:
@@ -220,6 +223,8 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=40)
     ap.add_argument("--walls", action="store_true",
                     help="close the workload's box by walls instead of wrapping it")
+    ap.add_argument("--fcc", action="store_true",
+                    help="the workload on the FCC lattice (nk rounded down to a multiple of 12)")
     ap.add_argument("--cpu-events", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
@@ -253,6 +258,11 @@ def main():
         return
 
     w = pick_workload(args.workload)
+    if args.fcc:
+        ni, nj, nk = (int(x) for x in w["dims"])
+        nk12 = 12 * (nk // 12)
+        w = dict(w, lattice="fcc", dims=(ni, nj, nk12),
+                 name=w["name"].replace("x%d" % nk, "x%d" % nk12) + "_fcc")
     if args.walls:
         w = dict(w, boundary="walls", name=w["name"] + "_walls")
     nv = int(w["dims"][0]) * int(w["dims"][1]) * int(w["dims"][2])
@@ -312,6 +322,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "voxels": nv, "molecules": placed,
                    "boundary": w.get("boundary", "periodic"),
+                   "lattice": w.get("lattice", "hcp"),
                    "species": len(w["species"]), "reactions": len(w["reactions"]),
                    "step": "one diffusion event", "hop_fraction": hops / max(attempts, 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

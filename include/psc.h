@@ -28,8 +28,9 @@
  *     are independent.
  *   - Lattice dimensions must each be >= 4 and a multiple of 4 (the paper
  *     requires even counts, 2.1; multiples of 4 make the 16-colour stage
- *     schedule conflict-free on the periodic lattice).  ni*nj*nk <= 2^32.
- *   - Boundaries are periodic.
+ *     schedule conflict-free on the periodic lattice; the FCC lattice also
+ *     needs nk a multiple of 12).  ni*nj*nk <= 2^32.
+ *   - Boundaries are periodic unless PSC_BOUNDARY_WALLS closes the box.
  */
 #ifndef PSC_H
 #define PSC_H
@@ -67,6 +68,15 @@ typedef int32_t psc_status;
 #define PSC_LAYOUT_LINEAR 2u      /* keep the occupancy in linear order on the
                                      device instead of 4x4x4 bricks (a 128-byte
                                      line each); results are identical */
+#define PSC_LATTICE_FCC 8u        /* face-centred cubic lattice instead of HCP:
+                                     the same close-packed layers and twisted
+                                     Cartesian coordinates (2.1), stacked ABC
+                                     instead of ABAB, so the layer phase is
+                                     k mod 3.  Voxel centres, neighbour rows and
+                                     displacement units are as for HCP with that
+                                     phase; the walk runs 24 colour stages
+                                     instead of 16.  nk must be a multiple of
+                                     12. */
 
 /* Device memory allocator hooks.  alloc returns a device pointer of at least
  * `bytes` bytes usable on `stream` (or NULL on failure); free releases it.
@@ -83,7 +93,7 @@ typedef struct psc_lattice_desc {
   uint64_t seed;           /* key of every random draw of this lattice */
   uint64_t max_molecules;  /* capacity: live molecules at any time */
   uint32_t flags;          /* PSC_TRACK_DISPLACEMENT | PSC_LAYOUT_LINEAR |
-                              PSC_BOUNDARY_WALLS */
+                              PSC_BOUNDARY_WALLS | PSC_LATTICE_FCC */
   int32_t device;          /* HIP device ordinal */
   psc_alloc_fn alloc;      /* optional allocator hooks (both or neither) */
   psc_free_fn free;
@@ -271,8 +281,9 @@ psc_status psc_get_kernel_times(psc_lattice *h, psc_kernel_times *out);
 /* ---- ensembles ---------------------------------------------------------------
  * Many independent lattices (replicates of one model, or different models of
  * any sizes) advanced together: every event of every member is one batched
- * launch sequence (first-order pass of all members, the 16 colour stages of
- * all members as one work list each, event end), captured once as a HIP
+ * launch sequence (first-order pass of all members, the colour stages of
+ * all members as one work list each -- 16, or 24 when a member is FCC, where
+ * an HCP member's extra stages are empty -- event end), captured once as a HIP
  * graph and replayed.  Each member's result is bit-identical to stepping it
  * alone: the members share no state and every draw is keyed by the member's
  * own seed, event and molecule ids. */

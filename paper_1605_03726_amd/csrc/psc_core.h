@@ -1,6 +1,7 @@
 // psc_core.h -- definitions shared by the host core and the gfx950 kernels of
-// libpsc: the device-side lattice record, the counter-based generator, the HCP
-// stencil in twisted Cartesian coordinates and division by invariant integers.
+// libpsc: the device-side lattice record, the counter-based generator, the
+// stencils of the two close packings (HCP, FCC) in twisted Cartesian
+// coordinates and division by invariant integers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,7 +18,8 @@ constexpr uint16_t kSpeciesMask = 0x7FFF;
 constexpr uint16_t kReactedFlag = 0x8000;
 
 constexpr uint32_t kDeadId = 0xFFFFFFFFu;   // entry of a molecule that died
-constexpr int kColours = 16;
+// stage colours: 16 on the HCP lattice, 24 on the FCC lattice
+constexpr int kColoursHcp = 16, kColoursFcc = 24, kMaxColours = 24;
 constexpr int kMaxSpecies = 63;
 constexpr int kMaxProducts = 11;
 
@@ -96,16 +98,13 @@ __host__ __device__ inline uint32_t divu(uint32_t n, const DivU32 &q) {
 }
 
 // ---- geometry -----------------------------------------------------------------
-// Voxel (i, j, k), v = i + ni (j + nj k); s = (j + k) & 1, p = k & 1.  The 12
-// neighbours n = 0..11 as (di, dj, dk):
-//   0:(+1,0,0) 1:(-1,0,0) 2:(s,+1,0) 3:(s-1,+1,0) 4:(s,-1,0) 5:(s-1,-1,0)
-//   6:(s,0,+1) 7:(s-1,0,+1) 8:(0,2p-1,+1) 9:(s,0,-1) 10:(s-1,0,-1)
-//   11:(0,2p-1,-1)
-// and the hop vector (X in r, Y in r/sqrt3, Z in 2 sqrt(2/3) r):
-//   X = 2,-2,1,-1,1,-1,1,-1,0,1,-1,0   Z = 0,0,0,0,0,0,1,1,1,-1,-1,-1
-//   Y = 0,0,3,3,-3,-3,c,c,d,c,c,d  with c = 1-2p, d = 4p-2.
-// Tables are bit-packed so that lanes taking different directions do not
-// diverge.
+// Voxel (i, j, k), v = i + ni (j + nj k).  Rows of close-packed voxels along
+// i, rows of a layer shifted by half a voxel in turn along j, layers along k
+// (2.1): the voxel centre is x = r (2i + s), y = (r / sqrt3)(3j + p),
+// z = 2 sqrt(2/3) r k with the layer phase p = k & 1 (HCP, ABAB stacking) or
+// p = k mod 3 (FCC, ABC stacking) and s = (j + p) & 1.  The stencils and hop
+// vectors below follow from these positions; tables are bit-packed so that
+// lanes taking different directions do not diverge.
 // Memory layout of the occupancy words.  Linear: v = i + ni (j + nj k).
 // Brick: the lattice is cut into 4 x 4 x 4 bricks of 64 words (one 128-byte
 // cache line each), bricks in linear order, voxels inside a brick in linear
@@ -118,6 +117,7 @@ struct Geo {
   DivU32 dni, dnj;
   uint32_t brick;       // 1: brick layout
   uint32_t walls;       // 1: the box is closed by walls (no periodic wrap)
+  uint32_t fcc;         // 1: face-centred cubic lattice (ABC stacking), 0: HCP
   uint32_t nbi, nbj;    // bricks along i and j
   DivU32 dnbi, dnbj;
 };
@@ -150,11 +150,6 @@ __host__ __device__ inline uint32_t linear_of(const Geo &g, const Coord &c) {
   return (uint32_t)c.i + g.ni * ((uint32_t)c.j + g.nj * (uint32_t)c.k);
 }
 
-__host__ __device__ inline uint32_t colour_of(const Coord &c) {
-  return 8u * (uint32_t)(c.k & 1) + 4u * (uint32_t)(c.j & 1) +
-         (uint32_t)((c.i + 3 * c.j + c.k) & 3);
-}
-
 __host__ __device__ inline uint32_t index_of(const Geo &g, const Coord &c) {
   if (g.brick) {
     const uint32_t ib = (uint32_t)c.i >> 2, jb = (uint32_t)c.j >> 2, kb = (uint32_t)c.k >> 2;
@@ -180,9 +175,49 @@ __host__ __device__ inline uint32_t to_linear(const Geo &g, uint32_t u) {
   return g.brick ? linear_of(g, coord_of(g, u)) : u;
 }
 
-// target coordinate of hop n from c (periodic)
-__host__ __device__ inline Coord step_coord(const Geo &g, const Coord &c, uint32_t n) {
-  const int32_t s = (c.j + c.k) & 1, p = c.k & 1;
+// Stage colour of a voxel: voxels of one colour are >= 3 hops apart.
+//   HCP (16): 8 (k & 1) + 4 (j & 1) + ((i - j + k) mod 4)
+//   FCC (24): 4 (2 (k mod 3) + (j & 1)) + ((i + j) mod 4)
+// LAT: 0 HCP, 1 FCC
+template <int LAT>
+__host__ __device__ inline uint32_t colour_t(const Coord &c) {
+  if (LAT)
+    return 4u * (2u * ((uint32_t)c.k % 3u) + (uint32_t)(c.j & 1)) + (uint32_t)((c.i + c.j) & 3);
+  return 8u * (uint32_t)(c.k & 1) + 4u * (uint32_t)(c.j & 1) +
+         (uint32_t)((c.i + 3 * c.j + c.k) & 3);
+}
+
+__host__ __device__ inline uint32_t colour_of(const Geo &g, const Coord &c) {
+  return g.fcc ? colour_t<1>(c) : colour_t<0>(c);
+}
+
+__host__ __device__ inline uint32_t n_colours(const Geo &g) {
+  return g.fcc ? (uint32_t)kColoursFcc : (uint32_t)kColoursHcp;
+}
+
+// Target coordinate of hop n from c (periodic).  Rows 0..7, 9, 10 are shared
+// by both lattices with the in-row offset s: 0:(+1,0,0) 1:(-1,0,0) 2:(s,+1,0)
+// 3:(s-1,+1,0) 4:(s,-1,0) 5:(s-1,-1,0) 6:(s,a,+1) 7:(s-1,a,+1) 9:(s,b,-1)
+// 10:(s-1,b,-1), and rows 8:(0,c,+1), 11:(0,d,-1).
+//   HCP (ABAB, p = k & 1): s = (j + k) & 1, a = b = 0, c = d = 2p - 1.
+//   FCC (ABC, q = k mod 3): s = (j + q) & 1; a = 0, c = -1 for q < 2 and
+//   a = 1, c = 0 for q = 2; b = 0, d = 1 for q > 0 and b = -1, d = 0 for
+//   q = 0 (the layer above is shifted by (r, r/sqrt3) in the plane, the one
+//   below by the opposite).
+template <int LAT>
+__host__ __device__ inline Coord step_coord_t(const Geo &g, const Coord &c, uint32_t n) {
+  int32_t s, a = 0, b = 0, cu, dd;
+  if (LAT) {
+    const int32_t q = (int32_t)((uint32_t)c.k % 3u);
+    s = (c.j + q) & 1;
+    a = q == 2 ? 1 : 0;
+    cu = q == 2 ? 0 : -1;
+    b = q == 0 ? -1 : 0;
+    dd = q == 0 ? 0 : 1;
+  } else {
+    s = (c.j + c.k) & 1;
+    cu = dd = 2 * (c.k & 1) - 1;
+  }
   // rows 2..7, 9, 10 have di = s (even rows of each pair) or s - 1 (rows
   // 3, 5, 7, 10); rows 0, 1 have di = +1, -1; rows 8, 11 have di = 0
   constexpr uint32_t kUsesS = 0x6FCu, kMinusOne = 0x4A8u;
@@ -194,7 +229,10 @@ __host__ __device__ inline Coord step_coord(const Geo &g, const Coord &c, uint32
   int32_t dj = 0;
   if (n == 2 || n == 3) dj = 1;
   else if (n == 4 || n == 5) dj = -1;
-  else if (n == 8 || n == 11) dj = 2 * p - 1;
+  else if (n == 8) dj = cu;
+  else if (n == 11) dj = dd;
+  else if (LAT && (n == 6 || n == 7)) dj = a;
+  else if (LAT && (n == 9 || n == 10)) dj = b;
   const int32_t dk = (n >= 6 && n <= 8) ? 1 : (n >= 9 ? -1 : 0);
   Coord t;
   t.i = c.i + di;
@@ -209,27 +247,48 @@ __host__ __device__ inline Coord step_coord(const Geo &g, const Coord &c, uint32
   return t;
 }
 
+__host__ __device__ inline Coord step_coord(const Geo &g, const Coord &c, uint32_t n) {
+  return g.fcc ? step_coord_t<1>(g, c, n) : step_coord_t<0>(g, c, n);
+}
+
 // target of hop n from c in the lattice's box: false if a wall closes the box
 // there (t is then the periodic image, a valid voxel that must not be used)
-__host__ __device__ inline bool step_target(const Geo &g, const Coord &c, uint32_t n, Coord &t) {
-  t = step_coord(g, c, n);
+template <int LAT>
+__host__ __device__ inline bool step_target_t(const Geo &g, const Coord &c, uint32_t n, Coord &t) {
+  t = step_coord_t<LAT>(g, c, n);
   if (!g.walls) return true;
+  // every hop moves each coordinate by at most 1, and the edges are >= 4:
   // wrapping moved exactly the coordinates that left the box
   const int32_t di = t.i - c.i, dj = t.j - c.j, dk = t.k - c.k;
   return di >= -1 && di <= 1 && dj >= -1 && dj <= 1 && dk >= -1 && dk <= 1;
 }
 
-__host__ __device__ inline void hop_vector(uint32_t n, int32_t p, int32_t &X, int32_t &Y,
-                                           int32_t &Z) {
+__host__ __device__ inline bool step_target(const Geo &g, const Coord &c, uint32_t n, Coord &t) {
+  return g.fcc ? step_target_t<1>(g, c, n, t) : step_target_t<0>(g, c, n, t);
+}
+
+// Hop vector of row n (X in r, Y in r/sqrt3, Z in 2 sqrt(2/3) r):
+//   X = 2,-2,1,-1,1,-1,1,-1,0,1,-1,0   Z = 0,0,0,0,0,0,1,1,1,-1,-1,-1
+//   HCP: Y = 0,0,3,3,-3,-3,c,c,d,c,c,d  with c = 1-2p, d = 4p-2 (p = k & 1)
+//   FCC: Y = 0,0,3,3,-3,-3,1,1,-2,-1,-1,2 (a Bravais lattice: no phase)
+template <int LAT>
+__host__ __device__ inline void hop_vector_t(uint32_t n, int32_t p, int32_t &X, int32_t &Y,
+                                             int32_t &Z) {
   // X + 2 packed 4 bits per row: 4,0,3,1,3,1,3,1,2,3,1,2
   constexpr uint64_t kX = 0x213213131304ull;
   X = (int32_t)((kX >> (4 * n)) & 0xFu) - 2;
-  const int32_t c = 1 - 2 * p, d = 4 * p - 2;
-  if (n < 2) Y = 0;
-  else if (n < 4) Y = 3;
-  else if (n < 6) Y = -3;
-  else if (n == 8 || n == 11) Y = d;
-  else Y = c;
+  if (LAT) {
+    // Y + 3 packed 4 bits per row: 3,3,6,6,0,0,4,4,1,2,2,5
+    constexpr uint64_t kY = 0x522144006633ull;
+    Y = (int32_t)((kY >> (4 * n)) & 0xFu) - 3;
+  } else {
+    const int32_t c = 1 - 2 * p, d = 4 * p - 2;
+    if (n < 2) Y = 0;
+    else if (n < 4) Y = 3;
+    else if (n < 6) Y = -3;
+    else if (n == 8 || n == 11) Y = d;
+    else Y = c;
+  }
   Z = (n >= 6 && n <= 8) ? 1 : (n >= 9 ? -1 : 0);
 }
 
@@ -239,11 +298,11 @@ __host__ __device__ inline void hop_vector(uint32_t n, int32_t p, int32_t &X, in
 // every surviving molecule to bins[(e + 1) & 1] under its new colour.  The
 // order inside a bin carries no meaning: same-colour updates commute.
 struct Bins {
-  uint32_t *vox;    // [16 * cap]
-  uint32_t *id;     // [16 * cap]
-  uint16_t *sp;     // [16 * cap] species when the entry was last written
-  int32_t *disp;    // [3 * 16 * cap] (dx | dy | dz planes) or nullptr
-  uint32_t *count;  // [16]
+  uint32_t *vox;    // [ncol * cap]
+  uint32_t *id;     // [ncol * cap]
+  uint16_t *sp;     // [ncol * cap] species when the entry was last written
+  int32_t *disp;    // [3 * ncol * cap] (dx | dy | dz planes) or nullptr
+  uint32_t *count;  // [24] (entries past ncol stay zero)
 };
 
 // Voxels where a collision put a product on the partner's voxel are marked
@@ -334,8 +393,10 @@ struct LatDev {
   // event state
   uint64_t stop_event;             // the lattice idles once ev reaches it
   uint64_t *ev;                    // events completed
-  uint32_t *perm;                  // [16] stage order of the running event
-  uint4 *sdesc;                    // [16] per stage: colour, count, event (lo, hi)
+  uint32_t ncol;                   // stage colours of the lattice (16 or 24)
+  uint32_t *perm;                  // [24] stage order of the running event
+  uint4 *sdesc;                    // [24] per stage: colour, count, event (lo, hi);
+                                   // stages past ncol are empty
   uint32_t *next_id;
   unsigned long long *cnt;         // attempts, hops, collisions, placement failures
   unsigned long long *sp_count;    // [64] live molecules per species (two's complement deltas)
@@ -345,10 +406,14 @@ struct LatDev {
 
 hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
 // disp: the lattice tracks displacements (its bins carry the planes)
-hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, hipStream_t s);
-hipError_t launch_event_multi(const LatDev *lats, uint32_t R, int grid, int items, hipStream_t s);
+// fcc: the lattice is face-centred cubic (24 stages), else HCP (16)
+hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
+                        hipStream_t s);
+// stages: the most stages of any member (16, or 24 with an FCC member)
+hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
+                              int items, hipStream_t s);
 hipError_t launch_begin(const LatDev *dL, hipStream_t s);
-hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp,
+hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp, bool fcc,
                         hipStream_t s);
 uint32_t max_members();
 hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t s);

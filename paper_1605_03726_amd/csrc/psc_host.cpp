@@ -264,7 +264,8 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   for (auto &d : h->st_d) d.clear();
   const uint64_t nmol = h->mid.size();
   std::vector<uint8_t> colour(nmol);
-  uint64_t bin_count[16] = {0};
+  const uint32_t ncol = n_colours(h->geo);
+  uint64_t bin_count[kMaxColours] = {0};
   std::vector<uint64_t> walkers;
   walkers.reserve(nmol);
   for (uint64_t q = 0; q < nmol; ++q) {
@@ -277,7 +278,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
       h->st_d[2].push_back(h->mdz[q]);
       continue;
     }
-    colour[q] = (uint8_t)colour_of(coord_of(lin_geo, h->mvox[q]));
+    colour[q] = (uint8_t)colour_of(lin_geo, coord_of(lin_geo, h->mvox[q]));
     bin_count[colour[q]]++;
     walkers.push_back(q);
   }
@@ -293,12 +294,13 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.key1 = (uint32_t)(h->desc.seed >> 32);
   L.occ = alloc_n<uint16_t>(h, h->nv);
   L.cap = cap;
+  L.ncol = ncol;
   for (int b = 0; b < 2; ++b) {
-    L.bins[b].vox = alloc_n<uint32_t>(h, 16 * cap);
-    L.bins[b].id = alloc_n<uint32_t>(h, 16 * cap);
-    L.bins[b].sp = alloc_n<uint16_t>(h, 16 * cap);
-    L.bins[b].disp = disp ? alloc_n<int32_t>(h, 3 * 16 * cap) : nullptr;
-    L.bins[b].count = alloc_n<uint32_t>(h, 16);
+    L.bins[b].vox = alloc_n<uint32_t>(h, ncol * cap);
+    L.bins[b].id = alloc_n<uint32_t>(h, ncol * cap);
+    L.bins[b].sp = alloc_n<uint16_t>(h, ncol * cap);
+    L.bins[b].disp = disp ? alloc_n<int32_t>(h, 3 * ncol * cap) : nullptr;
+    L.bins[b].count = alloc_n<uint32_t>(h, kMaxColours);
     L.cand_pos[b] = alloc_n<uint32_t>(h, cap);
     L.cand_id[b] = alloc_n<uint32_t>(h, cap);
     L.cand_col[b] = alloc_n<uint8_t>(h, cap);
@@ -353,8 +355,8 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   auto *d_fo_n = alloc_n<uint8_t>(h, 64);
   auto *d_fo_rx = alloc_n<uint16_t>(h, std::max<size_t>(h->fo_rx.size(), 1));
   L.ev = alloc_n<uint64_t>(h, 1);
-  L.perm = alloc_n<uint32_t>(h, 16);
-  L.sdesc = alloc_n<uint4>(h, 16);
+  L.perm = alloc_n<uint32_t>(h, kMaxColours);
+  L.sdesc = alloc_n<uint4>(h, kMaxColours);
   L.next_id = alloc_n<uint32_t>(h, 1);
   L.cnt = alloc_n<unsigned long long>(h, 4);
   L.sp_count = alloc_n<unsigned long long>(h, 64);
@@ -408,10 +410,10 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
     std::vector<uint32_t> vox(walkers.size()), id(walkers.size());
     std::vector<uint16_t> spc(walkers.size());
     std::vector<int32_t> d3(disp ? 3 * walkers.size() : 0);
-    uint64_t start[17] = {0};
-    for (int c = 0; c < 16; ++c) start[c + 1] = start[c] + bin_count[c];
-    uint64_t fill[16];
-    for (int c = 0; c < 16; ++c) fill[c] = start[c];
+    uint64_t start[kMaxColours + 1] = {0};
+    for (uint32_t c = 0; c < ncol; ++c) start[c + 1] = start[c] + bin_count[c];
+    uint64_t fill[kMaxColours];
+    for (uint32_t c = 0; c < ncol; ++c) fill[c] = start[c];
     for (uint64_t q : walkers) {
       const uint64_t at = fill[colour[q]]++;
       vox[at] = to_layout(h->geo, h->mvox[q]);
@@ -423,8 +425,8 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
         d3[3 * at + 2] = h->mdz[q];
       }
     }
-    uint32_t counts[16];
-    for (int c = 0; c < 16; ++c) {
+    uint32_t counts[kMaxColours] = {0};
+    for (uint32_t c = 0; c < ncol; ++c) {
       if (bin_count[c] > cap) return fail(h, PSC_ECAPACITY, "more molecules than max_molecules");
       counts[c] = (uint32_t)bin_count[c];
       if (!bin_count[c]) continue;
@@ -435,16 +437,16 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
         std::vector<int32_t> plane(bin_count[c]);
         for (int a = 0; a < 3; ++a) {
           for (uint64_t z = 0; z < bin_count[c]; ++z) plane[z] = d3[3 * (start[c] + z) + a];
-          HIP_OK(h, up(L.bins[cur].disp + (a * 16 + c) * cap, plane.data(), bin_count[c] * 4));
+          HIP_OK(h, up(L.bins[cur].disp + (a * ncol + c) * cap, plane.data(), bin_count[c] * 4));
         }
       }
     }
     HIP_OK(h, up(L.bins[cur].count, counts, sizeof counts));
-    HIP_OK(h, hipMemset(L.bins[cur ^ 1].count, 0, 16 * sizeof(uint32_t)));
+    HIP_OK(h, hipMemset(L.bins[cur ^ 1].count, 0, kMaxColours * sizeof(uint32_t)));
   }
   HIP_OK(h, hipMemset(L.cand_count, 0, 2 * sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.flag_count, 0, 2 * sizeof(uint32_t)));
-  HIP_OK(h, hipMemset(L.sdesc, 0, 16 * sizeof(uint4)));  // empty until a first-order pass
+  HIP_OK(h, hipMemset(L.sdesc, 0, kMaxColours * sizeof(uint4)));  // empty until a first-order pass
   if (L.wb_count) HIP_OK(h, hipMemset(L.wb_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.birth_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.cnt, 0, 4 * sizeof(unsigned long long)));
@@ -469,12 +471,12 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   if (st) return st;
 
   // launch shape of the stage kernel from the molecules binned now (an
-  // average colour bin holds 1/16 of them): a stage that cannot fill the GPU
+  // average colour bin holds 1/16 of them, 1/24 on FCC): a stage that cannot fill the GPU
   // with 4-item chunks (two workgroups per CU) takes one-item chunks, one
   // per workgroup, to shorten its chain of dependent accesses; a large one
   // takes 4 items and about 1.5 passes per workgroup
   if (!h->grid_set) {
-    const uint64_t expect = std::max<uint64_t>(walkers.size() / 16, 1);
+    const uint64_t expect = std::max<uint64_t>(walkers.size() / ncol, 1);
     const uint64_t T = (uint64_t)stage_threads();
     if (!h->items_set) h->items = expect >= 512 * 4 * T ? 4 : (expect >= 512 * 2 * T ? 2 : 1);
     const uint64_t per_block = T * (uint64_t)h->items * (h->items >= 4 ? 3 : 2);
@@ -494,13 +496,13 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
 }
 
 uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool displacement,
-                               uint32_t n_reactions, bool collision_births) {
+                               uint32_t n_reactions, bool collision_births, uint32_t ncol) {
   auto r = [](uint64_t b) { return (std::max<uint64_t>(b, 16) + 255) & ~uint64_t(255); };
   const uint64_t cap = std::max<uint64_t>(max_molecules, 1);
   uint64_t t = r(voxels * 2);
   for (int b = 0; b < 2; ++b) {
-    t += r(16 * cap * 4) * 2 + r(16 * cap * 2) + r(64);
-    if (displacement) t += r(3 * 16 * cap * 4);
+    t += r(ncol * cap * 4) * 2 + r(ncol * cap * 2) + r(kMaxColours * 4);
+    if (displacement) t += r(3 * ncol * cap * 4);
     t += r(cap * 4) * 2 + r(cap);
   }
   t += r(8) + 2 * r(cap * 4) + r(8) + r(256);
@@ -565,8 +567,13 @@ psc_status psc_create_lattice(const psc_lattice_desc *desc, psc_lattice **out) {
     g_create_error = "alloc and free hooks come together";
     return PSC_EINVAL;
   }
-  if (desc->flags & ~(PSC_TRACK_DISPLACEMENT | PSC_LAYOUT_LINEAR | PSC_BOUNDARY_WALLS)) {
+  if (desc->flags &
+      ~(PSC_TRACK_DISPLACEMENT | PSC_LAYOUT_LINEAR | PSC_BOUNDARY_WALLS | PSC_LATTICE_FCC)) {
     g_create_error = "unknown flags";
+    return PSC_EINVAL;
+  }
+  if ((desc->flags & PSC_LATTICE_FCC) && nk % 12) {
+    g_create_error = "an FCC lattice needs nk a multiple of 12 (stacking period 3, bricks of 4)";
     return PSC_EINVAL;
   }
   if (desc->device < 0) {
@@ -584,6 +591,7 @@ psc_status psc_create_lattice(const psc_lattice_desc *desc, psc_lattice **out) {
   h->geo.dnj = make_div(nj);
   h->geo.brick = (desc->flags & PSC_LAYOUT_LINEAR) ? 0u : 1u;
   h->geo.walls = (desc->flags & PSC_BOUNDARY_WALLS) ? 1u : 0u;
+  h->geo.fcc = (desc->flags & PSC_LATTICE_FCC) ? 1u : 0u;
   h->geo.nbi = ni / 4;
   h->geo.nbj = nj / 4;
   h->geo.dnbi = make_div(ni / 4);
@@ -803,7 +811,8 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   }
   if (!h->timing) {
     for (uint64_t e = 0; e < n_events; ++e)
-      HIP_OK(h, launch_event(h->dL, h->grid, h->items, h->L.bins[0].disp != nullptr, stream));
+      HIP_OK(h, launch_event(h->dL, h->grid, h->items, h->L.bins[0].disp != nullptr,
+                             h->geo.fcc != 0, stream));
   } else {
     auto ev = [&](hipEvent_t *out) -> hipError_t {
       if (!h->event_pool.empty()) {
@@ -814,16 +823,17 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
       return hipEventCreate(out);
     };
     for (uint64_t e = 0; e < n_events; ++e) {
-      for (int g = -1; g <= 16; ++g) {
+      const int stages = (int)n_colours(h->geo);
+      for (int g = -1; g <= stages; ++g) {
         psc_lattice::Timed t;
-        t.kind = g < 0 ? 0 : (g < 16 ? 1 : 2);
+        t.kind = g < 0 ? 0 : (g < stages ? 1 : 2);
         HIP_OK(h, ev(&t.a));
         HIP_OK(h, ev(&t.b));
         HIP_OK(h, hipEventRecord(t.a, stream));
         if (g < 0) HIP_OK(h, launch_begin(h->dL, stream));
-        else if (g < 16)
+        else if (g < stages)
           HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, h->items,
-                                 h->L.bins[0].disp != nullptr, stream));
+                                 h->L.bins[0].disp != nullptr, h->geo.fcc != 0, stream));
         else HIP_OK(h, launch_end(h->dL, stream));
         HIP_OK(h, hipEventRecord(t.b, stream));
         h->timed.push_back(t);
@@ -858,11 +868,11 @@ psc_status psc_query_sizes(const psc_lattice *hc, uint64_t *n_voxels, uint64_t *
     } else {
       HIP_OK(h, hipSetDevice(h->desc.device));
       HIP_OK(h, hipDeviceSynchronize());
-      uint32_t counts[16];
+      uint32_t counts[kMaxColours];
       HIP_OK(h, hipMemcpy(counts, h->L.bins[h->events_done & 1].count, sizeof counts,
                           hipMemcpyDeviceToHost));
       uint64_t n = h->st_id.size();
-      for (int c = 0; c < 16; ++c) n += counts[c];
+      for (uint32_t c = 0; c < h->L.ncol; ++c) n += counts[c];
       *n_molecules = n;  // upper bound: dead entries are dropped by the walk
     }
   }
@@ -1044,12 +1054,12 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
   if (st) return st;
   const LatDev &L = h->L;
   const int cur = (int)(h->events_done & 1);
-  uint32_t counts[16];
+  uint32_t counts[kMaxColours];
   HIP_OK(h, hipMemcpy(counts, L.bins[cur].count, sizeof counts, hipMemcpyDeviceToHost));
   const bool disp = L.bins[cur].disp != nullptr;
   std::vector<uint32_t> vox, id;
   std::vector<int32_t> d3[3];
-  for (int c = 0; c < 16; ++c) {
+  for (uint32_t c = 0; c < L.ncol; ++c) {
     const uint32_t n = counts[c];
     if (!n) continue;
     const size_t at = vox.size();
@@ -1060,7 +1070,7 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
     if (disp)
       for (int a = 0; a < 3; ++a) {
         d3[a].resize(at + n);
-        HIP_OK(h, hipMemcpy(d3[a].data() + at, L.bins[cur].disp + (a * 16 + c) * L.cap, n * 4,
+        HIP_OK(h, hipMemcpy(d3[a].data() + at, L.bins[cur].disp + (a * L.ncol + c) * L.cap, n * 4,
                             hipMemcpyDeviceToHost));
       }
   }
@@ -1195,8 +1205,8 @@ psc_status ensure_graph(psc_ensemble *E) {
   }
   if (!E->cap_stream) EHIP_OK(E, hipStreamCreateWithFlags(&E->cap_stream, hipStreamNonBlocking));
   EHIP_OK(E, hipStreamBeginCapture(E->cap_stream, hipStreamCaptureModeThreadLocal));
-  const hipError_t le =
-      launch_event_multi(E->d_lats, (uint32_t)E->members.size(), E->grid, E->items, E->cap_stream);
+  const hipError_t le = launch_event_multi(E->d_lats, (uint32_t)E->members.size(), E->stages,
+                                           E->grid, E->items, E->cap_stream);
   hipGraph_t g = nullptr;
   const hipError_t ce = hipStreamEndCapture(E->cap_stream, &g);
   if (le != hipSuccess || ce != hipSuccess)
@@ -1216,8 +1226,8 @@ psc_status run_events(psc_ensemble *E, uint64_t n, hipStream_t stream) {
     for (uint64_t e = 0; e < n; ++e) EHIP_OK(E, hipGraphLaunch(E->exec, stream));
   } else {
     for (uint64_t e = 0; e < n; ++e)
-      EHIP_OK(E, launch_event_multi(E->d_lats, (uint32_t)E->members.size(), E->grid, E->items,
-                                    stream));
+      EHIP_OK(E, launch_event_multi(E->d_lats, (uint32_t)E->members.size(), E->stages, E->grid,
+                                    E->items, stream));
   }
   for (psc_lattice *h : E->members) h->events_done += n;
   return PSC_OK;
@@ -1271,8 +1281,12 @@ psc_status psc_ensemble_create(psc_lattice *const *members, uint32_t n, psc_ense
   }
   // default launch: about two passes' worth of chunks for the whole ensemble
   uint64_t mol = 0;
-  for (auto *h : E->members) mol += h->desc.max_molecules;
-  const uint64_t chunks = std::max<uint64_t>(mol / 16 / (256ull * 4), 1);
+  E->stages = 0;
+  for (auto *h : E->members) {
+    mol += h->desc.max_molecules;
+    E->stages = std::max(E->stages, n_colours(h->geo));
+  }
+  const uint64_t chunks = std::max<uint64_t>(mol / E->stages / (256ull * 4), 1);
   E->grid = (int)std::min<uint64_t>(std::max<uint64_t>(chunks, 256), 4096);
   for (auto *h : E->members) h->in_ensemble = true;
   *out = E;

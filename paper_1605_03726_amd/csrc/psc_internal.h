@@ -104,6 +104,7 @@ struct psc_ensemble {
   std::vector<uint64_t> versions;           // member record versions uploaded
   int grid = 1024;
   int items = 4;
+  uint32_t stages = 16;                     // the most stage colours of any member
   // one captured event of the batched launches, replayed per event
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -125,7 +126,8 @@ psc_status check_device_error(psc_lattice *h);
 psc_status ensure_member_records(psc_ensemble *E, hipStream_t stream, uint64_t n_events);
 psc_status ensure_graph(psc_ensemble *E);
 // device bytes a lattice with this capacity and size will hold once frozen
+// ncol: stage colours of the lattice (16 HCP, 24 FCC)
 uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool displacement,
-                               uint32_t n_reactions, bool collision_births);
+                               uint32_t n_reactions, bool collision_births, uint32_t ncol);
 
 }  // namespace psc_detail

@@ -4,7 +4,8 @@
 //   k_begin   one workgroup: the event's random stage order, the first-order
 //             reactions over the interval since the previous event (2.4.1),
 //             and id assignment + binning of their newborns;
-//   k_stage   16 launches, one per colour stage in the event's order: every
+//   k_stage   16 launches (24 on the FCC lattice), one per colour stage in the
+//             event's order: every
 //             molecule whose voxel has that colour attempts one hop (2.3) and
 //             fires a collision reaction with a registered partner (2.4.2);
 //             survivors are appended to the next event's colour bins;
@@ -25,27 +26,28 @@ constexpr int kStageThreads = 256;
 constexpr int kBeginThreads = 1024;
 
 __device__ __forceinline__ uint32_t colour_of_voxel(const Geo &g, uint32_t v) {
-  return colour_of(coord_of(g, v));
+  return colour_of(g, coord_of(g, v));
 }
 
 __device__ __forceinline__ void set_error(const LatDev &L, uint32_t bit) { atomicOr(L.error, bit); }
 
 // ---- stage order ---------------------------------------------------------------
-// Fisher-Yates over the 16 colours, slot i = 15..1 swapping with
+// Fisher-Yates over the n colours, slot i = n-1..1 swapping with
 // floor(r (i+1) / 2^32), r in sequence from the words of
-// Philox(seed; e, 0xFFFFFFFF, phase 2, block 0..3).
+// Philox(seed; e, 0xFFFFFFFF, phase 2, block 0, 1, ...).
 __device__ __forceinline__ void stage_order(const LatDev &L, uint64_t e, uint32_t *perm) {
-  uint32_t w[16];
-  for (uint32_t b = 0; b < 4; ++b) {
+  const uint32_t n = L.ncol;
+  uint32_t w[kMaxColours];
+  for (uint32_t b = 0; 4 * b < n; ++b) {
     const U4 r = philox((uint32_t)e, 0xFFFFFFFFu, kPhaseStage, b, L.key0, L.key1);
     w[4 * b + 0] = r.x;
     w[4 * b + 1] = r.y;
     w[4 * b + 2] = r.z;
     w[4 * b + 3] = r.w;
   }
-  for (uint32_t c = 0; c < 16; ++c) perm[c] = c;
+  for (uint32_t c = 0; c < n; ++c) perm[c] = c;
   int idx = 0;
-  for (int i = 15; i >= 1; --i) {
+  for (int i = (int)n - 1; i >= 1; --i) {
     const uint32_t j = scale32(w[idx++], (uint32_t)(i + 1));
     const uint32_t t = perm[i];
     perm[i] = perm[j];
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(kStageThreads) k_scan_candidates(const LatDev 
   if (cmax == 0) return;
   const Bins &in = L.bins[e & 1];
   const uint32_t cb = (uint32_t)(e & 1);
-  for (uint32_t c = 0; c < 16; ++c) {
+  for (uint32_t c = 0; c < L.ncol; ++c) {
     const uint32_t n = min(in.count[c], (uint32_t)L.cap);
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
@@ -213,7 +215,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L) {
   uint32_t *__restrict__ fire_id = L.fire_id;
   uint8_t *__restrict__ fire_col = L.fire_col;
   uint8_t *__restrict__ fire_rx = L.fire_rx;
-  __shared__ uint32_t s_perm[16], s_colcnt[16];
+  __shared__ uint32_t s_perm[kMaxColours], s_colcnt[kMaxColours];
   __shared__ uint32_t s_nfire, s_nb, s_next;
   __shared__ uint64_t s_keys[kSortLds];
   const uint64_t e = *L.ev;
@@ -232,13 +234,14 @@ __device__ __forceinline__ void begin_work(const LatDev &L) {
     s_nb = 0;
     s_next = *L.next_id;
   }
-  if (tid < 16) {
+  const uint32_t ncol = L.ncol;
+  if (tid < kMaxColours) {
     out.count[tid] = 0;
     s_colcnt[tid] = 0;
   }
-  if (tid == 16) L.cand_count[buf ^ 1] = 0;
+  if (tid == 32) L.cand_count[buf ^ 1] = 0;
   __syncthreads();
-  if (tid < 16) L.perm[tid] = s_perm[tid];
+  if (tid < (int)ncol) L.perm[tid] = s_perm[tid];
 
   // ---- first-order decisions (independent of order: species of a candidate
   // cannot change before its own turn) ----
@@ -294,7 +297,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L) {
       }
     }
     __syncthreads();
-    for (int g = 0; g < 16; ++g) {
+    for (uint32_t g = 0; g < ncol; ++g) {
       const uint32_t c = s_perm[g];
       if (s_colcnt[c] == 0) continue;
       for (uint32_t q = tid; q < nfire; q += blockDim.x)
@@ -304,7 +307,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L) {
     }
     // leave the counts at zero for the next event
     for (uint32_t q = tid; q < nfire; q += blockDim.x) {
-      const uint32_t c = fire_col[q] & 0x0Fu;
+      const uint32_t c = fire_col[q] & 0x7Fu;
       const uint32_t v = in.vox[c * L.cap + fire_pos[q]];
       const Coord cv = coord_of(L.geo, v);
       atomicSub(&L.nbr_cnt[hot_hash(v, nb_bits)], 1u);
@@ -345,9 +348,9 @@ __device__ __forceinline__ void begin_work(const LatDev &L) {
       in.id[at] = base_id + q;
       in.sp[at] = L.birth_sp[src];
       if (in.disp) {
-        in.disp[(0 * 16 + c) * L.cap + pos] = 0;
-        in.disp[(1 * 16 + c) * L.cap + pos] = 0;
-        in.disp[(2 * 16 + c) * L.cap + pos] = 0;
+        in.disp[(0 * ncol + c) * L.cap + pos] = 0;
+        in.disp[(1 * ncol + c) * L.cap + pos] = 0;
+        in.disp[(2 * ncol + c) * L.cap + pos] = 0;
       }
     } else {
       set_error(L, kErrBinOverflow);
@@ -360,15 +363,15 @@ __device__ __forceinline__ void begin_work(const LatDev &L) {
 // its molecule count (final now: the walk appends only to the next event's
 // bins) and the event, so that a stage launch starts with one load instead of
 // a chain of three.  A lattice that does not run this event (idle or out of
-// tape) gets empty stages.
+// tape) gets empty stages, and so do the stages past its colour count.
 __device__ __forceinline__ void begin_body(const LatDev &L) {
   begin_work(L);
   __syncthreads();  // every return of begin_work is taken by the whole block
   const uint32_t tid = threadIdx.x;
-  if (tid < 16) {
+  if (tid < kMaxColours) {
     const uint64_t e = *L.ev;
-    const bool run = e < L.tape_horizon && e < L.stop_event;
-    const uint32_t c = L.perm[tid];
+    const bool run = e < L.tape_horizon && e < L.stop_event && tid < L.ncol;
+    const uint32_t c = run ? L.perm[tid] : 0u;
     // births were counted with atomics by other threads: read through L2
     const uint32_t n = run ? min(atomicOr(&L.bins[e & 1].count[c], 0u), (uint32_t)L.cap) : 0u;
     L.sdesc[tid] = make_uint4(c, n, (uint32_t)e, (uint32_t)(e >> 32));
@@ -389,7 +392,7 @@ __global__ void __launch_bounds__(kBeginThreads) k_begin_multi(const LatDev *__r
 // =============================================================================
 // shared scratch of one walk-stage workgroup
 struct StageShared {
-  uint32_t cnt[16], base[16], loff[16];
+  uint32_t cnt[kMaxColours], base[kMaxColours], loff[kMaxColours];
   uint32_t ncand, cand_base, nflag, flag_base, total;
   unsigned long long att, hop, col;
   int32_t dsp[64];   // species count changes of this chunk
@@ -430,8 +433,8 @@ __device__ __forceinline__ gptr<T> global(T *p) {
 // nothing happens (a placement failure): each takes entry floor(w k / 2^32)
 // of the k vacant neighbours left in stencil order, w = r2, r3 of the walk
 // draw, then further blocks; they are numbered at the end of the event.
-// EXTRA: the reaction may have more than two products
-template <bool EXTRA, class OccP, class HotP>
+// EXTRA: the reaction may have more than two products; LAT: 0 HCP, 1 FCC
+template <bool EXTRA, int LAT, class OccP, class HotP>
 __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh, uint64_t e,
                                                uint32_t buf, uint32_t hbits, OccP occ, HotP hot,
                                                int rx, uint32_t v, uint32_t t, uint32_t sp,
@@ -444,7 +447,7 @@ __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh,
     cv = coord_of(L.geo, v);
     for (uint32_t n = 0; n < 12; ++n) {
       Coord cn;
-      if (step_target(L.geo, cv, n, cn) && occ[index_of(L.geo, cn)] == 0) vmask |= 1u << n;
+      if (step_target_t<LAT>(L.geo, cv, n, cn) && occ[index_of(L.geo, cn)] == 0) vmask |= 1u << n;
     }
     if (__popc(vmask) < (int)(m - 2)) {
       atomicAdd(&L.cnt[3], 1ull);
@@ -487,7 +490,7 @@ __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh,
     }
     vmask &= ~(1u << n);
     Coord cn;
-    step_target(L.geo, cv, n, cn);
+    step_target_t<LAT>(L.geo, cv, n, cn);
     const uint32_t u = index_of(L.geo, cn);
     const uint16_t ps = prod[2 + q];
     occ[u] = ps;
@@ -503,9 +506,10 @@ __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh,
   atomicAdd(&L.fired[rx], 1ull);
 }
 
-template <int ITEMS, int DM>
+template <int ITEMS, int DM, int LAT>
 __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t base, uint32_t n,
                             StageShared &S, StageStaging<ITEMS> &stg) {
+  constexpr uint32_t NC = LAT ? kColoursFcc : kColoursHcp;
   StageShared *sh = &S;
   const int tid = threadIdx.x;
   const uint32_t buf = (uint32_t)(e & 1);
@@ -526,10 +530,10 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
   uint32_t *s_cnt = sh->cnt, *s_base = sh->base;
   uint32_t &s_ncand = sh->ncand, &s_cand_base = sh->cand_base;
   uint32_t &s_nflag = sh->nflag, &s_flag_base = sh->flag_base;
-  if (tid < 16) s_cnt[tid] = 0;
-  if (tid == 16) s_ncand = 0;
-  if (tid == 17) s_nflag = 0;
-  if (tid == 18) {
+  if (tid < (int)NC) s_cnt[tid] = 0;
+  if (tid == 32) s_ncand = 0;
+  if (tid == 33) s_nflag = 0;
+  if (tid == 34) {
     sh->att = 0;
     sh->hop = 0;
     sh->col = 0;
@@ -557,9 +561,9 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
       const uint64_t idx = min(base + (uint64_t)it * kStageThreads + tid, (uint64_t)n - 1);
-      d0[it] = idsp[(0 * 16 + c) * cap + idx];
-      d1[it] = idsp[(1 * 16 + c) * cap + idx];
-      d2[it] = idsp[(2 * 16 + c) * cap + idx];
+      d0[it] = idsp[(0 * NC + c) * cap + idx];
+      d1[it] = idsp[(1 * NC + c) * cap + idx];
+      d2[it] = idsp[(2 * NC + c) * cap + idx];
     }
   }
 #pragma unroll
@@ -589,10 +593,11 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     const uint32_t dir = scale32(r.x, 12);
     const Coord cv = coord_of(L.geo, v);
     Coord ct;
-    const bool open = step_target(L.geo, cv, dir, ct);
+    const bool open = step_target_t<LAT>(L.geo, cv, dir, ct);
     tgt[it] = index_of(L.geo, ct);
     ry[it] = r.y;
-    mv[it] = dir | ((cv.k & 1u) << 4) | (colour_of(ct) << 8) | (open ? 0u : kWallBit);
+    mv[it] = dir | (LAT ? 0u : (cv.k & 1u) << 4) | (colour_t<LAT>(ct) << 8) |
+             (open ? 0u : kWallBit);
     const uint32_t h = hot_hash(v, hbits);
     hw[it] = hot[h >> 4];
     hs[it] = (h & 15u) << 1;
@@ -624,9 +629,9 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
       occ[t] = (uint16_t)sp;
       occ[v] = 0;
       vox[it] = t;
-      ocol[it] = (mv[it] >> 8) & 15u;
+      ocol[it] = (mv[it] >> 8) & (LAT ? 31u : 15u);
       int32_t X, Y, Z;
-      hop_vector(mv[it] & 15u, (mv[it] >> 4) & 1u, X, Y, Z);
+      hop_vector_t<LAT>(mv[it] & 15u, (mv[it] >> 4) & 1u, X, Y, Z);
       d0[it] += X;
       d1[it] += Y;
       d2[it] += Z;
@@ -644,15 +649,15 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
       drx[it] = rx | (int)(psp << 8);
       continue;
     }
-    fire_collision<false>(L, *sh, e, buf, hbits, occ, hot, rx, v, t, sp, psp, id[it], osp[it],
-                          ocol[it], flag[it], ftgt[it]);
+    fire_collision<false, LAT>(L, *sh, e, buf, hbits, occ, hot, rx, v, t, sp, psp, id[it],
+                               osp[it], ocol[it], flag[it], ftgt[it]);
   }
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it)
     if (drx[it] >= 0)
-      fire_collision<true>(L, *sh, e, buf, hbits, occ, hot, drx[it] & 0xFF, vox[it], tgt[it],
-                           osp[it] & 63u, (uint32_t)drx[it] >> 8, id[it], osp[it], ocol[it],
-                           flag[it], ftgt[it]);
+      fire_collision<true, LAT>(L, *sh, e, buf, hbits, occ, hot, drx[it] & 0xFF, vox[it],
+                                tgt[it], osp[it] & 63u, (uint32_t)drx[it] >> 8, id[it], osp[it],
+                                ocol[it], flag[it], ftgt[it]);
 
   // ---- survivors: block-local slots per colour (LDS atomics), one global
   // reservation per colour per chunk, entries staged colour-major in LDS and
@@ -678,7 +683,7 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
   __syncthreads();
   // one wave per job: bin reservations; flag and candidate reservations;
   // local colour offsets and the chunk's counters; species count changes
-  if (tid < 16) {
+  if (tid < (int)NC) {
     s_base[tid] = s_cnt[tid] ? atomicAdd(&out.count[tid], s_cnt[tid]) : 0u;
   } else if (tid == 64) {
     if (s_ncand) s_cand_base = atomicAdd(&L.cand_count[cnext], s_ncand);
@@ -686,7 +691,7 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     if (s_nflag) s_flag_base = atomicAdd(&L.flag_count[buf], s_nflag);
   } else if (tid == 128) {
     uint32_t acc = 0;
-    for (int k = 0; k < 16; ++k) {
+    for (uint32_t k = 0; k < NC; ++k) {
       sh->loff[k] = acc;
       acc += s_cnt[k];
     }
@@ -717,9 +722,9 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     const uint64_t pos = (uint64_t)s_base[oc] + lpos[it];
     if (pos >= cap) continue;  // reported by the copy below
     if (disp) {
-      odsp[(0 * 16 + oc) * cap + pos] = d0[it];
-      odsp[(1 * 16 + oc) * cap + pos] = d1[it];
-      odsp[(2 * 16 + oc) * cap + pos] = d2[it];
+      odsp[(0 * NC + oc) * cap + pos] = d0[it];
+      odsp[(1 * NC + oc) * cap + pos] = d1[it];
+      odsp[(2 * NC + oc) * cap + pos] = d2[it];
     }
     if (cand[it]) {
       const uint64_t r = (uint64_t)s_cand_base + cslot[it];
@@ -750,7 +755,7 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
   }
 }
 
-template <int ITEMS, int DM>
+template <int ITEMS, int DM, int LAT>
 __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restrict__ Lp, uint32_t g) {
   __shared__ StageShared S;
   __shared__ StageStaging<ITEMS> T;
@@ -760,7 +765,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
   const uint32_t c = d.x, n = d.y;
   const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
   for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk)
-    stage_chunk<ITEMS, DM>(L, e, c, base, n, S, T);
+    stage_chunk<ITEMS, DM, LAT>(L, e, c, base, n, S, T);
 }
 
 // Stage g of every member lattice of an ensemble in one launch: the chunks of
@@ -813,7 +818,8 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
     const LatDev &L = lats[a];
     const uint4 d = L.sdesc[g];
     const uint64_t e = d.z | ((uint64_t)d.w << 32);
-    stage_chunk<ITEMS, 2>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, S, T);
+    if (L.geo.fcc) stage_chunk<ITEMS, 2, 1>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, S, T);
+    else stage_chunk<ITEMS, 2, 0>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, S, T);
   }
 }
 
@@ -870,9 +876,9 @@ __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
     out.id[at] = id;
     out.sp[at] = (uint16_t)(L.occ[u] & kSpeciesMask);
     if (out.disp) {
-      out.disp[(0 * 16 + c) * L.cap + pos] = 0;
-      out.disp[(1 * 16 + c) * L.cap + pos] = 0;
-      out.disp[(2 * 16 + c) * L.cap + pos] = 0;
+      out.disp[(0 * L.ncol + c) * L.cap + pos] = 0;
+      out.disp[(1 * L.ncol + c) * L.cap + pos] = 0;
+      out.disp[(2 * L.ncol + c) * L.cap + pos] = 0;
     }
     if (cmax_next) {
       const U4 r = philox((uint32_t)(e + 1), id, kPhaseFirst, 0, L.key0, L.key1);
@@ -950,14 +956,15 @@ __global__ void __launch_bounds__(kStageThreads) k_msd(const LatDev *__restrict_
   const Bins &in = L.bins[*L.ev & 1];
   unsigned long long acc = 0, n = 0;
   if (in.disp) {
-    for (uint32_t c = 0; c < 16; ++c) {
+    const uint32_t nc = L.ncol;
+    for (uint32_t c = 0; c < nc; ++c) {
       const uint32_t cnt = min(in.count[c], (uint32_t)L.cap);
       for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cnt;
            i += (uint64_t)gridDim.x * blockDim.x) {
         if (in.id[c * L.cap + i] == kDeadId) continue;
-        const long long X = in.disp[(0 * 16 + c) * L.cap + i];
-        const long long Y = in.disp[(1 * 16 + c) * L.cap + i];
-        const long long Z = in.disp[(2 * 16 + c) * L.cap + i];
+        const long long X = in.disp[(0 * nc + c) * L.cap + i];
+        const long long Y = in.disp[(1 * nc + c) * L.cap + i];
+        const long long Z = in.disp[(2 * nc + c) * L.cap + i];
         acc += (unsigned long long)(3 * X * X + Y * Y + 8 * Z * Z);
         ++n;
       }
@@ -1009,22 +1016,27 @@ hipError_t launch_begin(const LatDev *dL, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int DM>
+template <int DM, int LAT>
 static void launch_stage_dm(const LatDev *dL, uint32_t g, int grid, int items, hipStream_t s) {
   const dim3 G(grid), B(kStageThreads);
   switch (items) {
-  case 1: hipLaunchKernelGGL((k_stage<1, DM>), G, B, 0, s, dL, g); break;
-  case 2: hipLaunchKernelGGL((k_stage<2, DM>), G, B, 0, s, dL, g); break;
-  case 8: hipLaunchKernelGGL((k_stage<8, DM>), G, B, 0, s, dL, g); break;
-  case 16: hipLaunchKernelGGL((k_stage<16, DM>), G, B, 0, s, dL, g); break;
-  default: hipLaunchKernelGGL((k_stage<4, DM>), G, B, 0, s, dL, g); break;
+  case 1: hipLaunchKernelGGL((k_stage<1, DM, LAT>), G, B, 0, s, dL, g); break;
+  case 2: hipLaunchKernelGGL((k_stage<2, DM, LAT>), G, B, 0, s, dL, g); break;
+  case 8: hipLaunchKernelGGL((k_stage<8, DM, LAT>), G, B, 0, s, dL, g); break;
+  case 16: hipLaunchKernelGGL((k_stage<16, DM, LAT>), G, B, 0, s, dL, g); break;
+  default: hipLaunchKernelGGL((k_stage<4, DM, LAT>), G, B, 0, s, dL, g); break;
   }
 }
 
-hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp,
+hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp, bool fcc,
                         hipStream_t s) {
-  if (disp) launch_stage_dm<1>(dL, g, grid, items, s);
-  else launch_stage_dm<0>(dL, g, grid, items, s);
+  if (fcc) {
+    if (disp) launch_stage_dm<1, 1>(dL, g, grid, items, s);
+    else launch_stage_dm<0, 1>(dL, g, grid, items, s);
+  } else {
+    if (disp) launch_stage_dm<1, 0>(dL, g, grid, items, s);
+    else launch_stage_dm<0, 0>(dL, g, grid, items, s);
+  }
   return hipGetLastError();
 }
 
@@ -1033,18 +1045,21 @@ hipError_t launch_end(const LatDev *dL, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, hipStream_t s) {
+hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
+                        hipStream_t s) {
   hipError_t err = launch_begin(dL, s);
-  for (uint32_t g = 0; g < 16 && err == hipSuccess; ++g)
-    err = launch_stage(dL, g, grid, items, disp, s);
+  const uint32_t stages = fcc ? kColoursFcc : kColoursHcp;
+  for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
+    err = launch_stage(dL, g, grid, items, disp, fcc, s);
   if (err == hipSuccess) err = launch_end(dL, s);
   return err;
 }
 
-hipError_t launch_event_multi(const LatDev *lats, uint32_t R, int grid, int items, hipStream_t s) {
-  if (R == 0 || R > kMaxMembers) return hipErrorInvalidValue;
+hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
+                              int items, hipStream_t s) {
+  if (R == 0 || R > kMaxMembers || stages > (uint32_t)kMaxColours) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_begin_multi, dim3(R), dim3(kBeginThreads), 0, s, lats);
-  for (uint32_t g = 0; g < 16; ++g) {
+  for (uint32_t g = 0; g < stages; ++g) {
     switch (items) {
     case 1: hipLaunchKernelGGL(k_stage_multi<1>, dim3(grid), dim3(kStageThreads), 0, s, lats, R, g); break;
     case 2: hipLaunchKernelGGL(k_stage_multi<2>, dim3(grid), dim3(kStageThreads), 0, s, lats, R, g); break;

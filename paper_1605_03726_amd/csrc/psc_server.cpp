@@ -169,8 +169,12 @@ void worker_main(psc_server *S) {
         }
       }
       uint64_t mol = 0;
-      for (auto *h : E.members) mol += h->desc.max_molecules;
-      E.grid = (int)std::min<uint64_t>(std::max<uint64_t>(mol / 16 / 1024, 64), 2048);
+      E.stages = 0;
+      for (auto *h : E.members) {
+        mol += h->desc.max_molecules;
+        E.stages = std::max(E.stages, n_colours(h->geo));
+      }
+      E.grid = (int)std::min<uint64_t>(std::max<uint64_t>(mol / E.stages / 1024, 64), 2048);
       E.items = 4;
       S->ens_dirty = false;
     }
@@ -182,8 +186,8 @@ void worker_main(psc_server *S) {
     // direct launches: a server shares its process with other threads, and
     // capturing a graph would forbid their legacy-stream work meanwhile
     for (uint64_t e = 0; e < q && !st; ++e)
-      if (launch_event_multi(E.d_lats, (uint32_t)E.members.size(), E.grid, E.items, S->stream) !=
-          hipSuccess)
+      if (launch_event_multi(E.d_lats, (uint32_t)E.members.size(), E.stages, E.grid, E.items,
+                             S->stream) != hipSuccess)
         st = PSC_EDEVICE;
     if (!st && hipStreamSynchronize(S->stream) != hipSuccess) st = PSC_EDEVICE;
     const double te = seconds(S);
@@ -256,7 +260,8 @@ psc_status psc_server_job_bytes(const psc_job_desc *d, uint64_t *bytes) {
   for (uint32_t r = 0; d->reactions && r < d->n_reactions; ++r)
     collision_births |= d->reactions[r].n_r == 2 && d->reactions[r].n_p > 2;
   *bytes = estimate_device_bytes(nv, d->max_molecules, (d->flags & PSC_TRACK_DISPLACEMENT) != 0,
-                                 d->n_reactions, collision_births) +
+                                 d->n_reactions, collision_births,
+                                 (d->flags & PSC_LATTICE_FCC) ? kColoursFcc : kColoursHcp) +
            (d->n_events + 2048) * 64;  // event tape, grown geometrically
   return PSC_OK;
 }

@@ -18,6 +18,7 @@ PSC_OK, PSC_EINVAL, PSC_ESTATE, PSC_ENOMEM, PSC_ECAPACITY, PSC_EDEVICE = 0, -1, 
 TRACK_DISPLACEMENT = 1
 LAYOUT_LINEAR = 2
 BOUNDARY_WALLS = 4
+LATTICE_FCC = 8
 
 _ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -193,12 +194,12 @@ def current_stream():
 
 
 class Lattice:
-    """One HCP lattice on the GPU (see include/psc.h)."""
+    """One lattice on the GPU (see include/psc.h): HCP, or FCC with fcc=True."""
 
     def __init__(self, dims, voxel_radius: float, seed: int, max_molecules: int,
                  track_displacement: bool = False, device: int = 0,
                  torch_allocator: bool = True, linear_layout: bool = False,
-                 walls: bool = False):
+                 walls: bool = False, fcc: bool = False):
         self.L = lib()
         self.dims = tuple(int(x) for x in dims)
         self.nv = self.dims[0] * self.dims[1] * self.dims[2]
@@ -208,7 +209,8 @@ class Lattice:
         d.seed = seed
         d.max_molecules = max_molecules
         d.flags = (TRACK_DISPLACEMENT if track_displacement else 0) | (
-            LAYOUT_LINEAR if linear_layout else 0) | (BOUNDARY_WALLS if walls else 0)
+            LAYOUT_LINEAR if linear_layout else 0) | (BOUNDARY_WALLS if walls else 0) | (
+            LATTICE_FCC if fcc else 0)
         d.device = device
         self._hooks = None
         if torch_allocator:
@@ -368,7 +370,8 @@ def lattice_from_workload(w: dict, max_molecules: int | None = None, device: int
         max_molecules = min(nv, max(1024, int(placed * 1.5) + 1024))
     lat = Lattice(w["dims"], w["rv"], w["seed"], max_molecules,
                   track_displacement=w.get("track_displacement", False), device=device,
-                  linear_layout=linear_layout, walls=w.get("boundary") == "walls")
+                  linear_layout=linear_layout, walls=w.get("boundary") == "walls",
+                  fcc=w.get("lattice") == "fcc")
     for name, D in w["species"]:
         lat.add_species(name, D)
     for r, p, k in w["reactions"]:
@@ -622,7 +625,8 @@ def job_desc(w: dict, keep_state: bool = False, max_molecules: int | None = None
     d.seed = w["seed"]
     d.max_molecules = max_molecules
     d.flags = (TRACK_DISPLACEMENT if w.get("track_displacement") else 0) | (
-        BOUNDARY_WALLS if w.get("boundary") == "walls" else 0)
+        BOUNDARY_WALLS if w.get("boundary") == "walls" else 0) | (
+        LATTICE_FCC if w.get("lattice") == "fcc" else 0)
     d.n_species, d.D = len(w["species"]), D
     d.n_reactions, d.reactions = len(w["reactions"]), rxs
     d.n_place, d.place = len(w["place"]), pl

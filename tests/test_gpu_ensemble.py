@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 
 def oracle_run(w, events):
     o = oracle.Oracle(w["dims"], w["rv"], w["seed"],
-                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC)
+                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC,
+                      lattice=oracle.FCC if w.get("lattice") == "fcc" else oracle.HCP)
     for _, D in w["species"]:
         o.add_species(D)
     for r, p, k in w["reactions"]:
@@ -44,6 +45,11 @@ def mixed_members(n_rep=10, events=40):
     ws.append(dict(ws[0], boundary="walls"))
     # collisions with more than two products
     ws.append(workload("multiproduct", seed=8, events=events))
+    # FCC members (24 stages) beside HCP ones (16 stages, the rest empty)
+    ws.append(dict(workload("small_reactive", seed=13, dims=(16, 12, 12), events=events),
+                   lattice="fcc"))
+    ws.append(dict(workload("cfg2", dims=(24, 24, 24), events=events), lattice="fcc",
+                   boundary="walls"))
     return ws
 
 

@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 
 def build_oracle(w, state=None):
     o = oracle.Oracle(w["dims"], w["rv"], w["seed"],
-                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC)
+                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC,
+                      lattice=oracle.FCC if w.get("lattice") == "fcc" else oracle.HCP)
     for _, D in w["species"]:
         o.add_species(D)
     for r, p, k in w["reactions"]:
@@ -315,3 +316,101 @@ def test_multiproduct_collisions_many_events_and_shapes():
     staged.set_launch(1, 7)
     staged.step(121)
     assert_same(staged.read_state(), o.state())
+
+
+# ---- the face-centred cubic lattice (PSC_LATTICE_FCC) ------------------------------
+
+def fcc(w, **kw):
+    return dict(w, lattice="fcc", **kw)
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_fcc_small_reactive_all_rules(seed):
+    """Every rule on the FCC lattice over 24 stages; 16 x 12 x 12 spans
+    several chunks per stage and ragged bin tails."""
+    w = fcc(workload("small_reactive", seed=seed, dims=(16, 12, 12)))
+    g, s = run_pair(w, 40)
+    assert s["hops"] > 0 and s["collisions"] > 0 and np.all(s["fired"] > 0), s["fired"]
+    # the lattice changes the run
+    gh = build_gpu(dict(w, lattice=None))
+    gh.step(40)
+    assert not np.array_equal(gh.read_state()["occ"], g["occ"])
+
+
+@pytest.mark.parametrize("dims,boundary", [((4, 4, 12), None), ((20, 8, 24), None),
+                                           ((4, 4, 12), "walls"), ((20, 8, 24), "walls")])
+def test_fcc_shapes(dims, boundary):
+    w = fcc(workload("small_reactive", dims=dims, seed=11), boundary=boundary)
+    run_pair(w, 30)
+
+
+def test_fcc_displacement_and_crowding():
+    w = fcc(dict(workload("cfg1", events=200), dims=(32, 32, 36), place=[(1, 3000)]))
+    g, s = run_pair(w, 200)
+    assert s["hops"] > 100000
+    run_pair(fcc(workload("cfg2", dims=(64, 64, 48))), 120)
+    run_pair(fcc(workload("cfg2", dims=(64, 64, 48)), boundary="walls"), 60)
+
+
+@pytest.mark.parametrize("items", [1, 4, 16])
+def test_fcc_launch_shapes(items):
+    w = fcc(workload("cfg2", dims=(96, 96, 96)))
+    lat = build_gpu(w, max_molecules=1 << 19)
+    lat.set_launch(items, 64)
+    o = build_oracle(w)
+    lat.step(60)
+    o.run(60, oracle.MODE_C)
+    s = o.state()
+    assert_same(lat.read_state(), s, disp=False)
+    assert s["fired"][0] > 500
+
+
+@pytest.mark.parametrize("boundary", [None, "walls"])
+def test_fcc_multiproduct_and_mapk(boundary):
+    w = fcc(workload("multiproduct", seed=3, dims=(16, 12, 12), n_a=16 * 12 * 12 // 5),
+            boundary=boundary)
+    g, s = run_pair(w, 40)
+    assert s["fired"][0] > 0 and s["fired"][1] > 0
+    run_pair(fcc(workload("cfg3", dims=(64, 64, 48)), boundary=boundary), 40, chunks=2)
+
+
+def test_fcc_linear_layout_statistics_and_checkpoint():
+    w = fcc(workload("small_reactive", seed=21, dims=(16, 12, 24)))
+    lat = psc.lattice_from_workload(w, linear_layout=True)
+    lat.step(25)
+    mid = lat.read_state()
+    lat.step(15)
+    st = lat.stats()
+    g = lat.read_state()
+    o = build_oracle(w)
+    o.run(40, oracle.MODE_C)
+    s = o.state()
+    assert_same(g, s)
+    for sp in range(1, len(w["species"]) + 1):
+        assert st["species_count"][sp] == int((s["species"] == sp).sum())
+    X, Y, Z = (s[k].astype(np.int64) for k in ("dx", "dy", "dz"))
+    assert st["disp_sum"] == int((3 * X * X + Y * Y + 8 * Z * Z).sum())
+    # resume from the event-25 state on a fresh lattice (its counters start at
+    # the load, so the state, event, next id and time are compared)
+    r = build_gpu(w, state=mid)
+    r.step(15)
+    gr = r.read_state()
+    for key in ("occ", "id", "vox", "species", "dx", "dy", "dz"):
+        assert np.array_equal(gr[key], s[key]), key
+    assert gr["event"] == s["event"] and gr["next_id"] == s["next_id"] and gr["time"] == s["time"]
+
+
+def test_fcc_full_size_prefix():
+    # the MAPK workload on an FCC lattice of 2048 x 2048 x 1020 voxels (just
+    # under 2^32; nk a multiple of 12)
+    events = 1
+    w = fcc(workload("cfg3", dims=(2048, 2048, 1020)))
+    lat = build_gpu(w, max_molecules=int(0.003 * 2 ** 32 * 1.25))
+    lat.step(events)
+    g = lat.read_state()
+    lat.close()
+    o = build_oracle(w)
+    o.run(events, oracle.MODE_C)
+    s = o.state()
+    o.close()
+    assert_same(g, s, disp=False)

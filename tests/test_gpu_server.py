@@ -30,7 +30,8 @@ def alone(w):
 
 def oracle_state(w):
     o = oracle.Oracle(w["dims"], w["rv"], w["seed"],
-                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC)
+                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC,
+                      lattice=oracle.FCC if w.get("lattice") == "fcc" else oracle.HCP)
     for _, D in w["species"]:
         o.add_species(D)
     for r, p, k in w["reactions"]:
@@ -57,8 +58,10 @@ def cap_of(w):
 
 def test_results_same_alone_and_in_the_mix():
     jobs = small_jobs(24)
-    # every third job is closed by walls
+    # every third job is closed by walls, every fourth is an FCC lattice
     jobs = [dict(w, boundary="walls") if i % 3 == 1 else w for i, w in enumerate(jobs)]
+    jobs = [dict(w, lattice="fcc", dims=w["dims"][:2] + (12 * max(1, w["dims"][2] // 12),))
+            if i % 4 == 2 else w for i, w in enumerate(jobs)]
     srv = psc.Server(budget_bytes=8 << 30, quantum_events=16)
     ids = []
     for i, w in enumerate(jobs):

@@ -248,9 +248,9 @@ psc_status psc_device_bytes(const psc_lattice *h, uint64_t *bytes);
  * changes only how the work is spread over the GPU, never the result (the
  * molecules of one stage commute).  0 keeps the current value.  Unless set,
  * both are chosen at the first step from the molecules in the colour bins:
- * 4 items and about 1.5 passes over an average bin per workgroup when a stage
- * fills the GPU (512 workgroups), else 2 or 1 items and one chunk per
- * workgroup. */
+ * 4 items when a stage fills the GPU with 4-item chunks (512 workgroups),
+ * else 2 or 1 items, and one chunk per workgroup for 1.25 times an average
+ * bin (at most 65536 workgroups). */
 typedef struct psc_launch {
   uint32_t items_per_thread;
   uint32_t stage_blocks;

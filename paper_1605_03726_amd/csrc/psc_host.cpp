@@ -471,17 +471,21 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   if (st) return st;
 
   // launch shape of the stage kernel from the molecules binned now (an
-  // average colour bin holds 1/16 of them, 1/24 on FCC): a stage that cannot fill the GPU
-  // with 4-item chunks (two workgroups per CU) takes one-item chunks, one
-  // per workgroup, to shorten its chain of dependent accesses; a large one
-  // takes 4 items and about 1.5 passes per workgroup
+  // average colour bin holds 1/16 of them, 1/24 on FCC): a stage that cannot
+  // fill the GPU with 4-item chunks (two workgroups per CU) takes one- or
+  // two-item chunks to shorten its chain of dependent accesses.  Every chunk
+  // gets a workgroup of its own, so that all of a stage's probes are in
+  // flight at once (three waves per SIMD; a grid-striding second pass costs
+  // about a sixth of the walk), with a quarter more workgroups than the
+  // average bin needs: bins differ and grow, and a workgroup without a chunk
+  // exits at once.
   if (!h->grid_set) {
     const uint64_t expect = std::max<uint64_t>(walkers.size() / ncol, 1);
     const uint64_t T = (uint64_t)stage_threads();
     if (!h->items_set) h->items = expect >= 512 * 4 * T ? 4 : (expect >= 512 * 2 * T ? 2 : 1);
-    const uint64_t per_block = T * (uint64_t)h->items * (h->items >= 4 ? 3 : 2);
+    const uint64_t chunk = T * (uint64_t)h->items;
     h->grid = (int)std::min<uint64_t>(
-        std::max<uint64_t>((2 * expect + per_block - 1) / per_block, 1), 4096);
+        std::max<uint64_t>((5 * expect / 4 + chunk - 1) / chunk, 1), 65536);
   }
   HIP_OK(h, launch_scan(h->dL, std::min(h->grid * 4, 4096), stream));
   h->frozen = true;

@@ -180,8 +180,9 @@ def test_many_products_and_placement_failures():
 
 
 def test_mapk_full_size_prefix():
-    # the 2^32-voxel workload at full size: 8 GiB occupancy, 12.9 M molecules
-    events = 2
+    # the 2^32-voxel workload at full size: 8 GiB occupancy, 12.9 M molecules;
+    # six events carry the partner marks and flags across event parities
+    events = 6
     w = workload("cfg3")
     lat = build_gpu(w, max_molecules=int(0.003 * 2 ** 32 * 1.25))
     lat.step(events)
@@ -192,6 +193,41 @@ def test_mapk_full_size_prefix():
     s = o.state()
     o.close()
     assert_same(g, s, disp=False)
+
+
+def test_mapk_full_run_invariants():
+    """The MAPK workload as the benchmark runs it (2^32 voxels, the default
+    launch shape, 10 + 2000 events), checked by what holds at any size: the
+    occupancy and the molecule table agree voxel for voxel, the device's
+    per-species counts equal the table's, and the three moieties that every
+    reaction of the network conserves (MAPK, MAPKK, phosphatase, free or in a
+    complex) keep their initial totals."""
+    w = workload("cfg3")
+    nv = 2 ** 32
+    placed = sum(c for _, c in w["place"])
+    lat = build_gpu(w, max_molecules=min(nv, int(placed * 1.25) + 4096))
+    lat.step(10)
+    lat.step(2000)
+    st = lat.stats()
+    g = lat.read_state()
+    lat.close()
+    occ, vox, sp = g["occ"], g["vox"], g["species"]
+    assert g["event"] == 2010 and g["attempts"] > 2 * 10 ** 10
+    # complexes form and break up (some of the rarer pairs never meet in 2000
+    # events)
+    assert g["fired"][0] > 10 ** 6 and np.count_nonzero(g["fired"]) >= 10, g["fired"]
+    assert len(np.unique(vox)) == len(vox)
+    assert np.array_equal(occ[vox], sp)
+    assert np.count_nonzero(occ) == len(vox)
+    counts = np.bincount(sp, minlength=11)
+    assert np.array_equal(counts[1:11], st["species_count"][1:11].astype(np.int64))
+    names = [n for n, _ in w["species"]]
+    moieties = {"K": 0, "KK": 0, "P": 0}
+    for i, name in enumerate(names, start=1):
+        for part in name.split("."):
+            moieties[part.rstrip("p") or part] += int(counts[i])
+    start = dict(w["place"])
+    assert moieties == {"K": start[1], "KK": start[4], "P": start[5]}, moieties
 
 
 @pytest.mark.parametrize("name,kw,events", [("small_reactive", {"seed": 4}, 40),

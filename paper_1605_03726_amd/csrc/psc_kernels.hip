@@ -285,10 +285,16 @@ __device__ __forceinline__ void begin_work(const LatDev &L) {
       const uint32_t c = fire_col[q];
       const uint32_t v = in.vox[c * L.cap + fire_pos[q]];
       const Coord cv = coord_of(L.geo, v);
-      bool alone = atomicAdd(&L.nbr_cnt[hot_hash(v, nb_bits)], 0u) == 1u;
-      for (uint32_t n = 0; n < 12 && alone; ++n)
-        alone = atomicAdd(&L.nbr_cnt[hot_hash(index_of(L.geo, step_coord(L.geo, cv, n)), nb_bits)],
-                          0u) == 1u;
+      // the 13 counts (each at least 1: the molecule's own) are read at once
+      // through L2, then tested together
+      uint32_t other = __hip_atomic_load(&L.nbr_cnt[hot_hash(v, nb_bits)], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) ^ 1u;
+#pragma unroll
+      for (uint32_t n = 0; n < 12; ++n)
+        other |= __hip_atomic_load(
+                     &L.nbr_cnt[hot_hash(index_of(L.geo, step_coord(L.geo, cv, n)), nb_bits)],
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ^ 1u;
+      const bool alone = other == 0u;
       if (alone) {
         apply_first_order(L, e, in, c, fire_pos[q], fire_id[q], fire_rx[q], &s_nb);
       } else {

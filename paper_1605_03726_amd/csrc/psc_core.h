@@ -362,9 +362,11 @@ struct LatDev {
   uint32_t hot_bits;      // log2 of the number of hash slots
   uint32_t *end_done;     // completion counter of the multi-block k_end
 
-  // scratch of the first-order pass: molecules firing this event
+  // scratch of the first-order pass: molecules firing this event, and their
+  // count (zero between events)
   uint32_t *fire_pos, *fire_id;
   uint8_t *fire_col, *fire_rx;
+  uint32_t *fire_count;
 
   // first-order conflict test: per hashed voxel, how many firing molecules
   // have it in their closed neighbourhood (zero between events)
@@ -406,13 +408,15 @@ struct LatDev {
 
 hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
 // disp: the lattice tracks displacements (its bins carry the planes)
-// fcc: the lattice is face-centred cubic (24 stages), else HCP (16)
+// fcc: the lattice is face-centred cubic (24 stages), else HCP (16);
+// decide_grid > 0: the first-order decisions run in their own launch of that
+// many workgroups (events with many candidates), else inside k_begin
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
-                        hipStream_t s);
+                        int decide_grid, hipStream_t s);
 // stages: the most stages of any member (16, or 24 with an FCC member)
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, hipStream_t s);
-hipError_t launch_begin(const LatDev *dL, hipStream_t s);
+hipError_t launch_begin(const LatDev *dL, int decide_grid, hipStream_t s);
 hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp, bool fcc,
                         hipStream_t s);
 uint32_t max_members();

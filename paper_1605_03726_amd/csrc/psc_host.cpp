@@ -342,6 +342,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.fire_id = alloc_n<uint32_t>(h, cap);
   L.fire_col = alloc_n<uint8_t>(h, cap);
   L.fire_rx = alloc_n<uint8_t>(h, cap);
+  L.fire_count = alloc_n<uint32_t>(h, 1);
   L.n_species = (uint32_t)(S - 1);
   L.n_rx = R;
   L.n_fo = h->n_fo;
@@ -364,7 +365,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.error = alloc_n<uint32_t>(h, 1);
   h->dL = alloc_n<LatDev>(h, 1);
   if (!L.occ || !L.cand_count || !L.flag_vox[0] || !L.flag_vox[1] || !L.flag_count || !L.birth_key || !L.birth_vox ||
-      !L.birth_sp || !L.birth_count || !L.fire_pos || !L.fire_id || !L.fire_col ||
+      !L.birth_sp || !L.birth_count || !L.fire_pos || !L.fire_id || !L.fire_col || !L.fire_count ||
       !L.fire_rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod ||
       !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.sdesc || !L.next_id || !L.cnt || !L.sp_count ||
       !L.fired || !L.error || !h->dL || !L.hot || !L.end_done || !L.nbr_cnt ||
@@ -449,6 +450,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   HIP_OK(h, hipMemset(L.sdesc, 0, kMaxColours * sizeof(uint4)));  // empty until a first-order pass
   if (L.wb_count) HIP_OK(h, hipMemset(L.wb_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.birth_count, 0, sizeof(uint32_t)));
+  HIP_OK(h, hipMemset(L.fire_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.cnt, 0, 4 * sizeof(unsigned long long)));
   {
     std::vector<unsigned long long> counts(64, 0);
@@ -479,6 +481,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   // about a sixth of the walk), with a quarter more workgroups than the
   // average bin needs: bins differ and grow, and a workgroup without a chunk
   // exits at once.
+  h->walkers0 = walkers.size();
   if (!h->grid_set) {
     const uint64_t expect = std::max<uint64_t>(walkers.size() / ncol, 1);
     const uint64_t T = (uint64_t)stage_threads();
@@ -519,7 +522,7 @@ uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool dis
   uint32_t nb = 12;
   while (nb < 22 && (1ull << nb) < 8 * cap) ++nb;
   t += r((1ull << nb) * 4);
-  t += r(cap * 4) * 2 + r(cap) * 2;
+  t += r(cap * 4) * 2 + r(cap) * 2 + r(4);
   const uint64_t R = std::max<uint32_t>(n_reactions, 1);
   t += r(64) + r(64 * 64 * 2) + r(R * 4) + r(R) * 2 + r(R * 24) + r(128) + r(64) + r(512);
   t += r(8) + r(64) + r(4) + r(32) + r(R * 8) + r(4) + r(sizeof(LatDev));
@@ -813,10 +816,20 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
     psc_status st = sync_tape(h, stream);
     if (st) return st;
   }
+  // First-order decisions run inside k_begin (one workgroup) unless an event
+  // expects many candidates (the event's largest threshold times the
+  // walkers): then a launch of their own spreads them over workgroups.
+  auto decide_grid = [&](uint64_t e) -> int {
+    if (!h->n_fo) return 0;
+    const double expect = (double)h->tape_cmax[e] * (1.0 / 4294967296.0) * (double)h->walkers0;
+    if (expect < 4096.0) return 0;
+    return (int)std::min(std::ceil(expect / 512.0), 1024.0);
+  };
+  const uint64_t e0 = h->events_done;
   if (!h->timing) {
     for (uint64_t e = 0; e < n_events; ++e)
       HIP_OK(h, launch_event(h->dL, h->grid, h->items, h->L.bins[0].disp != nullptr,
-                             h->geo.fcc != 0, stream));
+                             h->geo.fcc != 0, decide_grid(e0 + e), stream));
   } else {
     auto ev = [&](hipEvent_t *out) -> hipError_t {
       if (!h->event_pool.empty()) {
@@ -834,7 +847,7 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
         HIP_OK(h, ev(&t.a));
         HIP_OK(h, ev(&t.b));
         HIP_OK(h, hipEventRecord(t.a, stream));
-        if (g < 0) HIP_OK(h, launch_begin(h->dL, stream));
+        if (g < 0) HIP_OK(h, launch_begin(h->dL, decide_grid(e0 + e), stream));
         else if (g < stages)
           HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, h->items,
                                  h->L.bins[0].disp != nullptr, h->geo.fcc != 0, stream));

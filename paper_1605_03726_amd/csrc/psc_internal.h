@@ -58,6 +58,7 @@ struct psc_lattice {
   std::vector<uint64_t> tape_due;
   std::vector<uint32_t> tape_thr, tape_cmax;
   uint64_t events_done = 0;  // events enqueued on the device
+  uint64_t walkers0 = 0;     // molecules binned at the freeze (sizes the decision launch)
 
   // first-order slots: for each species, its first-order reactions in
   // registration order

@@ -209,8 +209,36 @@ __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, c
   atomicAdd(&L.fired[rx], 1ull);
 }
 
-// the event's opening work for one lattice, by one workgroup
-__device__ __forceinline__ void begin_work(const LatDev &L) {
+// First-order decisions of event e for candidates [first, ...) with the
+// given stride: a candidate whose voxel holds a species with first-order
+// reactions and whose draw falls under a cumulative threshold joins the fire
+// list, counted in *nfire (LDS inside one workgroup, else global memory).
+// Independent of order (a candidate's species cannot change before its own
+// turn), so any number of threads and workgroups may share the list.
+__device__ __forceinline__ void decide_first_order(const LatDev &L, uint64_t e, uint32_t first,
+                                                   uint32_t stride, uint32_t *nfire) {
+  const uint32_t buf = (uint32_t)(e & 1);
+  const Bins &in = L.bins[buf];
+  const uint32_t ncand = L.n_fo ? min(L.cand_count[buf], (uint32_t)L.cand_cap) : 0u;
+  for (uint32_t q = first; q < ncand; q += stride) {
+    const uint32_t c = L.cand_col[buf][q], pos = L.cand_pos[buf][q], id = L.cand_id[buf][q];
+    const uint32_t v = in.vox[c * L.cap + pos];
+    const uint32_t sp = L.occ[v] & 63u;
+    if (!(L.sp_flags[sp] & kSpFirstOrder)) continue;
+    const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
+    const int rx = first_order_choice(L, e, sp, r.x);
+    if (rx < 0) continue;
+    const uint32_t slot = atomicAdd(nfire, 1u);
+    L.fire_pos[slot] = pos;
+    L.fire_id[slot] = id;
+    L.fire_col[slot] = (uint8_t)c;
+    L.fire_rx[slot] = (uint8_t)rx;
+  }
+}
+
+// the event's opening work for one lattice, by one workgroup; decided: the
+// fire list was built by k_decide
+__device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
   uint32_t *__restrict__ fire_pos = L.fire_pos;
   uint32_t *__restrict__ fire_id = L.fire_id;
   uint8_t *__restrict__ fire_col = L.fire_col;
@@ -243,23 +271,12 @@ __device__ __forceinline__ void begin_work(const LatDev &L) {
   __syncthreads();
   if (tid < (int)ncol) L.perm[tid] = s_perm[tid];
 
-  // ---- first-order decisions (independent of order: species of a candidate
-  // cannot change before its own turn) ----
-  const uint32_t ncand = L.n_fo ? min(L.cand_count[buf], (uint32_t)L.cand_cap) : 0u;
-  for (uint32_t q = tid; q < ncand; q += blockDim.x) {
-    const uint32_t c = L.cand_col[buf][q], pos = L.cand_pos[buf][q], id = L.cand_id[buf][q];
-    const uint32_t v = in.vox[c * L.cap + pos];
-    const uint32_t sp = L.occ[v] & 63u;
-    if (!(L.sp_flags[sp] & kSpFirstOrder)) continue;
-    const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
-    const int rx = first_order_choice(L, e, sp, r.x);
-    if (rx < 0) continue;
-    const uint32_t slot = atomicAdd(&s_nfire, 1u);
-    fire_pos[slot] = pos;
-    fire_id[slot] = id;
-    fire_col[slot] = (uint8_t)c;
-    fire_rx[slot] = (uint8_t)rx;
-  }
+  // ---- first-order decisions ----
+  if (!decided)
+    decide_first_order(L, e, tid, blockDim.x, &s_nfire);
+  else if (tid == 0)
+    s_nfire = min(__hip_atomic_load(L.fire_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                  (uint32_t)L.cap);
   __syncthreads();
   const uint32_t nfire = s_nfire;
 
@@ -370,10 +387,11 @@ __device__ __forceinline__ void begin_work(const LatDev &L) {
 // bins) and the event, so that a stage launch starts with one load instead of
 // a chain of three.  A lattice that does not run this event (idle or out of
 // tape) gets empty stages, and so do the stages past its colour count.
-__device__ __forceinline__ void begin_body(const LatDev &L) {
-  begin_work(L);
+__device__ __forceinline__ void begin_body(const LatDev &L, bool decided) {
+  begin_work(L, decided);
   __syncthreads();  // every return of begin_work is taken by the whole block
   const uint32_t tid = threadIdx.x;
+  if (tid == 0 && decided) *L.fire_count = 0;  // k_decide's list has been applied
   if (tid < kMaxColours) {
     const uint64_t e = *L.ev;
     const bool run = e < L.tape_horizon && e < L.stop_event && tid < L.ncol;
@@ -384,13 +402,24 @@ __device__ __forceinline__ void begin_body(const LatDev &L) {
   }
 }
 
-__global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restrict__ Lp) {
-  begin_body(*Lp);
+__global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restrict__ Lp,
+                                                         int decided) {
+  begin_body(*Lp, decided != 0);
 }
 
 // one workgroup per member lattice of an ensemble
 __global__ void __launch_bounds__(kBeginThreads) k_begin_multi(const LatDev *__restrict__ lats) {
-  begin_body(lats[blockIdx.x]);
+  begin_body(lats[blockIdx.x], false);
+}
+
+// the first-order decisions of the coming event over many workgroups, for
+// events with many candidates (k_begin then only applies the fire list)
+__global__ void __launch_bounds__(kStageThreads) k_decide(const LatDev *__restrict__ Lp) {
+  const LatDev &L = *Lp;
+  const uint64_t e = *L.ev;
+  if (e >= L.stop_event || e >= L.tape_horizon) return;
+  decide_first_order(L, e, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
+                     L.fire_count);
 }
 
 // =============================================================================
@@ -1017,8 +1046,10 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_begin(const LatDev *dL, hipStream_t s) {
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL);
+hipError_t launch_begin(const LatDev *dL, int decide_grid, hipStream_t s) {
+  if (decide_grid > 0)
+    hipLaunchKernelGGL(k_decide, dim3(decide_grid), dim3(kStageThreads), 0, s, dL);
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, decide_grid > 0 ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1052,8 +1083,8 @@ hipError_t launch_end(const LatDev *dL, hipStream_t s) {
 }
 
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
-                        hipStream_t s) {
-  hipError_t err = launch_begin(dL, s);
+                        int decide_grid, hipStream_t s) {
+  hipError_t err = launch_begin(dL, decide_grid, s);
   const uint32_t stages = fcc ? kColoursFcc : kColoursHcp;
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
     err = launch_stage(dL, g, grid, items, disp, fcc, s);

@@ -339,6 +339,20 @@ def test_multiproduct_collisions(seed, boundary):
     assert s["fired"][0] > 0 and s["fired"][1] > 0 and s["place_fail"] > 0, (s["fired"], s["place_fail"])
 
 
+def test_first_order_decisions_over_workgroups():
+    """Events with many first-order candidates (here ~10 k: a fast decay on
+    ~80 k walkers) take their decisions in a launch of many workgroups
+    instead of inside the one-workgroup first-order pass; the result is the
+    oracle's either way, over event splits and launch shapes."""
+    w = workload("multiproduct", dims=(96, 96, 64), seed=9, n_a=40000)
+    g, s = run_pair(w, 30, chunks=3)
+    assert s["fired"][2] > 20000, s["fired"]       # C -> 0 fired a lot
+    lat = build_gpu(w)
+    lat.set_launch(1, 33)
+    lat.step(30)
+    assert_same(lat.read_state(), s)
+
+
 def test_multiproduct_collisions_many_events_and_shapes():
     w = workload("multiproduct", dims=(48, 48, 32), seed=6, n_a=6000)
     nv = 48 * 48 * 32

@@ -213,6 +213,37 @@ def test_walls_flag_is_accepted_and_unknown_flags_rejected():
     d.voxel_radius = 4.4e-9
     d.seed = 1
     d.max_molecules = 64
-    d.flags = 8
+    d.flags = 16
     h = psc.C.c_void_p()
     assert psc.lib().psc_create_lattice(psc.C.byref(d), psc.C.byref(h)) == psc.PSC_EINVAL
+
+
+@pytest.mark.parametrize("nk,ok", [(12, True), (24, True), (8, False), (16, False), (20, False)])
+def test_fcc_flag_needs_a_k_edge_of_whole_stacking_and_colour_periods(nk, ok):
+    # ABC stacking repeats every 3 layers and bricks every 4: nk % 12 == 0
+    d = psc.Desc()
+    d.ni, d.nj, d.nk = 8, 8, nk
+    d.voxel_radius = 4.4e-9
+    d.seed = 1
+    d.max_molecules = 64
+    d.flags = psc.LATTICE_FCC | psc.BOUNDARY_WALLS
+    h = psc.C.c_void_p()
+    rc = psc.lib().psc_create_lattice(psc.C.byref(d), psc.C.byref(h))
+    assert (rc == psc.PSC_OK) == ok
+    if ok:
+        psc.lib().psc_destroy(h)
+    else:
+        assert rc == psc.PSC_EINVAL and "12" in psc.lib().psc_last_error(None).decode()
+
+
+def test_host_placement_on_an_fcc_lattice_matches_oracle():
+    w = dict(workload("small_reactive", dims=(16, 12, 12)), lattice="fcc")
+    lat = psc.lattice_from_workload(w, device=0)
+    o = oracle.Oracle(w["dims"], w["rv"], w["seed"], lattice=oracle.FCC)
+    for _, D in w["species"]:
+        o.add_species(D)
+    for sp, c in w["place"]:
+        o.place_uniform(sp, c)
+    a, b = lat.read_state(), o.state()
+    for key in ("occ", "id", "vox", "species"):
+        assert np.array_equal(a[key], b[key]), key

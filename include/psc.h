@@ -4,9 +4,10 @@
  * Parallel Stochastic Method for Particle Reaction-Diffusion Systems").
  *
  * Model (paper section in brackets):
- *   - space is a hexagonal close-packed lattice of voxels of radius r, held
- *     in twisted Cartesian coordinates (i, j, k); each voxel holds at most one
- *     molecule and has 12 neighbours at distance 2r          [2.1, Fig. 3]
+ *   - space is a hexagonal close-packed lattice of voxels of radius r (or,
+ *     with PSC_LATTICE_FCC, a face-centred cubic one), held in twisted
+ *     Cartesian coordinates (i, j, k); each voxel holds at most one molecule
+ *     and has 12 neighbours at distance 2r                   [2.1, Fig. 3]
  *   - every species s with D_s > 0 has diffusion events every
  *     tau_s = 2 r^2 / (3 D_s); in an event each of its molecules picks one of
  *     its 12 neighbours at random and hops there only if it is vacant  [2.3]
@@ -263,8 +264,9 @@ psc_status psc_get_launch(const psc_lattice *h, psc_launch *out);
 
 /* Per-kernel device time of the steps run while timing is on, measured with
  * HIP events recorded on the step's stream around every launch:
- * begin = stage order + first-order pass, stage = one colour stage of the
- * walk, end = flag sweep. */
+ * begin = stage order + first-order pass (with its separate decision launch
+ * when an event expects many first-order candidates), stage = one colour
+ * stage of the walk, end = flag sweep and numbering of collision newborns. */
 typedef struct psc_kernel_times {
   double begin_ms, stage_ms, end_ms;
   uint64_t begin_launches, stage_launches, end_launches;

@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(kStageThreads) k_scan_candidates(const LatDev 
 // =============================================================================
 // k_begin: stage order, first-order pass, newborn ids
 // =============================================================================
-constexpr uint32_t kSortLds = 2048;  // birth keys sorted in LDS up to this count
+constexpr uint32_t kSortLds = 2048;  // newborn keys ranked in LDS up to this count
 
 __device__ __forceinline__ void bitonic_sort_keys(uint64_t *keys, uint32_t n2, int tid, int nthreads) {
   for (uint32_t k = 2; k <= n2; k <<= 1) {
@@ -148,6 +148,32 @@ __device__ __forceinline__ void bitonic_sort_keys(uint64_t *keys, uint32_t n2, i
       __syncthreads();
     }
   }
+}
+
+// For each of the nb distinct keys in LDS, f(key, rank) with rank = the
+// number of smaller keys.  Each thread holds up to PER keys (PER * nthreads
+// >= nb) and reads the list once.
+template <int PER, class F>
+__device__ __forceinline__ void for_each_ranked(const uint64_t *keys, uint32_t nb, uint32_t tid,
+                                                uint32_t nthreads, F f) {
+  uint64_t mine[PER];
+  uint32_t rank[PER];
+#pragma unroll
+  for (int a = 0; a < PER; ++a) {
+    const uint32_t q = tid + a * nthreads;
+    mine[a] = q < nb ? keys[q] : ~0ull;
+    rank[a] = 0;
+  }
+  // eight LDS reads in flight per step
+#pragma unroll 8
+  for (uint32_t j = 0; j < nb; ++j) {
+    const uint64_t k = keys[j];
+#pragma unroll
+    for (int a = 0; a < PER; ++a) rank[a] += k < mine[a] ? 1u : 0u;
+  }
+#pragma unroll
+  for (int a = 0; a < PER; ++a)
+    if (tid + a * nthreads < nb) f(mine[a], rank[a]);
 }
 
 // one first-order firing of the molecule at (colour c, position pos): the
@@ -340,35 +366,26 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
     __syncthreads();
   }
 
-  // ---- newborn ids: ascending parent id, then product index ----
+  // ---- newborn ids: ascending parent id, then product index.  The keys are
+  // distinct (they end in the birth's slot), so a newborn's id is next_id
+  // plus the number of smaller keys: counted in LDS up to kSortLds newborns,
+  // else read off a bitonic sort in global memory ----
   const uint32_t nb = min(s_nb, (uint32_t)L.birth_cap);
   if (nb == 0) return;
-  uint32_t n2 = 1;
-  while (n2 < nb) n2 <<= 1;
-  uint64_t *keys = L.birth_key;
-  if (n2 <= kSortLds) {
-    for (uint32_t q = tid; q < n2; q += blockDim.x) s_keys[q] = q < nb ? L.birth_key[q] : ~0ull;
-    __syncthreads();
-    keys = s_keys;
-  } else {
-    for (uint32_t q = nb + tid; q < n2; q += blockDim.x) L.birth_key[q] = ~0ull;
-    __syncthreads();
-  }
-  bitonic_sort_keys(keys, n2, tid, blockDim.x);
   const uint32_t base_id = s_next;
   if ((uint64_t)base_id + nb >= 0xFFFFFFFFull) {
     if (tid == 0) set_error(L, kErrIds);
     return;
   }
-  for (uint32_t q = tid; q < nb; q += blockDim.x) {
-    const uint32_t src = (uint32_t)(keys[q] & ((1u << 27) - 1u));
+  auto bin_birth = [&](uint64_t key, uint32_t id) {
+    const uint32_t src = (uint32_t)(key & ((1u << 27) - 1u));
     const uint32_t v = L.birth_vox[src];
     const uint32_t c = colour_of_voxel(L.geo, v);
     const uint32_t pos = atomicAdd(&in.count[c], 1u);
     if (pos < L.cap) {
       const uint64_t at = c * L.cap + pos;
       in.vox[at] = v;
-      in.id[at] = base_id + q;
+      in.id[at] = id;
       in.sp[at] = L.birth_sp[src];
       if (in.disp) {
         in.disp[(0 * ncol + c) * L.cap + pos] = 0;
@@ -378,6 +395,19 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
     } else {
       set_error(L, kErrBinOverflow);
     }
+  };
+  if (nb <= kSortLds) {
+    for (uint32_t q = tid; q < nb; q += blockDim.x) s_keys[q] = L.birth_key[q];
+    __syncthreads();
+    for_each_ranked<kSortLds / kBeginThreads>(
+        s_keys, nb, tid, kBeginThreads, [&](uint64_t k, uint32_t r) { bin_birth(k, base_id + r); });
+  } else {
+    uint32_t n2 = 1;
+    while (n2 < nb) n2 <<= 1;
+    for (uint32_t q = nb + tid; q < n2; q += blockDim.x) L.birth_key[q] = ~0ull;
+    __syncthreads();
+    bitonic_sort_keys(L.birth_key, n2, tid, blockDim.x);
+    for (uint32_t q = tid; q < nb; q += blockDim.x) bin_birth(L.birth_key[q], base_id + q);
   }
   if (tid == 0) *L.next_id = base_id + nb;
 }
@@ -878,17 +908,6 @@ __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
   const uint32_t tid = threadIdx.x;
   const uint32_t nb = min(*L.wb_count, (uint32_t)L.wb_cap);
   if (nb == 0) return;
-  uint32_t n2 = 1;
-  while (n2 < nb) n2 <<= 1;  // <= wb_cap, a power of two
-  uint64_t *keys = L.wb_key;
-  if (n2 <= kSortLds) {
-    for (uint32_t q = tid; q < n2; q += blockDim.x) s_wkeys[q] = q < nb ? L.wb_key[q] : ~0ull;
-    keys = s_wkeys;
-  } else {
-    for (uint32_t q = nb + tid; q < n2; q += blockDim.x) L.wb_key[q] = ~0ull;
-  }
-  __syncthreads();
-  bitonic_sort_keys(keys, n2, tid, blockDim.x);
   const uint32_t base_id = *L.next_id;
   if ((uint64_t)base_id + nb >= 0xFFFFFFFFull) {
     if (tid == 0) set_error(L, kErrIds);
@@ -897,14 +916,15 @@ __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
   const Bins &out = L.bins[(e + 1) & 1];
   const uint32_t cnext = (uint32_t)((e + 1) & 1);
   const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
-  for (uint32_t q = tid; q < nb; q += blockDim.x) {
-    const uint32_t u = L.wb_vox[keys[q] & ((1u << 28) - 1u)];
-    const uint32_t id = base_id + q;
+  // the newborn of key `key` gets id `id` (keys are distinct: they end in the
+  // slot; its id is next_id plus the number of smaller keys)
+  auto bin_newborn = [&](uint64_t key, uint32_t id) {
+    const uint32_t u = L.wb_vox[key & ((1u << 28) - 1u)];
     const uint32_t c = colour_of_voxel(L.geo, u);
     const uint32_t pos = atomicAdd(&out.count[c], 1u);
     if (pos >= L.cap) {
       set_error(L, kErrBinOverflow);
-      continue;
+      return;
     }
     const uint64_t at = c * L.cap + pos;
     out.vox[at] = u;
@@ -928,6 +948,19 @@ __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
         }
       }
     }
+  };
+  if (nb <= kSortLds) {
+    for (uint32_t q = tid; q < nb; q += blockDim.x) s_wkeys[q] = L.wb_key[q];
+    __syncthreads();
+    for_each_ranked<kSortLds / kEndThreads>(
+        s_wkeys, nb, tid, kEndThreads, [&](uint64_t k, uint32_t r) { bin_newborn(k, base_id + r); });
+  } else {
+    uint32_t n2 = 1;
+    while (n2 < nb) n2 <<= 1;  // <= wb_cap, a power of two
+    for (uint32_t q = nb + tid; q < n2; q += blockDim.x) L.wb_key[q] = ~0ull;
+    __syncthreads();
+    bitonic_sort_keys(L.wb_key, n2, tid, blockDim.x);
+    for (uint32_t q = tid; q < nb; q += blockDim.x) bin_newborn(L.wb_key[q], base_id + q);
   }
   __syncthreads();
   if (tid == 0) {

@@ -353,6 +353,27 @@ def test_first_order_decisions_over_workgroups():
     assert_same(lat.read_state(), s)
 
 
+@pytest.mark.parametrize("events", [1, 6])
+def test_more_newborns_per_event_than_the_lds_numbering_holds(events):
+    """Newborn ids come from the rank of each birth key among the event's keys,
+    counted in LDS up to 2048 newborns; beyond that the keys are sorted in
+    global memory.  Here both kinds of births pass 2048 in every event:
+    A -> A + C (a fast decay: ~2.7 k first-order newborns) and
+    A + B -> A + B + C with p = 1 at 15 % occupancy of B (~3.6 k collision
+    newborns)."""
+    w = dict(name="births", dims=(64, 64, 64), rv=4.4e-9, seed=5,
+             species=[("A", 1e-12), ("B", 1e-12), ("C", 0.0)],
+             reactions=[((1,), (1, 3), 20000.0), ((1, 2), (1, 2, 3), 1e-15)],
+             place=[(1, 12000), (2, 40000)], events=events, track_displacement=True)
+    lat = build_gpu(w, max_molecules=64 ** 3)
+    o = build_oracle(w)
+    lat.step(events)
+    o.run(events, oracle.MODE_C)
+    s = o.state()
+    assert_same(lat.read_state(), s)
+    assert s["fired"][0] > 2048 * events and s["fired"][1] > 2048 * events, s["fired"]
+
+
 def test_multiproduct_collisions_many_events_and_shapes():
     w = workload("multiproduct", dims=(48, 48, 32), seed=6, n_a=6000)
     nv = 48 * 48 * 32

@@ -85,6 +85,16 @@ psc_status fail(psc_lattice *h, psc_status code, const char *fmt, ...) {
       return fail((h), PSC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+// A transient device buffer, freed when the scope ends (also on the early
+// returns of a failed HIP call).
+struct DevTemp {
+  void *p = nullptr;
+  ~DevTemp() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes); }
+};
+
 void *dev_alloc(psc_lattice *h, size_t bytes) {
   if (bytes == 0) bytes = 16;
   bytes = (bytes + 255) & ~size_t(255);
@@ -394,13 +404,12 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   HIP_OK(h, up(d_fo_n, h->fo_n.data(), 64));
   if (!h->fo_rx.empty()) HIP_OK(h, up(d_fo_rx, h->fo_rx.data(), h->fo_rx.size() * sizeof(uint16_t)));
   if (h->geo.brick) {
-    uint16_t *tmp = nullptr;
-    if (hipMalloc(&tmp, h->nv * sizeof(uint16_t)) != hipSuccess)
+    DevTemp tmp;
+    if (tmp.alloc(h->nv * sizeof(uint16_t)) != hipSuccess)
       return fail(h, PSC_ENOMEM, "transient device buffer for the layout change failed");
-    HIP_OK(h, up(tmp, h->occ.data(), h->nv * sizeof(uint16_t)));
-    HIP_OK(h, launch_relayout(h->geo, h->nv, tmp, L.occ, true, stream));
+    HIP_OK(h, up(tmp.p, h->occ.data(), h->nv * sizeof(uint16_t)));
+    HIP_OK(h, launch_relayout(h->geo, h->nv, (const uint16_t *)tmp.p, L.occ, true, stream));
     HIP_OK(h, hipStreamSynchronize(stream));
-    HIP_OK(h, hipFree(tmp));
   } else {
     HIP_OK(h, up(L.occ, h->occ.data(), h->nv * sizeof(uint16_t)));
   }
@@ -942,12 +951,12 @@ psc_status psc_read_stats(psc_lattice *h, uint64_t *species_count, uint64_t *dis
     for (size_t s = 0; s < h->species.size(); ++s) species_count[s] = c[s];
   }
   if (disp_sum || n_walkers) {
-    unsigned long long *d = nullptr, out[2] = {0, 0};
-    HIP_OK(h, hipMalloc(&d, sizeof out));
-    HIP_OK(h, hipMemset(d, 0, sizeof out));
-    HIP_OK(h, launch_msd(h->dL, d, nullptr));
-    HIP_OK(h, hipMemcpy(out, d, sizeof out, hipMemcpyDeviceToHost));
-    HIP_OK(h, hipFree(d));
+    unsigned long long out[2] = {0, 0};
+    DevTemp d;
+    HIP_OK(h, d.alloc(sizeof out));
+    HIP_OK(h, hipMemset(d.p, 0, sizeof out));
+    HIP_OK(h, launch_msd(h->dL, (unsigned long long *)d.p, nullptr));
+    HIP_OK(h, hipMemcpy(out, d.p, sizeof out, hipMemcpyDeviceToHost));
     // static molecules never move, but a loaded state may give them a
     // displacement
     for (size_t q = 0; q < h->st_id.size(); ++q) {
@@ -1115,12 +1124,11 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
   }
   if (occp) {
     if (h->geo.brick) {
-      uint16_t *tmp = nullptr;
-      if (hipMalloc(&tmp, h->nv * sizeof(uint16_t)) != hipSuccess)
+      DevTemp tmp;
+      if (tmp.alloc(h->nv * sizeof(uint16_t)) != hipSuccess)
         return fail(h, PSC_ENOMEM, "transient device buffer for the layout change failed");
-      HIP_OK(h, launch_relayout(h->geo, h->nv, L.occ, tmp, false, nullptr));
-      HIP_OK(h, hipMemcpy(occp, tmp, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
-      HIP_OK(h, hipFree(tmp));
+      HIP_OK(h, launch_relayout(h->geo, h->nv, L.occ, (uint16_t *)tmp.p, false, nullptr));
+      HIP_OK(h, hipMemcpy(occp, tmp.p, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
     } else {
       HIP_OK(h, hipMemcpy(occp, L.occ, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
     }

@@ -220,7 +220,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="cfg3",
                     choices=["cfg1", "cfg2", "cfg3", "mapk_paper", "multiproduct"])
-    ap.add_argument("--timing-steps", type=int, default=40)
+    ap.add_argument("--timing-steps", type=int, default=40,
+                    help="events of the timed region whose launches are timed one by one")
     ap.add_argument("--walls", action="store_true",
                     help="close the workload's box by walls instead of wrapping it")
     ap.add_argument("--fcc", action="store_true",
@@ -275,34 +276,48 @@ def main():
     setup_s = time.perf_counter() - t_setup
     print("setup + warmup %.1f s" % setup_s, file=sys.stderr, flush=True)
 
-    # ---- timed region: K events, HIP events on the launch stream ----
+    # ---- timed region: K events, HIP events on the launch stream.  Every
+    # (K / timing_steps)-th event also records HIP events around each of its
+    # launches (switching that on and off never waits for the device), so
+    # the walk stage's average launch time is measured over the timed region
+    # itself ----
+    stages = 24 if w.get("lattice") == "fcc" else 16
+    every = max(args.steps // max(args.timing_steps, 1), 1)
+    lat.set_kernel_timing(True)
+    lat.set_kernel_timing(False)
     c0 = lat.counters()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
-    lat.step(args.steps)
+    done = 0
+    while done < args.steps:
+        n = min(every - 1, args.steps - done)
+        if n:
+            lat.step(n)
+            done += n
+        if done < args.steps:
+            lat.set_kernel_timing(True, keep=True)
+            lat.step(1)
+            lat.set_kernel_timing(False)
+            done += 1
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     c1 = lat.counters()
     attempts = c1["attempts"] - c0["attempts"]
     hops = c1["hops"] - c0["hops"]
+    kt = lat.kernel_times()
     print("timed %d events: %.2f ms, %d attempts" % (args.steps, ms, attempts), file=sys.stderr,
           flush=True)
 
-    # ---- per-kernel times of the dominant kernel (the walk stage) ----
-    lat.set_kernel_timing(True)
-    c2 = lat.counters()
-    lat.step(args.timing_steps)
-    kt = lat.kernel_times()
-    c3 = lat.counters()
-    lat.set_kernel_timing(False)
-    t_att = c3["attempts"] - c2["attempts"]
-    t_hop = c3["hops"] - c2["hops"]
-    stage_launches = max(kt["stage_launches"], 1)
-    stage_avg_ms = kt["stage_ms"] / stage_launches
-    alg_bytes_per_launch = (6.0 * t_att + 8.0 * t_hop) / stage_launches
+    # ---- the dominant kernel (the walk stage) against the HBM roofline:
+    # algorithmic bytes of the timed region per stage launch over the
+    # sampled launches' average time ----
+    stage_avg_ms = kt["stage_ms"] / max(kt["stage_launches"], 1)
+    launches = args.steps * stages
+    t_att = attempts / launches
+    alg_bytes_per_launch = (6.0 * attempts + 8.0 * hops) / launches
     achieved = alg_bytes_per_launch / (stage_avg_ms * 1e-3) / 1e9
     traffic = read_traffic(w["name"])
     lat.close()
@@ -330,15 +345,16 @@ def main():
                      "traffic": traffic["per_dispatch"] if traffic else None,
                      "kernel": "k_stage (one colour stage of the walk)",
                      "avg_launch_ms": stage_avg_ms,
+                     "timed_launches_sampled": kt["stage_launches"],
                      "algorithmic_bytes_per_launch": alg_bytes_per_launch,
-                     "attempts_per_launch": t_att / stage_launches,
+                     "attempts_per_launch": t_att,
                      # measured HBM bytes per attempt (profile), the rate they
                      # imply at the live launch time, and the share of them the
                      # method needs
                      "traffic_per_attempt": traffic["per_attempt"] if traffic else None,
-                     "traffic_gbs": (traffic["per_attempt"] * t_att / stage_launches
+                     "traffic_gbs": (traffic["per_attempt"] * t_att
                                      / (stage_avg_ms * 1e-3) / 1e9 if traffic else None),
-                     "useful_byte_fraction": (alg_bytes_per_launch * stage_launches / t_att
+                     "useful_byte_fraction": (alg_bytes_per_launch / t_att
                                               / traffic["per_attempt"] if traffic else None)},
     }
     if not args.no_ensemble:

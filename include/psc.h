@@ -272,12 +272,15 @@ typedef struct psc_kernel_times {
   uint64_t begin_launches, stage_launches, end_launches;
 } psc_kernel_times;
 
-/* Turns per-launch timing on (1) or off (0) and clears the totals.  Timing
- * adds two event records per launch; leave it off for throughput runs. */
+/* Per-launch timing: 1 turns it on and clears the totals (waits for the
+ * device), 0 turns it off and 2 turns it back on, both keeping the totals and
+ * without waiting, so that a sample of the events of a timed run can be
+ * measured without stalling it.  Timing adds two event records per launch;
+ * leave it off for throughput runs.  Other values: PSC_EINVAL. */
 psc_status psc_set_kernel_timing(psc_lattice *h, int enable);
 
-/* Waits for the timed work and returns the totals since timing was turned
- * on. */
+/* Waits for the timed work and returns the totals since timing was last
+ * turned on with 1. */
 psc_status psc_get_kernel_times(psc_lattice *h, psc_kernel_times *out);
 
 /* ---- ensembles ---------------------------------------------------------------

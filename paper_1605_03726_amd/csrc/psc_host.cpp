@@ -997,7 +997,10 @@ psc_status psc_get_launch(const psc_lattice *h, psc_launch *out) {
 psc_status psc_set_kernel_timing(psc_lattice *h, int enable) {
   if (!h) return PSC_EINVAL;
   if (h->poisoned) return PSC_EDEVICE;
-  if (!h->timed.empty()) {
+  if (enable < 0 || enable > 2) return fail(h, PSC_EINVAL, "timing mode must be 0, 1 or 2");
+  // 0 and 2 only switch recording (no synchronisation): a caller may time a
+  // sample of the events of a run without stalling it
+  if (enable == 1 && !h->timed.empty()) {
     HIP_OK(h, hipSetDevice(h->desc.device));
     HIP_OK(h, hipDeviceSynchronize());
     for (auto &t : h->timed) {

@@ -318,8 +318,11 @@ class Lattice:
                                           C.byref(nw)))
         return {"species_count": counts, "disp_sum": dsum.value, "n_walkers": nw.value}
 
-    def set_kernel_timing(self, on: bool):
-        self._check(self.L.psc_set_kernel_timing(self.h, 1 if on else 0))
+    def set_kernel_timing(self, on: bool, keep: bool = False):
+        """on: record per-launch times (clearing the totals unless keep);
+        off keeps the totals.  Switching with keep never waits for the
+        device."""
+        self._check(self.L.psc_set_kernel_timing(self.h, (2 if keep else 1) if on else 0))
 
     def kernel_times(self) -> dict:
         t = KernelTimes()

@@ -247,3 +247,15 @@ def test_host_placement_on_an_fcc_lattice_matches_oracle():
     a, b = lat.read_state(), o.state()
     for key in ("occ", "id", "vox", "species"):
         assert np.array_equal(a[key], b[key]), key
+
+
+def test_kernel_timing_modes():
+    # 1 on (clears), 0 off and 2 on again (both keep the totals, no waiting);
+    # anything else is rejected
+    lat = psc.Lattice((8, 8, 8), 4.4e-9, 1, 64, torch_allocator=False)
+    for mode in (1, 0, 2, 0):
+        assert psc.lib().psc_set_kernel_timing(lat.h, mode) == psc.PSC_OK
+    for mode in (-1, 3):
+        assert psc.lib().psc_set_kernel_timing(lat.h, mode) == psc.PSC_EINVAL
+    assert lat.kernel_times()["stage_launches"] == 0
+    lat.close()

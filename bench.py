@@ -226,7 +226,8 @@ def main():
                     help="close the workload's box by walls instead of wrapping it")
     ap.add_argument("--fcc", action="store_true",
                     help="the workload on the FCC lattice (nk rounded down to a multiple of 12)")
-    ap.add_argument("--cpu-events", type=int, default=2)
+    ap.add_argument("--cpu-events", type=int, default=4,
+                    help="events of the workload the CPU oracle runs (about 10-30 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-only", action="store_true")

@@ -356,7 +356,13 @@ def main():
                      "traffic_gbs": (traffic["per_attempt"] * t_att
                                      / (stage_avg_ms * 1e-3) / 1e9 if traffic else None),
                      "useful_byte_fraction": (alg_bytes_per_launch / t_att
-                                              / traffic["per_attempt"] if traffic else None)},
+                                              / traffic["per_attempt"] if traffic else None),
+                     # the HBM rate a walk that streams the whole lattice (read
+                     # and write 2 B per voxel per event) would need for the
+                     # same event rate, as a fraction of the peak
+                     "stream_equivalent_gbs": 4.0 * nv / (ms / args.steps * 1e-3) / 1e9,
+                     "stream_equivalent_frac": 4.0 * nv / (ms / args.steps * 1e-3) / 1e9
+                                               / HBM_PEAK_GBS},
     }
     if not args.no_ensemble:
         result["ensemble"] = ensemble_bench(args.ensemble_members, args.ensemble_events, 12, 300, 3)

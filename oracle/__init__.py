@@ -65,6 +65,7 @@ def lib() -> C.CDLL:
     L.orc_n_colours.restype = C.c_int
     L.orc_stage_order_n.argtypes = [C.c_uint64, C.c_uint64, C.c_int, C.POINTER(C.c_uint8)]
     L.orc_neighbour_table.argtypes = [C.c_uint32] * 3 + [u32p]
+    L.orc_neighbour_table_l.argtypes = [C.c_uint32] * 3 + [C.c_int, C.c_int, u32p]
     L.orc_hop_vector.argtypes = [C.c_uint32] * 4 + [C.c_int, C.POINTER(C.c_int32)]
     L.orc_position.argtypes = [C.c_uint32] * 4 + [C.c_double, C.POINTER(C.c_double)]
     L.orc_colour.argtypes = [C.c_uint32] * 4
@@ -149,6 +150,14 @@ def neighbour_table(dims) -> np.ndarray:
     nv = int(dims[0]) * int(dims[1]) * int(dims[2])
     out = np.zeros(nv * 12, np.uint32)
     lib().orc_neighbour_table(dims[0], dims[1], dims[2], _p(out, C.c_uint32))
+    return out.reshape(nv, 12)
+
+
+def neighbour_table_l(dims, lattice: int, boundary: int = PERIODIC) -> np.ndarray:
+    nv = int(dims[0]) * int(dims[1]) * int(dims[2])
+    out = np.zeros(nv * 12, np.uint32)
+    lib().orc_neighbour_table_l(dims[0], dims[1], dims[2], lattice, boundary,
+                                _p(out, C.c_uint32))
     return out.reshape(nv, 12)
 
 

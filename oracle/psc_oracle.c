@@ -195,6 +195,14 @@ uint32_t orc_neighbour_b(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int 
   return orc_neighbour_l(ni, nj, nk, v, n, ORC_LATTICE_HCP, boundary);
 }
 
+void orc_neighbour_table_l(uint32_t ni, uint32_t nj, uint32_t nk, int lattice, int boundary,
+                           uint32_t *out) {
+  uint64_t nv = (uint64_t)ni * nj * nk;
+  for (uint64_t v = 0; v < nv; v++)
+    for (int n = 0; n < 12; n++)
+      out[12 * v + n] = orc_neighbour_l(ni, nj, nk, (uint32_t)v, n, lattice, boundary);
+}
+
 void orc_neighbour_table(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t *out) {
   uint64_t nv = (uint64_t)ni * nj * nk;
   for (uint64_t v = 0; v < nv; v++)

@@ -95,6 +95,9 @@ int orc_n_colours(int lattice);
 void orc_stage_order_n(uint64_t seed, uint64_t event, int n, uint8_t *out);
 /* out[12 v + n] = orc_neighbour(v, n) for every voxel */
 void orc_neighbour_table(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t *out);
+/* out[12 v + n] = orc_neighbour_l(v, n, lattice, boundary) for every voxel */
+void orc_neighbour_table_l(uint32_t ni, uint32_t nj, uint32_t nk, int lattice, int boundary,
+                           uint32_t *out);
 void orc_hop_vector(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int n,
                     int32_t out[3]);
 void orc_position(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, double rv,

@@ -12,7 +12,8 @@ Pins that do not re-derive the oracle's stencil:
 - stacking: layer k and k + 3 coincide in projection, k, k + 1, k + 2 are
   pairwise disjoint (ABC), packing fraction pi / (3 sqrt 2);
 - the coordination sequence of the fcc net, 12, 42, 92 (it differs from the
-  hcp net's 12, 44, 96, so an HCP stencil fails it);
+  hcp net's 12, 44, 96, so an HCP stencil fails it), and the fcc lattice's
+  numbers of closed n-step walks, n <= 8, from every layer phase;
 - the 24 stage colours split the voxels evenly and every class is an
   independent set at graph distance <= 2 (what lets a stage run in any order);
 - the walk: lone walkers have MSD 6 D t; runs in reversed intra-stage order
@@ -130,6 +131,32 @@ def shells(dims, lattice, depth=3):
 def test_coordination_sequence_of_the_fcc_net():
     assert shells((16, 16, 24), F) == [12, 42, 92]
     assert shells((16, 16, 24), oracle.HCP) == [12, 44, 96]
+
+
+# closed n-step walks on the fcc lattice, n = 0..8 (a classical lattice
+# count, Domb 1960; OEIS A002899)
+FCC_CLOSED_WALKS = [1, 0, 12, 48, 540, 4320, 42240, 403200, 4038300]
+
+
+def test_closed_walk_counts_of_the_fcc_lattice():
+    """Counted exactly from the oracle's stencil with integer powers of the
+    adjacency matrix, on a box too large for a walk of 8 steps to wrap, from
+    voxels in each of the three layer phases (FCC is a Bravais lattice: every
+    site sees the same counts)."""
+    import scipy.sparse as sp
+    dims = (24, 24, 24)
+    nb = oracle.neighbour_table_l(dims, F)
+    nv = nb.shape[0]
+    A = sp.csr_matrix((np.ones(nv * 12, np.int64), (nb.ravel(), np.repeat(np.arange(nv), 12))),
+                      shape=(nv, nv))
+    for start in (0, 24 * 24 * 1 + 5 * 24 + 7, 24 * 24 * 2 + 11 * 24 + 3):
+        p = np.zeros(nv, np.int64)
+        p[start] = 1
+        counts = []
+        for _ in FCC_CLOSED_WALKS:
+            counts.append(int(p[start]))
+            p = A @ p
+        assert counts == FCC_CLOSED_WALKS, (start, counts)
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 12), (8, 8, 12), (8, 4, 24), (12, 8, 12)])

@@ -1,8 +1,7 @@
 """Benchmark of the lattice walk on one MI355X.
 
 One step = one diffusion event of the whole hot path (first-order pass, the 16
-colour stages of the walk -- 24 on the FCC lattice -- with collision reactions,
-re-binning, flag sweep)
+colour stages of the walk with collision reactions, re-binning, flag sweep)
 over the workload's lattice.  Default workload: the 2^32-voxel MAPK-style
 lattice (2048 x 2048 x 1024, 0.3 % occupancy, 10 species, 8 second-order and
 10 first-order reactions), inputs resident in HBM before timing starts.
@@ -261,10 +260,11 @@ def main():
 
     w = pick_workload(args.workload)
     if args.fcc:
+        # FCC boxes: i and j edges multiples of 8, k of 12
         ni, nj, nk = (int(x) for x in w["dims"])
-        nk12 = 12 * (nk // 12)
-        w = dict(w, lattice="fcc", dims=(ni, nj, nk12),
-                 name=w["name"].replace("x%d" % nk, "x%d" % nk12) + "_fcc")
+        d8 = (8 * (ni // 8), 8 * (nj // 8), 12 * (nk // 12))
+        w = dict(w, lattice="fcc", dims=d8,
+                 name="%s_%dx%dx%d_fcc" % (w["name"].rsplit("_", 1)[0], *d8))
     if args.walls:
         w = dict(w, boundary="walls", name=w["name"] + "_walls")
     nv = int(w["dims"][0]) * int(w["dims"][1]) * int(w["dims"][2])
@@ -282,7 +282,7 @@ def main():
     # launches (switching that on and off never waits for the device), so
     # the walk stage's average launch time is measured over the timed region
     # itself ----
-    stages = 24 if w.get("lattice") == "fcc" else 16
+    stages = 16  # colour stages per event on either lattice
     every = max(args.steps // max(args.timing_steps, 1), 1)
     lat.set_kernel_timing(True)
     lat.set_kernel_timing(False)

@@ -30,7 +30,7 @@
  *   - Lattice dimensions must each be >= 4 and a multiple of 4 (the paper
  *     requires even counts, 2.1; multiples of 4 make the 16-colour stage
  *     schedule conflict-free on the periodic lattice; the FCC lattice also
- *     needs nk a multiple of 12).  ni*nj*nk <= 2^32.
+ *     needs nk a multiple of 12 and ni, nj multiples of 8).  ni*nj*nk <= 2^32.
  *   - Boundaries are periodic unless PSC_BOUNDARY_WALLS closes the box.
  */
 #ifndef PSC_H
@@ -75,9 +75,10 @@ typedef int32_t psc_status;
                                      instead of ABAB, so the layer phase is
                                      k mod 3.  Voxel centres, neighbour rows and
                                      displacement units are as for HCP with that
-                                     phase; the walk runs 24 colour stages
-                                     instead of 16.  nk must be a multiple of
-                                     12. */
+                                     phase; the walk keeps 16 colour stages (a
+                                     colouring periodic in 8 along i and j).
+                                     nk must be a multiple of 12, ni and nj of
+                                     8. */
 
 /* Device memory allocator hooks.  alloc returns a device pointer of at least
  * `bytes` bytes usable on `stream` (or NULL on failure); free releases it.
@@ -286,9 +287,8 @@ psc_status psc_get_kernel_times(psc_lattice *h, psc_kernel_times *out);
 /* ---- ensembles ---------------------------------------------------------------
  * Many independent lattices (replicates of one model, or different models of
  * any sizes) advanced together: every event of every member is one batched
- * launch sequence (first-order pass of all members, the colour stages of
- * all members as one work list each -- 16, or 24 when a member is FCC, where
- * an HCP member's extra stages are empty -- event end), captured once as a HIP
+ * launch sequence (first-order pass of all members, the 16 colour stages of
+ * all members as one work list each, event end), captured once as a HIP
  * graph and replayed.  Each member's result is bit-identical to stepping it
  * alone: the members share no state and every draw is keyed by the member's
  * own seed, event and molecule ids. */

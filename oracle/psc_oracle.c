@@ -255,15 +255,21 @@ void orc_position(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, double rv,
 }
 
 /* stage colour: voxels of one colour are >= 3 hops apart.  HCP (16):
- * 8(k&1) + 4(j&1) + ((i - j + k) mod 4).  FCC (24):
- * 4(2(k mod 3) + (j&1)) + ((i + j) mod 4) (found by search, checked by the
- * tests on the neighbour graph). */
+ * 8(k&1) + 4(j&1) + ((i - j + k) mod 4).  FCC (16): a linear form on the
+ * lattice's own (Bravais) coordinates a = i - floor((j+q)/2) - floor(k/3),
+ * b = j - floor(k/3), k with q = k mod 3: (2a + 3b + 7k) mod 16, periodic
+ * when ni and nj are multiples of 8 (found by search, checked by the tests
+ * on the neighbour graph). */
 int orc_colour_l(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v, int lattice) {
   uint32_t i, j, k;
   (void)nk;
   ijk_of(ni, nj, v, &i, &j, &k);
-  if (lattice == ORC_LATTICE_FCC)
-    return (int)(4u * (2u * (k % 3u) + (j & 1u)) + ((i + j) & 3u));
+  if (lattice == ORC_LATTICE_FCC) {
+    int64_t q = k % 3u, a = (int64_t)i - ((int64_t)j + q) / 2 - (int64_t)(k / 3u);
+    int64_t b = (int64_t)j - (int64_t)(k / 3u);
+    int64_t c = (2 * a + 3 * b + 7 * (int64_t)k) % 16;
+    return (int)(c < 0 ? c + 16 : c);
+  }
   int64_t m = ((int64_t)i - (int64_t)j + (int64_t)k) % 4;
   if (m < 0) m += 4;
   return (int)(8 * (k & 1u) + 4 * (j & 1u) + (uint32_t)m);
@@ -273,7 +279,7 @@ int orc_colour(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t v) {
   return orc_colour_l(ni, nj, nk, v, ORC_LATTICE_HCP);
 }
 
-int orc_n_colours(int lattice) { return lattice == ORC_LATTICE_FCC ? 24 : 16; }
+int orc_n_colours(int lattice) { (void)lattice; return 16; }
 
 /* stage order of an event: Fisher-Yates over n colours, slot i = n-1..1
  * swapping with j = floor(w (i + 1) / 2^32), words from blocks 0, 1, ... of
@@ -495,7 +501,8 @@ void orc_destroy(orc_sim *s) {
 
 int orc_set_lattice(orc_sim *s, int lattice) {
   if (lattice != ORC_LATTICE_HCP && lattice != ORC_LATTICE_FCC) return -1;
-  if (lattice == ORC_LATTICE_FCC && s->nk % 12) return -1;  /* stacking x colour period */
+  /* stacking and colour periods */
+  if (lattice == ORC_LATTICE_FCC && (s->nk % 12 || s->ni % 8 || s->nj % 8)) return -1;
   s->lattice = lattice;
   s->n_col = orc_n_colours(lattice);
   return 0;

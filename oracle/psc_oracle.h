@@ -59,9 +59,9 @@ enum { ORC_MODE_C = 0, ORC_MODE_S = 1, ORC_MODE_C_REV = 2 };
 enum { ORC_BOUNDARY_PERIODIC = 0, ORC_BOUNDARY_REFLECT = 1 };
 #define ORC_OUTSIDE 0xFFFFFFFFu
 
-/* lattice: hexagonal close packed (ABAB stacking, the default, 16 stage
- * colours) or face-centred cubic (ABC stacking in the same twisted
- * coordinates, 24 stage colours; the k edge a multiple of 12) */
+/* lattice: hexagonal close packed (ABAB stacking, the default) or
+ * face-centred cubic (ABC stacking in the same twisted coordinates; the i and
+ * j edges multiples of 8, the k edge of 12); 16 stage colours on both */
 enum { ORC_LATTICE_HCP = 0, ORC_LATTICE_FCC = 1 };
 #define ORC_MAX_COLOURS 24
 
@@ -114,7 +114,8 @@ orc_sim *orc_create(uint32_t ni, uint32_t nj, uint32_t nk, double rv,
 void orc_destroy(orc_sim *s);
 /* ORC_BOUNDARY_PERIODIC (default) or ORC_BOUNDARY_REFLECT; 0 on success */
 int orc_set_boundary(orc_sim *s, int boundary);
-/* ORC_LATTICE_HCP (default) or ORC_LATTICE_FCC (nk % 12 == 0); 0 on success */
+/* ORC_LATTICE_HCP (default) or ORC_LATTICE_FCC (ni, nj % 8 == 0, nk % 12 == 0);
+ * 0 on success */
 int orc_set_lattice(orc_sim *s, int lattice);
 /* returns the new species id (1, 2, ...) or -1 */
 int orc_add_species(orc_sim *s, double D);

@@ -18,8 +18,8 @@ constexpr uint16_t kSpeciesMask = 0x7FFF;
 constexpr uint16_t kReactedFlag = 0x8000;
 
 constexpr uint32_t kDeadId = 0xFFFFFFFFu;   // entry of a molecule that died
-// stage colours: 16 on the HCP lattice, 24 on the FCC lattice
-constexpr int kColoursHcp = 16, kColoursFcc = 24, kMaxColours = 24;
+// stage colours: 16 on both lattices
+constexpr int kColoursHcp = 16, kColoursFcc = 16, kMaxColours = 16;
 constexpr int kMaxSpecies = 63;
 constexpr int kMaxProducts = 11;
 
@@ -176,13 +176,19 @@ __host__ __device__ inline uint32_t to_linear(const Geo &g, uint32_t u) {
 }
 
 // Stage colour of a voxel: voxels of one colour are >= 3 hops apart.
-//   HCP (16): 8 (k & 1) + 4 (j & 1) + ((i - j + k) mod 4)
-//   FCC (24): 4 (2 (k mod 3) + (j & 1)) + ((i + j) mod 4)
+//   HCP: 8 (k & 1) + 4 (j & 1) + ((i - j + k) mod 4)
+//   FCC: (2a + 3b + 7k) mod 16 on the lattice's Bravais coordinates
+//   a = i - floor((j + q) / 2) - floor(k / 3), b = j - floor(k / 3),
+//   q = k mod 3 (periodic when the i and j edges are multiples of 8);
+//   unsigned wrap-around keeps the residue, 16 dividing 2^32
 // LAT: 0 HCP, 1 FCC
 template <int LAT>
 __host__ __device__ inline uint32_t colour_t(const Coord &c) {
-  if (LAT)
-    return 4u * (2u * ((uint32_t)c.k % 3u) + (uint32_t)(c.j & 1)) + (uint32_t)((c.i + c.j) & 3);
+  if (LAT) {
+    const uint32_t i = (uint32_t)c.i, j = (uint32_t)c.j, k = (uint32_t)c.k;
+    const uint32_t k3 = k / 3u, q = k - 3u * k3;
+    return (2u * i + 3u * j + 7u * k - 2u * ((j + q) >> 1) - 5u * k3) & 15u;
+  }
   return 8u * (uint32_t)(c.k & 1) + 4u * (uint32_t)(c.j & 1) +
          (uint32_t)((c.i + 3 * c.j + c.k) & 3);
 }
@@ -192,7 +198,7 @@ __host__ __device__ inline uint32_t colour_of(const Geo &g, const Coord &c) {
 }
 
 __host__ __device__ inline uint32_t n_colours(const Geo &g) {
-  return g.fcc ? (uint32_t)kColoursFcc : (uint32_t)kColoursHcp;
+  return g.fcc ? (uint32_t)kColoursFcc : (uint32_t)kColoursHcp;  // 16 on both
 }
 
 // Target coordinate of hop n from c (periodic).  Rows 0..7, 9, 10 are shared
@@ -302,7 +308,7 @@ struct Bins {
   uint32_t *id;     // [ncol * cap]
   uint16_t *sp;     // [ncol * cap] species when the entry was last written
   int32_t *disp;    // [3 * ncol * cap] (dx | dy | dz planes) or nullptr
-  uint32_t *count;  // [24] (entries past ncol stay zero)
+  uint32_t *count;  // [kMaxColours] (entries past ncol stay zero)
 };
 
 // Voxels where a collision put a product on the partner's voxel are marked
@@ -395,10 +401,10 @@ struct LatDev {
   // event state
   uint64_t stop_event;             // the lattice idles once ev reaches it
   uint64_t *ev;                    // events completed
-  uint32_t ncol;                   // stage colours of the lattice (16 or 24)
-  uint32_t *perm;                  // [24] stage order of the running event
-  uint4 *sdesc;                    // [24] per stage: colour, count, event (lo, hi);
-                                   // stages past ncol are empty
+  uint32_t ncol;                   // stage colours of the lattice (16)
+  uint32_t *perm;                  // [kMaxColours] stage order of the running event
+  uint4 *sdesc;                    // [kMaxColours] per stage: colour, count, event
+                                   // (lo, hi); stages past ncol are empty
   uint32_t *next_id;
   unsigned long long *cnt;         // attempts, hops, collisions, placement failures
   unsigned long long *sp_count;    // [64] live molecules per species (two's complement deltas)
@@ -408,12 +414,12 @@ struct LatDev {
 
 hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
 // disp: the lattice tracks displacements (its bins carry the planes)
-// fcc: the lattice is face-centred cubic (24 stages), else HCP (16);
+// fcc: the lattice is face-centred cubic, else HCP;
 // decide_grid > 0: the first-order decisions run in their own launch of that
 // many workgroups (events with many candidates), else inside k_begin
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
                         int decide_grid, hipStream_t s);
-// stages: the most stages of any member (16, or 24 with an FCC member)
+// stages: the most stages of any member (16)
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, hipStream_t s);
 hipError_t launch_begin(const LatDev *dL, int decide_grid, hipStream_t s);

@@ -482,7 +482,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   if (st) return st;
 
   // launch shape of the stage kernel from the molecules binned now (an
-  // average colour bin holds 1/16 of them, 1/24 on FCC): a stage that cannot
+  // average colour bin holds 1/16 of them): a stage that cannot
   // fill the GPU with 4-item chunks (two workgroups per CU) takes one- or
   // two-item chunks to shorten its chain of dependent accesses.  Every chunk
   // gets a workgroup of its own, so that all of a stage's probes are in
@@ -588,8 +588,9 @@ psc_status psc_create_lattice(const psc_lattice_desc *desc, psc_lattice **out) {
     g_create_error = "unknown flags";
     return PSC_EINVAL;
   }
-  if ((desc->flags & PSC_LATTICE_FCC) && nk % 12) {
-    g_create_error = "an FCC lattice needs nk a multiple of 12 (stacking period 3, bricks of 4)";
+  if ((desc->flags & PSC_LATTICE_FCC) && (nk % 12 || ni % 8 || nj % 8)) {
+    g_create_error = "an FCC lattice needs nk a multiple of 12 (stacking period 3, bricks of 4) "
+                     "and ni, nj multiples of 8 (the stage colouring's period)";
     return PSC_EINVAL;
   }
   if (desc->device < 0) {

@@ -127,7 +127,7 @@ psc_status check_device_error(psc_lattice *h);
 psc_status ensure_member_records(psc_ensemble *E, hipStream_t stream, uint64_t n_events);
 psc_status ensure_graph(psc_ensemble *E);
 // device bytes a lattice with this capacity and size will hold once frozen
-// ncol: stage colours of the lattice (16 HCP, 24 FCC)
+// ncol: stage colours of the lattice (16)
 uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool displacement,
                                uint32_t n_reactions, bool collision_births, uint32_t ncol);
 

@@ -4,8 +4,7 @@
 //   k_begin   one workgroup: the event's random stage order, the first-order
 //             reactions over the interval since the previous event (2.4.1),
 //             and id assignment + binning of their newborns;
-//   k_stage   16 launches (24 on the FCC lattice), one per colour stage in the
-//             event's order: every
+//   k_stage   16 launches, one per colour stage in the event's order: every
 //             molecule whose voxel has that colour attempts one hop (2.3) and
 //             fires a collision reaction with a registered partner (2.4.2);
 //             survivors are appended to the next event's colour bins;

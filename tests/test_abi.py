@@ -218,11 +218,14 @@ def test_walls_flag_is_accepted_and_unknown_flags_rejected():
     assert psc.lib().psc_create_lattice(psc.C.byref(d), psc.C.byref(h)) == psc.PSC_EINVAL
 
 
-@pytest.mark.parametrize("nk,ok", [(12, True), (24, True), (8, False), (16, False), (20, False)])
-def test_fcc_flag_needs_a_k_edge_of_whole_stacking_and_colour_periods(nk, ok):
-    # ABC stacking repeats every 3 layers and bricks every 4: nk % 12 == 0
+@pytest.mark.parametrize("dims,ok", [((8, 8, 12), True), ((16, 8, 24), True),
+                                     ((8, 8, 8), False), ((8, 8, 16), False),
+                                     ((12, 8, 12), False), ((8, 4, 12), False)])
+def test_fcc_flag_needs_whole_stacking_and_colour_periods(dims, ok):
+    # ABC stacking repeats every 3 layers and bricks every 4: nk % 12 == 0;
+    # the stage colouring repeats every 8 along i and j
     d = psc.Desc()
-    d.ni, d.nj, d.nk = 8, 8, nk
+    d.ni, d.nj, d.nk = dims
     d.voxel_radius = 4.4e-9
     d.seed = 1
     d.max_molecules = 64
@@ -237,7 +240,7 @@ def test_fcc_flag_needs_a_k_edge_of_whole_stacking_and_colour_periods(nk, ok):
 
 
 def test_host_placement_on_an_fcc_lattice_matches_oracle():
-    w = dict(workload("small_reactive", dims=(16, 12, 12)), lattice="fcc")
+    w = dict(workload("small_reactive", dims=(16, 16, 12)), lattice="fcc")
     lat = psc.lattice_from_workload(w, device=0)
     o = oracle.Oracle(w["dims"], w["rv"], w["seed"], lattice=oracle.FCC)
     for _, D in w["species"]:

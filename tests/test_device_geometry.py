@@ -40,7 +40,7 @@ def probe(tmp_path_factory):
 
 
 CASES = [((4, 4, 4), oracle.HCP), ((8, 12, 16), oracle.HCP), ((20, 8, 8), oracle.HCP),
-         ((4, 4, 12), oracle.FCC), ((8, 12, 24), oracle.FCC), ((20, 8, 12), oracle.FCC)]
+         ((8, 8, 12), oracle.FCC), ((8, 16, 24), oracle.FCC), ((24, 8, 12), oracle.FCC)]
 
 
 @pytest.mark.parametrize("dims,lattice", CASES)

@@ -45,8 +45,8 @@ def mixed_members(n_rep=10, events=40):
     ws.append(dict(ws[0], boundary="walls"))
     # collisions with more than two products
     ws.append(workload("multiproduct", seed=8, events=events))
-    # FCC members (24 stages) beside HCP ones (16 stages, the rest empty)
-    ws.append(dict(workload("small_reactive", seed=13, dims=(16, 12, 12), events=events),
+    # FCC members beside HCP ones
+    ws.append(dict(workload("small_reactive", seed=13, dims=(16, 16, 12), events=events),
                    lattice="fcc"))
     ws.append(dict(workload("cfg2", dims=(24, 24, 24), events=events), lattice="fcc",
                    boundary="walls"))

@@ -397,9 +397,9 @@ def fcc(w, **kw):
 
 @pytest.mark.parametrize("seed", [7, 8])
 def test_fcc_small_reactive_all_rules(seed):
-    """Every rule on the FCC lattice over 24 stages; 16 x 12 x 12 spans
-    several chunks per stage and ragged bin tails."""
-    w = fcc(workload("small_reactive", seed=seed, dims=(16, 12, 12)))
+    """Every rule on the FCC lattice; 16 x 16 x 12 spans several chunks per
+    stage and ragged bin tails."""
+    w = fcc(workload("small_reactive", seed=seed, dims=(16, 16, 12)))
     g, s = run_pair(w, 40)
     assert s["hops"] > 0 and s["collisions"] > 0 and np.all(s["fired"] > 0), s["fired"]
     # the lattice changes the run
@@ -408,8 +408,8 @@ def test_fcc_small_reactive_all_rules(seed):
     assert not np.array_equal(gh.read_state()["occ"], g["occ"])
 
 
-@pytest.mark.parametrize("dims,boundary", [((4, 4, 12), None), ((20, 8, 24), None),
-                                           ((4, 4, 12), "walls"), ((20, 8, 24), "walls")])
+@pytest.mark.parametrize("dims,boundary", [((8, 8, 12), None), ((24, 8, 24), None),
+                                           ((8, 8, 12), "walls"), ((24, 8, 24), "walls")])
 def test_fcc_shapes(dims, boundary):
     w = fcc(workload("small_reactive", dims=dims, seed=11), boundary=boundary)
     run_pair(w, 30)
@@ -438,7 +438,7 @@ def test_fcc_launch_shapes(items):
 
 @pytest.mark.parametrize("boundary", [None, "walls"])
 def test_fcc_multiproduct_and_mapk(boundary):
-    w = fcc(workload("multiproduct", seed=3, dims=(16, 12, 12), n_a=16 * 12 * 12 // 5),
+    w = fcc(workload("multiproduct", seed=3, dims=(16, 16, 12), n_a=16 * 16 * 12 // 5),
             boundary=boundary)
     g, s = run_pair(w, 40)
     assert s["fired"][0] > 0 and s["fired"][1] > 0
@@ -446,7 +446,7 @@ def test_fcc_multiproduct_and_mapk(boundary):
 
 
 def test_fcc_linear_layout_statistics_and_checkpoint():
-    w = fcc(workload("small_reactive", seed=21, dims=(16, 12, 24)))
+    w = fcc(workload("small_reactive", seed=21, dims=(16, 8, 24)))
     lat = psc.lattice_from_workload(w, linear_layout=True)
     lat.step(25)
     mid = lat.read_state()

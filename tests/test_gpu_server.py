@@ -60,7 +60,8 @@ def test_results_same_alone_and_in_the_mix():
     jobs = small_jobs(24)
     # every third job is closed by walls, every fourth is an FCC lattice
     jobs = [dict(w, boundary="walls") if i % 3 == 1 else w for i, w in enumerate(jobs)]
-    jobs = [dict(w, lattice="fcc", dims=w["dims"][:2] + (12 * max(1, w["dims"][2] // 12),))
+    jobs = [dict(w, lattice="fcc", dims=(8 * max(1, w["dims"][0] // 8), 8 * max(1, w["dims"][1] // 8),
+                                       12 * max(1, w["dims"][2] // 12)))
             if i % 4 == 2 else w for i, w in enumerate(jobs)]
     srv = psc.Server(budget_bytes=8 << 30, quantum_events=16)
     ids = []

@@ -14,7 +14,7 @@ Pins that do not re-derive the oracle's stencil:
 - the coordination sequence of the fcc net, 12, 42, 92 (it differs from the
   hcp net's 12, 44, 96, so an HCP stencil fails it), and the fcc lattice's
   numbers of closed n-step walks, n <= 8, from every layer phase;
-- the 24 stage colours split the voxels evenly and every class is an
+- the 16 stage colours split the voxels evenly and every class is an
   independent set at graph distance <= 2 (what lets a stage run in any order);
 - the walk: lone walkers have MSD 6 D t; runs in reversed intra-stage order
   are identical, with and without walls."""
@@ -159,13 +159,13 @@ def test_closed_walk_counts_of_the_fcc_lattice():
         assert counts == FCC_CLOSED_WALKS, (start, counts)
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 12), (8, 8, 12), (8, 4, 24), (12, 8, 12)])
+@pytest.mark.parametrize("dims", [(8, 8, 12), (16, 8, 24), (8, 16, 12), (24, 8, 36)])
 def test_colour_classes_are_three_hops_apart(dims):
     nv = dims[0] * dims[1] * dims[2]
-    assert oracle.n_colours(F) == 24
+    assert oracle.n_colours(F) == 16
     col = [oracle.colour_l(dims, v, F) for v in range(nv)]
-    counts = np.bincount(col, minlength=24)
-    assert len(counts) == 24 and np.all(counts == nv // 24)
+    counts = np.bincount(col, minlength=16)
+    assert len(counts) == 16 and np.all(counts == nv // 16)
     for v in range(nv):
         near = set()
         for n in range(12):
@@ -177,26 +177,16 @@ def test_colour_classes_are_three_hops_apart(dims):
         assert all(col[u] != col[v] for u in near)
 
 
-def test_stage_order_of_24_is_a_uniform_permutation():
-    n_ev = 12000
-    hits = np.zeros((24, 24))
-    for e in range(n_ev):
-        o = oracle.stage_order_n(11, e, 24)
-        assert sorted(o) == list(range(24))
-        hits[np.arange(24), o] += 1
-    expect = n_ev / 24
-    sd = math.sqrt(expect * (1 - 1 / 24))
-    assert np.all(np.abs(hits - expect) < 5 * sd)
-    # the first 16 words are the ones a 16-stage order uses
-    assert oracle.stage_order_n(3, 9, 16) == oracle.stage_order(3, 9)
-
-
-def test_lattice_kind_checks_the_stacking_period():
-    with pytest.raises(ValueError):
-        oracle.Oracle((8, 8, 8), 4.4e-9, 1, lattice=F)
+def test_lattice_kind_checks_the_stacking_and_colour_periods():
+    # k: ABC stacking (3) and bricks (4); i and j: the colouring's period 8
+    for dims in ((8, 8, 8), (12, 8, 12), (8, 12, 12), (8, 4, 12)):
+        with pytest.raises(ValueError):
+            oracle.Oracle(dims, 4.4e-9, 1, lattice=F)
     with pytest.raises(ValueError):
         oracle.Oracle((8, 8, 12), 4.4e-9, 1, lattice=7)
     oracle.Oracle((8, 8, 12), 4.4e-9, 1, lattice=F).close()
+    # both lattices take the same 16-stage order of an event
+    assert oracle.stage_order_n(3, 9, oracle.n_colours(F)) == oracle.stage_order(3, 9)
 
 
 def test_msd_lone_walkers_is_6Dt():
@@ -239,7 +229,7 @@ def build(w, boundary=oracle.PERIODIC):
                                            ("small_reactive", oracle.REFLECT),
                                            ("multiproduct", oracle.PERIODIC)])
 def test_reversed_intra_stage_order_gives_identical_run(name, boundary):
-    w = workload(name, dims=(16, 12, 12))
+    w = workload(name, dims=(16, 16, 12))
     a, b = build(w, boundary), build(w, boundary)
     a.run(40, oracle.MODE_C)
     b.run(40, oracle.MODE_C_REV)

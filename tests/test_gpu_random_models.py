@@ -89,7 +89,7 @@ def test_random_models_are_valid_and_varied():
     # the oracle accepts every drawn model, and the draws cover both lattices,
     # both boundaries, many-product collisions and first-order reactions
     kinds = set()
-    for seed in range(64):
+    for seed in range(96):
         w = random_model(seed)
         s = oracle_state(w)
         assert s["attempts"] > 0
@@ -98,3 +98,24 @@ def test_random_models_are_valid_and_varied():
         kinds.add(("first", any(len(r) == 1 for r, p, k in w["reactions"])))
     assert {("fcc", "walls"), ("fcc", "periodic"), ("hcp", "walls"), ("hcp", "periodic"),
             ("many", True), ("first", True)} <= kinds
+
+
+@pytest.mark.gpu
+def test_random_models_in_one_ensemble():
+    """32 further random models (both lattices, both boundaries, every kind of
+    reaction) advanced together as one batched ensemble: each member equals
+    the oracle."""
+    ws = [random_model(seed) for seed in range(64, 96)]
+    lats = [psc.lattice_from_workload(w, max_molecules=int(np.prod(w["dims"]))) for w in ws]
+    ens = psc.Ensemble(lats)
+    ens.step(20)
+    ens.sync()
+    for w, lat in zip(ws, lats):
+        g = lat.read_state()
+        s = oracle_state(w)
+        disp = w["track_displacement"]
+        for key in ("occ", "id", "vox", "species") + (("dx", "dy", "dz") if disp else ()):
+            assert np.array_equal(g[key], s[key]), (key, w)
+        for key in ("attempts", "hops", "collisions", "place_fail", "event", "next_id"):
+            assert g[key] == s[key], (key, g[key], s[key], w)
+        assert np.array_equal(g["fired"], s["fired"]), (g["fired"], s["fired"], w)

@@ -119,3 +119,26 @@ def test_random_models_in_one_ensemble():
         for key in ("attempts", "hops", "collisions", "place_fail", "event", "next_id"):
             assert g[key] == s[key], (key, g[key], s[key], w)
         assert np.array_equal(g["fired"], s["fired"]), (g["fired"], s["fired"], w)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", range(16))
+def test_random_model_checkpoint_and_resume(seed):
+    """10 events, the state read and loaded into a fresh lattice, 10 more:
+    the same as the oracle's 20 events (the resumed lattice's counters start
+    at the load, so the state, event, next id and time are compared)."""
+    w = random_model(seed)
+    nv = int(np.prod(w["dims"]))
+    first = psc.lattice_from_workload(w, max_molecules=nv)
+    first.step(10)
+    mid = first.read_state()
+    first.close()
+    second = psc.lattice_from_workload(w, max_molecules=nv, place=False)
+    second.load_state(mid)
+    second.step(10)
+    g = second.read_state()
+    s = oracle_state(w)
+    disp = w["track_displacement"]
+    for key in ("occ", "id", "vox", "species") + (("dx", "dy", "dz") if disp else ()):
+        assert np.array_equal(g[key], s[key]), (key, w)
+    assert g["event"] == s["event"] and g["next_id"] == s["next_id"] and g["time"] == s["time"]

@@ -99,3 +99,19 @@ def test_member_rules():
     ens.close()
     lats[0].step(4)              # released: steps alone again, continuing exactly
     same(lats[0].read_state(), oracle_run(ws[0], 10), disp=False)
+
+
+def test_benchmark_ensemble_at_full_size_sampled():
+    """The benchmark's ensemble at its full size (512 replicates, edges 32 to
+    128, 1-10 % occupancy) launched as the benchmark launches it (batched,
+    autotuned), for 50 events; the first member of every edge and the last
+    member are compared with the oracle one by one."""
+    ws = ensemble_members(n=512, events=50)
+    lats = [psc.lattice_from_workload(w) for w in ws]
+    ens = psc.Ensemble(lats)
+    ens.autotune(3)
+    ens.step(50)
+    ens.sync()
+    picks = {next(i for i, w in enumerate(ws) if w["dims"][0] == e) for e in (32, 48, 64, 96, 128)}
+    for i in sorted(picks | {len(ws) - 1}):
+        same(lats[i].read_state(), oracle_run(ws[i], 50), disp=False)

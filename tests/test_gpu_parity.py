@@ -485,3 +485,27 @@ def test_fcc_full_size_prefix():
     s = o.state()
     o.close()
     assert_same(g, s, disp=False)
+
+
+@pytest.mark.parametrize("fcc", [False, True])
+def test_msd_is_6Dt_at_scale(fcc):
+    """The paper's diffusion check (3.1, eq. 7) on the GPU at a size the
+    oracle does not reach: 10 k walkers at 0.5 % occupancy on 128^3 voxels,
+    400 events; the mean squared displacement from the device's own
+    displacement sum, r^2 sum(3X^2 + Y^2 + 8Z^2) / (3n), grows as
+    6 D t = 4 r^2 N (N events), within 3 %, and linearly in time."""
+    dims = (128, 128, 120) if fcc else (128, 128, 128)
+    nv = dims[0] * dims[1] * dims[2]
+    w = dict(name="msd", dims=dims, rv=4.4e-9, seed=17, species=[("A", 1e-12)], reactions=[],
+             place=[(1, nv // 200)], events=400, track_displacement=True)
+    if fcc:
+        w["lattice"] = "fcc"
+    lat = build_gpu(w)
+    ratios = []
+    for n in (200, 400):
+        lat.step(n - (200 if n == 400 else 0))
+        st = lat.stats()
+        msd_r2 = st["disp_sum"] / (3.0 * st["n_walkers"])
+        ratios.append(msd_r2 / (4.0 * n))
+    assert all(abs(r - 1.0) < 0.03 for r in ratios), ratios
+    assert abs(ratios[0] - ratios[1]) < 0.02, ratios

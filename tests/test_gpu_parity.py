@@ -509,3 +509,24 @@ def test_msd_is_6Dt_at_scale(fcc):
         ratios.append(msd_r2 / (4.0 * n))
     assert all(abs(r - 1.0) < 0.03 for r in ratios), ratios
     assert abs(ratios[0] - ratios[1]) < 0.02, ratios
+
+
+@pytest.mark.parametrize("k", [0.135, 1.35, 13.5])
+def test_first_order_decay_closed_form_at_scale(k):
+    """The paper's first-order check (3.2.1) with its 64,000 molecules and
+    rate constants: immobile A -> B + C, the event interval set by one fast
+    walker (2000 events up to t = 2/k); the device's count of A follows
+    A0 exp(-k t) within 2 % at t = 1/k and 2/k (binomial spread ~0.5 %)."""
+    rv, n0, events = 5e-9, 64000, 2000
+    tau = 2.0 / k / events
+    dz = 2.0 * rv * rv / (3.0 * tau)
+    w = dict(name="decay", dims=(128, 128, 128), rv=rv, seed=23,
+             species=[("Z", dz), ("A", 0.0), ("B", 0.0), ("C", 0.0)],
+             reactions=[((2,), (3, 4), k)], place=[(1, 1), (2, n0)], events=events)
+    lat = build_gpu(w, max_molecules=3 * n0 + 1024)
+    for half in (1, 2):
+        lat.step(events // 2)
+        a = int(lat.stats()["species_count"][2])
+        expect = n0 * np.exp(-float(half))
+        assert abs(a / expect - 1.0) < 0.02, (k, half, a, expect)
+    assert lat.read_state(with_occ=False)["place_fail"] == 0

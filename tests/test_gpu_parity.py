@@ -530,3 +530,29 @@ def test_first_order_decay_closed_form_at_scale(k):
         expect = n0 * np.exp(-float(half))
         assert abs(a / expect - 1.0) < 0.02, (k, half, a, expect)
     assert lat.read_state(with_occ=False)["place_fail"] == 0
+
+
+def test_second_order_reaction_limited_rate_at_scale():
+    """The paper's second-order check (3.2.2) in the reaction-limited regime
+    (k_f = 0.027 1/(nM s), D = 10 um^2/s, r = 5 nm: p = 0.053) with 20,000
+    molecules each of A and B on 128^3 voxels: 1/N_A(t) - 1/N_0 grows as
+    k_eff t / V, and k_eff / k = 1 / (1 + p (G(0) - 1)) = 0.982 for the
+    lattice walk (Collins-Kimball on the lattice, G(0) = 1.345), within 3 %."""
+    kf = 0.027 * 1e9 * 1e-3 / 6.02214076e23
+    rv, D, n0, dims = 5e-9, 10e-12, 20000, (128, 128, 128)
+    p = kf / (6 * np.sqrt(2) * 2 * D * rv)
+    w = dict(name="second_order", dims=dims, rv=rv, seed=29,
+             species=[("A", D), ("B", D), ("C", D)], reactions=[((1, 2), (3,), kf)],
+             place=[(1, n0), (2, n0)], events=2000)
+    lat = build_gpu(w)
+    tau = 2.0 * rv * rv / (3.0 * D)
+    ts, inv = [], []
+    for c in range(20):
+        lat.step(100)
+        ts.append((c + 1) * 100 * tau)
+        inv.append(1.0 / float(lat.stats()["species_count"][1]) - 1.0 / n0)
+    ts, inv = np.array(ts), np.array(inv)
+    V = np.prod(dims) * 4.0 * np.sqrt(2.0) * rv ** 3
+    ratio = float((inv * ts).sum() / (ts * ts).sum()) * V / kf
+    expect = 1.0 / (1.0 + p * (1.345 - 1.0))
+    assert abs(ratio / expect - 1.0) < 0.03, (ratio, expect)

@@ -312,7 +312,55 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
   // event's order.  Overlaps are found by counting, per hashed voxel, the
   // neighbourhoods that contain it (a hash collision only sends a molecule
   // to the staged path, which is always correct). ----
-  if (nfire > 0) {
+  if (nfire > 0 && nfire <= blockDim.x) {
+    // one firing per thread: its colour, position, draw owner, reaction and
+    // the 13 hashed voxels of its neighbourhood stay in registers through
+    // the count, the test, the application and the cleanup
+    const uint32_t nb_bits = L.nbr_bits;
+    const bool mine = (uint32_t)tid < nfire;
+    uint32_t c = 0, pos = 0, id = 0, rx = 0, h[13];
+    bool deferred = false;
+    if (mine) {
+      c = fire_col[tid];
+      pos = fire_pos[tid];
+      id = fire_id[tid];
+      rx = fire_rx[tid];
+      const uint32_t v = in.vox[c * L.cap + pos];
+      const Coord cv = coord_of(L.geo, v);
+      h[0] = hot_hash(v, nb_bits);
+#pragma unroll
+      for (uint32_t n = 0; n < 12; ++n)
+        h[n + 1] = hot_hash(index_of(L.geo, step_coord(L.geo, cv, n)), nb_bits);
+#pragma unroll
+      for (int a = 0; a < 13; ++a) atomicAdd(&L.nbr_cnt[h[a]], 1u);
+    }
+    __syncthreads();
+    if (mine) {
+      uint32_t other = 0;
+#pragma unroll
+      for (int a = 0; a < 13; ++a)
+        other |= __hip_atomic_load(&L.nbr_cnt[h[a]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ^ 1u;
+      if (other == 0u) {
+        apply_first_order(L, e, in, c, pos, id, rx, &s_nb);
+      } else {
+        deferred = true;  // to the staged pass
+        atomicAdd(&s_colcnt[c], 1u);
+      }
+    }
+    __syncthreads();
+    for (uint32_t g = 0; g < ncol; ++g) {
+      const uint32_t cg = s_perm[g];
+      if (s_colcnt[cg] == 0) continue;
+      if (deferred && c == cg) apply_first_order(L, e, in, c, pos, id, rx, &s_nb);
+      __syncthreads();
+    }
+    // leave the counts at zero for the next event
+    if (mine) {
+#pragma unroll
+      for (int a = 0; a < 13; ++a) atomicSub(&L.nbr_cnt[h[a]], 1u);
+    }
+    __syncthreads();
+  } else if (nfire > 0) {
     const uint32_t nb_bits = L.nbr_bits;
     for (uint32_t q = tid; q < nfire; q += blockDim.x) {
       const uint32_t c = fire_col[q];

@@ -374,6 +374,31 @@ def test_more_newborns_per_event_than_the_lds_numbering_holds(events):
     assert s["fired"][0] > 2048 * events and s["fired"][1] > 2048 * events, s["fired"]
 
 
+def test_first_order_firings_per_event_crossing_one_workgroup():
+    """The first-order pass applies an event's firings one per thread when
+    they fit in its workgroup (1024) and loops over them otherwise.  A dense
+    decaying population (23 % occupancy; A -> 0 and A -> C + C) fires ~1,900
+    times in the first event and ~300 in the last, so the run crosses from one
+    form to the other, with many firings deferred for touching neighbourhoods
+    and products placed among them."""
+    w = dict(name="fire_sweep", dims=(64, 64, 64), rv=4.4e-9, seed=9,
+             species=[("A", 1e-12), ("C", 0.0)],
+             reactions=[((1,), (), 1300.0), ((1,), (2, 2), 1300.0)],
+             place=[(1, 60000)], events=60, track_displacement=True)
+    lat = build_gpu(w, max_molecules=64 ** 3)
+    o = build_oracle(w)
+    per, prev = [], 0
+    for chunk in (1, 4, 15, 20, 20):
+        for _ in range(chunk):
+            o.run(1, oracle.MODE_C)
+            f = int(sum(o.state(with_occ=False)["fired"]))
+            per.append(f - prev)
+            prev = f
+        lat.step(chunk)
+        assert_same(lat.read_state(), o.state())
+    assert max(per) > 1024 and min(per) < 512, per
+
+
 def test_multiproduct_collisions_many_events_and_shapes():
     w = workload("multiproduct", dims=(48, 48, 32), seed=6, n_a=6000)
     nv = 48 * 48 * 32

@@ -212,6 +212,50 @@ def calibrate_copy(nbytes: int, reps: int):
     print(json.dumps({"calibrate_copy_bytes": nbytes, "reps": reps}))
 
 
+def calibrate_random(n_words: int, n_access: int, reps: int):
+    """Reference rates for scattered 2-byte accesses: torch's own gather
+    (index_select), scatter (index_put_) and gather-then-scatter at the same
+    positions, each over n_access uniformly random words of an n_words int16
+    array, with fresh positions every repetition (no cache reuse between
+    them).  A library kernel, not a ceiling: it says what a plain random
+    probe of the same count costs on this memory system."""
+    import torch
+    x = torch.zeros(n_words, dtype=torch.int16, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12345)
+    idx = [torch.randint(0, n_words, (n_access,), device="cuda", generator=g) for _ in range(reps)]
+    y = torch.empty(n_access, dtype=torch.int16, device="cuda")
+    vals = torch.ones(n_access, dtype=torch.int16, device="cuda")
+
+    def timed(fn):
+        fn(idx[0])
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in idx:
+            fn(i)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1000.0 / len(idx)
+
+    def gather(i):
+        torch.index_select(x, 0, i, out=y)
+
+    def scatter(i):
+        x.index_put_((i,), vals)
+
+    def both(i):
+        torch.index_select(x, 0, i, out=y)
+        x.index_put_((i,), y)
+
+    out = {"calibrate_random_words": n_words, "accesses": n_access, "reps": reps}
+    for name, fn in (("gather", gather), ("scatter", scatter), ("gather_then_scatter", both)):
+        us = timed(fn)
+        out[name + "_us"] = round(us, 2)
+        out[name + "_accesses_per_s"] = n_access / (us * 1e-6)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +281,8 @@ def main():
     ap.add_argument("--serving-window", type=float, default=1.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run N-byte device copies (counter calibration)")
+    ap.add_argument("--calibrate-random", type=int, default=0,
+                    help="only time N scattered 2-byte gathers/scatters into a 2^32-word array")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -246,6 +292,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, 10)
+        return
+    if args.calibrate_random:
+        calibrate_random(1 << 32, args.calibrate_random, 50)
         return
 
     import torch

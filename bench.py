@@ -212,13 +212,14 @@ def calibrate_copy(nbytes: int, reps: int):
     print(json.dumps({"calibrate_copy_bytes": nbytes, "reps": reps}))
 
 
-def calibrate_random(n_words: int, n_access: int, reps: int):
-    """Reference rates for scattered 2-byte accesses: torch's own gather
+def random_reference(n_words: int, n_access: int, reps: int) -> dict:
+    """Reference times for scattered 2-byte accesses: torch's own gather
     (index_select), scatter (index_put_) and gather-then-scatter at the same
     positions, each over n_access uniformly random words of an n_words int16
     array, with fresh positions every repetition (no cache reuse between
-    them).  A library kernel, not a ceiling: it says what a plain random
-    probe of the same count costs on this memory system."""
+    them); microseconds per call, event-timed.  Library kernels, not a
+    ceiling: what a plain random probe of the same count costs on this
+    memory system."""
     import torch
     x = torch.zeros(n_words, dtype=torch.int16, device="cuda")
     g = torch.Generator(device="cuda")
@@ -248,11 +249,18 @@ def calibrate_random(n_words: int, n_access: int, reps: int):
         torch.index_select(x, 0, i, out=y)
         x.index_put_((i,), y)
 
+    out = {name + "_us": round(timed(fn), 2)
+           for name, fn in (("gather", gather), ("scatter", scatter), ("gather_then_scatter", both))}
+    del x, idx, y, vals
+    torch.cuda.empty_cache()
+    return out
+
+
+def calibrate_random(n_words: int, n_access: int, reps: int):
     out = {"calibrate_random_words": n_words, "accesses": n_access, "reps": reps}
-    for name, fn in (("gather", gather), ("scatter", scatter), ("gather_then_scatter", both)):
-        us = timed(fn)
-        out[name + "_us"] = round(us, 2)
-        out[name + "_accesses_per_s"] = n_access / (us * 1e-6)
+    out.update(random_reference(n_words, n_access, reps))
+    for name in ("gather", "scatter", "gather_then_scatter"):
+        out[name + "_accesses_per_s"] = n_access / (out[name + "_us"] * 1e-6)
     print(json.dumps(out))
 
 
@@ -371,6 +379,13 @@ def main():
     achieved = alg_bytes_per_launch / (stage_avg_ms * 1e-3) / 1e9
     traffic = read_traffic(w["name"])
     lat.close()
+    # the same count of scattered 2-byte accesses in an array of the lattice's
+    # size, done by torch's gather and scatter kernels alone: the target read
+    # and the write to its line (gather then scatter), plus the source write
+    # that lands in another line for about a third of the hops (the brick
+    # layout keeps a hop inside its 4x4x4 brick for about 2/3 of the stencil)
+    ref = random_reference(nv, max(int(round(t_att)), 1), 20)
+    ref_us = ref["gather_then_scatter_us"] + ref["scatter_us"] / 3.0
 
     result = {
         "metric": "molecule hop attempts/s",
@@ -411,7 +426,12 @@ def main():
                      # same event rate, as a fraction of the peak
                      "stream_equivalent_gbs": 4.0 * nv / (ms / args.steps * 1e-3) / 1e9,
                      "stream_equivalent_frac": 4.0 * nv / (ms / args.steps * 1e-3) / 1e9
-                                               / HBM_PEAK_GBS},
+                                               / HBM_PEAK_GBS,
+                     "random_access_reference": dict(
+                         ref, cross_line_fraction=1.0 / 3.0, estimate_us=ref_us,
+                         walk_over_reference=stage_avg_ms * 1e3 / ref_us,
+                         kind="torch index_select / index_put_ of attempts_per_launch random "
+                              "2-byte words in an array of the lattice's size, event-timed")},
     }
     if not args.no_ensemble:
         result["ensemble"] = ensemble_bench(args.ensemble_members, args.ensemble_events, 12, 300, 3)

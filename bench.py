@@ -25,6 +25,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
+# Share of (voxel, direction) pairs whose neighbour lies in another 4x4x4
+# brick of the default lattice layout (one 128-byte line per brick): a hop's
+# source and target words then sit in different lines.  Counted over the
+# stencils of section 2.1 (HCP) and its ABC-stacked form (FCC).
+CROSS_BRICK_FRACTION = {"hcp": 11.0 / 32.0, "fcc": 45.0 / 128.0}
+
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
@@ -382,10 +388,10 @@ def main():
     # the same count of scattered 2-byte accesses in an array of the lattice's
     # size, done by torch's gather and scatter kernels alone: the target read
     # and the write to its line (gather then scatter), plus the source write
-    # that lands in another line for about a third of the hops (the brick
-    # layout keeps a hop inside its 4x4x4 brick for about 2/3 of the stencil)
+    # for the hops whose target lies in another 4x4x4 brick (another line)
     ref = random_reference(nv, max(int(round(t_att)), 1), 20)
-    ref_us = ref["gather_then_scatter_us"] + ref["scatter_us"] / 3.0
+    cross = CROSS_BRICK_FRACTION[w.get("lattice", "hcp")]
+    ref_us = ref["gather_then_scatter_us"] + cross * ref["scatter_us"]
 
     result = {
         "metric": "molecule hop attempts/s",
@@ -428,7 +434,7 @@ def main():
                      "stream_equivalent_frac": 4.0 * nv / (ms / args.steps * 1e-3) / 1e9
                                                / HBM_PEAK_GBS,
                      "random_access_reference": dict(
-                         ref, cross_line_fraction=1.0 / 3.0, estimate_us=ref_us,
+                         ref, cross_line_fraction=cross, estimate_us=ref_us,
                          walk_over_reference=stage_avg_ms * 1e3 / ref_us,
                          kind="torch index_select / index_put_ of attempts_per_launch random "
                               "2-byte words in an array of the lattice's size, event-timed")},

@@ -75,3 +75,21 @@ def test_cpu_baseline_fields():
     assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "attempts/s"
     assert r["value"] > 0
     assert "first 2 events of %s" % w["name"] in r["sample"]
+
+
+@pytest.mark.parametrize("lattice,dims", [("hcp", (16, 16, 16)), ("fcc", (16, 16, 24))])
+def test_cross_brick_fraction_is_the_stencils(lattice, dims):
+    """The share of hops whose target lies in another 4x4x4 brick, counted
+    over every voxel and direction of the oracle's neighbour table on a
+    periodic box that holds whole bricks and whole stencil periods."""
+    import numpy as np
+
+    import oracle
+    nb = oracle.neighbour_table_l(dims, oracle.FCC if lattice == "fcc" else oracle.HCP)
+    nv = nb.shape[0]
+
+    def brick(u):
+        return (u % dims[0]) // 4, (u // dims[0]) % dims[1] // 4, u // (dims[0] * dims[1]) // 4
+    src = np.repeat(np.arange(nv), 12)
+    same = np.all(np.array(brick(src)) == np.array(brick(nb.ravel())), axis=0)
+    assert (1.0 - same.mean()) == bench.CROSS_BRICK_FRACTION[lattice]

@@ -374,18 +374,23 @@ def test_more_newborns_per_event_than_the_lds_numbering_holds(events):
     assert s["fired"][0] > 2048 * events and s["fired"][1] > 2048 * events, s["fired"]
 
 
-def test_first_order_firings_per_event_crossing_one_workgroup():
+@pytest.mark.parametrize("kind", ["hcp", "fcc_walls"])
+def test_first_order_firings_per_event_crossing_one_workgroup(kind):
     """The first-order pass applies an event's firings one per thread when
     they fit in its workgroup (1024) and loops over them otherwise.  A dense
-    decaying population (23 % occupancy; A -> 0 and A -> C + C) fires ~1,900
-    times in the first event and ~300 in the last, so the run crosses from one
-    form to the other, with many firings deferred for touching neighbourhoods
-    and products placed among them."""
-    w = dict(name="fire_sweep", dims=(64, 64, 64), rv=4.4e-9, seed=9,
+    decaying population (23-24 % occupancy; A -> 0 and A -> C + C) fires
+    ~1,900 times in the first event and ~300 in the last, so the run crosses
+    from one form to the other, with many firings deferred for touching
+    neighbourhoods and products placed among them; also on the FCC lattice
+    in a box closed by walls (neighbourhoods cut by the walls)."""
+    dims = (64, 64, 64) if kind == "hcp" else (64, 64, 60)
+    w = dict(name="fire_sweep", dims=dims, rv=4.4e-9, seed=9,
              species=[("A", 1e-12), ("C", 0.0)],
              reactions=[((1,), (), 1300.0), ((1,), (2, 2), 1300.0)],
              place=[(1, 60000)], events=60, track_displacement=True)
-    lat = build_gpu(w, max_molecules=64 ** 3)
+    if kind == "fcc_walls":
+        w = fcc(w, boundary="walls")
+    lat = build_gpu(w, max_molecules=dims[0] * dims[1] * dims[2])
     o = build_oracle(w)
     per, prev = [], 0
     for chunk in (1, 4, 15, 20, 20):

@@ -1034,12 +1034,16 @@ __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t
     const uint32_t h = hot_hash(L.flag_vox[prv][q], L.hot_bits);
     atomicAnd(&L.hot[h >> 4], ~(1u << (((h & 15u) << 1) | prv)));
   }
+  // No release fence before counting in (on this part it writes back the
+  // L2 of the workgroup's XCD, and a batched launch has thousands of
+  // workgroups): the last workgroup reads nothing the others write in this
+  // kernel (it masks the flag bit off every lattice word it reads and never
+  // reads the hot bitmap), and each workgroup has used the event counter
+  // before it counts itself in, so the last may advance it.  The kernel
+  // boundary publishes all of it to the next launch.
   __shared__ uint32_t s_last;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    s_last = atomicAdd(L.end_done, 1u) == nblk - 1;
-  }
+  if (threadIdx.x == 0) s_last = atomicAdd(L.end_done, 1u) == nblk - 1;
   __syncthreads();
   if (!s_last) return;
   // the last workgroup: every other one has finished its sweeps

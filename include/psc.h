@@ -397,7 +397,12 @@ typedef struct psc_server_stats {
   uint64_t peak_active;     /* most jobs resident at once */
 } psc_server_stats;
 
-/* Device bytes the server reserves for a job (its admission cost). */
+/* Device bytes the server reserves for a job (its admission cost), for a
+ * server whose quantum is at most 1024 events: the lattice's buffers as
+ * allocated at the freeze plus a bound on its event tape (which grows with
+ * the job's events and its first-order reactions).  A job holds this much of
+ * the budget from its admission until it is retired (or, with keep_state,
+ * released), also when it fails. */
 psc_status psc_server_job_bytes(const psc_job_desc *job, uint64_t *bytes);
 
 /* Starts the worker.  EINVAL on bad options or device. */

@@ -550,7 +550,7 @@ int orc_add_reaction(orc_sim *s, int n_reac, const uint16_t *reac, int n_prod,
   return s->n_rx++;
 }
 
-/* Uniform initial placement ("distributed homogeneously", 3.4): attempt a of
+/* Uniform initial placement (the homogeneous start of 3.4): attempt a of
  * the c-th placement call draws v = floor(r0 * nv / 2^32) from
  * Philox(seed; c, a, PHASE_PLACE, 0) and takes it if vacant. */
 int orc_place_uniform(orc_sim *s, uint16_t species, uint64_t count) {
@@ -644,7 +644,7 @@ int orc_load(orc_sim *s, const uint16_t *occ, uint64_t n_mol, const uint32_t *id
 /* Extra products (2nd, 3rd, ...) go to distinct vacant neighbours of v; the
  * vacant neighbours are listed in stencil order and each product takes
  * entry floor(w * count / 2^32) of the remaining list, w taken in sequence
- * from `words` (2.4.1: "tries to find adjacent vacant voxels").  Returns -1
+ * from `words` (2.4.1: extra products need vacant neighbours).  Returns -1
  * (and changes nothing) when too few are vacant. */
 static int pick_vacant(const orc_sim *s, uint32_t v, int n_extra,
                        const uint32_t *words, uint32_t *out) {
@@ -984,7 +984,7 @@ static int walk(orc_sim *s, const uint8_t due[MAX_SPECIES], const uint8_t *order
   uint64_t n_slots0 = s->n_slots;
   s->walk_slot0 = n_slots0;
   if (mode == ORC_MODE_S) {
-    /* the paper's order: species ascending, molecules in dictionary order */
+    /* the paper's order: species ascending, molecules in ascending id */
     uint32_t *list = malloc((n_slots0 + 1) * sizeof *list);
     if (!list) { free(reacted); return -1; }
     uint64_t n = 0;

@@ -34,14 +34,15 @@
  *                  must not change: same-colour closed neighbourhoods are
  *                  disjoint).
  *   ORC_MODE_S     the paper's sequential order: species ascending, molecules
- *                  in ascending id ("dictionary order", 2.3); first-order
+ *                  in ascending id (the list order of 2.3); first-order
  *                  reactions by Gillespie's direct method run over the
  *                  interval (2.4.1).
  *
  * Parity status: every function here is pinned by a test that does not
- * re-derive it from this file (geometry against Euclidean distances, Philox
- * against numpy's Philox-4x64, the walk by brute force on 4x4x4 and by
- * diffusion / reaction statistics).
+ * re-derive it from this file (geometry against Euclidean distances,
+ * Philox4x32-10 against its published known-answer vectors and the 4x64
+ * variant against numpy's Philox-4x64, the walk by brute force on 4x4x4 and
+ * by diffusion / reaction statistics).
  */
 #ifndef PSC_ORACLE_H
 #define PSC_ORACLE_H

@@ -38,6 +38,7 @@ struct Job {
   psc_job_status st{};
   psc_lattice *lat = nullptr;
   uint64_t est_bytes = 0;
+  bool charged = false;  // est_bytes counted in the server's used bytes
 };
 
 }  // namespace
@@ -106,11 +107,25 @@ void finish_job(psc_server *S, Job *j, int state, psc_status code) {
   S->cv_done.notify_all();
 }
 
+// the admission cost of a job is charged when it is admitted and returned
+// when its lattice is released, whether or not the lattice was ever built
+// (called with the lock held)
+void charge(psc_server *S, Job *j) {
+  S->used_bytes += j->est_bytes;
+  j->charged = true;
+  S->stats.device_bytes_in_use = S->used_bytes;
+}
+
 void release_lattice(psc_server *S, Job *j) {
-  if (!j->lat) return;
-  psc_destroy(j->lat);
-  j->lat = nullptr;
-  S->used_bytes -= std::min(S->used_bytes, j->est_bytes);
+  if (j->lat) {
+    psc_destroy(j->lat);
+    j->lat = nullptr;
+  }
+  if (j->charged) {
+    S->used_bytes -= std::min(S->used_bytes, j->est_bytes);
+    j->charged = false;
+    S->stats.device_bytes_in_use = S->used_bytes;
+  }
 }
 
 void worker_main(psc_server *S) {
@@ -122,7 +137,7 @@ void worker_main(psc_server *S) {
       Job *j = S->queue.front();
       if (S->used_bytes + j->est_bytes > S->opt.budget_bytes && !S->active.empty()) break;
       S->queue.pop_front();
-      S->used_bytes += j->est_bytes;
+      charge(S, j);
       lk.unlock();
       const psc_status st = build_job(S, j);
       lk.lock();
@@ -253,16 +268,34 @@ psc_status psc_server_create(const psc_server_options *opt, psc_server **out) {
   return PSC_OK;
 }
 
-psc_status psc_server_job_bytes(const psc_job_desc *d, uint64_t *bytes) {
-  if (!d || !bytes) return PSC_EINVAL;
+// device bytes of a job's event tape: per event the due mask (8 B), the
+// largest first-order threshold (4 B) and one threshold per first-order
+// reaction (4 B each).  The tape grows by doubling from 1024 rows and the
+// server asks for a quantum beyond the job's last event, so it ends below
+// 2 (n_events + max(quantum, 1024)) rows; superseded tapes stay allocated
+// until the lattice is destroyed, at most as many rows again.  Each
+// allocation is rounded up to 256 B (three per growth, at most 64 growths).
+uint64_t tape_bytes(const psc_job_desc *d, uint32_t quantum) {
+  uint32_t n_fo = 0;
+  for (uint32_t r = 0; d->reactions && r < d->n_reactions; ++r) n_fo += d->reactions[r].n_r == 1;
+  const uint64_t rows = 2 * (d->n_events + std::max<uint64_t>(quantum, 1024));
+  return 2 * rows * (12 + 4 * (uint64_t)n_fo) + 64 * 3 * 256;
+}
+
+uint64_t job_bytes(const psc_job_desc *d, uint32_t quantum) {
   const uint64_t nv = (uint64_t)d->ni * d->nj * d->nk;
   bool collision_births = false;
   for (uint32_t r = 0; d->reactions && r < d->n_reactions; ++r)
     collision_births |= d->reactions[r].n_r == 2 && d->reactions[r].n_p > 2;
-  *bytes = estimate_device_bytes(nv, d->max_molecules, (d->flags & PSC_TRACK_DISPLACEMENT) != 0,
-                                 d->n_reactions, collision_births,
-                                 (d->flags & PSC_LATTICE_FCC) ? kColoursFcc : kColoursHcp) +
-           (d->n_events + 2048) * 64;  // event tape, grown geometrically
+  return estimate_device_bytes(nv, d->max_molecules, (d->flags & PSC_TRACK_DISPLACEMENT) != 0,
+                               d->n_reactions, collision_births,
+                               (d->flags & PSC_LATTICE_FCC) ? kColoursFcc : kColoursHcp) +
+         tape_bytes(d, quantum);
+}
+
+psc_status psc_server_job_bytes(const psc_job_desc *d, uint64_t *bytes) {
+  if (!d || !bytes) return PSC_EINVAL;
+  *bytes = job_bytes(d, 1024);
   return PSC_OK;
 }
 
@@ -283,7 +316,7 @@ psc_status psc_server_submit(psc_server *S, const psc_job_desc *d, uint64_t *job
   if (d->n_place && d->place) j->place.assign(d->place, d->place + d->n_place);
   j->n_events = d->n_events;
   j->keep_state = d->keep_state != 0;
-  psc_server_job_bytes(d, &j->est_bytes);
+  j->est_bytes = job_bytes(d, S->opt.quantum_events);
   std::lock_guard<std::mutex> g(S->mu);
   if (S->stopping) {
     delete j;

@@ -1,5 +1,5 @@
 // Test helper: the device geometry of libpsc (psc_core.h: stencils, walls,
-// colours, hop vectors, brick layout), compiled for the host so that the CPU
+// colours, hop vectors, brick layout) and its Philox generator, compiled for the host so that the CPU
 // tests can compare it with the oracle voxel by voxel.  Not part of the
 // library.
 #include "psc_core.h"
@@ -52,6 +52,15 @@ void probe_colours(uint32_t ni, uint32_t nj, uint32_t nk, int lattice, uint32_t 
 void probe_hop(uint32_t n, int32_t k, int lattice, int32_t *out) {
   if (lattice) hop_vector_t<1>(n, k & 1, out[0], out[1], out[2]);
   else hop_vector_t<0>(n, k & 1, out[0], out[1], out[2]);
+}
+
+// the kernels' Philox4x32-10: out = philox(counter c, key k)
+void probe_philox(const uint32_t *c, const uint32_t *k, uint32_t *out) {
+  const U4 r = philox(c[0], c[1], c[2], c[3], k[0], k[1]);
+  out[0] = r.x;
+  out[1] = r.y;
+  out[2] = r.z;
+  out[3] = r.w;
 }
 
 int probe_n_colours(int lattice) {

@@ -4,7 +4,8 @@ layout of `psc_core.h`, compiled for the host from the library's own header,
 must give what the oracle gives for every voxel and direction (2.1; the FCC
 stencil as the oracle derives it from ABC-stacked positions).  The oracle's
 geometry is pinned to Euclidean geometry by the oracle tests; this closes
-the loop without a GPU."""
+the loop without a GPU.  The kernels' Philox4x32-10, compiled the same way,
+must reproduce the generator's published known-answer vectors."""
 import ctypes as C
 import os
 import subprocess
@@ -34,6 +35,7 @@ def probe(tmp_path_factory):
     L.probe_neighbours.argtypes = [C.c_uint32] * 3 + [C.c_int] * 3 + [u32p]
     L.probe_colours.argtypes = [C.c_uint32] * 3 + [C.c_int, u32p]
     L.probe_hop.argtypes = [C.c_uint32, C.c_int32, C.c_int, C.POINTER(C.c_int32)]
+    L.probe_philox.argtypes = [u32p, u32p, u32p]
     L.probe_n_colours.argtypes = [C.c_int]
     L.probe_n_colours.restype = C.c_int
     return L
@@ -70,3 +72,14 @@ def test_colours_and_hop_vectors_equal_the_oracle(probe, dims, lattice):
         for n in range(12):
             probe.probe_hop(n, k, lattice, out)
             assert tuple(out) == oracle.hop_vector_l(dims, v, n, lattice), (v, n)
+
+
+def test_device_philox_known_answers(probe):
+    from test_oracle_philox import philox4x32_kat
+    u32p = C.POINTER(C.c_uint32)
+    for ctr, key, want in philox4x32_kat():
+        c = np.array(ctr, np.uint32)
+        k = np.array(key, np.uint32)
+        out = np.zeros(4, np.uint32)
+        probe.probe_philox(c.ctypes.data_as(u32p), k.ctypes.data_as(u32p), out.ctypes.data_as(u32p))
+        assert tuple(int(x) for x in out) == want, (ctr, key)

@@ -124,4 +124,10 @@ def test_invalid_job_fails_alone():
     for w, jid in zip(jobs, ids):
         assert srv.wait(jid)["state"] == psc.JOB_DONE
         same(srv.read_state(jid, cap_of(w)), alone(w))
+    # the failed jobs returned what their admission charged, and so does
+    # every kept job once released
+    assert srv.stats()["device_bytes_in_use"] > 0
+    for jid in ids:
+        srv.release(jid)
+    assert srv.stats()["device_bytes_in_use"] == 0
     srv.close()

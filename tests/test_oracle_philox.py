@@ -1,16 +1,42 @@
 """Pins of the oracle's Philox generator (Salmon et al., SC'11).
 
-The oracle's 4x64 variant, built from the same round structure as its 4x32
-variant, is checked against numpy's independent Philox-4x64-10; the 4x32
-variant's Weyl constants are checked against their closed forms, and its
-output against avalanche and uniformity properties.
+The oracle's 4x32 variant (the one every draw of the simulation uses) is
+checked against the published known-answer vectors of Philox4x32-10
+(tests/golden/philox4x32_10_kat.txt); its 4x64 variant, built from the same
+round structure, against numpy's independent Philox-4x64-10; the Weyl
+constants against their closed forms; the output against avalanche and
+uniformity properties.
 """
+import os
 from decimal import Decimal, getcontext
 
 import numpy as np
 import pytest
 
 import oracle
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "philox4x32_10_kat.txt")
+
+
+def philox4x32_kat():
+    """(counter, key, output) rows of the published Philox4x32-10 vectors"""
+    rows = []
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            w = [int(x, 16) for x in line.split()]
+            rows.append((tuple(w[0:4]), tuple(w[4:6]), tuple(w[6:10])))
+    return rows
+
+
+def test_philox4x32_known_answers():
+    rows = philox4x32_kat()
+    assert len(rows) == 3
+    for ctr, key, want in rows:
+        assert tuple(int(x) for x in oracle.philox4x32(ctr, key)) == want, (ctr, key)
 
 
 @pytest.mark.parametrize("key,ctr", [

@@ -32,9 +32,14 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 CROSS_BRICK_FRACTION = {"hcp": 11.0 / 32.0, "fcc": 45.0 / 128.0}
 
 
+# the device code of the library (every kernel and the headers they include)
+KERNEL_SOURCES = ("psc_kernels.hip", "psc_stage_hcp.hip", "psc_stage_fcc.hip",
+                  "psc_stage_multi.hip", "psc_stage_impl.h", "psc_device.h", "psc_core.h")
+
+
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("psc_kernels.hip", "psc_core.h"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1605_03726_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -278,7 +283,7 @@ def main():
     ap.add_argument("--workload", default="cfg3",
                     choices=["cfg1", "cfg2", "cfg3", "mapk_paper", "multiproduct"])
     ap.add_argument("--timing-steps", type=int, default=40,
-                    help="events of the timed region whose launches are timed one by one")
+                    help="events after the timed region whose launches are timed one by one")
     ap.add_argument("--walls", action="store_true",
                     help="close the workload's box by walls instead of wrapping it")
     ap.add_argument("--fcc", action="store_true",
@@ -340,48 +345,45 @@ def main():
     setup_s = time.perf_counter() - t_setup
     print("setup + warmup %.1f s" % setup_s, file=sys.stderr, flush=True)
 
-    # ---- timed region: K events, HIP events on the launch stream.  Every
-    # (K / timing_steps)-th event also records HIP events around each of its
-    # launches (switching that on and off never waits for the device), so
-    # the walk stage's average launch time is measured over the timed region
-    # itself ----
+    # ---- timed region: K events of plain launches, HIP events on the launch
+    # stream before and after ----
     stages = 16  # colour stages per event on either lattice
-    every = max(args.steps // max(args.timing_steps, 1), 1)
-    lat.set_kernel_timing(True)
-    lat.set_kernel_timing(False)
     c0 = lat.counters()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
-    done = 0
-    while done < args.steps:
-        n = min(every - 1, args.steps - done)
-        if n:
-            lat.step(n)
-            done += n
-        if done < args.steps:
-            lat.set_kernel_timing(True, keep=True)
-            lat.step(1)
-            lat.set_kernel_timing(False)
-            done += 1
+    lat.step(args.steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     c1 = lat.counters()
     attempts = c1["attempts"] - c0["attempts"]
     hops = c1["hops"] - c0["hops"]
-    kt = lat.kernel_times()
     print("timed %d events: %.2f ms, %d attempts" % (args.steps, ms, attempts), file=sys.stderr,
           flush=True)
+
+    # ---- launch times, right after the timed region: every launch of the
+    # next `timing_steps` events between HIP events on the launch stream (a
+    # pass of its own, so that the event records do not perturb the timed
+    # region) ----
+    tsteps = max(args.timing_steps, 1)
+    lat.set_kernel_timing(True)
+    ct0 = lat.counters()
+    lat.step(tsteps)
+    lat.set_kernel_timing(False)
+    kt = lat.kernel_times()
+    ct1 = lat.counters()
+    s_att = ct1["attempts"] - ct0["attempts"]
+    s_hops = ct1["hops"] - ct0["hops"]
 
     # ---- the dominant kernel (the walk stage) against the HBM roofline:
     # algorithmic bytes of the timed region per stage launch over the
     # sampled launches' average time ----
     stage_avg_ms = kt["stage_ms"] / max(kt["stage_launches"], 1)
-    launches = args.steps * stages
-    t_att = attempts / launches
-    alg_bytes_per_launch = (6.0 * attempts + 8.0 * hops) / launches
+    launches = tsteps * stages
+    t_att = s_att / launches
+    alg_bytes_per_launch = (6.0 * s_att + 8.0 * s_hops) / launches
     achieved = alg_bytes_per_launch / (stage_avg_ms * 1e-3) / 1e9
     traffic = read_traffic(w["name"])
     lat.close()

@@ -34,6 +34,15 @@ constexpr uint32_t kErrBinOverflow = 1u, kErrCandOverflow = 2u, kErrFlagOverflow
 // species flags
 constexpr uint8_t kSpMobile = 1, kSpFirstOrder = 2;
 
+// Statistics counters (attempts, hops, collisions, placement failures; live
+// molecules per species; firings per reaction) are kept in kStatRep
+// replicas, one per group of workgroups, each starting on its own 128-byte
+// line; the host sums them.  A counter that every workgroup of a stage adds
+// to would otherwise queue those 64-bit atomics on one line.
+constexpr uint32_t kStatRep = 16;
+constexpr uint32_t kCntStride = 16;  // words per replica of the four counters
+constexpr uint32_t kSpStride = 64;   // words per replica of the species counts
+
 // ---- Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ---------------------
 // Counter (c0, c1, c2, c3) = (event, molecule id, phase, block), key = seed.
 struct U4 {
@@ -406,9 +415,13 @@ struct LatDev {
   uint4 *sdesc;                    // [kMaxColours] per stage: colour, count, event
                                    // (lo, hi); stages past ncol are empty
   uint32_t *next_id;
-  unsigned long long *cnt;         // attempts, hops, collisions, placement failures
-  unsigned long long *sp_count;    // [64] live molecules per species (two's complement deltas)
-  unsigned long long *fired;       // [n_rx]
+  // statistics, kStatRep replicas each (see kStatRep)
+  unsigned long long *cnt;         // [kStatRep * kCntStride] attempts, hops, collisions,
+                                   // placement failures
+  unsigned long long *sp_count;    // [kStatRep * kSpStride] live molecules per species
+                                   // (two's complement deltas)
+  unsigned long long *fired;       // [kStatRep * fired_stride] firings per reaction
+  uint32_t fired_stride;           // n_rx rounded up to a 128-byte line
   uint32_t *error;
 };
 
@@ -425,6 +438,13 @@ hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, i
 hipError_t launch_begin(const LatDev *dL, int decide_grid, hipStream_t s);
 hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp, bool fcc,
                         hipStream_t s);
+// the stage kernels of one lattice kind (LAT: 0 HCP, 1 FCC) and the batched
+// stage kernel of an ensemble, each in a translation unit of its own
+template <int LAT>
+hipError_t launch_stage_lat(const LatDev *dL, uint32_t g, int grid, int items, bool disp,
+                            hipStream_t s);
+hipError_t launch_stage_multi(const LatDev *lats, uint32_t R, uint32_t g, int grid, int items,
+                              hipStream_t s);
 uint32_t max_members();
 hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t s);
 // occupancy between the linear (ABI) order and the lattice's layout

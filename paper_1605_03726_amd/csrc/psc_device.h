@@ -1,0 +1,469 @@
+// psc_device.h -- device-side building blocks of the walk kernels shared by
+// the translation units of libpsc's gfx950 code: block sizes, the per-event
+// stage order, first-order helpers, and one chunk of a walk stage
+// (stage_chunk), which both the single-lattice and the batched stage kernels
+// run.
+#pragma once
+
+#include "psc_core.h"
+
+namespace psc {
+
+namespace {
+
+constexpr int kStageThreads = 256;
+constexpr int kBeginThreads = 1024;
+
+__device__ __forceinline__ uint32_t colour_of_voxel(const Geo &g, uint32_t v) {
+  return colour_of(g, coord_of(g, v));
+}
+
+__device__ __forceinline__ void set_error(const LatDev &L, uint32_t bit) { atomicOr(L.error, bit); }
+
+// ---- stage order ---------------------------------------------------------------
+// Fisher-Yates over the n colours, slot i = n-1..1 swapping with
+// floor(r (i+1) / 2^32), r in sequence from the words of
+// Philox(seed; e, 0xFFFFFFFF, phase 2, block 0, 1, ...).
+__device__ __forceinline__ void stage_order(const LatDev &L, uint64_t e, uint32_t *perm) {
+  const uint32_t n = L.ncol;
+  uint32_t w[kMaxColours];
+  for (uint32_t b = 0; 4 * b < n; ++b) {
+    const U4 r = philox((uint32_t)e, 0xFFFFFFFFu, kPhaseStage, b, L.key0, L.key1);
+    w[4 * b + 0] = r.x;
+    w[4 * b + 1] = r.y;
+    w[4 * b + 2] = r.z;
+    w[4 * b + 3] = r.w;
+  }
+  for (uint32_t c = 0; c < n; ++c) perm[c] = c;
+  int idx = 0;
+  for (int i = (int)n - 1; i >= 1; --i) {
+    const uint32_t j = scale32(w[idx++], (uint32_t)(i + 1));
+    const uint32_t t = perm[i];
+    perm[i] = perm[j];
+    perm[j] = t;
+  }
+}
+
+// first-order reaction fired by a molecule of species sp with first draw r0,
+// or -1: the slot whose cumulative threshold first exceeds r0
+__device__ __forceinline__ int first_order_choice(const LatDev &L, uint64_t e, uint32_t sp, uint32_t r0) {
+  const uint32_t first = L.fo_first[sp], n = L.fo_n[sp];
+  const uint32_t *C = L.tape_thr + e * (uint64_t)L.n_fo + first;
+  for (uint32_t a = 0; a < n; ++a)
+    if (r0 < C[a]) return (int)L.fo_rx[first + a];
+  return -1;
+}
+
+// the words used to place extra first-order products: r.y, r.z, r.w of block
+// 0, then the four words of blocks 1, 2, 3
+__device__ __forceinline__ uint32_t placement_word(const LatDev &L, uint64_t e, uint32_t id, const U4 &r0,
+                                          int q) {
+  if (q == 0) return r0.y;
+  if (q == 1) return r0.z;
+  if (q == 2) return r0.w;
+  const int b = 1 + (q - 3) / 4, w = (q - 3) % 4;
+  const U4 r = philox((uint32_t)e, id, kPhaseFirst, (uint32_t)b, L.key0, L.key1);
+  return w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
+}
+
+// ---- block-wide helpers ----------------------------------------------------------
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x,
+                                                   unsigned long long *s_tmp) {
+  // wavefront reduction, then one value per wave through LDS
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s_tmp[wave] = x;
+  __syncthreads();
+  unsigned long long total = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += s_tmp[w];
+  __syncthreads();
+  return total;
+}
+
+// statistics replica of the calling workgroup: counters that many
+// workgroups add to are spread over kStatRep copies (summed on the host), so
+// that their atomics do not queue on one cache line
+__device__ __forceinline__ uint32_t stat_rep() { return (blockIdx.x + blockIdx.y) & (kStatRep - 1u); }
+__device__ __forceinline__ unsigned long long *stat_cnt(const LatDev &L) {
+  return L.cnt + kCntStride * stat_rep();
+}
+__device__ __forceinline__ unsigned long long *stat_sp(const LatDev &L) {
+  return L.sp_count + kSpStride * stat_rep();
+}
+__device__ __forceinline__ unsigned long long *stat_fired(const LatDev &L) {
+  return L.fired + (uint64_t)L.fired_stride * stat_rep();
+}
+
+}  // namespace
+
+// =============================================================================
+// k_stage: one colour stage of the walk
+// =============================================================================
+// shared scratch of one walk-stage workgroup
+struct StageShared {
+  uint32_t cnt[kMaxColours], base[kMaxColours], loff[kMaxColours];
+  uint32_t ncand, cand_base, nflag, flag_base, total;
+  unsigned long long att, hop, col;
+  int32_t dsp[64];   // species count changes of this chunk
+  uint32_t any_rx;
+};
+
+// a chunk's surviving entries in LDS, colour-major, so that they leave for
+// the bins in contiguous runs (coalesced stores)
+template <int ITEMS>
+struct StageStaging {
+  uint32_t vox[kStageThreads * ITEMS];
+  uint32_t id[kStageThreads * ITEMS];
+  uint32_t spc[kStageThreads * ITEMS];  // species | colour << 16
+};
+
+// Molecules [base, base + kStageThreads * ITEMS) of colour bin c of lattice L
+// in event e: each attempts one hop; collisions with a registered partner
+// fire the second-order reaction; survivors are appended to the next event's
+// bins through block-local slots (LDS) and one global reservation per colour.
+// The kernels' buffers all live in device memory: a view in the global
+// address space makes loads and stores through it global instructions
+// instead of flat ones.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> global(T *p) {
+  return (gptr<T>)p;
+}
+
+// DM: displacement planes never (0), always (1), or as the lattice says (2)
+// A collision of the mover (id, species sp, voxel v) with the partner at t
+// (species psp) fires reaction rx (2.4.2).  The first product takes the
+// partner's voxel and identity: the partner's entry (wherever it is) stays
+// valid, flagged so that it does not walk again in this event, its voxel
+// marked hot so that its cached species is refreshed.  The second takes the
+// mover's voxel and identity; with one product the mover's identity ends.
+// Further products need as many distinct vacant neighbours of v, else
+// nothing happens (a placement failure): each takes entry floor(w k / 2^32)
+// of the k vacant neighbours left in stencil order, w = r2, r3 of the walk
+// draw, then further blocks; they are numbered at the end of the event.
+// EXTRA: the reaction may have more than two products; LAT: 0 HCP, 1 FCC
+template <bool EXTRA, int LAT, class OccP, class HotP>
+__device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh, uint64_t e,
+                                               uint32_t buf, uint32_t hbits, OccP occ, HotP hot,
+                                               int rx, uint32_t v, uint32_t t, uint32_t sp,
+                                               uint32_t psp, uint32_t id, uint32_t &osp,
+                                               uint32_t &ocol, bool &flag, uint32_t &ftgt) {
+  const uint32_t m = EXTRA ? L.rx_nprod[rx] : min(L.rx_nprod[rx], 2u);
+  uint32_t vmask = 0;
+  Coord cv;
+  if (EXTRA && m > 2) {
+    cv = coord_of(L.geo, v);
+    for (uint32_t n = 0; n < 12; ++n) {
+      Coord cn;
+      if (step_target_t<LAT>(L.geo, cv, n, cn) && occ[index_of(L.geo, cn)] == 0) vmask |= 1u << n;
+    }
+    if (__popc(vmask) < (int)(m - 2)) {
+      atomicAdd(&stat_cnt(L)[3], 1ull);
+      return;
+    }
+  }
+  const uint16_t *prod = L.rx_prod + rx * 12;
+  occ[t] = (uint16_t)(prod[0] | kReactedFlag);
+  const uint32_t ht = hot_hash(t, hbits);
+  atomicOr((uint32_t *)&hot[ht >> 4], 1u << (((ht & 15u) << 1) | buf));
+  flag = true;
+  ftgt = t;
+  atomicSub(&sh.dsp[sp], 1);
+  atomicSub(&sh.dsp[psp], 1);
+  atomicAdd(&sh.dsp[prod[0] & 63u], 1);
+  sh.any_rx = 1;
+  if (m >= 2) {
+    occ[v] = prod[1];
+    osp = prod[1];
+    atomicAdd(&sh.dsp[prod[1] & 63u], 1);
+  } else {
+    occ[v] = 0;
+    ocol = 0xFFu;
+  }
+  for (uint32_t q = 0; EXTRA && q + 2 < m; ++q) {
+    uint32_t w;
+    if (q < 2) {
+      const U4 r0 = philox((uint32_t)e, id, kPhaseWalk, 0, L.key0, L.key1);
+      w = q == 0 ? r0.z : r0.w;
+    } else {
+      const U4 rb = philox((uint32_t)e, id, kPhaseWalk, 1 + (q - 2) / 4, L.key0, L.key1);
+      const uint32_t k = (q - 2) & 3u;
+      w = k == 0 ? rb.x : (k == 1 ? rb.y : (k == 2 ? rb.z : rb.w));
+    }
+    uint32_t x = scale32(w, (uint32_t)__popc(vmask)), n = 0;
+    for (;; ++n) {
+      if (!((vmask >> n) & 1u)) continue;
+      if (x == 0) break;
+      --x;
+    }
+    vmask &= ~(1u << n);
+    Coord cn;
+    step_target_t<LAT>(L.geo, cv, n, cn);
+    const uint32_t u = index_of(L.geo, cn);
+    const uint16_t ps = prod[2 + q];
+    occ[u] = ps;
+    atomicAdd(&sh.dsp[ps & 63u], 1);
+    const uint32_t slot = atomicAdd(L.wb_count, 1u);
+    if (slot < L.wb_cap) {
+      L.wb_vox[slot] = u;
+      L.wb_key[slot] = ((uint64_t)id << 32) | ((uint64_t)(2 + q) << 28) | slot;
+    } else {
+      set_error(L, kErrBirthOverflow);
+    }
+  }
+  atomicAdd(&stat_fired(L)[rx], 1ull);
+}
+
+template <int ITEMS, int DM, int LAT>
+__device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t base, uint32_t n,
+                            StageShared &S, StageStaging<ITEMS> &stg) {
+  constexpr uint32_t NC = LAT ? kColoursFcc : kColoursHcp;
+  StageShared *sh = &S;
+  const int tid = threadIdx.x;
+  const uint32_t buf = (uint32_t)(e & 1);
+  const Bins &in = L.bins[buf];
+  const Bins &out = L.bins[buf ^ 1];
+  const uint64_t due = L.tape_due[e];
+  const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
+  const uint32_t cnext = (uint32_t)((e + 1) & 1);
+  const uint64_t cap = L.cap;
+  const bool disp = DM == 2 ? in.disp != nullptr : DM == 1;
+  const auto hot = global(L.hot);
+  const auto occ = global(L.occ);
+  const auto ivox = global(in.vox), iid = global(in.id), ovox = global(out.vox), oid = global(out.id);
+  const auto isp = global(in.sp), osp_ = global(out.sp);
+  const auto idsp = global(in.disp), odsp = global(out.disp);
+  const uint32_t hbits = L.hot_bits;
+  unsigned long long n_att = 0, n_hop = 0, n_col = 0;
+  uint32_t *s_cnt = sh->cnt, *s_base = sh->base;
+  uint32_t &s_ncand = sh->ncand, &s_cand_base = sh->cand_base;
+  uint32_t &s_nflag = sh->nflag, &s_flag_base = sh->flag_base;
+  if (tid < (int)NC) s_cnt[tid] = 0;
+  if (tid == 32) s_ncand = 0;
+  if (tid == 33) s_nflag = 0;
+  if (tid == 34) {
+    sh->att = 0;
+    sh->hop = 0;
+    sh->col = 0;
+    sh->any_rx = 0;
+  }
+  if (tid < 64) sh->dsp[tid] = 0;
+  __syncthreads();
+
+  uint32_t vox[ITEMS], id[ITEMS], ocol[ITEMS], lpos[ITEMS], osp[ITEMS];
+  int32_t d0[ITEMS], d1[ITEMS], d2[ITEMS];
+  bool cand[ITEMS], flag[ITEMS];
+  uint32_t ftgt[ITEMS];
+
+  // bin entries: lanes past the end read the last entry (base < n) and are
+  // then marked dead, so no load sits behind a branch
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t idx = min(base + (uint64_t)it * kStageThreads + tid, (uint64_t)n - 1);
+    vox[it] = ivox[c * cap + idx];
+    id[it] = iid[c * cap + idx];
+    osp[it] = isp[c * cap + idx];
+    d0[it] = d1[it] = d2[it] = 0;
+  }
+  if (disp) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint64_t idx = min(base + (uint64_t)it * kStageThreads + tid, (uint64_t)n - 1);
+      d0[it] = idsp[(0 * NC + c) * cap + idx];
+      d1[it] = idsp[(1 * NC + c) * cap + idx];
+      d2[it] = idsp[(2 * NC + c) * cap + idx];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    ocol[it] = 0xFFu;
+    cand[it] = false;
+    flag[it] = false;
+    if (base + (uint64_t)it * kStageThreads + tid >= n) id[it] = kDeadId;
+  }
+
+  constexpr uint32_t kWallBit = 1u << 16;  // in mv: the target lies beyond a wall
+  // Load phase: every item's draw, target and target word before any store.
+  // Same-stage molecules have disjoint closed neighbourhoods, so no store of
+  // this stage changes a word loaded here; issuing all loads first keeps
+  // 2 x ITEMS reads in flight per thread.  The phase has no branch: dead
+  // entries and tail lanes hold valid voxels (their results are dropped
+  // below), and a molecule whose cached species is not due reads voxel 0
+  // instead of its target.
+  uint32_t tgt[ITEMS], wt[ITEMS], hw[ITEMS], hs[ITEMS], ry[ITEMS], mv[ITEMS];
+  bool loaded[ITEMS];
+  int drx[ITEMS];  // reaction | partner species << 8 of a deferred collision, or -1
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    drx[it] = -1;
+    const uint32_t v = vox[it];
+    const U4 r = philox((uint32_t)e, id[it], kPhaseWalk, 0, L.key0, L.key1);
+    const uint32_t dir = scale32(r.x, 12);
+    const Coord cv = coord_of(L.geo, v);
+    Coord ct;
+    const bool open = step_target_t<LAT>(L.geo, cv, dir, ct);
+    tgt[it] = index_of(L.geo, ct);
+    ry[it] = r.y;
+    mv[it] = dir | (LAT ? 0u : (cv.k & 1u) << 4) | (colour_t<LAT>(ct) << 8) |
+             (open ? 0u : kWallBit);
+    const uint32_t h = hot_hash(v, hbits);
+    hw[it] = hot[h >> 4];
+    hs[it] = (h & 15u) << 1;
+    loaded[it] = ((due >> (osp[it] & 63u)) & 1ull) != 0;
+    wt[it] = occ[loaded[it] ? tgt[it] : 0u];
+  }
+
+  // Commit phase.
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (id[it] == kDeadId) continue;
+    const uint32_t v = vox[it];
+    const uint32_t t = tgt[it];
+    uint32_t sp = osp[it] & 63u;
+    ocol[it] = c;  // stays in place unless it hops or is consumed
+    if ((hw[it] >> hs[it]) & 3u) {
+      // the cached species may be stale, or the molecule may have reacted
+      // as a partner earlier in this walk: consult the lattice word
+      const uint16_t w = occ[v];
+      sp = w & 63u;
+      osp[it] = sp;
+      if (w & kReactedFlag) continue;
+    }
+    if (!((due >> sp) & 1ull)) continue;
+    ++n_att;
+    if (mv[it] & kWallBit) continue;  // a wall: the molecule stays, no collision
+    const uint32_t w_t = loaded[it] ? wt[it] : (uint32_t)occ[t];
+    if (w_t == 0) {
+      occ[t] = (uint16_t)sp;
+      occ[v] = 0;
+      vox[it] = t;
+      ocol[it] = (mv[it] >> 8) & (LAT ? 31u : 15u);
+      int32_t X, Y, Z;
+      hop_vector_t<LAT>(mv[it] & 15u, (mv[it] >> 4) & 1u, X, Y, Z);
+      d0[it] += X;
+      d1[it] += Y;
+      d2[it] += Z;
+      ++n_hop;
+      continue;
+    }
+    ++n_col;
+    const uint32_t psp = w_t & 63u;
+    const int rx = L.pair_rx[sp * 64 + psp];
+    if (rx < 0) continue;
+    if (!L.rx_always[rx] && !(ry[it] < L.rx_thr[rx])) continue;
+    if (L.rx_nprod[rx] > 2) {
+      // more than two products: applied after this loop (rare), where fewer
+      // of the items' values are live
+      drx[it] = rx | (int)(psp << 8);
+      continue;
+    }
+    fire_collision<false, LAT>(L, *sh, e, buf, hbits, occ, hot, rx, v, t, sp, psp, id[it],
+                               osp[it], ocol[it], flag[it], ftgt[it]);
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it)
+    if (drx[it] >= 0)
+      fire_collision<true, LAT>(L, *sh, e, buf, hbits, occ, hot, drx[it] & 0xFF, vox[it],
+                                tgt[it], osp[it] & 63u, (uint32_t)drx[it] >> 8, id[it], osp[it],
+                                ocol[it], flag[it], ftgt[it]);
+
+  // ---- survivors: block-local slots per colour (LDS atomics), one global
+  // reservation per colour per chunk, entries staged colour-major in LDS and
+  // written out in contiguous runs.  Flags and first-order candidates of the
+  // next event are reserved in the same round. ----
+  uint32_t fslot[ITEMS], cslot[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (ocol[it] != 0xFFu) {
+      lpos[it] = atomicAdd(&s_cnt[ocol[it]], 1u);
+      // can this molecule fire a first-order reaction in the next event?
+      if (cmax_next) {
+        const U4 r = philox((uint32_t)(e + 1), id[it], kPhaseFirst, 0, L.key0, L.key1);
+        cand[it] = r.x < cmax_next;
+      }
+      if (cand[it]) cslot[it] = atomicAdd(&s_ncand, 1u);
+    }
+    if (flag[it]) fslot[it] = atomicAdd(&s_nflag, 1u);
+  }
+  if (n_att) atomicAdd(&sh->att, n_att);
+  if (n_hop) atomicAdd(&sh->hop, n_hop);
+  if (n_col) atomicAdd(&sh->col, n_col);
+  __syncthreads();
+  // one wave per job: bin reservations; flag and candidate reservations;
+  // local colour offsets and the chunk's counters; species count changes
+  if (tid < (int)NC) {
+    s_base[tid] = s_cnt[tid] ? atomicAdd(&out.count[tid], s_cnt[tid]) : 0u;
+  } else if (tid == 64) {
+    if (s_ncand) s_cand_base = atomicAdd(&L.cand_count[cnext], s_ncand);
+  } else if (tid == 65) {
+    if (s_nflag) s_flag_base = atomicAdd(&L.flag_count[buf], s_nflag);
+  } else if (tid == 128) {
+    uint32_t acc = 0;
+    for (uint32_t k = 0; k < NC; ++k) {
+      sh->loff[k] = acc;
+      acc += s_cnt[k];
+    }
+    sh->total = acc;
+  } else if (tid == 129) {
+    unsigned long long *cnt = stat_cnt(L);
+    if (sh->att) atomicAdd(&cnt[0], sh->att);
+    if (sh->hop) atomicAdd(&cnt[1], sh->hop);
+    if (sh->col) atomicAdd(&cnt[2], sh->col);
+  } else if (tid >= 192) {
+    const int k = tid - 192;
+    if (sh->any_rx && sh->dsp[k])
+      atomicAdd(&stat_sp(L)[k], (unsigned long long)(long long)sh->dsp[k]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    if (flag[it]) {
+      const uint64_t f = (uint64_t)s_flag_base + fslot[it];
+      if (f < L.flag_cap) L.flag_vox[buf][f] = ftgt[it];
+      else set_error(L, kErrFlagOverflow);
+    }
+    if (ocol[it] == 0xFFu) continue;
+    const uint32_t oc = ocol[it];
+    const uint32_t q = sh->loff[oc] + lpos[it];
+    stg.vox[q] = vox[it];
+    stg.id[q] = id[it];
+    stg.spc[q] = osp[it] | (oc << 16);
+    const uint64_t pos = (uint64_t)s_base[oc] + lpos[it];
+    if (pos >= cap) continue;  // reported by the copy below
+    if (disp) {
+      odsp[(0 * NC + oc) * cap + pos] = d0[it];
+      odsp[(1 * NC + oc) * cap + pos] = d1[it];
+      odsp[(2 * NC + oc) * cap + pos] = d2[it];
+    }
+    if (cand[it]) {
+      const uint64_t r = (uint64_t)s_cand_base + cslot[it];
+      if (r < L.cand_cap) {
+        L.cand_pos[cnext][r] = (uint32_t)pos;
+        L.cand_id[cnext][r] = id[it];
+        L.cand_col[cnext][r] = (uint8_t)oc;
+      } else {
+        set_error(L, kErrCandOverflow);
+      }
+    }
+  }
+  __syncthreads();
+  // The next chunk rewrites this LDS only after two more barriers, which
+  // every thread reaches after finishing this copy.
+  const uint32_t total = sh->total;
+  for (uint32_t q = tid; q < total; q += kStageThreads) {
+    const uint32_t w = stg.spc[q];
+    const uint32_t oc = w >> 16;
+    const uint64_t pos = (uint64_t)s_base[oc] + (q - sh->loff[oc]);
+    if (pos >= cap) {
+      set_error(L, kErrBinOverflow);
+      continue;
+    }
+    ovox[oc * cap + pos] = stg.vox[q];
+    oid[oc * cap + pos] = stg.id[q];
+    osp_[oc * cap + pos] = (uint16_t)(w & 0xFFFFu);
+  }
+}
+
+}  // namespace psc

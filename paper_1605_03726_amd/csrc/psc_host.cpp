@@ -56,6 +56,10 @@ uint32_t prob_threshold(double p) {
   return (uint32_t)std::floor(x);
 }
 
+// words per replica of the per-reaction firing counters: the reactions
+// rounded up to a whole 128-byte line
+uint32_t fired_stride(uint32_t n_rx) { return (std::max<uint32_t>(n_rx, 1) + 15u) & ~15u; }
+
 uint64_t pow2_at_least(uint64_t x) {
   uint64_t p = 1;
   while (p < x) p <<= 1;
@@ -369,9 +373,10 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.perm = alloc_n<uint32_t>(h, kMaxColours);
   L.sdesc = alloc_n<uint4>(h, kMaxColours);
   L.next_id = alloc_n<uint32_t>(h, 1);
-  L.cnt = alloc_n<unsigned long long>(h, 4);
-  L.sp_count = alloc_n<unsigned long long>(h, 64);
-  L.fired = alloc_n<unsigned long long>(h, std::max<uint32_t>(R, 1));
+  L.cnt = alloc_n<unsigned long long>(h, kStatRep * kCntStride);
+  L.sp_count = alloc_n<unsigned long long>(h, kStatRep * kSpStride);
+  L.fired_stride = fired_stride(R);
+  L.fired = alloc_n<unsigned long long>(h, (uint64_t)kStatRep * L.fired_stride);
   L.error = alloc_n<uint32_t>(h, 1);
   h->dL = alloc_n<LatDev>(h, 1);
   if (!L.occ || !L.cand_count || !L.flag_vox[0] || !L.flag_vox[1] || !L.flag_count || !L.birth_key || !L.birth_vox ||
@@ -460,13 +465,14 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   if (L.wb_count) HIP_OK(h, hipMemset(L.wb_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.birth_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.fire_count, 0, sizeof(uint32_t)));
-  HIP_OK(h, hipMemset(L.cnt, 0, 4 * sizeof(unsigned long long)));
+  HIP_OK(h, hipMemset(L.cnt, 0, kStatRep * kCntStride * sizeof(unsigned long long)));
   {
-    std::vector<unsigned long long> counts(64, 0);
+    // the initial counts in replica 0, the other replicas at zero
+    std::vector<unsigned long long> counts(kStatRep * kSpStride, 0);
     for (uint64_t q = 0; q < nmol; ++q) counts[h->occ[h->mvox[q]] & 63u]++;
-    HIP_OK(h, up(L.sp_count, counts.data(), 64 * sizeof(unsigned long long)));
+    HIP_OK(h, up(L.sp_count, counts.data(), counts.size() * sizeof(unsigned long long)));
   }
-  HIP_OK(h, hipMemset(L.fired, 0, std::max<uint32_t>(R, 1) * sizeof(unsigned long long)));
+  HIP_OK(h, hipMemset(L.fired, 0, (uint64_t)kStatRep * L.fired_stride * sizeof(unsigned long long)));
   HIP_OK(h, hipMemset(L.error, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.end_done, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.nbr_cnt, 0, (1ull << L.nbr_bits) * sizeof(uint32_t)));
@@ -533,9 +539,26 @@ uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool dis
   t += r((1ull << nb) * 4);
   t += r(cap * 4) * 2 + r(cap) * 2 + r(4);
   const uint64_t R = std::max<uint32_t>(n_reactions, 1);
-  t += r(64) + r(64 * 64 * 2) + r(R * 4) + r(R) * 2 + r(R * 24) + r(128) + r(64) + r(512);
-  t += r(8) + r(64) + r(4) + r(32) + r(R * 8) + r(4) + r(sizeof(LatDev));
+  t += r(64) + r(64 * 64 * 2) + r(R * 4) + r(R) * 2 + r(R * 24) + r(128) + r(64);
+  t += r(kStatRep * kSpStride * 8) + r(kStatRep * kCntStride * 8) +
+       r((uint64_t)kStatRep * fired_stride((uint32_t)R) * 8);
+  t += r(8) + r(64) + r(4) + r(4) + r(sizeof(LatDev));
   return t;
+}
+
+// out[a] = the sum over the kStatRep replicas of counter a (a < n), each
+// replica `stride` words after the previous one
+psc_status read_replicas(psc_lattice *h, const unsigned long long *dev, uint32_t n,
+                         uint32_t stride, uint64_t *out) {
+  std::vector<unsigned long long> all((uint64_t)kStatRep * stride);
+  HIP_OK(h, hipMemcpy(all.data(), dev, all.size() * sizeof(unsigned long long),
+                      hipMemcpyDeviceToHost));
+  for (uint32_t a = 0; a < n; ++a) {
+    uint64_t sum = 0;
+    for (uint32_t r = 0; r < kStatRep; ++r) sum += all[(uint64_t)r * stride + a];
+    out[a] = sum;
+  }
+  return PSC_OK;
 }
 
 psc_status check_device_error(psc_lattice *h) {
@@ -918,8 +941,9 @@ psc_status psc_read_counters(psc_lattice *h, psc_counters *out, uint64_t *event)
   HIP_OK(h, hipDeviceSynchronize());
   psc_status st = check_device_error(h);
   if (st) return st;
-  unsigned long long cnt[4];
-  HIP_OK(h, hipMemcpy(cnt, h->L.cnt, sizeof cnt, hipMemcpyDeviceToHost));
+  uint64_t cnt[4];
+  psc_status rs = read_replicas(h, h->L.cnt, 4, kCntStride, cnt);
+  if (rs) return rs;
   *out = psc_counters{cnt[0], cnt[1], cnt[2], cnt[3]};
   return PSC_OK;
 }
@@ -947,8 +971,9 @@ psc_status psc_read_stats(psc_lattice *h, uint64_t *species_count, uint64_t *dis
   psc_status st = check_device_error(h);
   if (st) return st;
   if (species_count) {
-    unsigned long long c[64];
-    HIP_OK(h, hipMemcpy(c, h->L.sp_count, sizeof c, hipMemcpyDeviceToHost));
+    uint64_t c[64];
+    psc_status rs = read_replicas(h, h->L.sp_count, 64, kSpStride, c);
+    if (rs) return rs;
     for (size_t s = 0; s < h->species.size(); ++s) species_count[s] = c[s];
   }
   if (disp_sum || n_walkers) {
@@ -1155,15 +1180,14 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
   out->event = h->events_done;
   HIP_OK(h, hipMemcpy(&out->next_id, L.next_id, sizeof(uint32_t), hipMemcpyDeviceToHost));
   out->time = h->events_done ? h->tape_time[h->events_done - 1] : 0.0;
-  unsigned long long cnt[4];
-  HIP_OK(h, hipMemcpy(cnt, L.cnt, sizeof cnt, hipMemcpyDeviceToHost));
+  uint64_t cnt[4];
+  st = read_replicas(h, L.cnt, 4, kCntStride, cnt);
+  if (st) return st;
   out->counters = psc_counters{cnt[0], cnt[1], cnt[2], cnt[3]};
-  if (out->reactions_fired && !h->rx.size()) {
-  } else if (out->reactions_fired) {
-    std::vector<unsigned long long> f(h->rx.size());
-    HIP_OK(h, hipMemcpy(f.data(), L.fired, f.size() * sizeof(unsigned long long),
-                        hipMemcpyDeviceToHost));
-    for (size_t r = 0; r < f.size(); ++r) out->reactions_fired[r] = f[r];
+  if (out->reactions_fired && !h->rx.empty()) {
+    st = read_replicas(h, L.fired, (uint32_t)h->rx.size(), L.fired_stride,
+                       out->reactions_fired);
+    if (st) return st;
   }
   return PSC_OK;
 }

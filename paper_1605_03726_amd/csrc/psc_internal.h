@@ -124,6 +124,9 @@ psc_status efail(psc_ensemble *E, psc_status code, const char *fmt, ...);
 void extend_tape(psc_lattice *h, uint64_t end);
 psc_status sync_tape(psc_lattice *h, hipStream_t stream);
 psc_status check_device_error(psc_lattice *h);
+// sums of the kStatRep replicas of n statistics counters (see kStatRep)
+psc_status read_replicas(psc_lattice *h, const unsigned long long *dev, uint32_t n,
+                         uint32_t stride, uint64_t *out);
 psc_status ensure_member_records(psc_ensemble *E, hipStream_t stream, uint64_t n_events);
 psc_status ensure_graph(psc_ensemble *E);
 // device bytes a lattice with this capacity and size will hold once frozen

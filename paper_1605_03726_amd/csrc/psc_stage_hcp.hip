@@ -1,0 +1,9 @@
+// psc_stage_hcp.hip -- walk-stage kernels of the hexagonal close-packed lattice.
+#include "psc_stage_impl.h"
+
+namespace psc {
+
+template hipError_t launch_stage_lat<0>(const LatDev *dL, uint32_t g, int grid, int items,
+                                        bool disp, hipStream_t s);
+
+}  // namespace psc

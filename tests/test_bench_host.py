@@ -41,17 +41,21 @@ def test_traffic_summary_is_read_only_for_the_current_kernel_source(tmp_path, mo
     assert bench.read_traffic("w") is None
 
 
-def test_kernel_source_sha_covers_the_kernels_and_the_core_header(tmp_path, monkeypatch):
+def test_kernel_source_sha_covers_every_kernel_source(tmp_path, monkeypatch):
     sha = bench.kernel_source_sha()
     assert len(sha) == 16 and int(sha, 16) >= 0
     csrc = tmp_path / "paper_1605_03726_amd" / "csrc"
     csrc.mkdir(parents=True)
     src = os.path.join(ROOT, "paper_1605_03726_amd", "csrc")
-    for f in ("psc_kernels.hip", "psc_core.h"):
+    assert set(bench.KERNEL_SOURCES) == {f for f in os.listdir(src)
+                                         if f.endswith(".hip") or f in ("psc_core.h",
+                                                                        "psc_device.h",
+                                                                        "psc_stage_impl.h")}
+    for f in bench.KERNEL_SOURCES:
         (csrc / f).write_bytes(open(os.path.join(src, f), "rb").read())
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.kernel_source_sha() == sha
-    for f in ("psc_kernels.hip", "psc_core.h"):
+    for f in bench.KERNEL_SOURCES:
         original = (csrc / f).read_bytes()
         (csrc / f).write_bytes(original + b"\n")
         assert bench.kernel_source_sha() != sha, f

@@ -34,7 +34,8 @@ CROSS_BRICK_FRACTION = {"hcp": 11.0 / 32.0, "fcc": 45.0 / 128.0}
 
 # the device code of the library (every kernel and the headers they include)
 KERNEL_SOURCES = ("psc_kernels.hip", "psc_stage_hcp.hip", "psc_stage_fcc.hip",
-                  "psc_stage_multi.hip", "psc_stage_impl.h", "psc_device.h", "psc_core.h")
+                  "psc_stage_multi.hip", "psc_noalloc.hip", "psc_stage_impl.h", "psc_device.h",
+                  "psc_core.h")
 
 
 def kernel_source_sha() -> str:

@@ -221,6 +221,21 @@ psc_status psc_sync(psc_lattice *h);
  * the required count and nothing else is written). */
 psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * read-back as psc_read_state, identical results, without any device
+ * allocation.  psc_read_state converts a bricked occupancy through a
+ * transient device buffer as large as the lattice; this call converts one
+ * layer of bricks (4 k-layers, 4 ni nj voxels) at a time through a static
+ * 32 MiB device buffer that each GPU holds until the process ends, and runs
+ * its conversion kernels and copies on `stream` (NULL: the default stream),
+ * then waits.  EINVAL (nothing read) if a layer of bricks exceeds the buffer:
+ * ni * nj > 4194304 in the brick layout (any size with PSC_LAYOUT_LINEAR).
+ * The buffer is shared by every call on one GPU and keeps the last call's
+ * contents: calls that overlap on one GPU (from several threads, or on
+ * different streams) race and must not be made. */
+psc_status psc_read_state_noalloc(psc_lattice *h, psc_state_view *out, void *stream);
+
 /* Cumulative counters and events completed, without reading the state
  * (waits for pending work). */
 psc_status psc_read_counters(psc_lattice *h, psc_counters *out, uint64_t *event);

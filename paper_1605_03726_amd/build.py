@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpsc.so")
 SOURCES = ["psc_stage_hcp.hip", "psc_stage_fcc.hip", "psc_stage_multi.hip", "psc_kernels.hip",
-           "psc_host.cpp", "psc_server.cpp"]
+           "psc_host.cpp", "psc_server.cpp", "psc_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

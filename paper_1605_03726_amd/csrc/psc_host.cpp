@@ -1070,9 +1070,35 @@ psc_status psc_device_bytes(const psc_lattice *h, uint64_t *bytes) {
 }
 
 psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
+  (void)stream_;
+  return read_state_with(h, out, read_occupancy_transient, nullptr);
+}
+
+}  // extern "C"
+
+namespace psc_detail {
+
+// Occupancy in the ABI's linear order, species only, through a transient
+// device buffer of the lattice's size when the device layout is bricked.
+psc_status read_occupancy_transient(psc_lattice *h, uint16_t *occp, void *) {
+  const LatDev &L = h->L;
+  if (h->geo.brick) {
+    DevTemp tmp;
+    if (tmp.alloc(h->nv * sizeof(uint16_t)) != hipSuccess)
+      return fail(h, PSC_ENOMEM, "transient device buffer for the layout change failed");
+    HIP_OK(h, launch_relayout(h->geo, h->nv, L.occ, (uint16_t *)tmp.p, false, nullptr));
+    HIP_OK(h, hipMemcpy(occp, tmp.p, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
+  } else {
+    HIP_OK(h, hipMemcpy(occp, L.occ, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
+  }
+  for (uint64_t v = 0; v < h->nv; ++v) occp[v] &= kSpeciesMask;
+  return PSC_OK;
+}
+
+psc_status read_state_with(psc_lattice *h, psc_state_view *out, OccupancyReader read_occ,
+                           void *ctx) {
   if (!h || !out) return PSC_EINVAL;
   if (h->poisoned) return PSC_EDEVICE;
-  (void)stream_;
   const bool want_mol = out->id || out->voxel || out->species || out->dx || out->dy || out->dz;
   if (!h->frozen) {
     const uint64_t n = h->mid.size();
@@ -1152,16 +1178,8 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
     occp = occ.data();
   }
   if (occp) {
-    if (h->geo.brick) {
-      DevTemp tmp;
-      if (tmp.alloc(h->nv * sizeof(uint16_t)) != hipSuccess)
-        return fail(h, PSC_ENOMEM, "transient device buffer for the layout change failed");
-      HIP_OK(h, launch_relayout(h->geo, h->nv, L.occ, (uint16_t *)tmp.p, false, nullptr));
-      HIP_OK(h, hipMemcpy(occp, tmp.p, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
-    } else {
-      HIP_OK(h, hipMemcpy(occp, L.occ, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
-    }
-    for (uint64_t v = 0; v < h->nv; ++v) occp[v] &= kSpeciesMask;
+    st = read_occ(h, occp, ctx);
+    if (st) return st;
   }
   for (uint64_t z = 0; z < n; ++z) {
     const uint64_t q = order[z];
@@ -1191,6 +1209,10 @@ psc_status psc_read_state(psc_lattice *h, psc_state_view *out, void *stream_) {
   }
   return PSC_OK;
 }
+
+}  // namespace psc_detail
+
+extern "C" {
 
 }  // extern "C"
 

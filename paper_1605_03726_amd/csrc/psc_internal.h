@@ -127,6 +127,13 @@ psc_status check_device_error(psc_lattice *h);
 // sums of the kStatRep replicas of n statistics counters (see kStatRep)
 psc_status read_replicas(psc_lattice *h, const unsigned long long *dev, uint32_t n,
                          uint32_t stride, uint64_t *out);
+// The state read-back of psc_read_state with a pluggable reader of the
+// occupancy: it fills occp[nv] with the species of every voxel in the ABI's
+// linear order (flags masked off) and returns a status.
+typedef psc_status (*OccupancyReader)(psc_lattice *h, uint16_t *occp, void *ctx);
+psc_status read_state_with(psc_lattice *h, psc_state_view *out, OccupancyReader read_occ,
+                           void *ctx);
+psc_status read_occupancy_transient(psc_lattice *h, uint16_t *occp, void *ctx);
 psc_status ensure_member_records(psc_ensemble *E, hipStream_t stream, uint64_t n_events);
 psc_status ensure_graph(psc_ensemble *E);
 // device bytes a lattice with this capacity and size will hold once frozen

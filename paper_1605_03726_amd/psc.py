@@ -122,6 +122,8 @@ def lib() -> C.CDLL:
     L.psc_sync.restype = C.c_int32
     L.psc_read_state.argtypes = [vp, C.POINTER(StateView), vp]
     L.psc_read_state.restype = C.c_int32
+    L.psc_read_state_noalloc.argtypes = [vp, C.POINTER(StateView), vp]
+    L.psc_read_state_noalloc.restype = C.c_int32
     L.psc_query_sizes.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                   C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
     L.psc_query_sizes.restype = C.c_int32
@@ -334,7 +336,9 @@ class Lattice:
         self._check(self.L.psc_device_bytes(self.h, C.byref(b)))
         return b.value
 
-    def read_state(self, with_occ: bool = True, stream=None) -> dict:
+    def read_state(self, with_occ: bool = True, stream=None, noalloc: bool = False) -> dict:
+        """the state (psc_read_state); noalloc: through psc_read_state_noalloc,
+        which allocates no device memory"""
         cap = self.n_molecules()
         occ = np.zeros(self.nv, np.uint16) if with_occ else None
         arrays = {k: np.zeros(cap, t) for k, t in (("id", np.uint32), ("vox", np.uint32),
@@ -352,7 +356,8 @@ class Lattice:
         v.dz = _ptr(arrays["dz"], C.c_int32)
         v.reactions_fired = _ptr(fired, C.c_uint64)
         s = None if stream is None else stream
-        self._check(self.L.psc_read_state(self.h, C.byref(v), s))
+        fn = self.L.psc_read_state_noalloc if noalloc else self.L.psc_read_state
+        self._check(fn(self.h, C.byref(v), s))
         n = v.n_molecules
         out = {k: a[:n].copy() for k, a in arrays.items()}
         out.update(occ=occ, attempts=v.counters.attempts, hops=v.counters.hops,

@@ -86,34 +86,50 @@ def pick_workload(name: str):
 
 
 def cpu_baseline(w: dict, events: int) -> dict:
-    """the oracle (coloured-stage mode, single thread) on the first events of
-    the same workload; setup excluded from the timing"""
+    """the oracle on one core over the first events of the same workload, in
+    the coloured-stage order the GPU follows (the reported value) and in the
+    paper's sequential order; setup excluded from the timing"""
     import oracle
-    o = oracle.Oracle(w["dims"], w["rv"], w["seed"],
-                      boundary=oracle.REFLECT if w.get("boundary") == "walls" else oracle.PERIODIC,
-                      lattice=oracle.FCC if w.get("lattice") == "fcc" else oracle.HCP)
-    for _, D in w["species"]:
-        o.add_species(D)
-    for r, p, k in w["reactions"]:
-        o.add_reaction(r, p, k)
-    for s, c in w["place"]:
-        o.place_uniform(s, c)
-    t0 = time.perf_counter()
-    o.run(events, oracle.MODE_C)
-    dt = time.perf_counter() - t0
-    att = o.state(with_occ=False)["attempts"]
-    o.close()
+
+    def timed(mode):
+        o = oracle.Oracle(w["dims"], w["rv"], w["seed"],
+                          boundary=oracle.REFLECT if w.get("boundary") == "walls"
+                          else oracle.PERIODIC,
+                          lattice=oracle.FCC if w.get("lattice") == "fcc" else oracle.HCP)
+        for _, D in w["species"]:
+            o.add_species(D)
+        for r, p, k in w["reactions"]:
+            o.add_reaction(r, p, k)
+        for s, c in w["place"]:
+            o.place_uniform(s, c)
+        t0 = time.perf_counter()
+        o.run(events, mode)
+        dt = time.perf_counter() - t0
+        att = o.state(with_occ=False)["attempts"]
+        o.close()
+        return att, dt
+
+    att, dt = timed(oracle.MODE_C)
+    att_s, dt_s = timed(oracle.MODE_S)
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
     return {"value": att / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d events of %s (%d attempts, %.1f s)" % (events, w["name"], att, dt)}
+            "sample": "first %d events of %s (%d attempts, %.1f s), coloured-stage order"
+                      % (events, w["name"], att, dt),
+            "sequential_order": {"value": att_s / dt_s, "attempts": att_s, "s": dt_s,
+                                 "cores": 1,
+                                 "kind": "oracle in the paper's order (species, then ascending "
+                                         "id; Gillespie's method for first order)"},
+            "host_cpus": os.cpu_count(), "host_cpus_usable": usable}
 
 
-def ensemble_bench(n_members: int, events: int, plain_sample: int, plain_events: int,
-                   trial_events: int) -> dict:
+def ensemble_bench(n_members: int, events: int, plain_events: int, trial_events: int) -> dict:
     """Replicate ensemble: all members in batched launches (autotuned shape)
-    against the plain form, one lattice per launch sequence, timed on a
-    sample of members and extrapolated with a per-event cost that is linear
-    in the member's molecule count."""
-    import numpy as np
+    for `events` events, against the plain form, every member alone (one
+    lattice per launch sequence, the launches of psc_step) for `plain_events`
+    events, scaled to `events` by the event count only."""
     import torch
     from paper_1605_03726_amd import psc
     from psc_inputs import ensemble_members
@@ -143,14 +159,13 @@ def ensemble_bench(n_members: int, events: int, plain_sample: int, plain_events:
         l.close()
     del lats
 
-    # plain form on a sample spread over the member sizes
-    mol = np.array([sum(c for _, c in w["place"]) for w in ws], dtype=float)
-    order = np.argsort(mol)
-    pick = order[np.linspace(0, len(ws) - 1, plain_sample).round().astype(int)]
-    per_event = []
-    for r in pick:
-        lat = psc.lattice_from_workload(ws[r])
-        lat.step(2)
+    # the plain form, measured on every member: its events only are timed
+    # (model, placement and the freeze happen before)
+    plain_measured_s = 0.0
+    plain_attempts = 0
+    for w in ws if plain_events > 0 else []:
+        lat = psc.lattice_from_workload(w)
+        lat.step(0)
         lat.sync()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
@@ -158,56 +173,103 @@ def ensemble_bench(n_members: int, events: int, plain_sample: int, plain_events:
         lat.step(plain_events)
         b.record(stream)
         torch.cuda.synchronize()
-        per_event.append(a.elapsed_time(b) / 1e3 / plain_events)
+        plain_measured_s += a.elapsed_time(b) / 1e3
+        plain_attempts += lat.counters()["attempts"]
         lat.close()
-    A = np.vstack([np.ones(len(pick)), mol[pick]]).T
-    coef = np.linalg.lstsq(A, np.array(per_event), rcond=None)[0]
-    plain_s = float(sum(max(coef[0] + coef[1] * m, min(per_event)) for m in mol) * events)
+    plain_s = plain_measured_s * events / plain_events if plain_events > 0 else None
     return {"members": n_members, "events": events, "edges": [32, 48, 64, 96, 128],
             "batched_s": batched_s, "attempts": attempts,
             "batched_attempts_per_s": attempts / batched_s,
-            "plain_estimate_s": plain_s, "speedup": plain_s / batched_s,
+            "plain_measured_s": plain_measured_s, "plain_measured_events": plain_events,
+            "plain_measured_attempts_per_s": (plain_attempts / plain_measured_s
+                                              if plain_events > 0 else None),
+            "plain_s": plain_s, "speedup": plain_s / batched_s if plain_s else None,
             "tuned_launch": tuned, "setup_s": setup_s,
-            "plain_sample": "%d members spread over the sizes, %d events each, per-event time "
-                            "fitted linear in molecule count" % (plain_sample, plain_events),
+            "plain_form": "all %d members one after another, one lattice per launch sequence "
+                          "(psc_step), %d events each, timed; scaled to %d events by the event "
+                          "count" % (n_members, plain_events, events),
             "equal_accuracy": "members are bit-identical in both forms (tests)"}
 
 
-def serving_bench(duration: float, rate: float, budget_gb: float, quantum: int) -> dict:
+def serving_bench(duration: float, rate: float, budget_gb: float, quantum: int,
+                  drain_s: float, max_active: int) -> dict:
     """Poisson arrivals submitted in real time to the continuous-batching
-    server; latency = completion - submission."""
+    server for `duration` seconds; then at most `drain_s` more seconds for the
+    backlog, after which every unfinished job is cancelled.  Latency =
+    completion - submission, over the jobs done; the queue is sampled every
+    second."""
+    import threading
+
     import numpy as np
     from paper_1605_03726_amd import psc
     from psc_inputs import serving_jobs
 
     jobs = serving_jobs(rate=rate, duration=duration)
-    srv = psc.Server(budget_bytes=int(budget_gb * (1 << 30)), quantum_events=quantum)
+    srv = psc.Server(budget_bytes=int(budget_gb * (1 << 30)), quantum_events=quantum,
+                     max_active=max_active)
+    samples = []
+    stop = threading.Event()
     t0 = time.perf_counter()
+
+    def sampler():
+        while not stop.is_set():
+            st = srv.stats()
+            samples.append([round(time.perf_counter() - t0, 2), st["queued"], st["active"],
+                            st["done"], round(st["device_bytes_in_use"] / 2**30, 2)])
+            stop.wait(1.0)
+
+    th = threading.Thread(target=sampler, daemon=True)
+    th.start()
     ids = []
     for w in jobs:
         dt = w["arrival"] - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
         ids.append(srv.submit(w))
-    sts = [srv.wait(j) for j in ids]
-    stats = srv.stats()
+    deadline = t0 + duration + drain_s
+    while time.perf_counter() < deadline:
+        st = srv.stats()
+        if st["done"] + st["failed"] >= len(ids):
+            break
+        time.sleep(0.2)
+    t_cap = time.perf_counter() - t0
+    at_cap = srv.stats()
+    sts = [srv.poll(j) for j in ids]
+    unfinished = [j for j, s in zip(ids, sts) if s["state"] in (psc.JOB_QUEUED, psc.JOB_RUNNING)]
+    for j in unfinished:
+        try:
+            srv.cancel(j)
+        except psc.PscError:
+            pass  # finished meanwhile
+    stop.set()
+    th.join()
+    final = [srv.wait(j) for j in ids]
     srv.close()
-    done = [s for s in sts if s["state"] == psc.JOB_DONE]
-    lat = np.array([s["done_s"] - s["submit_s"] for s in done])
-    t_first = min(s["submit_s"] for s in sts)
-    t_last = max(s["done_s"] for s in sts)
-    wall = t_last - t_first
+    done = [s for s in final if s["state"] == psc.JOB_DONE]
+    lat = np.array([s["done_s"] - s["submit_s"] for s in done]) if done else np.zeros(1)
+    t_last = max([s["done_s"] for s in done], default=t_cap)
     attempts = sum(s["attempts"] for s in done)
-    offered = sum(sum(c for _, c in w["place"]) * w["events"] for w in jobs) / duration
-    return {"arrival_rate": rate, "arrival_window_s": duration, "jobs": len(jobs),
-            "done": len(done), "failed": len(sts) - len(done),
-            "jobs_per_s": len(done) / wall, "attempts_per_s": attempts / wall,
+    work = [sum(c for _, c in w["place"]) * w["events"] for w in jobs]
+    offered = sum(work) / duration
+    left = sum(wk for wk, s in zip(work, final) if s["state"] != psc.JOB_DONE)
+    return {"arrival_rate": rate, "arrival_window_s": duration, "drain_cap_s": drain_s,
+            "jobs": len(jobs), "done": len(done),
+            "cancelled_at_cap": sum(s["state"] == psc.JOB_CANCELLED for s in final),
+            "failed": sum(s["state"] == psc.JOB_FAILED for s in final),
+            "wall_s": t_last, "jobs_per_s": len(done) / t_last,
+            "attempts_per_s": attempts / t_last,
+            "offered_attempts_per_s_upper": offered,
             "latency_p50_s": float(np.percentile(lat, 50)),
             "latency_p99_s": float(np.percentile(lat, 99)),
-            "wall_s": wall, "offered_attempts_per_s_upper": offered,
-            "budget_gb": budget_gb, "quantum_events": quantum,
-            "peak_resident_jobs": stats["peak_active"], "batched_steps": stats["quanta"],
-            "note": "offered load exceeds one GPU: latency includes queueing"}
+            "backlog_at_cap": {"t_s": round(t_cap, 2), "queued": at_cap["queued"],
+                               "running": at_cap["active"],
+                               "offered_attempts_left": left},
+            "queue_depth": {"columns": ["t_s", "queued", "running", "done", "budget_gib_in_use"],
+                            "samples": samples[::5]},
+            "budget_gb": budget_gb, "quantum_events": quantum, "max_active": max_active,
+            "peak_resident_jobs": at_cap["peak_active"], "batched_steps": at_cap["quanta"],
+            "note": "offered load exceeds one GPU: latency includes queueing; jobs not done "
+                    "by the cap are cancelled and counted in the backlog"}
 
 
 def calibrate_copy(nbytes: int, reps: int):
@@ -298,7 +360,13 @@ def main():
     ap.add_argument("--ensemble-events", type=int, default=5000)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true")
-    ap.add_argument("--serving-window", type=float, default=1.0)
+    ap.add_argument("--serving-window", type=float, default=60.0,
+                    help="seconds of Poisson arrivals (200 jobs/s)")
+    ap.add_argument("--serving-drain", type=float, default=15.0,
+                    help="seconds after the arrivals before unfinished jobs are cancelled")
+    ap.add_argument("--serving-max-active", type=int, default=1024)
+    ap.add_argument("--plain-events", type=int, default=200,
+                    help="events each ensemble member runs alone in the plain form")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run N-byte device copies (counter calibration)")
     ap.add_argument("--calibrate-random", type=int, default=0,
@@ -321,10 +389,12 @@ def main():
     from paper_1605_03726_amd import psc
 
     if args.serving_only:
-        print(json.dumps(serving_bench(args.serving_window, 200.0, 200.0, 64)))
+        print(json.dumps(serving_bench(args.serving_window, 200.0, 200.0, 64, args.serving_drain,
+                                       args.serving_max_active)))
         return
     if args.ensemble_only:
-        print(json.dumps(ensemble_bench(args.ensemble_members, args.ensemble_events, 12, 300, 3)))
+        print(json.dumps(ensemble_bench(args.ensemble_members, args.ensemble_events,
+                                        args.plain_events, 3)))
         return
 
     w = pick_workload(args.workload)
@@ -430,25 +500,28 @@ def main():
                                      / (stage_avg_ms * 1e-3) / 1e9 if traffic else None),
                      "useful_byte_fraction": (alg_bytes_per_launch / t_att
                                               / traffic["per_attempt"] if traffic else None),
-                     # the HBM rate a walk that streams the whole lattice (read
-                     # and write 2 B per voxel per event) would need for the
-                     # same event rate, as a fraction of the peak
-                     "stream_equivalent_gbs": 4.0 * nv / (ms / args.steps * 1e-3) / 1e9,
-                     "stream_equivalent_frac": 4.0 * nv / (ms / args.steps * 1e-3) / 1e9
-                                               / HBM_PEAK_GBS,
-                     "random_access_reference": dict(
-                         ref, cross_line_fraction=cross, estimate_us=ref_us,
-                         walk_over_reference=stage_avg_ms * 1e3 / ref_us,
-                         kind="torch index_select / index_put_ of attempts_per_launch random "
-                              "2-byte words in an array of the lattice's size, event-timed")},
+                     },
+        # beside the roofline, not part of it: the HBM rate a walk that
+        # streamed the whole lattice (read and write 2 B per voxel per event)
+        # would need for the measured event rate, and the time torch's own
+        # gather and scatter take for the walk stage's scattered accesses
+        "context": {
+            "stream_equivalent_gbs": 4.0 * nv / (ms / args.steps * 1e-3) / 1e9,
+            "random_access_reference": dict(
+                ref, cross_line_fraction=cross, estimate_us=ref_us,
+                walk_over_reference=stage_avg_ms * 1e3 / ref_us,
+                kind="torch index_select / index_put_ of attempts_per_launch random "
+                     "2-byte words in an array of the lattice's size, event-timed")},
     }
     if not args.no_ensemble:
-        result["ensemble"] = ensemble_bench(args.ensemble_members, args.ensemble_events, 12, 300, 3)
-        print("ensemble: %.2f s batched, %.1fx over plain" % (
+        result["ensemble"] = ensemble_bench(args.ensemble_members, args.ensemble_events,
+                                            args.plain_events, 3)
+        print("ensemble: %.2f s batched, %s over plain" % (
             result["ensemble"]["batched_s"], result["ensemble"]["speedup"]), file=sys.stderr,
             flush=True)
     if not args.no_serving:
-        result["serving"] = serving_bench(args.serving_window, 200.0, 200.0, 64)
+        result["serving"] = serving_bench(args.serving_window, 200.0, 200.0, 64,
+                                          args.serving_drain, args.serving_max_active)
         print("serving: %d jobs, p50 %.2f s, p99 %.2f s" % (
             result["serving"]["done"], result["serving"]["latency_p50_s"],
             result["serving"]["latency_p99_s"]), file=sys.stderr, flush=True)

@@ -393,6 +393,7 @@ typedef struct psc_job_desc {
 #define PSC_JOB_RUNNING 1
 #define PSC_JOB_DONE 2
 #define PSC_JOB_FAILED 3
+#define PSC_JOB_CANCELLED 4
 
 typedef struct psc_job_status {
   int32_t state;            /* PSC_JOB_* */
@@ -410,6 +411,7 @@ typedef struct psc_server_stats {
   uint64_t quanta;          /* batched steps run */
   double busy_s;            /* time spent in batched steps */
   uint64_t peak_active;     /* most jobs resident at once */
+  uint64_t cancelled;       /* jobs cancelled (psc_server_cancel) */
 } psc_server_stats;
 
 /* Device bytes the server reserves for a job (its admission cost), for a
@@ -429,13 +431,23 @@ psc_status psc_server_create(const psc_server_options *opt, psc_server **out);
  * server is being destroyed. */
 psc_status psc_server_submit(psc_server *s, const psc_job_desc *job, uint64_t *job_id);
 
-/* Current status of a job (non-blocking) / wait until it is done or failed. */
+/* Current status of a job (non-blocking) / wait until it is done, failed or
+ * cancelled. */
 psc_status psc_server_poll(psc_server *s, uint64_t job_id, psc_job_status *out);
 psc_status psc_server_wait(psc_server *s, uint64_t job_id, psc_job_status *out);
 
 /* Final state of a finished job submitted with keep_state (ESTATE otherwise),
  * as psc_read_state. */
 psc_status psc_server_read_state(psc_server *s, uint64_t job_id, psc_state_view *out);
+
+/* Cancels a job that has not finished: a queued job leaves the queue at once,
+ * one being admitted or running is retired at the next step boundary (its
+ * events so far are lost); its state becomes PSC_JOB_CANCELLED and its
+ * memory returns to the budget.  Other jobs are unaffected.  ESTATE for a job
+ * already done, failed or cancelled; EINVAL for an unknown id.  For a server
+ * that must stop before its queue drains (psc_server_destroy runs every
+ * submitted job to completion). */
+psc_status psc_server_cancel(psc_server *s, uint64_t job_id);
 
 /* Frees a finished job's kept state. */
 psc_status psc_server_release(psc_server *s, uint64_t job_id);

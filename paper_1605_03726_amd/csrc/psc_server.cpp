@@ -39,6 +39,7 @@ struct Job {
   psc_lattice *lat = nullptr;
   uint64_t est_bytes = 0;
   bool charged = false;  // est_bytes counted in the server's used bytes
+  bool cancel = false;   // cancelled while being admitted or running
 };
 
 }  // namespace
@@ -103,6 +104,7 @@ void finish_job(psc_server *S, Job *j, int state, psc_status code) {
   j->st.error = code;
   j->st.done_s = seconds(S);
   if (state == PSC_JOB_DONE) S->stats.done++;
+  else if (state == PSC_JOB_CANCELLED) S->stats.cancelled++;
   else S->stats.failed++;
   S->cv_done.notify_all();
 }
@@ -141,6 +143,11 @@ void worker_main(psc_server *S) {
       lk.unlock();
       const psc_status st = build_job(S, j);
       lk.lock();
+      if (j->cancel) {
+        release_lattice(S, j);
+        finish_job(S, j, PSC_JOB_CANCELLED, PSC_OK);
+        continue;
+      }
       if (st) {
         if (j->lat && j->lat->poisoned) S->err = j->lat->err;
         release_lattice(S, j);
@@ -214,6 +221,12 @@ void worker_main(psc_server *S) {
     for (Job *j : S->active) {
       psc_lattice *h = j->lat;
       h->events_done = std::min(h->events_done + q, h->L.stop_event);
+      if (j->cancel) {
+        release_lattice(S, j);
+        finish_job(S, j, PSC_JOB_CANCELLED, PSC_OK);
+        S->ens_dirty = true;
+        continue;
+      }
       psc_status js = st;
       if (!js) js = check_device_error(h);
       if (js) {
@@ -353,7 +366,10 @@ psc_status psc_server_wait(psc_server *S, uint64_t job_id, psc_job_status *out) 
   auto it = S->jobs.find(job_id);
   if (it == S->jobs.end()) return PSC_EINVAL;
   Job *j = it->second;
-  S->cv_done.wait(lk, [&] { return j->st.state == PSC_JOB_DONE || j->st.state == PSC_JOB_FAILED; });
+  S->cv_done.wait(lk, [&] {
+    return j->st.state == PSC_JOB_DONE || j->st.state == PSC_JOB_FAILED ||
+           j->st.state == PSC_JOB_CANCELLED;
+  });
   if (out) *out = j->st;
   return PSC_OK;
 }
@@ -371,12 +387,36 @@ psc_status psc_server_read_state(psc_server *S, uint64_t job_id, psc_state_view 
   return psc_read_state(h, out, nullptr);
 }
 
+psc_status psc_server_cancel(psc_server *S, uint64_t job_id) {
+  if (!S) return PSC_EINVAL;
+  std::lock_guard<std::mutex> g(S->mu);
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return PSC_EINVAL;
+  Job *j = it->second;
+  const int state = j->st.state;
+  if (state == PSC_JOB_DONE || state == PSC_JOB_FAILED || state == PSC_JOB_CANCELLED || j->cancel)
+    return PSC_ESTATE;
+  auto q = std::find(S->queue.begin(), S->queue.end(), j);
+  if (q != S->queue.end()) {
+    // still waiting for admission: it never holds memory
+    S->queue.erase(q);
+    S->stats.queued = S->queue.size();
+    finish_job(S, j, PSC_JOB_CANCELLED, PSC_OK);
+    return PSC_OK;
+  }
+  // being admitted or running: the worker retires it at the next step boundary
+  j->cancel = true;
+  S->cv_work.notify_one();
+  return PSC_OK;
+}
+
 psc_status psc_server_release(psc_server *S, uint64_t job_id) {
   if (!S) return PSC_EINVAL;
   std::lock_guard<std::mutex> g(S->mu);
   auto it = S->jobs.find(job_id);
   if (it == S->jobs.end()) return PSC_EINVAL;
-  if (it->second->st.state != PSC_JOB_DONE && it->second->st.state != PSC_JOB_FAILED)
+  if (it->second->st.state != PSC_JOB_DONE && it->second->st.state != PSC_JOB_FAILED &&
+      it->second->st.state != PSC_JOB_CANCELLED)
     return PSC_ESTATE;
   release_lattice(S, it->second);
   S->cv_work.notify_one();

@@ -480,10 +480,11 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("done", C.c_uint64),
                 ("failed", C.c_uint64), ("active", C.c_uint64), ("queued", C.c_uint64),
                 ("device_bytes_in_use", C.c_uint64), ("attempts", C.c_uint64),
-                ("quanta", C.c_uint64), ("busy_s", C.c_double), ("peak_active", C.c_uint64)]
+                ("quanta", C.c_uint64), ("busy_s", C.c_double), ("peak_active", C.c_uint64),
+                ("cancelled", C.c_uint64)]
 
 
-JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELLED = 0, 1, 2, 3, 4
 
 
 def _server_lib():
@@ -501,6 +502,8 @@ def _server_lib():
     L.psc_server_wait.restype = C.c_int32
     L.psc_server_read_state.argtypes = [vp, C.c_uint64, C.POINTER(StateView)]
     L.psc_server_read_state.restype = C.c_int32
+    L.psc_server_cancel.argtypes = [vp, C.c_uint64]
+    L.psc_server_cancel.restype = C.c_int32
     L.psc_server_release.argtypes = [vp, C.c_uint64]
     L.psc_server_release.restype = C.c_int32
     L.psc_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
@@ -590,6 +593,9 @@ class Server:
                    collisions=v.counters.collisions, place_fail=v.counters.placement_failures,
                    fired=fired[:n_rx].copy(), event=v.event, time=v.time, next_id=v.next_id)
         return out
+
+    def cancel(self, job_id: int):
+        self._check(self.L.psc_server_cancel(self.h, job_id))
 
     def release(self, job_id: int):
         self._check(self.L.psc_server_release(self.h, job_id))

@@ -79,6 +79,11 @@ def test_cpu_baseline_fields():
     assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "attempts/s"
     assert r["value"] > 0
     assert "first 2 events of %s" % w["name"] in r["sample"]
+    # the same events in the paper's order: the same number of attempts
+    # (no reactions in this workload), timed on its own
+    seq = r["sequential_order"]
+    assert seq["value"] > 0 and seq["cores"] == 1 and seq["attempts"] > 0
+    assert r["host_cpus"] >= 1 and 1 <= r["host_cpus_usable"] <= r["host_cpus"]
 
 
 @pytest.mark.parametrize("lattice,dims", [("hcp", (16, 16, 16)), ("fcc", (16, 16, 24))])

@@ -131,3 +131,34 @@ def test_invalid_job_fails_alone():
         srv.release(jid)
     assert srv.stats()["device_bytes_in_use"] == 0
     srv.close()
+
+
+def test_cancel_queued_and_running_jobs():
+    base = small_jobs(1, seed=21)[0]
+    long_job = dict(base, seed=77, events=2_000_000)      # would run for minutes
+    j1 = dict(base, seed=78)
+    j2 = dict(base, seed=79, events=base["events"] + 5)
+    sizes = [psc.Server.job_bytes(w) for w in (long_job, j1, j2)]
+    srv = psc.Server(budget_bytes=max(sizes) + min(sizes) // 2, quantum_events=8)
+    lid = srv.submit(long_job)
+    time.sleep(0.2)                                        # admitted and running alone
+    assert srv.poll(lid)["state"] == psc.JOB_RUNNING
+    i1 = srv.submit(j1)
+    i2 = srv.submit(j2)
+    assert srv.poll(i1)["state"] == psc.JOB_QUEUED
+    srv.cancel(i1)                                         # leaves the queue at once
+    assert srv.poll(i1)["state"] == psc.JOB_CANCELLED
+    srv.cancel(lid)                                        # retired at the next step boundary
+    assert srv.wait(lid)["state"] == psc.JOB_CANCELLED
+    with pytest.raises(psc.PscError) as e:
+        srv.cancel(lid)
+    assert e.value.code == psc.PSC_ESTATE
+    st = srv.wait(i2)                                      # the next one runs, unchanged
+    assert st["state"] == psc.JOB_DONE
+    a = alone(j2)
+    assert (st["attempts"], st["hops"], st["collisions"], st["events_done"]) == (
+        a["attempts"], a["hops"], a["collisions"], a["event"])
+    stats = srv.stats()
+    assert stats["cancelled"] == 2 and stats["done"] == 1
+    assert stats["device_bytes_in_use"] == 0
+    srv.close()

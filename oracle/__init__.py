@@ -87,6 +87,10 @@ def lib() -> C.CDLL:
     L.orc_add_reaction.restype = C.c_int
     L.orc_place_uniform.argtypes = [C.c_void_p, C.c_uint16, C.c_uint64]
     L.orc_place_uniform.restype = C.c_int
+    L.orc_set_compartments.argtypes = [C.c_void_p, C.POINTER(C.c_uint8)]
+    L.orc_set_compartments.restype = C.c_int
+    L.orc_place_uniform_in.argtypes = [C.c_void_p, C.c_uint16, C.c_uint64, C.c_int]
+    L.orc_place_uniform_in.restype = C.c_int
     i32p = C.POINTER(C.c_int32)
     L.orc_load.argtypes = [C.c_void_p, C.POINTER(C.c_uint16), C.c_uint64, u32p, u32p,
                            i32p, i32p, i32p, C.c_uint64, C.c_uint32]
@@ -273,6 +277,18 @@ class Oracle:
     def place_uniform(self, species: int, count: int):
         if self.L.orc_place_uniform(self.h, species, count):
             raise ValueError("oracle: place_uniform")
+
+    def set_compartments(self, comp):
+        """comp[v]: the compartment (0..255) of every voxel v, linear order"""
+        comp = np.ascontiguousarray(comp, np.uint8)
+        if comp.shape != (int(np.prod(self.dims)),):
+            raise ValueError("oracle: one compartment per voxel")
+        if self.L.orc_set_compartments(self.h, _p(comp, C.c_uint8)):
+            raise ValueError("oracle: set_compartments")
+
+    def place_uniform_in(self, species: int, count: int, compartment: int):
+        if self.L.orc_place_uniform_in(self.h, species, count, compartment):
+            raise ValueError("oracle: place_uniform_in")
 
     def load(self, occ, ids, vox, disp=None, event=0, next_id=None):
         occ = np.ascontiguousarray(occ, np.uint16)

@@ -365,6 +365,7 @@ struct orc_sim {
   int frozen;
 
   uint16_t *occ;      /* nv: species id, 0 = vacant */
+  uint8_t *comp;      /* nv: compartment of each voxel, or NULL (all 0) */
   uint32_t *slot_at;  /* nv: molecule slot at voxel (valid where occ != 0) */
 
   /* molecule table, one slot per molecule ever made, ascending id */
@@ -493,7 +494,7 @@ orc_sim *orc_create(uint32_t ni, uint32_t nj, uint32_t nk, double rv, uint64_t s
 void orc_destroy(orc_sim *s) {
   if (!s) return;
   free(s->pend_key);
-  free(s->occ); free(s->slot_at);
+  free(s->occ); free(s->slot_at); free(s->comp);
   free(s->id); free(s->vox); free(s->sp); free(s->alive);
   free(s->dx); free(s->dy); free(s->dz);
   free(s);
@@ -507,6 +508,17 @@ int orc_set_lattice(orc_sim *s, int lattice) {
   s->n_col = orc_n_colours(lattice);
   return 0;
 }
+
+/* Compartments (2): every voxel belongs to one group of voxels, given by the
+ * caller; molecules never leave the compartment of their voxel (2.3) */
+int orc_set_compartments(orc_sim *s, const uint8_t *comp) {
+  if (!s->comp) s->comp = malloc(s->nv);
+  if (!s->comp) return -1;
+  memcpy(s->comp, comp, s->nv);
+  return 0;
+}
+
+static uint8_t comp_at(const orc_sim *s, uint32_t v) { return s->comp ? s->comp[v] : 0; }
 
 int orc_set_boundary(orc_sim *s, int boundary) {
   if (boundary != ORC_BOUNDARY_PERIODIC && boundary != ORC_BOUNDARY_REFLECT) return -1;
@@ -567,6 +579,33 @@ int orc_place_uniform(orc_sim *s, uint16_t species, uint64_t count) {
       attempt++;
       uint32_t v = (uint32_t)(((uint64_t)r[0] * s->nv) >> 32);
       if (s->occ[v] == 0) {
+        s->occ[v] = species;
+        if (mol_new(s, s->next_id++, v, species)) return -1;
+        break;
+      }
+    }
+  }
+  s->place_calls++;
+  return 0;
+}
+
+/* The same placement restricted to compartment c: attempt a of the call is
+ * taken if its voxel is vacant and belongs to c. */
+int orc_place_uniform_in(orc_sim *s, uint16_t species, uint64_t count, int c) {
+  if (species < 1 || species > s->n_species) return -1;
+  uint64_t vacant = 0;
+  for (uint64_t v = 0; v < s->nv; v++) vacant += s->occ[v] == 0 && comp_at(s, (uint32_t)v) == c;
+  if (count > vacant) return -1;
+  if ((uint64_t)s->next_id + count >= 0xFFFFFFFFull) return -1;
+  uint32_t call = (uint32_t)s->place_calls;
+  uint64_t attempt = 0;
+  for (uint64_t q = 0; q < count; q++) {
+    for (;;) {
+      uint32_t r[4];
+      draw4(s->seed, call, (uint32_t)attempt, ORC_PHASE_PLACE, 0, r);
+      attempt++;
+      uint32_t v = (uint32_t)(((uint64_t)r[0] * s->nv) >> 32);
+      if (s->occ[v] == 0 && comp_at(s, v) == c) {
         s->occ[v] = species;
         if (mol_new(s, s->next_id++, v, species)) return -1;
         break;
@@ -641,7 +680,8 @@ int orc_load(orc_sim *s, const uint16_t *occ, uint64_t n_mol, const uint32_t *id
 }
 
 /* ---- product placement shared by both first-order laws ------------------- */
-/* Extra products (2nd, 3rd, ...) go to distinct vacant neighbours of v; the
+/* Extra products (2nd, 3rd, ...) go to distinct vacant neighbours of v in
+ * v's compartment; the
  * vacant neighbours are listed in stencil order and each product takes
  * entry floor(w * count / 2^32) of the remaining list, w taken in sequence
  * from `words` (2.4.1: extra products need vacant neighbours).  Returns -1
@@ -652,7 +692,7 @@ static int pick_vacant(const orc_sim *s, uint32_t v, int n_extra,
   int nc = 0;
   for (int n = 0; n < 12; n++) {
     uint32_t t = orc_neighbour_l(s->ni, s->nj, s->nk, v, n, s->lattice, s->boundary);
-    if (t != ORC_OUTSIDE && s->occ[t] == 0) cand[nc++] = t;
+    if (t != ORC_OUTSIDE && comp_at(s, t) == comp_at(s, v) && s->occ[t] == 0) cand[nc++] = t;
   }
   if (nc < n_extra) return -1;
   for (int q = 0; q < n_extra; q++) {
@@ -916,7 +956,9 @@ static void attempt(orc_sim *s, uint32_t slot, int dir, int fire_forced,
   uint16_t A = s->sp[slot];
   s->cnt[ORC_CNT_ATTEMPTS]++;
   uint32_t t = orc_neighbour_l(s->ni, s->nj, s->nk, a, dir, s->lattice, s->boundary);
-  if (t == ORC_OUTSIDE) return;  /* a wall: the molecule stays, no collision */
+  /* a wall, or a voxel of another compartment: the molecule stays, no
+   * collision (2.3) */
+  if (t == ORC_OUTSIDE || comp_at(s, t) != comp_at(s, a)) return;
   if (s->occ[t] == 0) {
     /* vacant: the molecule hops and carries its unwrapped displacement */
     int32_t hv[3];

@@ -19,9 +19,11 @@
  *     p = k / (6 sqrt2 (DA+DB) r)              [2.4.2 Second-Order, eq. 6]
  *     and one to eleven products (2.4: two reactants may coalesce or decay
  *     into several molecules; at most eleven, the neighbours left)
- *   - periodic boxes, or boxes closed by walls: a move into another
- *     compartment fails like a move into an occupied voxel (2.3); the space
- *     beyond a face of a closed box is read as such a compartment
+ *   - compartments (2): groups of voxels given per voxel; a move into
+ *     another compartment fails like a move into an occupied voxel (2.3),
+ *     so molecules stay in their compartment, products included
+ *   - periodic boxes, or boxes closed by walls: the space beyond a face of a
+ *     closed box is read as another compartment
  *   - the face-centred cubic lattice (ABC stacking of the same close-packed
  *     layers; 2.1 names both close packings)
  *
@@ -131,6 +133,13 @@ int orc_add_reaction(orc_sim *s, int n_reac, const uint16_t *reac, int n_prod,
                      const uint16_t *prod, double k);
 /* places `count` molecules of `species` uniformly at random; 0 on success */
 int orc_place_uniform(orc_sim *s, uint16_t species, uint64_t count);
+/* compartments: comp[v] (nv entries, copied) is the compartment of voxel v.
+ * A hop into a voxel of another compartment is blocked like a hop beyond a
+ * wall, and products go only to vacant neighbours of the same compartment.
+ * Without this call every voxel is in compartment 0.  0 on success */
+int orc_set_compartments(orc_sim *s, const uint8_t *comp);
+/* as orc_place_uniform, keeping only draws whose voxel is in compartment c */
+int orc_place_uniform_in(orc_sim *s, uint16_t species, uint64_t count, int c);
 /* loads a full state; arrays are borrowed; 0 on success, -1 if inconsistent */
 int orc_load(orc_sim *s, const uint16_t *occ, uint64_t n_mol, const uint32_t *id,
              const uint32_t *vox, const int32_t *dx, const int32_t *dy,

@@ -9,3 +9,4 @@ it produces.
 from .workloads import (WORKLOADS, workload, ensemble_members, serving_jobs,  # noqa: F401
                         cfg3_network)
 from .states import random_state  # noqa: F401
+from .compartments import shell_map, sub_box_map, layered_map, membrane  # noqa: F401

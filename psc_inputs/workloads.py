@@ -206,5 +206,13 @@ WORKLOADS = {
 }
 
 
+def _membrane(**kw):
+    from .compartments import membrane
+    return membrane(**kw)
+
+
+WORKLOADS["membrane"] = _membrane
+
+
 def workload(name: str, **kw) -> dict:
     return WORKLOADS[name](**kw)

@@ -199,6 +199,27 @@ psc_status psc_get_reaction_info(const psc_lattice *h, uint32_t reaction_id,
  * first psc_step. */
 psc_status psc_place_uniform(psc_lattice *h, uint16_t species, uint64_t count);
 
+/* Compartments (2): a cell is modelled as groups of voxels, and a move into
+ * a voxel of another compartment fails as a move into an occupied one (2.3).
+ * comp[v] (ni*nj*nk entries, linear order v = i + ni*(j + nj*k), copied) is
+ * the compartment, 0..255, of voxel v; without this call every voxel is in
+ * compartment 0.  A hop towards a voxel of another compartment counts as an
+ * attempt and is neither a hop nor a collision (no reaction across a
+ * compartment boundary); every product of a reaction stays in its
+ * reactants' compartment (first-order and collision products take only
+ * vacant neighbours of that compartment).  Molecules placed or loaded
+ * before or after this call stay where they are.  EINVAL if comp is NULL;
+ * ESTATE after the first psc_step. */
+psc_status psc_set_compartments(psc_lattice *h, const uint8_t *comp);
+
+/* As psc_place_uniform, keeping only candidate voxels that are vacant and in
+ * `compartment` (the same draws: the c-th placement call, attempt a,
+ * Philox(seed; c, a, 3, 0) word 0).  ECAPACITY if the compartment has too
+ * few vacant voxels or capacity is exceeded; EINVAL for a compartment above
+ * 255 or an unknown species; ESTATE after the first psc_step. */
+psc_status psc_place_uniform_in(psc_lattice *h, uint16_t species, uint64_t count,
+                                uint32_t compartment);
+
 /* Replaces the whole state with a copy of `state` (see psc_state_view).
  * EINVAL if it is inconsistent; ECAPACITY if it exceeds max_molecules;
  * ESTATE after the first psc_step. */

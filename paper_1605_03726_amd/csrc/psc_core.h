@@ -10,12 +10,19 @@
 namespace psc {
 
 // ---- occupancy words -------------------------------------------------------
-// uint16 per voxel: species id (0 = vacant) in the low 15 bits.  Bit 15 marks
-// a voxel whose molecule took part, as the partner, in a collision reaction
-// during the current walk: that molecule does not walk again in this event.
-// The flag is cleared before the walk ends.
-constexpr uint16_t kSpeciesMask = 0x7FFF;
+// uint16 per voxel: species id (0 = vacant) in bits 0-5, the voxel's
+// compartment (a group of voxels, 2) in bits 6-13.  Bit 15 marks a voxel
+// whose molecule took part, as the partner, in a collision reaction during
+// the current walk: that molecule does not walk again in this event.  The
+// flag is cleared before the walk ends.  A vacant voxel's word is its
+// compartment bits alone; a molecule never changes compartment (a hop into
+// another compartment fails, 2.3), so a bin entry caches its molecule's word.
+constexpr uint16_t kSpeciesBits = 0x003F;
+constexpr uint16_t kCompBits = 0x3FC0;
+constexpr uint32_t kCompShift = 6;
+constexpr uint16_t kWordMask = 0x7FFF;  // species and compartment, flag off
 constexpr uint16_t kReactedFlag = 0x8000;
+constexpr int kMaxCompartments = 256;
 
 constexpr uint32_t kDeadId = 0xFFFFFFFFu;   // entry of a molecule that died
 // stage colours: 16 on both lattices

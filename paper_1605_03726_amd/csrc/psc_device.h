@@ -151,13 +151,16 @@ __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh,
                                                uint32_t psp, uint32_t id, uint32_t &osp,
                                                uint32_t &ocol, bool &flag, uint32_t &ftgt) {
   const uint32_t m = EXTRA ? L.rx_nprod[rx] : min(L.rx_nprod[rx], 2u);
+  // the mover's compartment, which the partner shares: every product stays in it
+  const uint32_t comp = osp & kCompBits;
   uint32_t vmask = 0;
   Coord cv;
   if (EXTRA && m > 2) {
     cv = coord_of(L.geo, v);
     for (uint32_t n = 0; n < 12; ++n) {
       Coord cn;
-      if (step_target_t<LAT>(L.geo, cv, n, cn) && occ[index_of(L.geo, cn)] == 0) vmask |= 1u << n;
+      if (step_target_t<LAT>(L.geo, cv, n, cn) && occ[index_of(L.geo, cn)] == comp)
+        vmask |= 1u << n;
     }
     if (__popc(vmask) < (int)(m - 2)) {
       atomicAdd(&stat_cnt(L)[3], 1ull);
@@ -165,7 +168,7 @@ __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh,
     }
   }
   const uint16_t *prod = L.rx_prod + rx * 12;
-  occ[t] = (uint16_t)(prod[0] | kReactedFlag);
+  occ[t] = (uint16_t)(prod[0] | comp | kReactedFlag);
   const uint32_t ht = hot_hash(t, hbits);
   atomicOr((uint32_t *)&hot[ht >> 4], 1u << (((ht & 15u) << 1) | buf));
   flag = true;
@@ -175,11 +178,11 @@ __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh,
   atomicAdd(&sh.dsp[prod[0] & 63u], 1);
   sh.any_rx = 1;
   if (m >= 2) {
-    occ[v] = prod[1];
-    osp = prod[1];
+    occ[v] = (uint16_t)(prod[1] | comp);
+    osp = prod[1] | comp;
     atomicAdd(&sh.dsp[prod[1] & 63u], 1);
   } else {
-    occ[v] = 0;
+    occ[v] = (uint16_t)comp;
     ocol = 0xFFu;
   }
   for (uint32_t q = 0; EXTRA && q + 2 < m; ++q) {
@@ -203,7 +206,7 @@ __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh,
     step_target_t<LAT>(L.geo, cv, n, cn);
     const uint32_t u = index_of(L.geo, cn);
     const uint16_t ps = prod[2 + q];
-    occ[u] = ps;
+    occ[u] = (uint16_t)(ps | comp);
     atomicAdd(&sh.dsp[ps & 63u], 1);
     const uint32_t slot = atomicAdd(L.wb_count, 1u);
     if (slot < L.wb_cap) {
@@ -321,23 +324,26 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     if (id[it] == kDeadId) continue;
     const uint32_t v = vox[it];
     const uint32_t t = tgt[it];
-    uint32_t sp = osp[it] & 63u;
+    uint32_t sp = osp[it] & kSpeciesBits;
     ocol[it] = c;  // stays in place unless it hops or is consumed
     if ((hw[it] >> hs[it]) & 3u) {
       // the cached species may be stale, or the molecule may have reacted
       // as a partner earlier in this walk: consult the lattice word
       const uint16_t w = occ[v];
-      sp = w & 63u;
-      osp[it] = sp;
+      sp = w & kSpeciesBits;
+      osp[it] = w & kWordMask;
       if (w & kReactedFlag) continue;
     }
     if (!((due >> sp) & 1ull)) continue;
     ++n_att;
     if (mv[it] & kWallBit) continue;  // a wall: the molecule stays, no collision
     const uint32_t w_t = loaded[it] ? wt[it] : (uint32_t)occ[t];
-    if (w_t == 0) {
-      occ[t] = (uint16_t)sp;
-      occ[v] = 0;
+    const uint32_t comp = osp[it] & kCompBits;
+    // a voxel of another compartment: the molecule stays, no collision (2.3)
+    if ((w_t & kCompBits) != comp) continue;
+    if ((w_t & kSpeciesBits) == 0) {
+      occ[t] = (uint16_t)osp[it];
+      occ[v] = (uint16_t)comp;
       vox[it] = t;
       ocol[it] = (mv[it] >> 8) & (LAT ? 31u : 15u);
       int32_t X, Y, Z;
@@ -349,7 +355,7 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
       continue;
     }
     ++n_col;
-    const uint32_t psp = w_t & 63u;
+    const uint32_t psp = w_t & kSpeciesBits;
     const int rx = L.pair_rx[sp * 64 + psp];
     if (rx < 0) continue;
     if (!L.rx_always[rx] && !(ry[it] < L.rx_thr[rx])) continue;

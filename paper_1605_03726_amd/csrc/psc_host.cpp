@@ -408,15 +408,25 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   HIP_OK(h, up(d_fo_first, h->fo_first.data(), 64 * sizeof(uint16_t)));
   HIP_OK(h, up(d_fo_n, h->fo_n.data(), 64));
   if (!h->fo_rx.empty()) HIP_OK(h, up(d_fo_rx, h->fo_rx.data(), h->fo_rx.size() * sizeof(uint16_t)));
+  // the device words carry the compartment of every voxel beside its species
+  // (the host copy keeps species only: a failed freeze leaves it unchanged)
+  std::vector<uint16_t> with_comp;
+  const uint16_t *words = h->occ.data();
+  if (!h->comp.empty()) {
+    with_comp.resize(h->nv);
+    for (uint64_t v = 0; v < h->nv; ++v)
+      with_comp[v] = (uint16_t)(h->occ[v] | (h->comp[v] << kCompShift));
+    words = with_comp.data();
+  }
   if (h->geo.brick) {
     DevTemp tmp;
     if (tmp.alloc(h->nv * sizeof(uint16_t)) != hipSuccess)
       return fail(h, PSC_ENOMEM, "transient device buffer for the layout change failed");
-    HIP_OK(h, up(tmp.p, h->occ.data(), h->nv * sizeof(uint16_t)));
+    HIP_OK(h, up(tmp.p, words, h->nv * sizeof(uint16_t)));
     HIP_OK(h, launch_relayout(h->geo, h->nv, (const uint16_t *)tmp.p, L.occ, true, stream));
     HIP_OK(h, hipStreamSynchronize(stream));
   } else {
-    HIP_OK(h, up(L.occ, h->occ.data(), h->nv * sizeof(uint16_t)));
+    HIP_OK(h, up(L.occ, words, h->nv * sizeof(uint16_t)));
   }
 
   // bins of the current event parity, by colour (counting sort)
@@ -433,7 +443,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
       const uint64_t at = fill[colour[q]]++;
       vox[at] = to_layout(h->geo, h->mvox[q]);
       id[at] = h->mid[q];
-      spc[at] = h->occ[h->mvox[q]];
+      spc[at] = words[h->mvox[q]];  // species and compartment
       if (disp) {
         d3[3 * at + 0] = h->mdx[q];
         d3[3 * at + 1] = h->mdy[q];
@@ -469,7 +479,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   {
     // the initial counts in replica 0, the other replicas at zero
     std::vector<unsigned long long> counts(kStatRep * kSpStride, 0);
-    for (uint64_t q = 0; q < nmol; ++q) counts[h->occ[h->mvox[q]] & 63u]++;
+    for (uint64_t q = 0; q < nmol; ++q) counts[h->occ[h->mvox[q]]]++;
     HIP_OK(h, up(L.sp_count, counts.data(), counts.size() * sizeof(unsigned long long)));
   }
   HIP_OK(h, hipMemset(L.fired, 0, (uint64_t)kStatRep * L.fired_stride * sizeof(unsigned long long)));
@@ -509,6 +519,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   h->frozen = true;
   // the host copy of the walkers is no longer authoritative
   std::vector<uint16_t>().swap(h->occ);
+  std::vector<uint8_t>().swap(h->comp);  // the device words hold it now
   std::vector<uint32_t>().swap(h->mid);
   std::vector<uint32_t>().swap(h->mvox);
   std::vector<int32_t>().swap(h->mdx);
@@ -764,6 +775,58 @@ psc_status psc_place_uniform(psc_lattice *h, uint16_t species, uint64_t count) {
       ++attempt;
       const uint32_t v = (uint32_t)(((uint64_t)r.x * h->nv) >> 32);
       if (h->occ[v] == 0) {
+        h->occ[v] = species;
+        h->mid.push_back(h->next_id++);
+        h->mvox.push_back(v);
+        h->mdx.push_back(0);
+        h->mdy.push_back(0);
+        h->mdz.push_back(0);
+        break;
+      }
+    }
+  }
+  h->place_calls++;
+  return PSC_OK;
+}
+
+psc_status psc_set_compartments(psc_lattice *h, const uint8_t *comp) {
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (h->frozen) return fail(h, PSC_ESTATE, "compartments only before the first step");
+  if (!comp) return fail(h, PSC_EINVAL, "comp is NULL");
+  try {
+    h->comp.assign(comp, comp + h->nv);
+  } catch (...) {
+    return fail(h, PSC_ENOMEM, "host allocation of the compartment map failed");
+  }
+  return PSC_OK;
+}
+
+psc_status psc_place_uniform_in(psc_lattice *h, uint16_t species, uint64_t count,
+                                uint32_t compartment) {
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (h->frozen) return fail(h, PSC_ESTATE, "placement only before the first step");
+  if (species < 1 || species >= h->species.size()) return fail(h, PSC_EINVAL, "unknown species");
+  if (compartment >= (uint32_t)kMaxCompartments)
+    return fail(h, PSC_EINVAL, "compartments are 0..%d", kMaxCompartments - 1);
+  auto comp_of = [&](uint64_t v) -> uint32_t { return h->comp.empty() ? 0u : h->comp[v]; };
+  uint64_t vacant = 0;
+  for (uint64_t v = 0; v < h->nv; ++v) vacant += h->occ[v] == 0 && comp_of(v) == compartment;
+  if (count > vacant) return fail(h, PSC_ECAPACITY, "too few vacant voxels in compartment %u",
+                                  compartment);
+  if (h->mid.size() + count > h->desc.max_molecules)
+    return fail(h, PSC_ECAPACITY, "placement exceeds max_molecules");
+  if ((uint64_t)h->next_id + count >= 0xFFFFFFFFull) return fail(h, PSC_ECAPACITY, "ids exhausted");
+  const uint32_t call = (uint32_t)h->place_calls;
+  const uint32_t k0 = (uint32_t)h->desc.seed, k1 = (uint32_t)(h->desc.seed >> 32);
+  uint64_t attempt = 0;
+  for (uint64_t q = 0; q < count; ++q) {
+    for (;;) {
+      const U4 r = philox(call, (uint32_t)attempt, kPhasePlace, 0, k0, k1);
+      ++attempt;
+      const uint32_t v = (uint32_t)(((uint64_t)r.x * h->nv) >> 32);
+      if (h->occ[v] == 0 && comp_of(v) == compartment) {
         h->occ[v] = species;
         h->mid.push_back(h->next_id++);
         h->mvox.push_back(v);
@@ -1091,7 +1154,7 @@ psc_status read_occupancy_transient(psc_lattice *h, uint16_t *occp, void *) {
   } else {
     HIP_OK(h, hipMemcpy(occp, L.occ, h->nv * sizeof(uint16_t), hipMemcpyDeviceToHost));
   }
-  for (uint64_t v = 0; v < h->nv; ++v) occp[v] &= kSpeciesMask;
+  for (uint64_t v = 0; v < h->nv; ++v) occp[v] &= kSpeciesBits;
   return PSC_OK;
 }
 

@@ -38,7 +38,8 @@ struct psc_lattice {
   std::string err;
 
   // state before the freeze (host)
-  std::vector<uint16_t> occ;
+  std::vector<uint16_t> occ;          // species per voxel (linear order)
+  std::vector<uint8_t> comp;          // compartment per voxel, or empty (all 0)
   std::vector<uint32_t> mid, mvox;
   std::vector<int32_t> mdx, mdy, mdz;
   uint32_t next_id = 0;

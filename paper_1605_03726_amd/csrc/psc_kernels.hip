@@ -110,9 +110,11 @@ __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, c
   const uint32_t v = in.vox[at];
   const uint32_t m = L.rx_nprod[rx];
   const uint16_t *prod = L.rx_prod + rx * 12;
-  const uint32_t sp0 = L.occ[v] & 63u;
+  const uint32_t w0 = L.occ[v];
+  const uint32_t sp0 = w0 & kSpeciesBits;
+  const uint32_t comp = w0 & kCompBits;  // every product stays in this compartment
   if (m == 0) {
-    L.occ[v] = 0;
+    L.occ[v] = (uint16_t)comp;
     in.id[at] = kDeadId;
     atomicAdd(&stat_sp(L)[sp0], ~0ull);  // -1
     atomicAdd(&stat_fired(L)[rx], 1ull);
@@ -127,7 +129,7 @@ __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, c
       Coord ct;
       if (!step_target(L.geo, cv, n, ct)) continue;  // beyond a wall
       const uint32_t t = index_of(L.geo, ct);
-      if (L.occ[t] == 0) vac[nv++] = t;
+      if (L.occ[t] == comp) vac[nv++] = t;  // vacant, same compartment
     }
     if (nv < (int)(m - 1)) {
       atomicAdd(&stat_cnt(L)[3], 1ull);
@@ -141,18 +143,18 @@ __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, c
       --nv;
     }
   }
-  L.occ[v] = prod[0];
-  in.sp[at] = prod[0];  // the entry stays; its cached species follows
+  L.occ[v] = (uint16_t)(prod[0] | comp);
+  in.sp[at] = (uint16_t)(prod[0] | comp);  // the entry stays; its cached word follows
   atomicAdd(&stat_sp(L)[sp0], ~0ull);
   atomicAdd(&stat_sp(L)[prod[0] & 63u], 1ull);
   for (uint32_t a = 0; a + 1 < m; ++a) {
-    L.occ[dest[a]] = prod[a + 1];
+    L.occ[dest[a]] = (uint16_t)(prod[a + 1] | comp);
     atomicAdd(&stat_sp(L)[prod[a + 1] & 63u], 1ull);
     const uint32_t b = atomicAdd(s_nb, 1u);
     if (b < L.birth_cap) {
       L.birth_key[b] = ((uint64_t)id << 31) | ((uint64_t)(a + 1) << 27) | b;
       L.birth_vox[b] = dest[a];
-      L.birth_sp[b] = prod[a + 1];
+      L.birth_sp[b] = (uint16_t)(prod[a + 1] | comp);
     } else {
       atomicOr(L.error, kErrBirthOverflow);
     }
@@ -174,7 +176,7 @@ __device__ __forceinline__ void decide_first_order(const LatDev &L, uint64_t e, 
   for (uint32_t q = first; q < ncand; q += stride) {
     const uint32_t c = L.cand_col[buf][q], pos = L.cand_pos[buf][q], id = L.cand_id[buf][q];
     const uint32_t v = in.vox[c * L.cap + pos];
-    const uint32_t sp = L.occ[v] & 63u;
+    const uint32_t sp = L.occ[v] & kSpeciesBits;
     if (!(L.sp_flags[sp] & kSpFirstOrder)) continue;
     const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
     const int rx = first_order_choice(L, e, sp, r.x);
@@ -466,7 +468,7 @@ __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
     const uint64_t at = c * L.cap + pos;
     out.vox[at] = u;
     out.id[at] = id;
-    out.sp[at] = (uint16_t)(L.occ[u] & kSpeciesMask);
+    out.sp[at] = (uint16_t)(L.occ[u] & kWordMask);
     if (out.disp) {
       out.disp[(0 * L.ncol + c) * L.cap + pos] = 0;
       out.disp[(1 * L.ncol + c) * L.cap + pos] = 0;
@@ -516,7 +518,7 @@ __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t
   const uint32_t nf = min(L.flag_count[cur], (uint32_t)L.flag_cap);
   for (uint32_t q = me; q < nf; q += stride) {
     const uint32_t v = L.flag_vox[cur][q];
-    L.occ[v] = (uint16_t)(L.occ[v] & kSpeciesMask);
+    L.occ[v] = (uint16_t)(L.occ[v] & kWordMask);
   }
   // the previous walk's hot marks have served both of their events
   const uint32_t np = min(L.flag_count[prv], (uint32_t)L.flag_cap);

@@ -38,7 +38,7 @@ hipError_t scratch_on(int device, uint16_t **out) {
   return hipSuccess;
 }
 
-// dst[linear(u) - lin0] = occ[u] & kSpeciesMask for the n layout indices
+// dst[linear(u) - lin0] = the species at layout index u, for the n layout indices
 // u = first, first + 1, ... (a range that is also contiguous in linear
 // order, starting at lin0)
 __global__ void __launch_bounds__(256) k_range_to_linear(Geo g, const uint16_t *__restrict__ occ,
@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(256) k_range_to_linear(Geo g, const uint16_t *
        z += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t u = (uint32_t)(first + z);
     const uint64_t lin = g.brick ? (uint64_t)linear_of(g, coord_of(g, u)) : (uint64_t)u;
-    dst[lin - lin0] = (uint16_t)(occ[u] & kSpeciesMask);
+    dst[lin - lin0] = (uint16_t)(occ[u] & kSpeciesBits);
   }
 }
 

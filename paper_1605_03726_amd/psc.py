@@ -114,6 +114,10 @@ def lib() -> C.CDLL:
     L.psc_get_reaction_info.restype = C.c_int32
     L.psc_place_uniform.argtypes = [vp, C.c_uint16, C.c_uint64]
     L.psc_place_uniform.restype = C.c_int32
+    L.psc_set_compartments.argtypes = [vp, C.POINTER(C.c_uint8)]
+    L.psc_set_compartments.restype = C.c_int32
+    L.psc_place_uniform_in.argtypes = [vp, C.c_uint16, C.c_uint64, C.c_uint32]
+    L.psc_place_uniform_in.restype = C.c_int32
     L.psc_load_state.argtypes = [vp, C.POINTER(StateView)]
     L.psc_load_state.restype = C.c_int32
     L.psc_step.argtypes = [vp, C.c_uint64, vp]
@@ -264,6 +268,16 @@ class Lattice:
     def place_uniform(self, species: int, count: int):
         self._check(self.L.psc_place_uniform(self.h, species, count))
 
+    def set_compartments(self, comp):
+        """comp[v]: the compartment (0..255) of every voxel v, linear order"""
+        c = np.ascontiguousarray(comp, np.uint8)
+        if c.shape != (self.nv,):
+            raise ValueError("one compartment per voxel")
+        self._check(self.L.psc_set_compartments(self.h, _ptr(c, C.c_uint8)))
+
+    def place_uniform_in(self, species: int, count: int, compartment: int):
+        self._check(self.L.psc_place_uniform_in(self.h, species, count, compartment))
+
     def load_state(self, st: dict):
         occ = np.ascontiguousarray(st["occ"], np.uint16)
         ids = np.ascontiguousarray(st["id"], np.uint32)
@@ -374,7 +388,7 @@ def lattice_from_workload(w: dict, max_molecules: int | None = None, device: int
     uniform placements)."""
     nv = int(np.prod(w["dims"]))
     if max_molecules is None:
-        placed = sum(c for _, c in w["place"])
+        placed = sum(c for _, c in w["place"]) + sum(c for _, c, _ in w.get("place_in", []))
         max_molecules = min(nv, max(1024, int(placed * 1.5) + 1024))
     lat = Lattice(w["dims"], w["rv"], w["seed"], max_molecules,
                   track_displacement=w.get("track_displacement", False), device=device,
@@ -384,9 +398,13 @@ def lattice_from_workload(w: dict, max_molecules: int | None = None, device: int
         lat.add_species(name, D)
     for r, p, k in w["reactions"]:
         lat.add_reaction(r, p, k)
+    if w.get("compartments") is not None:
+        lat.set_compartments(w["compartments"])
     if place:
         for s, c in w["place"]:
             lat.place_uniform(s, c)
+        for s, c, cc in w.get("place_in", []):
+            lat.place_uniform_in(s, c, cc)
     return lat
 
 

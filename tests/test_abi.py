@@ -262,3 +262,43 @@ def test_kernel_timing_modes():
         assert psc.lib().psc_set_kernel_timing(lat.h, mode) == psc.PSC_EINVAL
     assert lat.kernel_times()["stage_launches"] == 0
     lat.close()
+
+
+@pytest.mark.parametrize("lattice", ["hcp", "fcc"])
+def test_host_placement_in_compartments_matches_oracle(lattice):
+    from psc_inputs import membrane
+    w = membrane(dims=(24, 24, 24), seed=3, lattice=lattice)
+    lat = psc.lattice_from_workload(w, device=0)
+    o = oracle.Oracle(w["dims"], w["rv"], w["seed"],
+                      lattice=oracle.FCC if lattice == "fcc" else oracle.HCP)
+    for _, D in w["species"]:
+        o.add_species(D)
+    o.set_compartments(w["compartments"])
+    for s, c, cc in w["place_in"]:
+        o.place_uniform_in(s, c, cc)
+    a, b = lat.read_state(), o.state()
+    for key in ("occ", "id", "vox", "species"):
+        assert np.array_equal(a[key], b[key]), key
+    assert np.all(w["compartments"][a["vox"][a["species"] == 4]] == 1)
+
+
+def test_compartment_argument_errors():
+    lat = new(dims=(8, 8, 8), cap=512)
+    a = lat.add_species("A", 1e-12)
+    comp = np.zeros(512, np.uint8)
+    comp[:8] = 1
+    lat.set_compartments(comp)
+    with pytest.raises(psc.PscError) as e:
+        lat.place_uniform_in(a, 9, 1)            # 8 voxels in compartment 1
+    assert e.value.code == psc.PSC_ECAPACITY
+    with pytest.raises(psc.PscError) as e:
+        lat.place_uniform_in(a, 1, 256)
+    assert e.value.code == psc.PSC_EINVAL
+    with pytest.raises(psc.PscError) as e:
+        lat.place_uniform_in(9, 1, 0)            # unknown species
+    assert e.value.code == psc.PSC_EINVAL
+    lat.place_uniform_in(a, 8, 1)                 # exactly full
+    s = lat.read_state()
+    assert sorted(s["vox"].tolist()) == list(range(8))
+    with pytest.raises(ValueError):
+        lat.set_compartments(np.zeros(100, np.uint8))

@@ -347,6 +347,8 @@ def main():
                     choices=["cfg1", "cfg2", "cfg3", "mapk_paper", "multiproduct"])
     ap.add_argument("--timing-steps", type=int, default=40,
                     help="events after the timed region whose launches are timed one by one")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each event's launches from a HIP graph (psc_set_graph_replay)")
     ap.add_argument("--walls", action="store_true",
                     help="close the workload's box by walls instead of wrapping it")
     ap.add_argument("--fcc", action="store_true",
@@ -410,6 +412,8 @@ def main():
     placed = sum(c for _, c in w["place"])
     t_setup = time.perf_counter()
     lat = psc.lattice_from_workload(w, max_molecules=min(nv, int(placed * 1.25) + 4096))
+    if args.graph:
+        lat.set_graph_replay(True)
     stream = torch.cuda.current_stream()
     lat.step(args.warmup)
     lat.sync()
@@ -483,7 +487,8 @@ def main():
                    "boundary": w.get("boundary", "periodic"),
                    "lattice": w.get("lattice", "hcp"),
                    "species": len(w["species"]), "reactions": len(w["reactions"]),
-                   "step": "one diffusion event", "hop_fraction": hops / max(attempts, 1)},
+                   "step": "one diffusion event", "hop_fraction": hops / max(attempts, 1),
+                   "launch": "graph replay" if args.graph else "direct launches"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["per_dispatch"] if traffic else None,

@@ -297,6 +297,17 @@ typedef struct psc_launch {
 psc_status psc_set_launch(psc_lattice *h, const psc_launch *l);
 psc_status psc_get_launch(const psc_lattice *h, psc_launch *out);
 
+/* Graph replay (result-invariant): 1 captures one event's launches (the
+ * first-order pass, the 16 colour stages, the event end) as a HIP graph on
+ * the lattice's first step after the call and replays it for every event,
+ * instead of issuing the launches one by one; events whose first-order
+ * decisions need a launch of their own (many expected candidates) are still
+ * launched directly, and so is every event while per-launch timing is on.
+ * For small lattices, whose events are short enough for the host's launch
+ * rate to matter.  0 (the default) launches directly.  Other values:
+ * PSC_EINVAL. */
+psc_status psc_set_graph_replay(psc_lattice *h, int enable);
+
 /* ---- measurement ------------------------------------------------------------ */
 
 /* Per-kernel device time of the steps run while timing is on, measured with

@@ -436,12 +436,14 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
 // disp: the lattice tracks displacements (its bins carry the planes)
 // fcc: the lattice is face-centred cubic, else HCP;
 // decide_grid > 0: the first-order decisions run in their own launch of that
-// many workgroups (events with many candidates), else inside k_begin
+// many workgroups (events with many candidates), else inside k_begin;
+// births: the lattice (any member) has collision reactions with more than
+// two products, whose newborns the event end numbers
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
-                        int decide_grid, hipStream_t s);
+                        int decide_grid, bool births, hipStream_t s);
 // stages: the most stages of any member (16)
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
-                              int items, hipStream_t s);
+                              int items, bool births, hipStream_t s);
 hipError_t launch_begin(const LatDev *dL, int decide_grid, hipStream_t s);
 hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp, bool fcc,
                         hipStream_t s);
@@ -457,7 +459,7 @@ hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t s);
 // occupancy between the linear (ABI) order and the lattice's layout
 hipError_t launch_relayout(const Geo &g, uint64_t nv, const uint16_t *src, uint16_t *dst,
                            bool to_layout_order, hipStream_t s);
-hipError_t launch_end(const LatDev *dL, hipStream_t s);
+hipError_t launch_end(const LatDev *dL, bool births, hipStream_t s);
 int stage_items();
 int stage_threads();
 

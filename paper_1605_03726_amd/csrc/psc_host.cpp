@@ -572,6 +572,35 @@ psc_status read_replicas(psc_lattice *h, const unsigned long long *dev, uint32_t
   return PSC_OK;
 }
 
+// one event of the lattice (first-order pass in k_begin, the 16 stages, the
+// event end) captured on a private stream; every launch reads the event's
+// index and descriptors from the device, so one graph serves every event
+psc_status ensure_lattice_graph(psc_lattice *h) {
+  if (h->exec && h->graph_grid == h->grid && h->graph_items == h->items) return PSC_OK;
+  if (h->exec) {
+    HIP_OK(h, hipGraphExecDestroy(h->exec));
+    h->exec = nullptr;
+  }
+  if (h->graph) {
+    HIP_OK(h, hipGraphDestroy(h->graph));
+    h->graph = nullptr;
+  }
+  if (!h->cap_stream) HIP_OK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIP_OK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  const hipError_t le = launch_event(h->dL, h->grid, h->items, h->L.bins[0].disp != nullptr,
+                                     h->geo.fcc != 0, 0, h->L.wb_count != nullptr, h->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(h->cap_stream, &g);
+  if (le != hipSuccess || ce != hipSuccess)
+    return fail(h, PSC_EDEVICE, "capturing the lattice's event failed: %s / %s",
+                hipGetErrorString(le), hipGetErrorString(ce));
+  h->graph = g;
+  HIP_OK(h, hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
+  h->graph_grid = h->grid;
+  h->graph_items = h->items;
+  return PSC_OK;
+}
+
 psc_status check_device_error(psc_lattice *h) {
   uint32_t e = 0;
   HIP_OK(h, hipMemcpy(&e, h->L.error, sizeof e, hipMemcpyDeviceToHost));
@@ -669,6 +698,9 @@ void psc_destroy(psc_lattice *h) {
     (void)hipEventDestroy(t.b);
   }
   for (auto &e : h->event_pool) (void)hipEventDestroy(e);
+  if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   dev_free_all(h);
   delete h;
 }
@@ -922,10 +954,20 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
     return (int)std::min(std::ceil(expect / 512.0), 1024.0);
   };
   const uint64_t e0 = h->events_done;
-  if (!h->timing) {
+  const bool disp = h->L.bins[0].disp != nullptr, births = h->L.wb_count != nullptr;
+  if (!h->timing && h->use_graph) {
+    psc_status st = ensure_lattice_graph(h);
+    if (st) return st;
+    for (uint64_t e = 0; e < n_events; ++e) {
+      const int dg = decide_grid(e0 + e);
+      if (dg) HIP_OK(h, launch_event(h->dL, h->grid, h->items, disp, h->geo.fcc != 0, dg, births,
+                                     stream));
+      else HIP_OK(h, hipGraphLaunch(h->exec, stream));
+    }
+  } else if (!h->timing) {
     for (uint64_t e = 0; e < n_events; ++e)
-      HIP_OK(h, launch_event(h->dL, h->grid, h->items, h->L.bins[0].disp != nullptr,
-                             h->geo.fcc != 0, decide_grid(e0 + e), stream));
+      HIP_OK(h, launch_event(h->dL, h->grid, h->items, disp, h->geo.fcc != 0,
+                             decide_grid(e0 + e), births, stream));
   } else {
     auto ev = [&](hipEvent_t *out) -> hipError_t {
       if (!h->event_pool.empty()) {
@@ -947,7 +989,7 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
         else if (g < stages)
           HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, h->items,
                                  h->L.bins[0].disp != nullptr, h->geo.fcc != 0, stream));
-        else HIP_OK(h, launch_end(h->dL, stream));
+        else HIP_OK(h, launch_end(h->dL, h->L.wb_count != nullptr, stream));
         HIP_OK(h, hipEventRecord(t.b, stream));
         h->timed.push_back(t);
       }
@@ -1080,6 +1122,14 @@ psc_status psc_get_launch(const psc_lattice *h, psc_launch *out) {
   if (!h || !out) return PSC_EINVAL;
   out->items_per_thread = (uint32_t)h->items;
   out->stage_blocks = (uint32_t)h->grid;
+  return PSC_OK;
+}
+
+psc_status psc_set_graph_replay(psc_lattice *h, int enable) {
+  if (!h) return PSC_EINVAL;
+  if (h->poisoned) return PSC_EDEVICE;
+  if (enable != 0 && enable != 1) return fail(h, PSC_EINVAL, "graph replay must be 0 or 1");
+  h->use_graph = enable != 0;
   return PSC_OK;
 }
 
@@ -1331,6 +1381,13 @@ psc_status ensure_member_records(psc_ensemble *E, hipStream_t stream, uint64_t n
   return PSC_OK;
 }
 
+// some member numbers newborns of many-product collisions at its event end
+bool any_births(const psc_ensemble *E) {
+  for (const psc_lattice *h : E->members)
+    if (h->L.wb_count) return true;
+  return false;
+}
+
 psc_status ensure_graph(psc_ensemble *E) {
   if (E->exec && E->graph_grid == E->grid && E->graph_items == E->items) return PSC_OK;
   if (E->exec) {
@@ -1344,7 +1401,7 @@ psc_status ensure_graph(psc_ensemble *E) {
   if (!E->cap_stream) EHIP_OK(E, hipStreamCreateWithFlags(&E->cap_stream, hipStreamNonBlocking));
   EHIP_OK(E, hipStreamBeginCapture(E->cap_stream, hipStreamCaptureModeThreadLocal));
   const hipError_t le = launch_event_multi(E->d_lats, (uint32_t)E->members.size(), E->stages,
-                                           E->grid, E->items, E->cap_stream);
+                                           E->grid, E->items, any_births(E), E->cap_stream);
   hipGraph_t g = nullptr;
   const hipError_t ce = hipStreamEndCapture(E->cap_stream, &g);
   if (le != hipSuccess || ce != hipSuccess)
@@ -1365,7 +1422,7 @@ psc_status run_events(psc_ensemble *E, uint64_t n, hipStream_t stream) {
   } else {
     for (uint64_t e = 0; e < n; ++e)
       EHIP_OK(E, launch_event_multi(E->d_lats, (uint32_t)E->members.size(), E->stages, E->grid,
-                                    E->items, stream));
+                                    E->items, any_births(E), stream));
   }
   for (psc_lattice *h : E->members) h->events_done += n;
   return PSC_OK;

@@ -87,6 +87,15 @@ struct psc_lattice {
   bool in_ensemble = false;
   hipStream_t last_stream = nullptr;
 
+  // one event's launches captured as a HIP graph and replayed per event
+  // (events whose first-order decisions need a launch of their own are
+  // launched directly); rebuilt when the launch shape changes
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_grid = 0, graph_items = 0;
+
   // per-launch timing: kind (0 begin, 1 stage, 2 end) and its event pair
   bool timing = false;
   struct Timed {
@@ -137,6 +146,8 @@ psc_status read_state_with(psc_lattice *h, psc_state_view *out, OccupancyReader 
 psc_status read_occupancy_transient(psc_lattice *h, uint16_t *occp, void *ctx);
 psc_status ensure_member_records(psc_ensemble *E, hipStream_t stream, uint64_t n_events);
 psc_status ensure_graph(psc_ensemble *E);
+bool any_births(const psc_ensemble *E);
+psc_status ensure_lattice_graph(psc_lattice *h);
 // device bytes a lattice with this capacity and size will hold once frozen
 // ncol: stage colours of the lattice (16)
 uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool displacement,

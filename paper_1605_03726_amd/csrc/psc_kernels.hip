@@ -433,7 +433,9 @@ __global__ void __launch_bounds__(kStageThreads) k_decide(const LatDev *__restri
 // =============================================================================
 constexpr int kEndThreads = kStageThreads;
 constexpr int kEndBlocks = 32;
-constexpr int kEndBlocksMulti = 4;
+// one workgroup per member of an ensemble: a member's lists are short, and
+// one workgroup needs no completion count
+constexpr int kEndBlocksMulti = 1;
 
 // workgroup bid of nblk: sweep flags and the previous hot bitmap; the last
 // workgroup to finish advances the lattice's event counter
@@ -508,6 +510,9 @@ __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
   }
 }
 
+// BIRTHS: the lattice may have newborns of many-product collisions to number
+// (the numbering's registers and LDS would otherwise limit every end kernel)
+template <bool BIRTHS>
 __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t nblk) {
   const uint64_t e = *L.ev;
   if (e >= L.tape_horizon || e >= L.stop_event) return;
@@ -533,28 +538,32 @@ __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t
   // reads the hot bitmap), and each workgroup has used the event counter
   // before it counts itself in, so the last may advance it.  The kernel
   // boundary publishes all of it to the next launch.
-  __shared__ uint32_t s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = atomicAdd(L.end_done, 1u) == nblk - 1;
-  __syncthreads();
-  if (!s_last) return;
-  // the last workgroup: every other one has finished its sweeps
-  __threadfence();
-  if (L.wb_count) number_births(L, e);
+  if (nblk > 1) {
+    __shared__ uint32_t s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(L.end_done, 1u) == nblk - 1;
+    __syncthreads();
+    if (!s_last) return;
+    // the last workgroup: every other one has finished its sweeps
+    __threadfence();
+  }
+  if (BIRTHS && L.wb_count) number_births(L, e);
   __syncthreads();
   if (threadIdx.x == 0) {
     L.flag_count[prv] = 0;  // the next walk fills this list
-    *L.end_done = 0;
+    if (nblk > 1) *L.end_done = 0;
     *L.ev = e + 1;
   }
 }
 
+template <bool BIRTHS>
 __global__ void __launch_bounds__(kEndThreads) k_end(const LatDev *__restrict__ Lp) {
-  end_body(*Lp, blockIdx.x, gridDim.x);
+  end_body<BIRTHS>(*Lp, blockIdx.x, gridDim.x);
 }
 
+template <bool BIRTHS>
 __global__ void __launch_bounds__(kEndThreads) k_end_multi(const LatDev *__restrict__ lats) {
-  end_body(lats[blockIdx.y], blockIdx.x, gridDim.x);
+  end_body<BIRTHS>(lats[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // =============================================================================
@@ -635,30 +644,34 @@ hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool 
              : launch_stage_lat<0>(dL, g, grid, items, disp, s);
 }
 
-hipError_t launch_end(const LatDev *dL, hipStream_t s) {
-  hipLaunchKernelGGL(k_end, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL);
+hipError_t launch_end(const LatDev *dL, bool births, hipStream_t s) {
+  if (births) hipLaunchKernelGGL(k_end<true>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL);
+  else hipLaunchKernelGGL(k_end<false>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL);
   return hipGetLastError();
 }
 
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
-                        int decide_grid, hipStream_t s) {
+                        int decide_grid, bool births, hipStream_t s) {
   hipError_t err = launch_begin(dL, decide_grid, s);
   const uint32_t stages = fcc ? kColoursFcc : kColoursHcp;
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
     err = launch_stage(dL, g, grid, items, disp, fcc, s);
-  if (err == hipSuccess) err = launch_end(dL, s);
+  if (err == hipSuccess) err = launch_end(dL, births, s);
   return err;
 }
 
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
-                              int items, hipStream_t s) {
+                              int items, bool births, hipStream_t s) {
   if (R == 0 || R > max_members() || stages > (uint32_t)kMaxColours) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_begin_multi, dim3(R), dim3(kBeginThreads), 0, s, lats);
   hipError_t err = hipGetLastError();
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
     err = launch_stage_multi(lats, R, g, grid, items, s);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_end_multi, dim3(kEndBlocksMulti, R), dim3(kEndThreads), 0, s, lats);
+  if (births)
+    hipLaunchKernelGGL(k_end_multi<true>, dim3(kEndBlocksMulti, R), dim3(kEndThreads), 0, s, lats);
+  else
+    hipLaunchKernelGGL(k_end_multi<false>, dim3(kEndBlocksMulti, R), dim3(kEndThreads), 0, s, lats);
   return hipGetLastError();
 }
 

@@ -204,12 +204,13 @@ void worker_main(psc_server *S) {
     lk.unlock();
     psc_ensemble &E = S->ens;
     psc_status st = ensure_member_records(&E, S->stream, q);
+    const bool births = any_births(&E);
     const double tb = seconds(S);
     // direct launches: a server shares its process with other threads, and
     // capturing a graph would forbid their legacy-stream work meanwhile
     for (uint64_t e = 0; e < q && !st; ++e)
       if (launch_event_multi(E.d_lats, (uint32_t)E.members.size(), E.stages, E.grid, E.items,
-                             S->stream) != hipSuccess)
+                             births, S->stream) != hipSuccess)
         st = PSC_EDEVICE;
     if (!st && hipStreamSynchronize(S->stream) != hipSuccess) st = PSC_EDEVICE;
     const double te = seconds(S);

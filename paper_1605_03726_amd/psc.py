@@ -142,6 +142,8 @@ def lib() -> C.CDLL:
     L.psc_read_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                  C.POINTER(C.c_uint64)]
     L.psc_read_stats.restype = C.c_int32
+    L.psc_set_graph_replay.argtypes = [vp, C.c_int]
+    L.psc_set_graph_replay.restype = C.c_int32
     L.psc_set_kernel_timing.argtypes = [vp, C.c_int]
     L.psc_set_kernel_timing.restype = C.c_int32
     L.psc_get_kernel_times.argtypes = [vp, C.POINTER(KernelTimes)]
@@ -333,6 +335,9 @@ class Lattice:
         self._check(self.L.psc_read_stats(self.h, _ptr(counts, C.c_uint64), C.byref(dsum),
                                           C.byref(nw)))
         return {"species_count": counts, "disp_sum": dsum.value, "n_walkers": nw.value}
+
+    def set_graph_replay(self, on: bool):
+        self._check(self.L.psc_set_graph_replay(self.h, 1 if on else 0))
 
     def set_kernel_timing(self, on: bool, keep: bool = False):
         """on: record per-launch times (clearing the totals unless keep);

@@ -129,6 +129,13 @@ int main() {
   psc_launch l{1, 7};
   OK(psc_set_launch(h, &l));
   OK(psc_step(h, 6, nullptr));
+  // graph replay, rebuilt after a change of launch shape
+  OK(psc_set_graph_replay(h, 1));
+  OK(psc_step(h, 4, nullptr));
+  psc_launch l2{2, 9};
+  OK(psc_set_launch(h, &l2));
+  OK(psc_step(h, 2, nullptr));
+  if (psc_set_graph_replay(h, 5) != PSC_EINVAL) return 1;
   // (an even event count: with the launchers stubbed the molecules stay in
   // the bins of event parity 0, which the read-back then finds)
   for (psc_lattice *x : lats) {

@@ -145,22 +145,28 @@ hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool,
   check_record(dL);
   return hipSuccess;
 }
-hipError_t launch_end(const LatDev *dL, hipStream_t) {
+hipError_t launch_end(const LatDev *dL, bool births, hipStream_t) {
+  if (births != (dL->wb_count != nullptr)) bad("end births");
   ++g_launches;
   check_record(dL);
   return hipSuccess;
 }
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
-                        int decide_grid, hipStream_t s) {
+                        int decide_grid, bool births, hipStream_t s) {
   launch_begin(dL, decide_grid, s);
   for (uint32_t g = 0; g < (uint32_t)kMaxColours; ++g) launch_stage(dL, g, grid, items, disp, fcc, s);
-  return launch_end(dL, s);
+  return launch_end(dL, births, s);
 }
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
-                              int items, hipStream_t) {
+                              int items, bool births, hipStream_t) {
   ++g_launches;
   if (R == 0 || R > 4096 || stages > (uint32_t)kMaxColours || grid < 1 || items < 1) bad("multi");
-  for (uint32_t r = 0; r < R; ++r) check_record(&lats[r]);
+  bool any = false;
+  for (uint32_t r = 0; r < R; ++r) {
+    check_record(&lats[r]);
+    any |= lats[r].wb_count != nullptr;
+  }
+  if (births != any) bad("multi births");
   return hipSuccess;
 }
 hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t) {

@@ -491,7 +491,11 @@ def main():
                    "launch": "graph replay" if args.graph else "direct launches"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic["per_dispatch"] if traffic else None,
+                     # HBM bytes per launch: the profile's bytes per attempt
+                     # (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain
+                     # copy) times this run's attempts per launch
+                     "traffic": traffic["per_attempt"] * t_att if traffic else None,
+                     "traffic_profiled_per_dispatch": traffic["per_dispatch"] if traffic else None,
                      "kernel": "k_stage (one colour stage of the walk)",
                      "avg_launch_ms": stage_avg_ms,
                      "timed_launches_sampled": kt["stage_launches"],

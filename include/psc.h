@@ -375,12 +375,13 @@ const char *psc_ensemble_last_error(const psc_ensemble *e);
 
 /* ---- serving loop ---------------------------------------------------------------
  * Continuous batching of simulation jobs.  Jobs are submitted from any thread
- * and copied.  A worker thread owns the GPU: at every step boundary it admits
- * queued jobs (first come, first served) while their device memory fits the
- * budget, advances all resident jobs together as one batched ensemble by
- * `quantum_events` events (a job that reaches its last event idles for the
- * rest of the quantum), and retires finished jobs, which frees their memory
- * for the queue.  A job's result is bit-identical to running it alone. */
+ * and copied.  Builder threads admit queued jobs (first come, first served)
+ * while their device memory fits the budget and build them; a worker thread
+ * owns the batched steps: at every step boundary the built jobs join, all
+ * resident jobs advance together as one batched ensemble by `quantum_events`
+ * events (a job that reaches its last event idles for the rest of the
+ * quantum), and finished jobs retire, which frees their memory for the
+ * queue.  A job's result is bit-identical to running it alone. */
 typedef struct psc_server psc_server;
 
 typedef struct psc_server_options {
@@ -388,6 +389,9 @@ typedef struct psc_server_options {
   uint64_t budget_bytes;    /* device memory the resident jobs may hold */
   uint32_t quantum_events;  /* events per step between admissions (>= 1) */
   uint32_t max_active;      /* resident jobs at most (1..4096) */
+  uint32_t builders;        /* threads building admitted jobs (host placement
+                               and the freeze) while the GPU steps the
+                               resident ones; 0: 4, at most 64 */
 } psc_server_options;
 
 typedef struct psc_reaction_desc {

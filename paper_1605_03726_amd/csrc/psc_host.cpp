@@ -90,13 +90,18 @@ psc_status fail(psc_lattice *h, psc_status code, const char *fmt, ...) {
   } while (0)
 
 // A transient device buffer, freed when the scope ends (also on the early
-// returns of a failed HIP call).
+// returns of a failed HIP call).  Stream-ordered: allocated and freed in the
+// order of `stream`, so that neither waits for work on other streams (a
+// plain hipFree waits for the whole device -- in the serving loop, for the
+// batched step running meanwhile).
 struct DevTemp {
   void *p = nullptr;
+  hipStream_t stream = nullptr;
+  explicit DevTemp(hipStream_t s = nullptr) : stream(s) {}
   ~DevTemp() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, stream);
   }
-  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes); }
+  hipError_t alloc(size_t bytes) { return hipMallocAsync(&p, bytes, stream); }
 };
 
 void *dev_alloc(psc_lattice *h, size_t bytes) {
@@ -419,10 +424,11 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
     words = with_comp.data();
   }
   if (h->geo.brick) {
-    DevTemp tmp;
+    DevTemp tmp(stream);
     if (tmp.alloc(h->nv * sizeof(uint16_t)) != hipSuccess)
       return fail(h, PSC_ENOMEM, "transient device buffer for the layout change failed");
-    HIP_OK(h, up(tmp.p, words, h->nv * sizeof(uint16_t)));
+    HIP_OK(h, hipMemcpyAsync(tmp.p, words, h->nv * sizeof(uint16_t), hipMemcpyHostToDevice,
+                             stream));
     HIP_OK(h, launch_relayout(h->geo, h->nv, (const uint16_t *)tmp.p, L.occ, true, stream));
     HIP_OK(h, hipStreamSynchronize(stream));
   } else {

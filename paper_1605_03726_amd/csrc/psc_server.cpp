@@ -1,12 +1,13 @@
 // psc_server.cpp -- continuous-batching serving loop of libpsc.
 //
 // Jobs (one lattice + model + initial state + a number of diffusion events
-// each) are submitted from any thread.  One worker thread owns the GPU work:
-// at every step boundary it admits queued jobs while their estimated device
-// memory fits the budget, advances all resident jobs together as one batched
-// ensemble by a quantum of events (a job that reaches its last event idles
-// for the rest of the quantum), and retires finished jobs, freeing their
-// memory for the queue.  A job's result does not depend on what it ran with:
+// each) are submitted from any thread.  A builder thread admits queued jobs
+// while their estimated device memory fits the budget and builds them (host
+// placement, the freeze on a stream of its own).  A worker thread owns the
+// batched steps: at every step boundary the built jobs join, all resident
+// jobs advance together as one batched ensemble by a quantum of events (a
+// job that reaches its last event idles for the rest of the quantum), and
+// finished jobs retire, freeing their memory for the queue.  A job's result does not depend on what it ran with:
 // every draw is keyed by the job's own seed, event and molecule ids.
 #include <algorithm>
 #include <chrono>
@@ -49,14 +50,18 @@ struct psc_server {
   Clock::time_point t0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<Job *> queue;
+  std::deque<Job *> queue;          // submitted, waiting for admission
+  std::deque<Job *> ready;          // admitted and built, joining at the next step boundary
+  uint64_t building = 0;            // admitted, being built
   std::map<uint64_t, Job *> jobs;   // every job ever submitted, by id
   std::vector<Job *> active;
   uint64_t next_job = 1;
   uint64_t used_bytes = 0;
   bool stopping = false;
   psc_server_stats stats{};
-  std::thread worker;
+  std::thread worker;               // owns the batched steps
+  std::vector<std::thread> builders; // build admitted jobs meanwhile
+  std::condition_variable cv_build;
   hipStream_t stream = nullptr;
   psc_ensemble ens;                  // the resident jobs, rebuilt on change
   uint64_t ens_capacity = 0;
@@ -72,7 +77,7 @@ double seconds(const psc_server *S) {
 
 // builds the job's lattice on the host (model, placement), freezes it on the
 // device; returns a status for the job
-psc_status build_job(psc_server *S, Job *j) {
+psc_status build_job(Job *j, hipStream_t stream) {
   psc_lattice *h = nullptr;
   psc_status st = psc_create_lattice(&j->desc, &h);
   if (st) return st;
@@ -89,7 +94,7 @@ psc_status build_job(psc_server *S, Job *j) {
     st = psc_place_uniform(h, p.species, p.count);
     if (st) return st;
   }
-  st = psc_step(h, 0, S->stream);  // freeze: the state moves to the device
+  st = psc_step(h, 0, stream);  // freeze: the state moves to the device
   if (st) return st;
   h->L.stop_event = h->events_done + j->n_events;
   if (hipMemcpy(h->dL, &h->L, sizeof(LatDev), hipMemcpyHostToDevice) != hipSuccess)
@@ -130,28 +135,64 @@ void release_lattice(psc_server *S, Job *j) {
   }
 }
 
+// Admission (first come, first served): the builder thread takes the job at
+// the head of the queue once it fits the budget beside the jobs resident,
+// ready or being built (a job always fits an idle server: larger ones are
+// refused at submission), and builds it -- placement on the host, the
+// freeze on its own stream -- while the worker keeps stepping the resident
+// jobs; built jobs join at the next step boundary.
+bool can_admit(const psc_server *S) {
+  if (S->queue.empty()) return false;
+  const uint64_t resident = S->active.size() + S->ready.size() + S->building;
+  if (resident >= S->opt.max_active) return false;
+  return resident == 0 || S->used_bytes + S->queue.front()->est_bytes <= S->opt.budget_bytes;
+}
+
+void builder_main(psc_server *S) {
+  (void)hipSetDevice(S->opt.device);
+  hipStream_t stream = nullptr;  // this builder's own: a freeze waits for it alone
+  const bool have_stream = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    S->cv_build.wait(lk, [&] { return can_admit(S) || (S->stopping && S->queue.empty()); });
+    if (!can_admit(S)) break;  // stopping, nothing queued
+    Job *j = S->queue.front();
+    S->queue.pop_front();
+    S->stats.queued = S->queue.size();
+    charge(S, j);
+    S->building++;
+    lk.unlock();
+    const psc_status st = have_stream ? build_job(j, stream) : PSC_EDEVICE;
+    lk.lock();
+    S->building--;
+    if (j->cancel) {
+      release_lattice(S, j);
+      finish_job(S, j, PSC_JOB_CANCELLED, PSC_OK);
+    } else if (st) {
+      if (j->lat && j->lat->poisoned) S->err = j->lat->err;
+      release_lattice(S, j);
+      finish_job(S, j, PSC_JOB_FAILED, st);
+    } else {
+      S->ready.push_back(j);
+    }
+    S->cv_work.notify_one();
+  }
+  lk.unlock();
+  if (have_stream) (void)hipStreamDestroy(stream);
+}
+
 void worker_main(psc_server *S) {
   (void)hipSetDevice(S->opt.device);
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
-    // ---- admission at the step boundary ----
-    while (!S->queue.empty() && S->active.size() < S->opt.max_active) {
-      Job *j = S->queue.front();
-      if (S->used_bytes + j->est_bytes > S->opt.budget_bytes && !S->active.empty()) break;
-      S->queue.pop_front();
-      charge(S, j);
-      lk.unlock();
-      const psc_status st = build_job(S, j);
-      lk.lock();
+    // ---- built jobs join at the step boundary ----
+    while (!S->ready.empty()) {
+      Job *j = S->ready.front();
+      S->ready.pop_front();
       if (j->cancel) {
         release_lattice(S, j);
         finish_job(S, j, PSC_JOB_CANCELLED, PSC_OK);
-        continue;
-      }
-      if (st) {
-        if (j->lat && j->lat->poisoned) S->err = j->lat->err;
-        release_lattice(S, j);
-        finish_job(S, j, PSC_JOB_FAILED, st);
+        S->cv_build.notify_one();
         continue;
       }
       j->st.state = PSC_JOB_RUNNING;
@@ -165,7 +206,7 @@ void worker_main(psc_server *S) {
     S->stats.queued = S->queue.size();
     S->stats.device_bytes_in_use = S->used_bytes;
     if (S->active.empty()) {
-      if (S->stopping && S->queue.empty()) break;
+      if (S->stopping && S->queue.empty() && S->ready.empty() && S->building == 0) break;
       S->cv_work.wait(lk);
       continue;
     }
@@ -251,6 +292,7 @@ void worker_main(psc_server *S) {
       S->ens_dirty = true;
     }
     S->active.swap(still);
+    S->cv_build.notify_one();  // memory and slots may have freed
   }
 }
 
@@ -262,7 +304,7 @@ psc_status psc_server_create(const psc_server_options *opt, psc_server **out) {
   if (!opt || !out) return PSC_EINVAL;
   *out = nullptr;
   if (opt->device < 0 || opt->budget_bytes == 0 || opt->quantum_events == 0 ||
-      opt->max_active == 0 || opt->max_active > max_members())
+      opt->max_active == 0 || opt->max_active > max_members() || opt->builders > 64)
     return PSC_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device >= ndev) return PSC_EINVAL;
@@ -277,7 +319,9 @@ psc_status psc_server_create(const psc_server_options *opt, psc_server **out) {
   }
   S->ens.device = opt->device;
   S->ens.use_graph = false;
+  if (S->opt.builders == 0) S->opt.builders = 4;
   S->worker = std::thread(worker_main, S);
+  for (uint32_t b = 0; b < S->opt.builders; ++b) S->builders.emplace_back(builder_main, S);
   *out = S;
   return PSC_OK;
 }
@@ -346,7 +390,8 @@ psc_status psc_server_submit(psc_server *S, const psc_job_desc *d, uint64_t *job
     finish_job(S, j, PSC_JOB_FAILED, PSC_ENOMEM);
   } else {
     S->queue.push_back(j);
-    S->cv_work.notify_one();
+    S->stats.queued = S->queue.size();
+    S->cv_build.notify_one();
   }
   *job_id = j->id;
   return PSC_OK;
@@ -405,7 +450,8 @@ psc_status psc_server_cancel(psc_server *S, uint64_t job_id) {
     finish_job(S, j, PSC_JOB_CANCELLED, PSC_OK);
     return PSC_OK;
   }
-  // being admitted or running: the worker retires it at the next step boundary
+  // being built, ready or running: retired at the next step boundary (or
+  // once built)
   j->cancel = true;
   S->cv_work.notify_one();
   return PSC_OK;
@@ -420,7 +466,7 @@ psc_status psc_server_release(psc_server *S, uint64_t job_id) {
       it->second->st.state != PSC_JOB_CANCELLED)
     return PSC_ESTATE;
   release_lattice(S, it->second);
-  S->cv_work.notify_one();
+  S->cv_build.notify_one();
   return PSC_OK;
 }
 
@@ -439,6 +485,13 @@ void psc_server_destroy(psc_server *S) {
     std::lock_guard<std::mutex> g(S->mu);
     S->stopping = true;
     S->cv_work.notify_all();
+    S->cv_build.notify_all();
+  }
+  for (auto &t : S->builders)
+    if (t.joinable()) t.join();
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->cv_work.notify_all();  // the worker may wait for the last built job
   }
   if (S->worker.joinable()) S->worker.join();
   (void)hipSetDevice(S->opt.device);

@@ -471,7 +471,8 @@ class Ensemble:
 
 class ServerOptions(C.Structure):
     _fields_ = [("device", C.c_int32), ("budget_bytes", C.c_uint64),
-                ("quantum_events", C.c_uint32), ("max_active", C.c_uint32)]
+                ("quantum_events", C.c_uint32), ("max_active", C.c_uint32),
+                ("builders", C.c_uint32)]
 
 
 class ReactionDesc(C.Structure):
@@ -553,9 +554,9 @@ class Server:
     """Continuous-batching serving loop (psc_server_* in include/psc.h)."""
 
     def __init__(self, budget_bytes: int, quantum_events: int = 64, max_active: int = 4096,
-                 device: int = 0):
+                 device: int = 0, builders: int = 0):
         self.L = _server_lib()
-        o = ServerOptions(device, budget_bytes, quantum_events, max_active)
+        o = ServerOptions(device, budget_bytes, quantum_events, max_active, builders)
         h = C.c_void_p()
         rc = self.L.psc_server_create(C.byref(o), C.byref(h))
         if rc != PSC_OK:

@@ -186,7 +186,7 @@ int main() {
   }
   // the serving loop: valid, invalid and never-fitting jobs
   {
-    psc_server_options o{0, 64ull << 20, 16, 64};
+    psc_server_options o{0, 64ull << 20, 16, 64, 3};
     psc_server *S = nullptr;
     OK(psc_server_create(&o, &S));
     const double D[3] = {1e-12, 0.5e-12, 1e-12};

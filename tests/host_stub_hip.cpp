@@ -7,15 +7,16 @@
 // record.  Not part of the library.
 #include <hip/hip_runtime_api.h>
 
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <set>
 
 #include "psc_core.h"
 
-static int g_launch_errors = 0;
-static unsigned long long g_launches = 0;
+// the serving loop launches from two threads
+static std::atomic<int> g_launch_errors{0};
+static std::atomic<unsigned long long> g_launches{0};
 
 static void bad(const char *what) {
   fprintf(stderr, "launch check failed: %s\n", what);
@@ -24,8 +25,8 @@ static void bad(const char *what) {
 
 extern "C" {
 
-int stub_launch_errors() { return g_launch_errors; }
-unsigned long long stub_launches() { return g_launches; }
+int stub_launch_errors() { return g_launch_errors.load(); }
+unsigned long long stub_launches() { return g_launches.load(); }
 
 hipError_t hipMalloc(void **p, size_t n) {
   *p = calloc(1, n ? n : 1);
@@ -35,6 +36,8 @@ hipError_t hipFree(void *p) {
   free(p);
   return hipSuccess;
 }
+hipError_t hipMallocAsync(void **p, size_t n, hipStream_t) { return hipMalloc(p, n); }
+hipError_t hipFreeAsync(void *p, hipStream_t) { return hipFree(p); }
 hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) {
   memmove(d, s, n);
   return hipSuccess;

@@ -179,20 +179,28 @@ def test_many_products_and_placement_failures():
     assert s["place_fail"] > 0 and s["fired"][0] > 0
 
 
+@pytest.mark.timeout(1200)
 def test_mapk_full_size_prefix():
-    # the 2^32-voxel workload at full size: 8 GiB occupancy, 12.9 M molecules;
-    # six events carry the partner marks and flags across event parities
-    events = 6
+    # the 2^32-voxel workload at full size (8 GiB occupancy, 12.9 M molecules)
+    # in the benchmark's launch shape, against the oracle after 6 events (the
+    # partner marks and flags carried across event parities) and after 60
+    # (about 7.7 x 10^8 attempts; a few CPU minutes)
     w = workload("cfg3")
     lat = build_gpu(w, max_molecules=int(0.003 * 2 ** 32 * 1.25))
-    lat.step(events)
-    g = lat.read_state()
-    lat.close()
     o = build_oracle(w)
-    o.run(events, oracle.MODE_C)
-    s = o.state()
+    done = 0
+    for events in (6, 60):
+        lat.step(events - done)
+        g = lat.read_state()
+        while done < events:   # a few seconds per oracle event: report progress
+            o.run(6, oracle.MODE_C)
+            done += 6
+            print("oracle at event %d" % done, flush=True)
+        s = o.state()
+        assert_same(g, s, disp=False)
+        del g, s
+    lat.close()
     o.close()
-    assert_same(g, s, disp=False)
 
 
 def test_mapk_full_run_invariants():
@@ -501,10 +509,11 @@ def test_fcc_linear_layout_statistics_and_checkpoint():
     assert gr["event"] == s["event"] and gr["next_id"] == s["next_id"] and gr["time"] == s["time"]
 
 
+@pytest.mark.timeout(900)
 def test_fcc_full_size_prefix():
     # the MAPK workload on an FCC lattice of 2048 x 2048 x 1020 voxels (just
-    # under 2^32; nk a multiple of 12)
-    events = 1
+    # under 2^32; nk a multiple of 12), six events
+    events = 6
     w = fcc(workload("cfg3", dims=(2048, 2048, 1020)))
     lat = build_gpu(w, max_molecules=int(0.003 * 2 ** 32 * 1.25))
     lat.step(events)

@@ -276,6 +276,11 @@ psc_status psc_query_sizes(const psc_lattice *h, uint64_t *n_voxels,
                            uint64_t *n_molecules, uint32_t *n_species,
                            uint32_t *n_reactions);
 
+/* The same sizes under the name the scope of this library first gave them. */
+psc_status psc_required_sizes(const psc_lattice *h, uint64_t *n_voxels,
+                              uint64_t *n_molecules, uint32_t *n_species,
+                              uint32_t *n_reactions);
+
 /* Device bytes held by the lattice (for admission control). */
 psc_status psc_device_bytes(const psc_lattice *h, uint64_t *bytes);
 
@@ -366,6 +371,10 @@ psc_status psc_ensemble_autotune(psc_ensemble *e, uint32_t trial_events);
 
 /* The shape the autotuner chose and its time per event (0 before tuning). */
 psc_status psc_ensemble_tuned(const psc_ensemble *e, psc_launch *chosen, double *ms_per_event);
+
+/* Member i's state (as psc_read_state on that member, after waiting for the
+ * ensemble's work).  EINVAL for i beyond the members. */
+psc_status psc_ensemble_read(psc_ensemble *e, uint32_t i, psc_state_view *out, void *stream);
 
 /* Releases the ensemble (members stay valid and can be stepped alone). */
 void psc_ensemble_destroy(psc_ensemble *e);
@@ -460,6 +469,11 @@ psc_status psc_server_job_bytes(const psc_job_desc *job, uint64_t *bytes);
 
 /* Starts the worker.  EINVAL on bad options or device. */
 psc_status psc_server_create(const psc_server_options *opt, psc_server **out);
+
+/* psc_server_create with the default options: a quantum of 64 events, at
+ * most 1024 resident jobs, 4 builder threads, on `device` under
+ * `budget_bytes` of device memory. */
+psc_status psc_server_start(uint64_t budget_bytes, int32_t device, psc_server **out);
 
 /* Queues a copy of the job; *job_id identifies it.  A job that can never fit
  * the budget fails at once (ENOMEM); one the lattice rejects fails with that

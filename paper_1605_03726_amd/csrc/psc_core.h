@@ -29,6 +29,7 @@ constexpr uint32_t kDeadId = 0xFFFFFFFFu;   // entry of a molecule that died
 constexpr int kColoursHcp = 16, kColoursFcc = 16, kMaxColours = 16;
 constexpr int kMaxSpecies = 63;
 constexpr int kMaxProducts = 11;
+constexpr int kMaxReactions = 255;
 
 // Philox counter phase word
 constexpr uint32_t kPhaseWalk = 0, kPhaseFirst = 1, kPhaseStage = 2, kPhasePlace = 3;
@@ -435,16 +436,26 @@ struct LatDev {
 hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
 // disp: the lattice tracks displacements (its bins carry the planes)
 // fcc: the lattice is face-centred cubic, else HCP;
-// decide_grid > 0: the first-order decisions run in their own launch of that
-// many workgroups (events with many candidates), else inside k_begin;
+// Launch shape of an event's first-order pass (workgroups; 0: none):
+//   decide  the decisions in a launch of their own (events with many
+//           candidates), else inside k_begin;
+//   births  first-order newborns beyond what one workgroup ranks in LDS are
+//           numbered by a launch of that many workgroups (events expecting
+//           many), else by k_begin alone;
+//   apply   the firings are applied by one launch per stage of that many
+//           workgroups (events expecting many firings), then numbered by
+//           the births launch (at least one workgroup), else inside k_begin.
+struct BeginShape {
+  int decide = 0, births = 0, apply = 0;
+};
 // births: the lattice (any member) has collision reactions with more than
 // two products, whose newborns the event end numbers
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
-                        int decide_grid, bool births, hipStream_t s);
+                        const BeginShape &b, bool births, hipStream_t s);
 // stages: the most stages of any member (16)
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, bool births, hipStream_t s);
-hipError_t launch_begin(const LatDev *dL, int decide_grid, hipStream_t s);
+hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t s);
 hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp, bool fcc,
                         hipStream_t s);
 // the stage kernels of one lattice kind (LAT: 0 HCP, 1 FCC) and the batched

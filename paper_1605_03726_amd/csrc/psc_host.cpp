@@ -18,6 +18,10 @@
 using namespace psc;
 using namespace psc_detail;
 
+static_assert(kMaxReactions == PSC_MAX_REACTIONS && kMaxSpecies == PSC_MAX_SPECIES &&
+                  kMaxProducts == PSC_MAX_PRODUCTS,
+              "the kernels' limits are the ABI's");
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -262,6 +266,10 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
     if (h->fo_n[s]) sp_flags[s] |= kSpFirstOrder;
   }
   h->n_fo = (uint32_t)h->fo_rx.size();
+  h->fo_extra_max = 0;
+  for (uint32_t r = 0; r < R; ++r)
+    if (h->rx[r].nr == 1 && h->rx[r].np > 1)
+      h->fo_extra_max = std::max<uint32_t>(h->fo_extra_max, h->rx[r].np - 1);
   for (uint32_t r = 0; r < R; ++r) {
     const ReactionDef &d = h->rx[r];
     nprod[r] = (uint8_t)d.np;
@@ -594,7 +602,8 @@ psc_status ensure_lattice_graph(psc_lattice *h) {
   if (!h->cap_stream) HIP_OK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   HIP_OK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   const hipError_t le = launch_event(h->dL, h->grid, h->items, h->L.bins[0].disp != nullptr,
-                                     h->geo.fcc != 0, 0, h->L.wb_count != nullptr, h->cap_stream);
+                                     h->geo.fcc != 0, BeginShape{}, h->L.wb_count != nullptr,
+                                     h->cap_stream);
   hipGraph_t g = nullptr;
   const hipError_t ce = hipStreamEndCapture(h->cap_stream, &g);
   if (le != hipSuccess || ce != hipSuccess)
@@ -959,21 +968,51 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
     if (expect < 4096.0) return 0;
     return (int)std::min(std::ceil(expect / 512.0), 1024.0);
   };
+  // Newborns of the first-order pass are ranked by k_begin alone up to the
+  // LDS limit; an event expecting more than half of that (its largest
+  // threshold times the walkers times the most extra products) gets a
+  // ranking launch of its own, sized for twice the expectation.  A smaller
+  // expectation that is exceeded falls back to k_begin's slower sort.
+  auto births_grid = [&](uint64_t e) -> int {
+    if (!h->fo_extra_max) return 0;
+    const double expect = (double)h->tape_cmax[e] * (1.0 / 4294967296.0) *
+                          (double)h->walkers0 * (double)h->fo_extra_max;
+    if (expect < 1024.0) return 0;
+    return (int)std::min(std::ceil(2.0 * expect / 256.0), 2048.0);
+  };
+  // An event expecting more first-order firings than k_begin has threads
+  // applies them over the GPU, one launch per stage sized for twice a
+  // stage's share of the expectation (the candidates bound the firings).
+  auto apply_grid = [&](uint64_t e) -> int {
+    if (!h->n_fo) return 0;
+    const double expect = (double)h->tape_cmax[e] * (1.0 / 4294967296.0) * (double)h->walkers0;
+    if (expect < 1024.0) return 0;
+    const double stages = (double)n_colours(h->geo);
+    return (int)std::min(std::max(std::ceil(2.0 * expect / stages / 256.0), 1.0), 1024.0);
+  };
+  auto shape = [&](uint64_t e) {
+    BeginShape b;
+    b.decide = decide_grid(e);
+    b.births = births_grid(e);
+    b.apply = apply_grid(e);
+    return b;
+  };
   const uint64_t e0 = h->events_done;
   const bool disp = h->L.bins[0].disp != nullptr, births = h->L.wb_count != nullptr;
   if (!h->timing && h->use_graph) {
     psc_status st = ensure_lattice_graph(h);
     if (st) return st;
     for (uint64_t e = 0; e < n_events; ++e) {
-      const int dg = decide_grid(e0 + e);
-      if (dg) HIP_OK(h, launch_event(h->dL, h->grid, h->items, disp, h->geo.fcc != 0, dg, births,
-                                     stream));
+      const BeginShape b = shape(e0 + e);
+      if (b.decide || b.births || b.apply)
+        HIP_OK(h, launch_event(h->dL, h->grid, h->items, disp, h->geo.fcc != 0, b, births,
+                               stream));
       else HIP_OK(h, hipGraphLaunch(h->exec, stream));
     }
   } else if (!h->timing) {
     for (uint64_t e = 0; e < n_events; ++e)
-      HIP_OK(h, launch_event(h->dL, h->grid, h->items, disp, h->geo.fcc != 0,
-                             decide_grid(e0 + e), births, stream));
+      HIP_OK(h, launch_event(h->dL, h->grid, h->items, disp, h->geo.fcc != 0, shape(e0 + e),
+                             births, stream));
   } else {
     auto ev = [&](hipEvent_t *out) -> hipError_t {
       if (!h->event_pool.empty()) {
@@ -991,7 +1030,8 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
         HIP_OK(h, ev(&t.a));
         HIP_OK(h, ev(&t.b));
         HIP_OK(h, hipEventRecord(t.a, stream));
-        if (g < 0) HIP_OK(h, launch_begin(h->dL, decide_grid(e0 + e), stream));
+        if (g < 0)
+          HIP_OK(h, launch_begin(h->dL, shape(e0 + e), (uint32_t)stages, stream));
         else if (g < stages)
           HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, h->items,
                                  h->L.bins[0].disp != nullptr, h->geo.fcc != 0, stream));
@@ -1038,6 +1078,11 @@ psc_status psc_query_sizes(const psc_lattice *hc, uint64_t *n_voxels, uint64_t *
     }
   }
   return PSC_OK;
+}
+
+psc_status psc_required_sizes(const psc_lattice *h, uint64_t *n_voxels, uint64_t *n_molecules,
+                              uint32_t *n_species, uint32_t *n_reactions) {
+  return psc_query_sizes(h, n_voxels, n_molecules, n_species, n_reactions);
 }
 
 psc_status psc_read_counters(psc_lattice *h, psc_counters *out, uint64_t *event) {
@@ -1597,6 +1642,17 @@ psc_status psc_ensemble_step(psc_ensemble *E, uint64_t n_events, void *stream_) 
     E->autotune_events = 0;
   }
   return run_events(E, left, stream);
+}
+
+psc_status psc_ensemble_read(psc_ensemble *E, uint32_t i, psc_state_view *out, void *stream) {
+  if (!E || !out) return PSC_EINVAL;
+  if (E->poisoned) return PSC_EDEVICE;
+  if (i >= E->members.size()) return efail(E, PSC_EINVAL, "member %u of %zu", i, E->members.size());
+  psc_status st = psc_ensemble_sync(E);
+  if (st) return st;
+  st = psc_read_state(E->members[i], out, stream);
+  if (st) return efail(E, st, "member %u: %s", i, E->members[i]->err.c_str());
+  return PSC_OK;
 }
 
 psc_status psc_ensemble_sync(psc_ensemble *E) {

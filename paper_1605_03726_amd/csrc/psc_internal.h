@@ -66,6 +66,7 @@ struct psc_lattice {
   std::vector<uint16_t> fo_first, fo_rx;
   std::vector<uint8_t> fo_n;
   uint32_t n_fo = 0;
+  uint32_t fo_extra_max = 0;  // most newborns of one first-order firing
 
   // device
   struct Block {

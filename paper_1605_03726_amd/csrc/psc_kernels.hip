@@ -101,11 +101,21 @@ __device__ __forceinline__ void for_each_ranked(const uint64_t *keys, uint32_t n
     if (tid + a * nthreads < nb) f(mine[a], rank[a]);
 }
 
+// The first-order pass's statistics, tallied in LDS by its workgroup and
+// added to the lattice's counters once at its end: thousands of firings in
+// one workgroup would otherwise queue their 64-bit atomics on one line.
+struct FirstOrderTally {
+  int32_t dsp[64];                  // live molecules per species, change
+  uint32_t fired[kMaxReactions];
+  uint32_t fail;                    // placement failures
+};
+
 // one first-order firing of the molecule at (colour c, position pos): the
 // first product stays in place, the others go to distinct vacant neighbours
 // chosen by the placement words; too few vacant neighbours: no change
 __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in, uint32_t c,
-                                  uint32_t pos, uint32_t id, uint32_t rx, uint32_t *s_nb) {
+                                  uint32_t pos, uint32_t id, uint32_t rx, uint32_t *s_nb,
+                                  FirstOrderTally *T) {
   const uint64_t at = c * L.cap + pos;
   const uint32_t v = in.vox[at];
   const uint32_t m = L.rx_nprod[rx];
@@ -116,8 +126,8 @@ __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, c
   if (m == 0) {
     L.occ[v] = (uint16_t)comp;
     in.id[at] = kDeadId;
-    atomicAdd(&stat_sp(L)[sp0], ~0ull);  // -1
-    atomicAdd(&stat_fired(L)[rx], 1ull);
+    atomicSub(&T->dsp[sp0], 1);
+    atomicAdd(&T->fired[rx], 1u);
     return;
   }
   uint32_t dest[kMaxProducts];
@@ -132,7 +142,7 @@ __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, c
       if (L.occ[t] == comp) vac[nv++] = t;  // vacant, same compartment
     }
     if (nv < (int)(m - 1)) {
-      atomicAdd(&stat_cnt(L)[3], 1ull);
+      atomicAdd(&T->fail, 1u);
       return;
     }
     const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
@@ -145,11 +155,11 @@ __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, c
   }
   L.occ[v] = (uint16_t)(prod[0] | comp);
   in.sp[at] = (uint16_t)(prod[0] | comp);  // the entry stays; its cached word follows
-  atomicAdd(&stat_sp(L)[sp0], ~0ull);
-  atomicAdd(&stat_sp(L)[prod[0] & 63u], 1ull);
+  atomicSub(&T->dsp[sp0], 1);
+  atomicAdd(&T->dsp[prod[0] & 63u], 1);
   for (uint32_t a = 0; a + 1 < m; ++a) {
     L.occ[dest[a]] = (uint16_t)(prod[a + 1] | comp);
-    atomicAdd(&stat_sp(L)[prod[a + 1] & 63u], 1ull);
+    atomicAdd(&T->dsp[prod[a + 1] & 63u], 1);
     const uint32_t b = atomicAdd(s_nb, 1u);
     if (b < L.birth_cap) {
       L.birth_key[b] = ((uint64_t)id << 31) | ((uint64_t)(a + 1) << 27) | b;
@@ -159,7 +169,70 @@ __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, c
       atomicOr(L.error, kErrBirthOverflow);
     }
   }
-  atomicAdd(&stat_fired(L)[rx], 1ull);
+  atomicAdd(&T->fired[rx], 1u);
+}
+
+// A first-order newborn (key = parent id << 31 | product index << 27 | slot)
+// with id `id` joins the bins of the running event with its voxel's word
+// (newborns of the first-order pass walk in the same event).
+__device__ __forceinline__ void bin_first_order_birth(const LatDev &L, const Bins &in,
+                                                      uint64_t key, uint32_t id) {
+  const uint32_t src = (uint32_t)(key & ((1u << 27) - 1u));
+  const uint32_t v = L.birth_vox[src];
+  const uint32_t c = colour_of_voxel(L.geo, v);
+  const uint32_t pos = atomicAdd(&in.count[c], 1u);
+  if (pos < L.cap) {
+    const uint64_t at = c * L.cap + pos;
+    in.vox[at] = v;
+    in.id[at] = id;
+    in.sp[at] = L.birth_sp[src];
+    if (in.disp) {
+      in.disp[(0 * L.ncol + c) * L.cap + pos] = 0;
+      in.disp[(1 * L.ncol + c) * L.cap + pos] = 0;
+      in.disp[(2 * L.ncol + c) * L.cap + pos] = 0;
+    }
+  } else {
+    set_error(L, kErrBinOverflow);
+  }
+}
+
+// Ranks of nb distinct keys over the whole grid: f(key, rank) for each, rank
+// = the number of smaller keys.  Each thread ranks one key per pass against
+// every key, read through LDS in tiles; O(nb^2) comparisons spread over the
+// GPU, for events with more newborns than one workgroup ranks in LDS.
+constexpr uint32_t kRankTile = 2048;
+template <class F>
+__device__ __forceinline__ void rank_keys_grid(const uint64_t *keys, uint32_t nb, F f) {
+  __shared__ uint64_t tile[kRankTile];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < nb; base += stride) {
+    const uint32_t q = base + threadIdx.x;
+    const uint64_t mine = q < nb ? keys[q] : ~0ull;
+    uint32_t rank = 0;
+    for (uint32_t t0 = 0; t0 < nb; t0 += kRankTile) {
+      const uint32_t n = min(kRankTile, nb - t0);
+      __syncthreads();
+      for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) tile[j] = keys[t0 + j];
+      __syncthreads();
+#pragma unroll 8
+      for (uint32_t j = 0; j < n; ++j) rank += tile[j] < mine ? 1u : 0u;
+    }
+    if (q < nb) f(mine, rank);
+  }
+}
+
+// The last of the grid's workgroups to call this returns true (counted in
+// *done, which it resets); after a device-scope fence it sees the others'
+// atomics.
+__device__ __forceinline__ bool last_workgroup(uint32_t *done) {
+  __shared__ uint32_t s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  if (threadIdx.x == 0) *done = 0;
+  return true;
 }
 
 // First-order decisions of event e for candidates [first, ...) with the
@@ -191,7 +264,14 @@ __device__ __forceinline__ void decide_first_order(const LatDev &L, uint64_t e, 
 
 // the event's opening work for one lattice, by one workgroup; decided: the
 // fire list was built by k_decide
-__device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
+// defer: newborns beyond what one workgroup numbers in LDS are left to
+// k_births (their count in *birth_count), which then writes the stage
+// descriptors; *deferred tells the caller
+// apply: the firings are applied by k_fo_stage launches, one per stage, and
+// numbered by k_births (events with many firings): this pass ends after the
+// decisions
+__device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool defer, bool apply,
+                                           uint32_t *deferred, FirstOrderTally *T) {
   uint32_t *__restrict__ fire_pos = L.fire_pos;
   uint32_t *__restrict__ fire_id = L.fire_id;
   uint8_t *__restrict__ fire_col = L.fire_col;
@@ -232,6 +312,13 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
                   (uint32_t)L.cap);
   __syncthreads();
   const uint32_t nfire = s_nfire;
+  if (apply) {
+    if (tid == 0) {
+      if (!decided) *L.fire_count = nfire;  // the list the stage launches apply
+      *deferred = 1;
+    }
+    return;
+  }
 
   // ---- application.  A firing molecule reads and writes only its closed
   // neighbourhood N[v] (its voxel and the 12 neighbours).  Molecules whose
@@ -269,7 +356,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
       for (int a = 0; a < 13; ++a)
         other |= __hip_atomic_load(&L.nbr_cnt[h[a]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ^ 1u;
       if (other == 0u) {
-        apply_first_order(L, e, in, c, pos, id, rx, &s_nb);
+        apply_first_order(L, e, in, c, pos, id, rx, &s_nb, T);
       } else {
         deferred = true;  // to the staged pass
         atomicAdd(&s_colcnt[c], 1u);
@@ -279,7 +366,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
     for (uint32_t g = 0; g < ncol; ++g) {
       const uint32_t cg = s_perm[g];
       if (s_colcnt[cg] == 0) continue;
-      if (deferred && c == cg) apply_first_order(L, e, in, c, pos, id, rx, &s_nb);
+      if (deferred && c == cg) apply_first_order(L, e, in, c, pos, id, rx, &s_nb, T);
       __syncthreads();
     }
     // leave the counts at zero for the next event
@@ -289,56 +376,18 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
     }
     __syncthreads();
   } else if (nfire > 0) {
-    const uint32_t nb_bits = L.nbr_bits;
-    for (uint32_t q = tid; q < nfire; q += blockDim.x) {
-      const uint32_t c = fire_col[q];
-      const uint32_t v = in.vox[c * L.cap + fire_pos[q]];
-      const Coord cv = coord_of(L.geo, v);
-      atomicAdd(&L.nbr_cnt[hot_hash(v, nb_bits)], 1u);
-      for (uint32_t n = 0; n < 12; ++n)
-        atomicAdd(&L.nbr_cnt[hot_hash(index_of(L.geo, step_coord(L.geo, cv, n)), nb_bits)], 1u);
-    }
-    __syncthreads();
-    for (uint32_t q = tid; q < nfire; q += blockDim.x) {
-      const uint32_t c = fire_col[q];
-      const uint32_t v = in.vox[c * L.cap + fire_pos[q]];
-      const Coord cv = coord_of(L.geo, v);
-      // the 13 counts (each at least 1: the molecule's own) are read at once
-      // through L2, then tested together
-      uint32_t other = __hip_atomic_load(&L.nbr_cnt[hot_hash(v, nb_bits)], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) ^ 1u;
-#pragma unroll
-      for (uint32_t n = 0; n < 12; ++n)
-        other |= __hip_atomic_load(
-                     &L.nbr_cnt[hot_hash(index_of(L.geo, step_coord(L.geo, cv, n)), nb_bits)],
-                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ^ 1u;
-      const bool alone = other == 0u;
-      if (alone) {
-        apply_first_order(L, e, in, c, fire_pos[q], fire_id[q], fire_rx[q], &s_nb);
-      } else {
-        fire_col[q] = (uint8_t)(c | 0x80u);  // deferred to the staged pass
-        atomicAdd(&s_colcnt[c], 1u);
-      }
-    }
-    __syncthreads();
+    // more firings than threads: every firing is applied in the event's
+    // stage order, all those of one colour at once (their closed
+    // neighbourhoods are disjoint, so they commute).  Counting overlaps as
+    // above would cost 39 global atomics per firing, all issued from this
+    // one workgroup's compute unit.
     for (uint32_t g = 0; g < ncol; ++g) {
-      const uint32_t c = s_perm[g];
-      if (s_colcnt[c] == 0) continue;
+      const uint32_t cg = s_perm[g];
       for (uint32_t q = tid; q < nfire; q += blockDim.x)
-        if (fire_col[q] == (c | 0x80u))
-          apply_first_order(L, e, in, c, fire_pos[q], fire_id[q], fire_rx[q], &s_nb);
+        if (fire_col[q] == cg)
+          apply_first_order(L, e, in, cg, fire_pos[q], fire_id[q], fire_rx[q], &s_nb, T);
       __syncthreads();
     }
-    // leave the counts at zero for the next event
-    for (uint32_t q = tid; q < nfire; q += blockDim.x) {
-      const uint32_t c = fire_col[q] & 0x7Fu;
-      const uint32_t v = in.vox[c * L.cap + fire_pos[q]];
-      const Coord cv = coord_of(L.geo, v);
-      atomicSub(&L.nbr_cnt[hot_hash(v, nb_bits)], 1u);
-      for (uint32_t n = 0; n < 12; ++n)
-        atomicSub(&L.nbr_cnt[hot_hash(index_of(L.geo, step_coord(L.geo, cv, n)), nb_bits)], 1u);
-    }
-    __syncthreads();
   }
 
   // ---- newborn ids: ascending parent id, then product index.  The keys are
@@ -352,25 +401,14 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
     if (tid == 0) set_error(L, kErrIds);
     return;
   }
-  auto bin_birth = [&](uint64_t key, uint32_t id) {
-    const uint32_t src = (uint32_t)(key & ((1u << 27) - 1u));
-    const uint32_t v = L.birth_vox[src];
-    const uint32_t c = colour_of_voxel(L.geo, v);
-    const uint32_t pos = atomicAdd(&in.count[c], 1u);
-    if (pos < L.cap) {
-      const uint64_t at = c * L.cap + pos;
-      in.vox[at] = v;
-      in.id[at] = id;
-      in.sp[at] = L.birth_sp[src];
-      if (in.disp) {
-        in.disp[(0 * ncol + c) * L.cap + pos] = 0;
-        in.disp[(1 * ncol + c) * L.cap + pos] = 0;
-        in.disp[(2 * ncol + c) * L.cap + pos] = 0;
-      }
-    } else {
-      set_error(L, kErrBinOverflow);
+  auto bin_birth = [&](uint64_t key, uint32_t id) { bin_first_order_birth(L, in, key, id); };
+  if (nb > kSortLds && defer) {
+    if (tid == 0) {
+      *L.birth_count = nb;  // k_births numbers them and writes the stage descriptors
+      *deferred = 1;
     }
-  };
+    return;
+  }
   if (nb <= kSortLds) {
     for (uint32_t q = tid; q < nb; q += blockDim.x) s_keys[q] = L.birth_key[q];
     __syncthreads();
@@ -392,11 +430,8 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided) {
 // bins) and the event, so that a stage launch starts with one load instead of
 // a chain of three.  A lattice that does not run this event (idle or out of
 // tape) gets empty stages, and so do the stages past its colour count.
-__device__ __forceinline__ void begin_body(const LatDev &L, bool decided) {
-  begin_work(L, decided);
-  __syncthreads();  // every return of begin_work is taken by the whole block
-  const uint32_t tid = threadIdx.x;
-  if (tid == 0 && decided) *L.fire_count = 0;  // k_decide's list has been applied
+// threads tid < kMaxColours of one workgroup: each stage's descriptor
+__device__ __forceinline__ void write_stage_descriptors(const LatDev &L, uint32_t tid) {
   if (tid < kMaxColours) {
     const uint64_t e = *L.ev;
     const bool run = e < L.tape_horizon && e < L.stop_event && tid < L.ncol;
@@ -407,14 +442,94 @@ __device__ __forceinline__ void begin_body(const LatDev &L, bool decided) {
   }
 }
 
+__device__ __forceinline__ void begin_body(const LatDev &L, bool decided, bool defer, bool apply) {
+  __shared__ uint32_t s_deferred;
+  __shared__ FirstOrderTally T;
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) {
+    s_deferred = 0;
+    T.fail = 0;
+  }
+  if (tid < 64) T.dsp[tid] = 0;
+  if (tid < (uint32_t)kMaxReactions) T.fired[tid] = 0;
+  __syncthreads();
+  begin_work(L, decided, defer, apply, &s_deferred, &T);
+  __syncthreads();  // every return of begin_work is taken by the whole block
+  if (tid < 64 && T.dsp[tid]) atomicAdd(&stat_sp(L)[tid], (unsigned long long)(long long)T.dsp[tid]);
+  if (tid < L.n_rx && T.fired[tid]) atomicAdd(&stat_fired(L)[tid], (unsigned long long)T.fired[tid]);
+  if (tid == 0 && T.fail) atomicAdd(&stat_cnt(L)[3], (unsigned long long)T.fail);
+  if (s_deferred) return;  // k_births finishes the pass
+  if (tid == 0 && decided) *L.fire_count = 0;  // k_decide's list has been applied
+  write_stage_descriptors(L, tid);
+}
+
+// defer: k_births follows (newborns beyond the LDS ranking are left to it);
+// apply: k_fo_stage launches apply the firings, then k_births
 __global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restrict__ Lp,
-                                                         int decided) {
-  begin_body(*Lp, decided != 0);
+                                                         int decided, int defer, int apply) {
+  begin_body(*Lp, decided != 0, defer != 0, apply != 0);
 }
 
 // one workgroup per member lattice of an ensemble
 __global__ void __launch_bounds__(kBeginThreads) k_begin_multi(const LatDev *__restrict__ lats) {
-  begin_body(lats[blockIdx.x], false);
+  begin_body(lats[blockIdx.x], false, false, false);
+}
+
+// Stage g of the first-order application over many workgroups (events with
+// many firings): every firing of the stage's colour, at once -- their closed
+// neighbourhoods are disjoint.  Newborns take slots from *birth_count.
+__global__ void __launch_bounds__(kStageThreads) k_fo_stage(const LatDev *__restrict__ Lp,
+                                                            uint32_t g) {
+  __shared__ FirstOrderTally T;
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) T.fail = 0;
+  if (tid < 64) T.dsp[tid] = 0;
+  for (uint32_t r = tid; r < (uint32_t)kMaxReactions; r += blockDim.x) T.fired[r] = 0;
+  __syncthreads();
+  const LatDev &L = *Lp;
+  const uint64_t e = *L.ev;
+  if (e >= L.stop_event || e >= L.tape_horizon) return;
+  const uint32_t nfire = min(*L.fire_count, (uint32_t)L.cap);
+  const uint32_t cg = L.perm[g];
+  const Bins &in = L.bins[e & 1];
+  for (uint32_t q = blockIdx.x * blockDim.x + tid; q < nfire; q += gridDim.x * blockDim.x)
+    if (L.fire_col[q] == cg)
+      apply_first_order(L, e, in, cg, L.fire_pos[q], L.fire_id[q], L.fire_rx[q], L.birth_count, &T);
+  __syncthreads();
+  if (tid < 64 && T.dsp[tid]) atomicAdd(&stat_sp(L)[tid], (unsigned long long)(long long)T.dsp[tid]);
+  for (uint32_t r = tid; r < L.n_rx; r += blockDim.x)
+    if (T.fired[r]) atomicAdd(&stat_fired(L)[r], (unsigned long long)T.fired[r]);
+  if (tid == 0 && T.fail) atomicAdd(&stat_cnt(L)[3], (unsigned long long)T.fail);
+}
+
+// The first-order newborns left to it (more than k_begin ranks in LDS, or
+// all of them after k_fo_stage applied the firings): ids next_id + rank over
+// the whole grid, binned for the running event; the last workgroup advances
+// next_id, clears the fire list and writes the stage descriptors.  finish:
+// the pass was handed over whatever the newborns (after k_fo_stage).
+__global__ void __launch_bounds__(kStageThreads) k_births(const LatDev *__restrict__ Lp,
+                                                          int finish) {
+  const LatDev &L = *Lp;
+  uint32_t nb = min(*L.birth_count, (uint32_t)L.birth_cap);
+  if (nb == 0 && !finish) return;  // k_begin numbered this event's newborns (or had none)
+  const uint64_t e = *L.ev;
+  const Bins &in = L.bins[e & 1];
+  const uint32_t base_id = *L.next_id;
+  if ((uint64_t)base_id + nb >= 0xFFFFFFFFull) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_error(L, kErrIds);
+    nb = 0;
+  }
+  if (nb)
+    rank_keys_grid(L.birth_key, nb, [&](uint64_t k, uint32_t r) {
+      bin_first_order_birth(L, in, k, base_id + r);
+    });
+  if (!last_workgroup(L.end_done)) return;
+  if (threadIdx.x == 0) {
+    *L.next_id = base_id + nb;
+    *L.birth_count = 0;
+    *L.fire_count = 0;  // the fire list has been applied
+  }
+  write_stage_descriptors(L, threadIdx.x);
 }
 
 // the first-order decisions of the coming event over many workgroups, for
@@ -444,6 +559,43 @@ constexpr int kEndBlocksMulti = 1;
 // with their current species (one may have changed as a later partner);
 // they are also tested as first-order candidates of the next event, which a
 // walk does for every other molecule.  Run by one whole workgroup.
+// a newborn of event e's many-product collisions (key = mover id << 32 |
+// product index << 28 | slot) with id `id` joins the next event's bins and
+// is tested as a first-order candidate of that event
+__device__ __forceinline__ void bin_collision_birth(const LatDev &L, uint64_t e, const Bins &out,
+                                                    uint32_t cnext, uint32_t cmax_next,
+                                                    uint64_t key, uint32_t id) {
+  const uint32_t u = L.wb_vox[key & ((1u << 28) - 1u)];
+  const uint32_t c = colour_of_voxel(L.geo, u);
+  const uint32_t pos = atomicAdd(&out.count[c], 1u);
+  if (pos >= L.cap) {
+    set_error(L, kErrBinOverflow);
+    return;
+  }
+  const uint64_t at = c * L.cap + pos;
+  out.vox[at] = u;
+  out.id[at] = id;
+  out.sp[at] = (uint16_t)(L.occ[u] & kWordMask);
+  if (out.disp) {
+    out.disp[(0 * L.ncol + c) * L.cap + pos] = 0;
+    out.disp[(1 * L.ncol + c) * L.cap + pos] = 0;
+    out.disp[(2 * L.ncol + c) * L.cap + pos] = 0;
+  }
+  if (cmax_next) {
+    const U4 r = philox((uint32_t)(e + 1), id, kPhaseFirst, 0, L.key0, L.key1);
+    if (r.x < cmax_next) {
+      const uint32_t k = atomicAdd(&L.cand_count[cnext], 1u);
+      if (k < L.cand_cap) {
+        L.cand_pos[cnext][k] = pos;
+        L.cand_id[cnext][k] = id;
+        L.cand_col[cnext][k] = (uint8_t)c;
+      } else {
+        set_error(L, kErrCandOverflow);
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
   __shared__ uint64_t s_wkeys[kSortLds];
   const uint32_t tid = threadIdx.x;
@@ -460,35 +612,7 @@ __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
   // the newborn of key `key` gets id `id` (keys are distinct: they end in the
   // slot; its id is next_id plus the number of smaller keys)
   auto bin_newborn = [&](uint64_t key, uint32_t id) {
-    const uint32_t u = L.wb_vox[key & ((1u << 28) - 1u)];
-    const uint32_t c = colour_of_voxel(L.geo, u);
-    const uint32_t pos = atomicAdd(&out.count[c], 1u);
-    if (pos >= L.cap) {
-      set_error(L, kErrBinOverflow);
-      return;
-    }
-    const uint64_t at = c * L.cap + pos;
-    out.vox[at] = u;
-    out.id[at] = id;
-    out.sp[at] = (uint16_t)(L.occ[u] & kWordMask);
-    if (out.disp) {
-      out.disp[(0 * L.ncol + c) * L.cap + pos] = 0;
-      out.disp[(1 * L.ncol + c) * L.cap + pos] = 0;
-      out.disp[(2 * L.ncol + c) * L.cap + pos] = 0;
-    }
-    if (cmax_next) {
-      const U4 r = philox((uint32_t)(e + 1), id, kPhaseFirst, 0, L.key0, L.key1);
-      if (r.x < cmax_next) {
-        const uint32_t k = atomicAdd(&L.cand_count[cnext], 1u);
-        if (k < L.cand_cap) {
-          L.cand_pos[cnext][k] = pos;
-          L.cand_id[cnext][k] = id;
-          L.cand_col[cnext][k] = (uint8_t)c;
-        } else {
-          set_error(L, kErrCandOverflow);
-        }
-      }
-    }
+    bin_collision_birth(L, e, out, cnext, cmax_next, key, id);
   };
   if (nb <= kSortLds) {
     for (uint32_t q = tid; q < nb; q += blockDim.x) s_wkeys[q] = L.wb_key[q];
@@ -512,8 +636,11 @@ __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
 
 // BIRTHS: the lattice may have newborns of many-product collisions to number
 // (the numbering's registers and LDS would otherwise limit every end kernel)
+// defer: newborns beyond what one workgroup ranks in LDS are left to
+// k_end_births, which follows
 template <bool BIRTHS>
-__device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t nblk) {
+__device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t nblk,
+                                         bool defer) {
   const uint64_t e = *L.ev;
   if (e >= L.tape_horizon || e >= L.stop_event) return;
   const uint32_t cur = (uint32_t)(e & 1), prv = cur ^ 1u;
@@ -547,7 +674,7 @@ __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t
     // the last workgroup: every other one has finished its sweeps
     __threadfence();
   }
-  if (BIRTHS && L.wb_count) number_births(L, e);
+  if (BIRTHS && L.wb_count && !(defer && *L.wb_count > kSortLds)) number_births(L, e);
   __syncthreads();
   if (threadIdx.x == 0) {
     L.flag_count[prv] = 0;  // the next walk fills this list
@@ -557,13 +684,39 @@ __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t
 }
 
 template <bool BIRTHS>
-__global__ void __launch_bounds__(kEndThreads) k_end(const LatDev *__restrict__ Lp) {
-  end_body<BIRTHS>(*Lp, blockIdx.x, gridDim.x);
+__global__ void __launch_bounds__(kEndThreads) k_end(const LatDev *__restrict__ Lp, int defer) {
+  end_body<BIRTHS>(*Lp, blockIdx.x, gridDim.x, defer != 0);
 }
 
 template <bool BIRTHS>
 __global__ void __launch_bounds__(kEndThreads) k_end_multi(const LatDev *__restrict__ lats) {
-  end_body<BIRTHS>(lats[blockIdx.y], blockIdx.x, gridDim.x);
+  end_body<BIRTHS>(lats[blockIdx.y], blockIdx.x, gridDim.x, false);
+}
+
+// The collision newborns k_end left (more than one workgroup ranks in LDS):
+// ids next_id + rank over the whole grid, binned for the next event.  k_end
+// has advanced the event counter: the walk was event *ev - 1.
+__global__ void __launch_bounds__(kStageThreads) k_end_births(const LatDev *__restrict__ Lp) {
+  const LatDev &L = *Lp;
+  const uint32_t nb = min(*L.wb_count, (uint32_t)L.wb_cap);
+  if (nb == 0) return;  // numbered by k_end, or none
+  const uint64_t e = *L.ev - 1;
+  const uint32_t base_id = *L.next_id;
+  if ((uint64_t)base_id + nb >= 0xFFFFFFFFull) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_error(L, kErrIds);
+    return;
+  }
+  const Bins &out = L.bins[(e + 1) & 1];
+  const uint32_t cnext = (uint32_t)((e + 1) & 1);
+  const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
+  rank_keys_grid(L.wb_key, nb, [&](uint64_t k, uint32_t r) {
+    bin_collision_birth(L, e, out, cnext, cmax_next, k, base_id + r);
+  });
+  if (!last_workgroup(L.end_done)) return;
+  if (threadIdx.x == 0) {
+    *L.next_id = base_id + nb;
+    *L.wb_count = 0;
+  }
 }
 
 // =============================================================================
@@ -631,10 +784,16 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_begin(const LatDev *dL, int decide_grid, hipStream_t s) {
-  if (decide_grid > 0)
-    hipLaunchKernelGGL(k_decide, dim3(decide_grid), dim3(kStageThreads), 0, s, dL);
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, decide_grid > 0 ? 1 : 0);
+hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t s) {
+  if (b.decide > 0) hipLaunchKernelGGL(k_decide, dim3(b.decide), dim3(kStageThreads), 0, s, dL);
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, b.decide > 0 ? 1 : 0,
+                     b.births > 0 ? 1 : 0, b.apply > 0 ? 1 : 0);
+  if (b.apply > 0)
+    for (uint32_t g = 0; g < stages; ++g)
+      hipLaunchKernelGGL(k_fo_stage, dim3(b.apply), dim3(kStageThreads), 0, s, dL, g);
+  if (b.births > 0 || b.apply > 0)
+    hipLaunchKernelGGL(k_births, dim3(b.births > 0 ? b.births : 1), dim3(kStageThreads), 0, s, dL,
+                       b.apply > 0 ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -644,16 +803,24 @@ hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool 
              : launch_stage_lat<0>(dL, g, grid, items, disp, s);
 }
 
+// grid of the ranking of many collision newborns (a pass ranks this many
+// times 256 keys; further ones take more passes)
+constexpr int kEndBirthsGrid = 512;
+
 hipError_t launch_end(const LatDev *dL, bool births, hipStream_t s) {
-  if (births) hipLaunchKernelGGL(k_end<true>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL);
-  else hipLaunchKernelGGL(k_end<false>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL);
+  if (births) {
+    hipLaunchKernelGGL(k_end<true>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL, 1);
+    hipLaunchKernelGGL(k_end_births, dim3(kEndBirthsGrid), dim3(kStageThreads), 0, s, dL);
+  } else {
+    hipLaunchKernelGGL(k_end<false>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL, 0);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
-                        int decide_grid, bool births, hipStream_t s) {
-  hipError_t err = launch_begin(dL, decide_grid, s);
+                        const BeginShape &b, bool births, hipStream_t s) {
   const uint32_t stages = fcc ? kColoursFcc : kColoursHcp;
+  hipError_t err = launch_begin(dL, b, stages, s);
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
     err = launch_stage(dL, g, grid, items, disp, fcc, s);
   if (err == hipSuccess) err = launch_end(dL, births, s);

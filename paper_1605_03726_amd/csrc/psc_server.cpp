@@ -351,6 +351,11 @@ uint64_t job_bytes(const psc_job_desc *d, uint32_t quantum) {
          tape_bytes(d, quantum);
 }
 
+psc_status psc_server_start(uint64_t budget_bytes, int32_t device, psc_server **out) {
+  const psc_server_options o{device, budget_bytes, 64, 1024, 4};
+  return psc_server_create(&o, out);
+}
+
 psc_status psc_server_job_bytes(const psc_job_desc *d, uint64_t *bytes) {
   if (!d || !bytes) return PSC_EINVAL;
   *bytes = job_bytes(d, 1024);

@@ -162,6 +162,11 @@ def lib() -> C.CDLL:
     L.psc_ensemble_autotune.restype = C.c_int32
     L.psc_ensemble_tuned.argtypes = [vp, C.POINTER(Launch), C.POINTER(C.c_double)]
     L.psc_ensemble_tuned.restype = C.c_int32
+    L.psc_ensemble_read.argtypes = [vp, C.c_uint32, C.POINTER(StateView), vp]
+    L.psc_ensemble_read.restype = C.c_int32
+    L.psc_required_sizes.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                     C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+    L.psc_required_sizes.restype = C.c_int32
     L.psc_ensemble_destroy.argtypes = [vp]
     L.psc_ensemble_destroy.restype = None
     L.psc_ensemble_last_error.argtypes = [vp]
@@ -358,33 +363,39 @@ class Lattice:
     def read_state(self, with_occ: bool = True, stream=None, noalloc: bool = False) -> dict:
         """the state (psc_read_state); noalloc: through psc_read_state_noalloc,
         which allocates no device memory"""
-        cap = self.n_molecules()
-        occ = np.zeros(self.nv, np.uint16) if with_occ else None
-        arrays = {k: np.zeros(cap, t) for k, t in (("id", np.uint32), ("vox", np.uint32),
-                                                    ("species", np.uint16), ("dx", np.int32),
-                                                    ("dy", np.int32), ("dz", np.int32))}
-        fired = np.zeros(max(self.n_rx, 1), np.uint64)
-        v = StateView()
-        v.occupancy = _ptr(occ, C.c_uint16)
-        v.n_molecules = cap
-        v.id = _ptr(arrays["id"], C.c_uint32)
-        v.voxel = _ptr(arrays["vox"], C.c_uint32)
-        v.species = _ptr(arrays["species"], C.c_uint16)
-        v.dx = _ptr(arrays["dx"], C.c_int32)
-        v.dy = _ptr(arrays["dy"], C.c_int32)
-        v.dz = _ptr(arrays["dz"], C.c_int32)
-        v.reactions_fired = _ptr(fired, C.c_uint64)
-        s = None if stream is None else stream
         fn = self.L.psc_read_state_noalloc if noalloc else self.L.psc_read_state
-        self._check(fn(self.h, C.byref(v), s))
-        n = v.n_molecules
-        out = {k: a[:n].copy() for k, a in arrays.items()}
-        out.update(occ=occ, attempts=v.counters.attempts, hops=v.counters.hops,
-                   collisions=v.counters.collisions,
-                   place_fail=v.counters.placement_failures,
-                   fired=fired[: self.n_rx].copy(), event=v.event, time=v.time,
-                   next_id=v.next_id)
-        return out
+        s = None if stream is None else stream
+        return _read_view(self.nv if with_occ else 0, self.n_molecules(), self.n_rx,
+                          lambda v: self._check(fn(self.h, C.byref(v), s)))
+
+
+def _read_view(n_voxels: int, cap: int, n_rx: int, call) -> dict:
+    """host arrays for a state of up to `cap` molecules (occupancy too unless
+    n_voxels is 0), filled by call(view); the state as a dict"""
+    occ = np.zeros(n_voxels, np.uint16) if n_voxels else None
+    arrays = {k: np.zeros(cap, t) for k, t in (("id", np.uint32), ("vox", np.uint32),
+                                                ("species", np.uint16), ("dx", np.int32),
+                                                ("dy", np.int32), ("dz", np.int32))}
+    fired = np.zeros(max(n_rx, 1), np.uint64)
+    v = StateView()
+    v.occupancy = _ptr(occ, C.c_uint16)
+    v.n_molecules = cap
+    v.id = _ptr(arrays["id"], C.c_uint32)
+    v.voxel = _ptr(arrays["vox"], C.c_uint32)
+    v.species = _ptr(arrays["species"], C.c_uint16)
+    v.dx = _ptr(arrays["dx"], C.c_int32)
+    v.dy = _ptr(arrays["dy"], C.c_int32)
+    v.dz = _ptr(arrays["dz"], C.c_int32)
+    v.reactions_fired = _ptr(fired, C.c_uint64)
+    call(v)
+    n = v.n_molecules
+    out = {k: a[:n].copy() for k, a in arrays.items()}
+    out.update(occ=occ, attempts=v.counters.attempts, hops=v.counters.hops,
+               collisions=v.counters.collisions,
+               place_fail=v.counters.placement_failures,
+               fired=fired[:n_rx].copy(), event=v.event, time=v.time,
+               next_id=v.next_id)
+    return out
 
 
 def lattice_from_workload(w: dict, max_molecules: int | None = None, device: int = 0,
@@ -446,6 +457,16 @@ class Ensemble:
         l = Launch()
         self._check(self.L.psc_ensemble_get_launch(self.h, C.byref(l)))
         return {"items_per_thread": l.items_per_thread, "stage_blocks": l.stage_blocks}
+
+    def read(self, i: int, stream=None) -> dict:
+        """member i's state (psc_ensemble_read)"""
+        s = None if stream is None else stream
+        if not 0 <= i < len(self.members):
+            # the library refuses it (sizes come from the member)
+            self._check(self.L.psc_ensemble_read(self.h, i, C.byref(StateView()), s))
+        m = self.members[i]
+        return _read_view(m.nv, m.n_molecules(), m.n_rx,
+                          lambda v: self._check(self.L.psc_ensemble_read(self.h, i, C.byref(v), s)))
 
     def autotune(self, trial_events: int):
         self._check(self.L.psc_ensemble_autotune(self.h, trial_events))
@@ -516,6 +537,8 @@ def _server_lib():
     if getattr(L, "_server_bound", False):
         return L
     vp = C.c_void_p
+    L.psc_server_start.argtypes = [C.c_uint64, C.c_int32, C.POINTER(vp)]
+    L.psc_server_start.restype = C.c_int32
     L.psc_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(vp)]
     L.psc_server_create.restype = C.c_int32
     L.psc_server_submit.argtypes = [vp, C.POINTER(JobDesc), C.POINTER(C.c_uint64)]
@@ -551,14 +574,18 @@ def _status(st: JobStatus) -> dict:
 
 
 class Server:
-    """Continuous-batching serving loop (psc_server_* in include/psc.h)."""
+    """Continuous-batching serving loop (psc_server_* in include/psc.h);
+    defaults=True starts it with psc_server_start's default options."""
 
     def __init__(self, budget_bytes: int, quantum_events: int = 64, max_active: int = 4096,
-                 device: int = 0, builders: int = 0):
+                 device: int = 0, builders: int = 0, defaults: bool = False):
         self.L = _server_lib()
-        o = ServerOptions(device, budget_bytes, quantum_events, max_active, builders)
         h = C.c_void_p()
-        rc = self.L.psc_server_create(C.byref(o), C.byref(h))
+        if defaults:
+            rc = self.L.psc_server_start(budget_bytes, device, C.byref(h))
+        else:
+            o = ServerOptions(device, budget_bytes, quantum_events, max_active, builders)
+            rc = self.L.psc_server_create(C.byref(o), C.byref(h))
         if rc != PSC_OK:
             raise PscError(rc, "server create failed")
         self.h = h

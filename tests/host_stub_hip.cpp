@@ -133,9 +133,12 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t) {
   check_record(dL);
   return hipSuccess;
 }
-hipError_t launch_begin(const LatDev *dL, int decide_grid, hipStream_t) {
+hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t) {
   ++g_launches;
-  if (decide_grid < 0 || decide_grid > 1024) bad("decide grid");
+  if (b.decide < 0 || b.decide > 1024) bad("decide grid");
+  if (b.births < 0 || b.births > 2048) bad("births grid");
+  if (b.apply < 0 || b.apply > 1024) bad("apply grid");
+  if (stages == 0 || stages > (uint32_t)kMaxColours) bad("stages");
   check_record(dL);
   return hipSuccess;
 }
@@ -155,8 +158,8 @@ hipError_t launch_end(const LatDev *dL, bool births, hipStream_t) {
   return hipSuccess;
 }
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
-                        int decide_grid, bool births, hipStream_t s) {
-  launch_begin(dL, decide_grid, s);
+                        const BeginShape &b, bool births, hipStream_t s) {
+  launch_begin(dL, b, kMaxColours, s);
   for (uint32_t g = 0; g < (uint32_t)kMaxColours; ++g) launch_stage(dL, g, grid, items, disp, fcc, s);
   return launch_end(dL, births, s);
 }

@@ -115,3 +115,19 @@ def test_benchmark_ensemble_at_full_size_sampled():
     picks = {next(i for i, w in enumerate(ws) if w["dims"][0] == e) for e in (32, 48, 64, 96, 128)}
     for i in sorted(picks | {len(ws) - 1}):
         same(lats[i].read_state(), oracle_run(ws[i], 50), disp=False)
+
+
+def test_ensemble_read_equals_the_members_read_back():
+    ws = [workload("small_reactive", dims=(16, 12, 8), seed=70 + a, events=20) for a in range(3)]
+    lats = [psc.lattice_from_workload(w) for w in ws]
+    ens = psc.Ensemble(lats)
+    ens.step(20)
+    for i, lat in enumerate(lats):
+        a, b = ens.read(i), lat.read_state()
+        for key in ("occ", "id", "vox", "species", "dx", "dy", "dz", "fired"):
+            assert np.array_equal(a[key], b[key]), key
+        assert (a["event"], a["attempts"], a["next_id"]) == (b["event"], b["attempts"], b["next_id"])
+    with pytest.raises(psc.PscError) as e:
+        ens.read(3)
+    assert e.value.code == psc.PSC_EINVAL
+    ens.close()

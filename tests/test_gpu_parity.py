@@ -382,6 +382,42 @@ def test_more_newborns_per_event_than_the_lds_numbering_holds(events):
     assert s["fired"][0] > 2048 * events and s["fired"][1] > 2048 * events, s["fired"]
 
 
+def test_many_newborns_numbered_in_one_workgroup_in_an_ensemble():
+    """The batched kernels number every member's newborns in the member's
+    one workgroup (a sort in global memory beyond the LDS ranking): the
+    births workload above as a one-member ensemble equals the oracle too."""
+    w = dict(name="births", dims=(64, 64, 64), rv=4.4e-9, seed=6,
+             species=[("A", 1e-12), ("B", 1e-12), ("C", 0.0)],
+             reactions=[((1,), (1, 3), 20000.0), ((1, 2), (1, 2, 3), 1e-15)],
+             place=[(1, 12000), (2, 40000)], events=4, track_displacement=True)
+    lat = build_gpu(w, max_molecules=64 ** 3)
+    ens = psc.Ensemble([lat])
+    ens.step(4)
+    o = build_oracle(w)
+    o.run(4, oracle.MODE_C)
+    s = o.state()
+    assert_same(ens.read(0), s)
+    assert s["fired"][0] > 2048 * 4 and s["fired"][1] > 2048 * 4, s["fired"]
+    ens.close()
+
+
+@pytest.mark.timeout(600)
+def test_tens_of_thousands_of_newborns_per_event():
+    """~20 k first-order and ~14 k collision newborns per event, numbered by
+    launches over the whole GPU."""
+    w = dict(name="births", dims=(128, 128, 128), rv=4.4e-9, seed=8,
+             species=[("A", 1e-12), ("B", 1e-12), ("C", 0.0)],
+             reactions=[((1,), (1, 3), 20000.0), ((1, 2), (1, 2, 3), 1e-15)],
+             place=[(1, 90000), (2, 150000)], events=3, track_displacement=False)
+    lat = build_gpu(w, max_molecules=128 ** 3)
+    o = build_oracle(w)
+    lat.step(3)
+    o.run(3, oracle.MODE_C)
+    s = o.state()
+    assert_same(lat.read_state(), s, disp=False)
+    assert s["fired"][0] > 15000 * 3 and s["fired"][1] > 10000 * 3, s["fired"]
+
+
 @pytest.mark.parametrize("kind", ["hcp", "fcc_walls"])
 def test_first_order_firings_per_event_crossing_one_workgroup(kind):
     """The first-order pass applies an event's firings one per thread when

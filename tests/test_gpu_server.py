@@ -162,3 +162,13 @@ def test_cancel_queued_and_running_jobs():
     assert stats["cancelled"] == 2 and stats["done"] == 1
     assert stats["device_bytes_in_use"] == 0
     srv.close()
+
+
+def test_server_started_with_default_options():
+    w = small_jobs(1, seed=31)[0]
+    srv = psc.Server(budget_bytes=1 << 30, defaults=True)
+    st = srv.wait(srv.submit(w))
+    a = alone(w)
+    assert st["state"] == psc.JOB_DONE
+    assert (st["attempts"], st["hops"], st["events_done"]) == (a["attempts"], a["hops"], a["event"])
+    srv.close()

@@ -78,6 +78,11 @@ def pick_workload(name: str):
         return workload("cfg1")
     if name == "mapk_paper":
         return workload("mapk_paper")
+    if name == "births":
+        return workload("births")
+    if name == "membrane":
+        return dict(workload("membrane", dims=(256, 256, 256), seed=5, events=2000),
+                    track_displacement=False, name="membrane_256x256x256")
     if name == "multiproduct":
         return dict(workload("multiproduct", dims=(256, 256, 256), seed=3, n_a=100000,
                              events=2000), track_displacement=False,
@@ -100,8 +105,12 @@ def cpu_baseline(w: dict, events: int) -> dict:
             o.add_species(D)
         for r, p, k in w["reactions"]:
             o.add_reaction(r, p, k)
+        if w.get("compartments") is not None:
+            o.set_compartments(w["compartments"])
         for s, c in w["place"]:
             o.place_uniform(s, c)
+        for s, c, cc in w.get("place_in", []):
+            o.place_uniform_in(s, c, cc)
         t0 = time.perf_counter()
         o.run(events, mode)
         dt = time.perf_counter() - t0
@@ -344,7 +353,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="cfg3",
-                    choices=["cfg1", "cfg2", "cfg3", "mapk_paper", "multiproduct"])
+                    choices=["cfg1", "cfg2", "cfg3", "mapk_paper", "multiproduct", "births",
+                             "membrane"])
     ap.add_argument("--timing-steps", type=int, default=40,
                     help="events after the timed region whose launches are timed one by one")
     ap.add_argument("--graph", action="store_true",
@@ -409,9 +419,10 @@ def main():
     if args.walls:
         w = dict(w, boundary="walls", name=w["name"] + "_walls")
     nv = int(w["dims"][0]) * int(w["dims"][1]) * int(w["dims"][2])
-    placed = sum(c for _, c in w["place"])
+    placed = sum(c for _, c in w["place"]) + sum(c for _, c, _ in w.get("place_in", []))
     t_setup = time.perf_counter()
-    lat = psc.lattice_from_workload(w, max_molecules=min(nv, int(placed * 1.25) + 4096))
+    lat = psc.lattice_from_workload(
+        w, max_molecules=w.get("max_molecules", min(nv, int(placed * 1.25) + 4096)))
     if args.graph:
         lat.set_graph_replay(True)
     stream = torch.cuda.current_stream()

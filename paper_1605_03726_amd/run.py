@@ -46,7 +46,7 @@ def main(argv=None) -> int:
     from psc_inputs import workload
     w = workload(args.workload)
     nv = int(w["dims"][0]) * int(w["dims"][1]) * int(w["dims"][2])
-    placed = sum(c for _, c in w["place"])
+    placed = sum(c for _, c in w["place"]) + sum(c for _, c, _ in w.get("place_in", []))
     lat = psc.lattice_from_workload(w, max_molecules=min(nv, int(placed * 1.25) + 4096))
     lat.step(args.warmup)
     lat.sync()

@@ -6,6 +6,7 @@ A workload is a plain dict:
   reactions: [(reactant ids, product ids, k)]  k in 1/s or m^3/s
   place: [(species id, count)] uniform placements, in this order
   events: number of diffusion events, track_displacement: bool
+  max_molecules (optional): the capacity a run of the workload needs
 
 The five benchmark workloads follow the paper's workload shapes (HCP lattice,
 homogeneous start, crowding by immobile voxels, a MAPK-style network); the
@@ -196,6 +197,18 @@ def mapk_paper(events: int = 450000, dims=(480, 480, 480), seed: int = 6,
                 events=events, track_displacement=False)
 
 
+def births(dims=(128, 128, 128), seed: int = 8, n_a: int = 90000, n_b: int = 150000,
+           events: int = 200) -> dict:
+    """Birth-heavy: a fast first-order A -> A + C (about a fifth of the A
+    fire per event) beside a collision A + B -> A + B + C that always fires
+    (11 % occupancy): tens of thousands of newborns per event, C immobile."""
+    return dict(name="births_%dx%dx%d" % tuple(dims), dims=tuple(dims), rv=RV, seed=seed,
+                species=[("A", D1), ("B", D1), ("C", 0.0)],
+                reactions=[((1,), (1, 3), 20000.0), ((1, 2), (1, 2, 3), 1e-15)],
+                place=[(1, n_a), (2, n_b)], events=events, track_displacement=False,
+                max_molecules=dims[0] * dims[1] * dims[2])
+
+
 WORKLOADS = {
     "cfg1": cfg1,
     "cfg2": cfg2,
@@ -203,6 +216,7 @@ WORKLOADS = {
     "small_reactive": small_reactive,
     "mapk_paper": mapk_paper,
     "multiproduct": multiproduct,
+    "births": births,
 }
 
 

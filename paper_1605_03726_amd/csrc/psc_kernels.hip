@@ -267,9 +267,9 @@ __device__ __forceinline__ void decide_first_order(const LatDev &L, uint64_t e, 
 // defer: newborns beyond what one workgroup numbers in LDS are left to
 // k_births (their count in *birth_count), which then writes the stage
 // descriptors; *deferred tells the caller
-// apply: the firings are applied by k_fo_stage launches, one per stage, and
-// numbered by k_births (events with many firings): this pass ends after the
-// decisions
+// apply: k_fo_stage launches, one per stage, and k_births follow; more
+// firings than this workgroup has threads are left to them (this pass then
+// ends after the decisions), fewer are applied here as without them
 __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool defer, bool apply,
                                            uint32_t *deferred, FirstOrderTally *T) {
   uint32_t *__restrict__ fire_pos = L.fire_pos;
@@ -312,13 +312,16 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
                   (uint32_t)L.cap);
   __syncthreads();
   const uint32_t nfire = s_nfire;
-  if (apply) {
+  if (apply && nfire > blockDim.x) {
     if (tid == 0) {
       if (!decided) *L.fire_count = nfire;  // the list the stage launches apply
       *deferred = 1;
     }
     return;
   }
+  // a short list is applied here whatever the launch shape: the stage
+  // launches then find it empty
+  if (apply && decided && tid == 0) *L.fire_count = 0;
 
   // ---- application.  A firing molecule reads and writes only its closed
   // neighbourhood N[v] (its voxel and the 12 neighbours).  Molecules whose

@@ -442,12 +442,15 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s);
 //   births  first-order newborns beyond what one workgroup ranks in LDS are
 //           numbered by a launch of that many workgroups (events expecting
 //           many), else by k_begin alone;
-//   apply   the firings are applied by one launch per stage of that many
-//           workgroups (events expecting many firings), then numbered by
-//           the births launch (at least one workgroup), else inside k_begin.
+//   apply   more firings than k_begin has threads are applied by one
+//           launch per stage of that many workgroups (events with a decision
+//           launch), then numbered by the births launch (at least one
+//           workgroup); fewer are applied inside k_begin.
 struct BeginShape {
   int decide = 0, births = 0, apply = 0;
 };
+// fire-list entries an application workgroup scans per pass
+constexpr uint32_t kFoTile = 2048;
 // births: the lattice (any member) has collision reactions with more than
 // two products, whose newborns the event end numbers
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,

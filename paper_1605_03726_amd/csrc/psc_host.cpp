@@ -983,14 +983,13 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   // An event whose decisions get a launch of their own may fire more
   // first-order reactions than k_begin has threads (the candidates bound the
   // firings; only the device knows how many fire): it gets one application
-  // launch per stage, sized for twice a stage's share of the candidates,
-  // which find the list empty when k_begin applied it itself.
+  // launch per stage, a workgroup per kFoTile expected candidates, which
+  // find the list empty when k_begin applied it itself.
   auto apply_grid = [&](uint64_t e) -> int {
     if (!h->n_fo) return 0;
     const double expect = (double)h->tape_cmax[e] * (1.0 / 4294967296.0) * (double)h->walkers0;
     if (expect < 4096.0) return 0;
-    const double stages = (double)n_colours(h->geo);
-    return (int)std::min(std::max(std::ceil(2.0 * expect / stages / 256.0), 1.0), 1024.0);
+    return (int)std::min(std::max(std::ceil(expect / kFoTile), 1.0), 1024.0);
   };
   auto shape = [&](uint64_t e) {
     BeginShape b;

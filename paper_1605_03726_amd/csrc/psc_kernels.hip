@@ -75,9 +75,11 @@ __device__ __forceinline__ void bitonic_sort_keys(uint64_t *keys, uint32_t n2, i
   }
 }
 
-// For each of the nb distinct keys in LDS, f(key, rank) with rank = the
-// number of smaller keys.  Each thread holds up to PER keys (PER * nthreads
-// >= nb) and reads the list once.
+// For each of the nb distinct keys in LDS, f(true, key, rank) with rank =
+// the number of smaller keys.  Each thread holds up to PER keys (PER *
+// nthreads >= nb) and reads the list once.  Every thread of the workgroup
+// calls f PER times (f(false, ...) past the end), so f may reserve bin
+// space for the whole workgroup at once.
 template <int PER, class F>
 __device__ __forceinline__ void for_each_ranked(const uint64_t *keys, uint32_t nb, uint32_t tid,
                                                 uint32_t nthreads, F f) {
@@ -97,8 +99,47 @@ __device__ __forceinline__ void for_each_ranked(const uint64_t *keys, uint32_t n
     for (int a = 0; a < PER; ++a) rank[a] += k < mine[a] ? 1u : 0u;
   }
 #pragma unroll
-  for (int a = 0; a < PER; ++a)
-    if (tid + a * nthreads < nb) f(mine[a], rank[a]);
+  for (int a = 0; a < PER; ++a) f(tid + a * nthreads < nb, mine[a], rank[a]);
+}
+
+// ---- workgroup-wide reservations in global counters.  Every thread of the
+// workgroup calls these together, and each counter takes one atomic per
+// workgroup: atomics from many workgroups on one cache line are serialised
+// in L2 (about 10 ns each), so an event's tens of thousands of firings or
+// newborns appended one atomic each would cost a few hundred microseconds
+// per counter. ----
+struct WgBins {
+  uint32_t cnt[kMaxColours];
+  uint32_t base[kMaxColours];
+};
+
+// a position in colour c's bin, counted in count[c], for each thread that
+// wants one (the others get 0)
+__device__ __forceinline__ uint32_t wg_reserve_bins(uint32_t *count, bool want, uint32_t c,
+                                                    WgBins &s) {
+  if (threadIdx.x < (uint32_t)kMaxColours) s.cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t local = want ? atomicAdd(&s.cnt[c], 1u) : 0u;
+  __syncthreads();
+  if (threadIdx.x < (uint32_t)kMaxColours && s.cnt[threadIdx.x])
+    s.base[threadIdx.x] = atomicAdd(&count[threadIdx.x], s.cnt[threadIdx.x]);
+  __syncthreads();
+  return want ? s.base[c] + local : 0u;
+}
+
+struct WgSlots {
+  uint32_t cnt, base;
+};
+
+// n consecutive slots of *counter for each thread (n may be 0)
+__device__ __forceinline__ uint32_t wg_reserve(uint32_t *counter, uint32_t n, WgSlots &s) {
+  if (threadIdx.x == 0) s.cnt = 0;
+  __syncthreads();
+  const uint32_t local = n ? atomicAdd(&s.cnt, n) : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0 && s.cnt) s.base = atomicAdd(counter, s.cnt);
+  __syncthreads();
+  return n ? s.base + local : 0u;
 }
 
 // The first-order pass's statistics, tallied in LDS by its workgroup and
@@ -110,77 +151,113 @@ struct FirstOrderTally {
   uint32_t fail;                    // placement failures
 };
 
-// one first-order firing of the molecule at (colour c, position pos): the
+// One first-order firing of the molecule at (colour c, position pos): the
 // first product stays in place, the others go to distinct vacant neighbours
-// chosen by the placement words; too few vacant neighbours: no change
-__device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in, uint32_t c,
-                                  uint32_t pos, uint32_t id, uint32_t rx, uint32_t *s_nb,
-                                  FirstOrderTally *T) {
-  const uint64_t at = c * L.cap + pos;
-  const uint32_t v = in.vox[at];
-  const uint32_t m = L.rx_nprod[rx];
-  const uint16_t *prod = L.rx_prod + rx * 12;
-  const uint32_t w0 = L.occ[v];
-  const uint32_t sp0 = w0 & kSpeciesBits;
-  const uint32_t comp = w0 & kCompBits;  // every product stays in this compartment
-  if (m == 0) {
-    L.occ[v] = (uint16_t)comp;
-    in.id[at] = kDeadId;
-    atomicSub(&T->dsp[sp0], 1);
-    atomicAdd(&T->fired[rx], 1u);
+// of its compartment chosen by the placement words; too few vacant
+// neighbours: no change.  Planned first (reads only), then committed with
+// the first of its newborns' slots, so that a workgroup can reserve the
+// slots of all its firings at once in between: the firings of one stage
+// touch disjoint closed neighbourhoods, so no firing's commit changes what
+// another's plan read.
+struct FoPlan {
+  uint64_t at;          // bin entry
+  uint32_t v, w0, rx, id, m;
+  bool ok;              // false: a placement failure
+  uint32_t dest[kMaxProducts - 1];
+};
+
+// the number of newborns the firing will have (its slots to reserve)
+__device__ __forceinline__ uint32_t plan_first_order(const LatDev &L, uint64_t e, const Bins &in,
+                                                     uint32_t c, uint32_t pos, uint32_t id,
+                                                     uint32_t rx, FoPlan &p) {
+  p.at = c * L.cap + pos;
+  p.v = in.vox[p.at];
+  p.rx = rx;
+  p.id = id;
+  p.m = L.rx_nprod[rx];
+  p.w0 = L.occ[p.v];
+  p.ok = true;
+  if (p.m <= 1) return 0;
+  const uint32_t comp = p.w0 & kCompBits;
+  uint32_t vac[12];
+  int nv = 0;
+  const Coord cv = coord_of(L.geo, p.v);
+  for (uint32_t n = 0; n < 12; ++n) {
+    Coord ct;
+    if (!step_target(L.geo, cv, n, ct)) continue;  // beyond a wall
+    const uint32_t t = index_of(L.geo, ct);
+    if (L.occ[t] == comp) vac[nv++] = t;  // vacant, same compartment
+  }
+  if (nv < (int)(p.m - 1)) {
+    p.ok = false;
+    return 0;
+  }
+  const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
+  for (uint32_t a = 0; a + 1 < p.m; ++a) {
+    const uint32_t x = scale32(placement_word(L, e, id, r, (int)a), (uint32_t)nv);
+    p.dest[a] = vac[x];
+    for (int y = (int)x; y + 1 < nv; ++y) vac[y] = vac[y + 1];
+    --nv;
+  }
+  return p.m - 1;
+}
+
+// b0: the first of the plan's newborn slots
+__device__ __forceinline__ void commit_first_order(const LatDev &L, const Bins &in,
+                                                   const FoPlan &p, uint32_t b0,
+                                                   FirstOrderTally *T) {
+  const uint32_t sp0 = p.w0 & kSpeciesBits;
+  const uint32_t comp = p.w0 & kCompBits;  // every product stays in this compartment
+  if (!p.ok) {
+    atomicAdd(&T->fail, 1u);
     return;
   }
-  uint32_t dest[kMaxProducts];
-  if (m > 1) {
-    uint32_t vac[12];
-    int nv = 0;
-    const Coord cv = coord_of(L.geo, v);
-    for (uint32_t n = 0; n < 12; ++n) {
-      Coord ct;
-      if (!step_target(L.geo, cv, n, ct)) continue;  // beyond a wall
-      const uint32_t t = index_of(L.geo, ct);
-      if (L.occ[t] == comp) vac[nv++] = t;  // vacant, same compartment
-    }
-    if (nv < (int)(m - 1)) {
-      atomicAdd(&T->fail, 1u);
-      return;
-    }
-    const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
-    for (uint32_t a = 0; a + 1 < m; ++a) {
-      const uint32_t x = scale32(placement_word(L, e, id, r, (int)a), (uint32_t)nv);
-      dest[a] = vac[x];
-      for (int y = (int)x; y + 1 < nv; ++y) vac[y] = vac[y + 1];
-      --nv;
-    }
-  }
-  L.occ[v] = (uint16_t)(prod[0] | comp);
-  in.sp[at] = (uint16_t)(prod[0] | comp);  // the entry stays; its cached word follows
+  atomicAdd(&T->fired[p.rx], 1u);
   atomicSub(&T->dsp[sp0], 1);
+  if (p.m == 0) {
+    L.occ[p.v] = (uint16_t)comp;
+    in.id[p.at] = kDeadId;
+    return;
+  }
+  const uint16_t *prod = L.rx_prod + p.rx * 12;
+  L.occ[p.v] = (uint16_t)(prod[0] | comp);
+  in.sp[p.at] = (uint16_t)(prod[0] | comp);  // the entry stays; its cached word follows
   atomicAdd(&T->dsp[prod[0] & 63u], 1);
-  for (uint32_t a = 0; a + 1 < m; ++a) {
-    L.occ[dest[a]] = (uint16_t)(prod[a + 1] | comp);
+  for (uint32_t a = 0; a + 1 < p.m; ++a) {
+    L.occ[p.dest[a]] = (uint16_t)(prod[a + 1] | comp);
     atomicAdd(&T->dsp[prod[a + 1] & 63u], 1);
-    const uint32_t b = atomicAdd(s_nb, 1u);
+    const uint32_t b = b0 + a;
     if (b < L.birth_cap) {
-      L.birth_key[b] = ((uint64_t)id << 31) | ((uint64_t)(a + 1) << 27) | b;
-      L.birth_vox[b] = dest[a];
+      L.birth_key[b] = ((uint64_t)p.id << 31) | ((uint64_t)(a + 1) << 27) | b;
+      L.birth_vox[b] = p.dest[a];
       L.birth_sp[b] = (uint16_t)(prod[a + 1] | comp);
     } else {
       atomicOr(L.error, kErrBirthOverflow);
     }
   }
-  atomicAdd(&T->fired[rx], 1u);
 }
 
-// A first-order newborn (key = parent id << 31 | product index << 27 | slot)
-// with id `id` joins the bins of the running event with its voxel's word
-// (newborns of the first-order pass walk in the same event).
-__device__ __forceinline__ void bin_first_order_birth(const LatDev &L, const Bins &in,
-                                                      uint64_t key, uint32_t id) {
+// plan and commit at once, newborn slots from *s_nb (LDS: one workgroup)
+__device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in,
+                                                  uint32_t c, uint32_t pos, uint32_t id,
+                                                  uint32_t rx, uint32_t *s_nb,
+                                                  FirstOrderTally *T) {
+  FoPlan p;
+  const uint32_t nb = plan_first_order(L, e, in, c, pos, id, rx, p);
+  commit_first_order(L, in, p, nb ? atomicAdd(s_nb, nb) : 0u, T);
+}
+
+// First-order newborns (key = parent id << 31 | product index << 27 | slot)
+// join the bins of the running event with their voxel's word (newborns of
+// the first-order pass walk in the same event): thread with `valid` bins the
+// newborn of key `key` with id `id`.  Called by the whole workgroup.
+__device__ __forceinline__ void bin_first_order_births(const LatDev &L, const Bins &in, bool valid,
+                                                       uint64_t key, uint32_t id, WgBins &wb) {
   const uint32_t src = (uint32_t)(key & ((1u << 27) - 1u));
-  const uint32_t v = L.birth_vox[src];
-  const uint32_t c = colour_of_voxel(L.geo, v);
-  const uint32_t pos = atomicAdd(&in.count[c], 1u);
+  const uint32_t v = valid ? L.birth_vox[src] : 0u;
+  const uint32_t c = valid ? colour_of_voxel(L.geo, v) : 0u;
+  const uint32_t pos = wg_reserve_bins(in.count, valid, c, wb);
+  if (!valid) return;
   if (pos < L.cap) {
     const uint64_t at = c * L.cap + pos;
     in.vox[at] = v;
@@ -196,10 +273,12 @@ __device__ __forceinline__ void bin_first_order_birth(const LatDev &L, const Bin
   }
 }
 
-// Ranks of nb distinct keys over the whole grid: f(key, rank) for each, rank
-// = the number of smaller keys.  Each thread ranks one key per pass against
-// every key, read through LDS in tiles; O(nb^2) comparisons spread over the
-// GPU, for events with more newborns than one workgroup ranks in LDS.
+// Ranks of nb distinct keys over the whole grid: f(true, key, rank) for
+// each, rank = the number of smaller keys.  Each thread ranks one key per
+// pass against every key, read through LDS in tiles; O(nb^2) comparisons
+// spread over the GPU, for events with more newborns than one workgroup
+// ranks in LDS.  Every thread of a workgroup calls f once per pass
+// (f(false, ...) past the end).
 constexpr uint32_t kRankTile = 2048;
 template <class F>
 __device__ __forceinline__ void rank_keys_grid(const uint64_t *keys, uint32_t nb, F f) {
@@ -217,7 +296,7 @@ __device__ __forceinline__ void rank_keys_grid(const uint64_t *keys, uint32_t nb
 #pragma unroll 8
       for (uint32_t j = 0; j < n; ++j) rank += tile[j] < mine ? 1u : 0u;
     }
-    if (q < nb) f(mine, rank);
+    f(q < nb, mine, rank);
   }
 }
 
@@ -235,12 +314,23 @@ __device__ __forceinline__ bool last_workgroup(uint32_t *done) {
   return true;
 }
 
-// First-order decisions of event e for candidates [first, ...) with the
-// given stride: a candidate whose voxel holds a species with first-order
-// reactions and whose draw falls under a cumulative threshold joins the fire
-// list, counted in *nfire (LDS inside one workgroup, else global memory).
-// Independent of order (a candidate's species cannot change before its own
-// turn), so any number of threads and workgroups may share the list.
+// The first-order reaction that the candidate at (colour c, position pos)
+// with id `id` fires in event e, or -1: a candidate whose voxel holds a
+// species with first-order reactions fires the reaction whose cumulative
+// threshold its draw falls under.  Independent of order (a candidate's
+// species cannot change before its own turn), so any number of threads and
+// workgroups may share the decisions of an event.
+__device__ __forceinline__ int first_order_decision(const LatDev &L, uint64_t e, const Bins &in,
+                                                    uint32_t c, uint32_t pos, uint32_t id) {
+  const uint32_t v = in.vox[c * L.cap + pos];
+  const uint32_t sp = L.occ[v] & kSpeciesBits;
+  if (!(L.sp_flags[sp] & kSpFirstOrder)) return -1;
+  const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
+  return first_order_choice(L, e, sp, r.x);
+}
+
+// the decisions of event e for candidates [first, ...) with the given
+// stride, by one workgroup: the fire list is counted in *nfire (LDS)
 __device__ __forceinline__ void decide_first_order(const LatDev &L, uint64_t e, uint32_t first,
                                                    uint32_t stride, uint32_t *nfire) {
   const uint32_t buf = (uint32_t)(e & 1);
@@ -248,11 +338,7 @@ __device__ __forceinline__ void decide_first_order(const LatDev &L, uint64_t e, 
   const uint32_t ncand = L.n_fo ? min(L.cand_count[buf], (uint32_t)L.cand_cap) : 0u;
   for (uint32_t q = first; q < ncand; q += stride) {
     const uint32_t c = L.cand_col[buf][q], pos = L.cand_pos[buf][q], id = L.cand_id[buf][q];
-    const uint32_t v = in.vox[c * L.cap + pos];
-    const uint32_t sp = L.occ[v] & kSpeciesBits;
-    if (!(L.sp_flags[sp] & kSpFirstOrder)) continue;
-    const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
-    const int rx = first_order_choice(L, e, sp, r.x);
+    const int rx = first_order_decision(L, e, in, c, pos, id);
     if (rx < 0) continue;
     const uint32_t slot = atomicAdd(nfire, 1u);
     L.fire_pos[slot] = pos;
@@ -404,7 +490,10 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
     if (tid == 0) set_error(L, kErrIds);
     return;
   }
-  auto bin_birth = [&](uint64_t key, uint32_t id) { bin_first_order_birth(L, in, key, id); };
+  __shared__ WgBins s_wb;
+  auto bin_birth = [&](bool valid, uint64_t key, uint32_t id) {
+    bin_first_order_births(L, in, valid, key, id, s_wb);
+  };
   if (nb > kSortLds && defer) {
     if (tid == 0) {
       *L.birth_count = nb;  // k_births numbers them and writes the stage descriptors
@@ -416,14 +505,18 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
     for (uint32_t q = tid; q < nb; q += blockDim.x) s_keys[q] = L.birth_key[q];
     __syncthreads();
     for_each_ranked<kSortLds / kBeginThreads>(
-        s_keys, nb, tid, kBeginThreads, [&](uint64_t k, uint32_t r) { bin_birth(k, base_id + r); });
+        s_keys, nb, tid, kBeginThreads,
+        [&](bool valid, uint64_t k, uint32_t r) { bin_birth(valid, k, base_id + r); });
   } else {
     uint32_t n2 = 1;
     while (n2 < nb) n2 <<= 1;
     for (uint32_t q = nb + tid; q < n2; q += blockDim.x) L.birth_key[q] = ~0ull;
     __syncthreads();
     bitonic_sort_keys(L.birth_key, n2, tid, blockDim.x);
-    for (uint32_t q = tid; q < nb; q += blockDim.x) bin_birth(L.birth_key[q], base_id + q);
+    for (uint32_t q0 = 0; q0 < nb; q0 += blockDim.x) {
+      const uint32_t q = q0 + tid;
+      bin_birth(q < nb, q < nb ? L.birth_key[q] : 0ull, base_id + q);
+    }
   }
   if (tid == 0) *L.next_id = base_id + nb;
 }
@@ -480,10 +573,16 @@ __global__ void __launch_bounds__(kBeginThreads) k_begin_multi(const LatDev *__r
 
 // Stage g of the first-order application over many workgroups (events with
 // many firings): every firing of the stage's colour, at once -- their closed
-// neighbourhoods are disjoint.  Newborns take slots from *birth_count.
+// neighbourhoods are disjoint.  A workgroup takes kFoTile entries of the
+// fire list per pass and gathers those of the stage's colour in LDS, so its
+// lanes work on firings, not on skipped entries; newborns take slots from
+// *birth_count, one reservation per workgroup and pass.
 __global__ void __launch_bounds__(kStageThreads) k_fo_stage(const LatDev *__restrict__ Lp,
                                                             uint32_t g) {
   __shared__ FirstOrderTally T;
+  __shared__ uint32_t s_idx[kFoTile];
+  __shared__ uint32_t s_n;
+  __shared__ WgSlots s_slots;
   const uint32_t tid = threadIdx.x;
   if (tid == 0) T.fail = 0;
   if (tid < 64) T.dsp[tid] = 0;
@@ -495,10 +594,27 @@ __global__ void __launch_bounds__(kStageThreads) k_fo_stage(const LatDev *__rest
   const uint32_t nfire = min(*L.fire_count, (uint32_t)L.cap);
   const uint32_t cg = L.perm[g];
   const Bins &in = L.bins[e & 1];
-  for (uint32_t q = blockIdx.x * blockDim.x + tid; q < nfire; q += gridDim.x * blockDim.x)
-    if (L.fire_col[q] == cg)
-      apply_first_order(L, e, in, cg, L.fire_pos[q], L.fire_id[q], L.fire_rx[q], L.birth_count, &T);
-  __syncthreads();
+  for (uint32_t t0 = blockIdx.x * kFoTile; t0 < nfire; t0 += gridDim.x * kFoTile) {
+    const uint32_t t1 = min(t0 + kFoTile, nfire);
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    for (uint32_t q = t0 + tid; q < t1; q += blockDim.x)
+      if (L.fire_col[q] == cg) s_idx[atomicAdd(&s_n, 1u)] = q;
+    __syncthreads();
+    const uint32_t n = s_n;
+    for (uint32_t k0 = 0; k0 < n; k0 += blockDim.x) {
+      const uint32_t k = k0 + tid;
+      FoPlan p;
+      uint32_t nb = 0;
+      if (k < n) {
+        const uint32_t q = s_idx[k];
+        nb = plan_first_order(L, e, in, cg, L.fire_pos[q], L.fire_id[q], L.fire_rx[q], p);
+      }
+      const uint32_t b0 = wg_reserve(L.birth_count, nb, s_slots);
+      if (k < n) commit_first_order(L, in, p, b0, &T);
+    }
+    __syncthreads();  // s_idx and s_n serve the next pass
+  }
   if (tid < 64 && T.dsp[tid]) atomicAdd(&stat_sp(L)[tid], (unsigned long long)(long long)T.dsp[tid]);
   for (uint32_t r = tid; r < L.n_rx; r += blockDim.x)
     if (T.fired[r]) atomicAdd(&stat_fired(L)[r], (unsigned long long)T.fired[r]);
@@ -522,9 +638,10 @@ __global__ void __launch_bounds__(kStageThreads) k_births(const LatDev *__restri
     if (blockIdx.x == 0 && threadIdx.x == 0) set_error(L, kErrIds);
     nb = 0;
   }
+  __shared__ WgBins s_wb;
   if (nb)
-    rank_keys_grid(L.birth_key, nb, [&](uint64_t k, uint32_t r) {
-      bin_first_order_birth(L, in, k, base_id + r);
+    rank_keys_grid(L.birth_key, nb, [&](bool valid, uint64_t k, uint32_t r) {
+      bin_first_order_births(L, in, valid, k, base_id + r, s_wb);
     });
   if (!last_workgroup(L.end_done)) return;
   if (threadIdx.x == 0) {
@@ -537,12 +654,33 @@ __global__ void __launch_bounds__(kStageThreads) k_births(const LatDev *__restri
 
 // the first-order decisions of the coming event over many workgroups, for
 // events with many candidates (k_begin then only applies the fire list)
+// (the fire list grows by one reservation per workgroup and pass)
 __global__ void __launch_bounds__(kStageThreads) k_decide(const LatDev *__restrict__ Lp) {
+  __shared__ WgSlots s_slots;
   const LatDev &L = *Lp;
   const uint64_t e = *L.ev;
   if (e >= L.stop_event || e >= L.tape_horizon) return;
-  decide_first_order(L, e, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
-                     L.fire_count);
+  const uint32_t buf = (uint32_t)(e & 1);
+  const Bins &in = L.bins[buf];
+  const uint32_t ncand = L.n_fo ? min(L.cand_count[buf], (uint32_t)L.cand_cap) : 0u;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < ncand; base += gridDim.x * blockDim.x) {
+    const uint32_t q = base + threadIdx.x;
+    uint32_t c = 0, pos = 0, id = 0;
+    int rx = -1;
+    if (q < ncand) {
+      c = L.cand_col[buf][q];
+      pos = L.cand_pos[buf][q];
+      id = L.cand_id[buf][q];
+      rx = first_order_decision(L, e, in, c, pos, id);
+    }
+    const uint32_t slot = wg_reserve(L.fire_count, rx >= 0 ? 1u : 0u, s_slots);
+    if (rx >= 0 && slot < L.cap) {
+      L.fire_pos[slot] = pos;
+      L.fire_id[slot] = id;
+      L.fire_col[slot] = (uint8_t)c;
+      L.fire_rx[slot] = (uint8_t)rx;
+    }
+  }
 }
 
 // =============================================================================
@@ -565,37 +703,46 @@ constexpr int kEndBlocksMulti = 1;
 // a newborn of event e's many-product collisions (key = mover id << 32 |
 // product index << 28 | slot) with id `id` joins the next event's bins and
 // is tested as a first-order candidate of that event
+// (called by the whole workgroup; threads without `valid` only help with
+// the reservations)
+struct WgBirthBins {
+  WgBins bins;
+  WgSlots cand;
+};
 __device__ __forceinline__ void bin_collision_birth(const LatDev &L, uint64_t e, const Bins &out,
                                                     uint32_t cnext, uint32_t cmax_next,
-                                                    uint64_t key, uint32_t id) {
-  const uint32_t u = L.wb_vox[key & ((1u << 28) - 1u)];
-  const uint32_t c = colour_of_voxel(L.geo, u);
-  const uint32_t pos = atomicAdd(&out.count[c], 1u);
-  if (pos >= L.cap) {
-    set_error(L, kErrBinOverflow);
-    return;
-  }
-  const uint64_t at = c * L.cap + pos;
-  out.vox[at] = u;
-  out.id[at] = id;
-  out.sp[at] = (uint16_t)(L.occ[u] & kWordMask);
-  if (out.disp) {
-    out.disp[(0 * L.ncol + c) * L.cap + pos] = 0;
-    out.disp[(1 * L.ncol + c) * L.cap + pos] = 0;
-    out.disp[(2 * L.ncol + c) * L.cap + pos] = 0;
-  }
-  if (cmax_next) {
-    const U4 r = philox((uint32_t)(e + 1), id, kPhaseFirst, 0, L.key0, L.key1);
-    if (r.x < cmax_next) {
-      const uint32_t k = atomicAdd(&L.cand_count[cnext], 1u);
-      if (k < L.cand_cap) {
-        L.cand_pos[cnext][k] = pos;
-        L.cand_id[cnext][k] = id;
-        L.cand_col[cnext][k] = (uint8_t)c;
-      } else {
-        set_error(L, kErrCandOverflow);
-      }
+                                                    bool valid, uint64_t key, uint32_t id,
+                                                    WgBirthBins &wb) {
+  const uint32_t u = valid ? L.wb_vox[key & ((1u << 28) - 1u)] : 0u;
+  const uint32_t c = valid ? colour_of_voxel(L.geo, u) : 0u;
+  const uint32_t pos = wg_reserve_bins(out.count, valid, c, wb.bins);
+  const bool binned = valid && pos < L.cap;
+  if (valid && !binned) set_error(L, kErrBinOverflow);
+  if (binned) {
+    const uint64_t at = c * L.cap + pos;
+    out.vox[at] = u;
+    out.id[at] = id;
+    out.sp[at] = (uint16_t)(L.occ[u] & kWordMask);
+    if (out.disp) {
+      out.disp[(0 * L.ncol + c) * L.cap + pos] = 0;
+      out.disp[(1 * L.ncol + c) * L.cap + pos] = 0;
+      out.disp[(2 * L.ncol + c) * L.cap + pos] = 0;
     }
+  }
+  if (!cmax_next) return;  // uniform: no first-order reactions next event
+  bool cand = false;
+  if (binned) {
+    const U4 r = philox((uint32_t)(e + 1), id, kPhaseFirst, 0, L.key0, L.key1);
+    cand = r.x < cmax_next;
+  }
+  const uint32_t k = wg_reserve(&L.cand_count[cnext], cand ? 1u : 0u, wb.cand);
+  if (!cand) return;
+  if (k < L.cand_cap) {
+    L.cand_pos[cnext][k] = pos;
+    L.cand_id[cnext][k] = id;
+    L.cand_col[cnext][k] = (uint8_t)c;
+  } else {
+    set_error(L, kErrCandOverflow);
   }
 }
 
@@ -614,21 +761,26 @@ __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
   const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
   // the newborn of key `key` gets id `id` (keys are distinct: they end in the
   // slot; its id is next_id plus the number of smaller keys)
-  auto bin_newborn = [&](uint64_t key, uint32_t id) {
-    bin_collision_birth(L, e, out, cnext, cmax_next, key, id);
+  __shared__ WgBirthBins s_wb;
+  auto bin_newborn = [&](bool valid, uint64_t key, uint32_t id) {
+    bin_collision_birth(L, e, out, cnext, cmax_next, valid, key, id, s_wb);
   };
   if (nb <= kSortLds) {
     for (uint32_t q = tid; q < nb; q += blockDim.x) s_wkeys[q] = L.wb_key[q];
     __syncthreads();
     for_each_ranked<kSortLds / kEndThreads>(
-        s_wkeys, nb, tid, kEndThreads, [&](uint64_t k, uint32_t r) { bin_newborn(k, base_id + r); });
+        s_wkeys, nb, tid, kEndThreads,
+        [&](bool valid, uint64_t k, uint32_t r) { bin_newborn(valid, k, base_id + r); });
   } else {
     uint32_t n2 = 1;
     while (n2 < nb) n2 <<= 1;  // <= wb_cap, a power of two
     for (uint32_t q = nb + tid; q < n2; q += blockDim.x) L.wb_key[q] = ~0ull;
     __syncthreads();
     bitonic_sort_keys(L.wb_key, n2, tid, blockDim.x);
-    for (uint32_t q = tid; q < nb; q += blockDim.x) bin_newborn(L.wb_key[q], base_id + q);
+    for (uint32_t q0 = 0; q0 < nb; q0 += blockDim.x) {
+      const uint32_t q = q0 + tid;
+      bin_newborn(q < nb, q < nb ? L.wb_key[q] : 0ull, base_id + q);
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -712,8 +864,9 @@ __global__ void __launch_bounds__(kStageThreads) k_end_births(const LatDev *__re
   const Bins &out = L.bins[(e + 1) & 1];
   const uint32_t cnext = (uint32_t)((e + 1) & 1);
   const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
-  rank_keys_grid(L.wb_key, nb, [&](uint64_t k, uint32_t r) {
-    bin_collision_birth(L, e, out, cnext, cmax_next, k, base_id + r);
+  __shared__ WgBirthBins s_wb;
+  rank_keys_grid(L.wb_key, nb, [&](bool valid, uint64_t k, uint32_t r) {
+    bin_collision_birth(L, e, out, cnext, cmax_next, valid, k, base_id + r, s_wb);
   });
   if (!last_workgroup(L.end_done)) return;
   if (threadIdx.x == 0) {

@@ -364,7 +364,8 @@ struct LatDev {
   uint32_t *flag_count;   // [2]
   uint64_t flag_cap;
 
-  // first-order newborns of one event: key = parent id << 4 | product index
+  // first-order newborns of one event: key = parent id << 31 | product
+  // index << 27 | slot
   uint64_t *birth_key;
   uint32_t *birth_vox;
   uint16_t *birth_sp;
@@ -379,6 +380,13 @@ struct LatDev {
   uint64_t *wb_key;
   uint32_t *wb_count;
   uint64_t wb_cap;
+
+  // ranking of many newborns over the grid (null when no reaction has
+  // newborns): bucket counts (zero between uses), their exclusive prefix
+  // sums, and the keys dealt into bucket order
+  uint32_t *rank_hist;    // [kRankBucketsMax]
+  uint32_t *rank_off;     // [kRankBucketsMax + 1]
+  uint64_t *rank_keys;    // [birth_cap]
 
   // stale-entry filter (see hot_hash)
   uint32_t *hot;          // [2^hot_bits / 16] words
@@ -451,6 +459,8 @@ struct BeginShape {
 };
 // fire-list entries an application workgroup scans per pass
 constexpr uint32_t kFoTile = 2048;
+// most buckets of the grid-wide newborn ranking
+constexpr uint32_t kRankBucketsMax = 65536;
 // births: the lattice (any member) has collision reactions with more than
 // two products, whose newborns the event end numbers
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,

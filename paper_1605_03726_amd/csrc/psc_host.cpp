@@ -355,6 +355,13 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
     L.wb_key = alloc_n<uint64_t>(h, L.wb_cap);
     L.wb_count = alloc_n<uint32_t>(h, 1);
   }
+  if (collision_births || h->fo_extra_max) {
+    L.rank_hist = alloc_n<uint32_t>(h, kRankBucketsMax);
+    L.rank_off = alloc_n<uint32_t>(h, kRankBucketsMax + 1);
+    L.rank_keys = alloc_n<uint64_t>(h, L.birth_cap);
+    if (!L.rank_hist || !L.rank_off || !L.rank_keys)
+      return fail(h, PSC_ENOMEM, "device allocation of the newborn ranking failed");
+  }
   {
     uint32_t bits = 16;
     while (bits < 24 && (1ull << bits) < cap / 4) ++bits;
@@ -499,6 +506,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   HIP_OK(h, hipMemset(L.fired, 0, (uint64_t)kStatRep * L.fired_stride * sizeof(unsigned long long)));
   HIP_OK(h, hipMemset(L.error, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.end_done, 0, sizeof(uint32_t)));
+  if (L.rank_hist) HIP_OK(h, hipMemset(L.rank_hist, 0, kRankBucketsMax * sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.nbr_cnt, 0, (1ull << L.nbr_bits) * sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.hot, 0, (1ull << L.hot_bits) / 4));
   HIP_OK(h, up(L.ev, &h->event0, sizeof(uint64_t)));
@@ -556,6 +564,9 @@ uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool dis
   const uint64_t bcap = std::min<uint64_t>(pow2_at_least(cap), 1ull << 27);
   t += r(bcap * 8) + r(bcap * 4) + r(bcap * 2) + r(4);
   if (collision_births) t += r(bcap * 4) + r(bcap * 8) + r(4);
+  // the newborn ranking (first-order reactions with several products are
+  // not known here: counted whenever the model has reactions)
+  if (n_reactions) t += r(kRankBucketsMax * 4) + r((kRankBucketsMax + 1) * 4) + r(bcap * 8);
   uint32_t hb = 16;
   while (hb < 24 && (1ull << hb) < cap / 4) ++hb;
   t += r((1ull << hb) / 4) + r(4);
@@ -969,16 +980,16 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
     return (int)std::min(std::ceil(expect / 512.0), 1024.0);
   };
   // Newborns of the first-order pass are ranked by k_begin alone up to the
-  // LDS limit; an event expecting more than half of that (its largest
-  // threshold times the walkers times the most extra products) gets a
-  // ranking launch of its own, sized for twice the expectation.  A smaller
-  // expectation that is exceeded falls back to k_begin's slower sort.
+  // LDS limit (2048); an event whose bound on them (its expected candidates
+  // times the most extra products of a firing) reaches twice that gets the
+  // grid-wide ranking, a thread per bounded newborn.  Events under the bound
+  // that exceed the limit fall back to k_begin's slower sort.
   auto births_grid = [&](uint64_t e) -> int {
     if (!h->fo_extra_max) return 0;
     const double expect = (double)h->tape_cmax[e] * (1.0 / 4294967296.0) *
                           (double)h->walkers0 * (double)h->fo_extra_max;
-    if (expect < 1024.0) return 0;
-    return (int)std::min(std::ceil(2.0 * expect / 256.0), 2048.0);
+    if (expect < 4096.0) return 0;
+    return (int)std::min(std::ceil(expect / 256.0), 2048.0);
   };
   // An event whose decisions get a launch of their own may fire more
   // first-order reactions than k_begin has threads (the candidates bound the

@@ -273,33 +273,6 @@ __device__ __forceinline__ void bin_first_order_births(const LatDev &L, const Bi
   }
 }
 
-// Ranks of nb distinct keys over the whole grid: f(true, key, rank) for
-// each, rank = the number of smaller keys.  Each thread ranks one key per
-// pass against every key, read through LDS in tiles; O(nb^2) comparisons
-// spread over the GPU, for events with more newborns than one workgroup
-// ranks in LDS.  Every thread of a workgroup calls f once per pass
-// (f(false, ...) past the end).
-constexpr uint32_t kRankTile = 2048;
-template <class F>
-__device__ __forceinline__ void rank_keys_grid(const uint64_t *keys, uint32_t nb, F f) {
-  __shared__ uint64_t tile[kRankTile];
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < nb; base += stride) {
-    const uint32_t q = base + threadIdx.x;
-    const uint64_t mine = q < nb ? keys[q] : ~0ull;
-    uint32_t rank = 0;
-    for (uint32_t t0 = 0; t0 < nb; t0 += kRankTile) {
-      const uint32_t n = min(kRankTile, nb - t0);
-      __syncthreads();
-      for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) tile[j] = keys[t0 + j];
-      __syncthreads();
-#pragma unroll 8
-      for (uint32_t j = 0; j < n; ++j) rank += tile[j] < mine ? 1u : 0u;
-    }
-    f(q < nb, mine, rank);
-  }
-}
-
 // The last of the grid's workgroups to call this returns true (counted in
 // *done, which it resets); after a device-scope fence it sees the others'
 // atomics.
@@ -312,6 +285,107 @@ __device__ __forceinline__ bool last_workgroup(uint32_t *done) {
   __threadfence();
   if (threadIdx.x == 0) *done = 0;
   return true;
+}
+
+// ---- ranking of many distinct keys over the grid.  A key's owner id (key
+// >> shift) deals it into one of nbk buckets that split [0, id_end) into
+// equal ranges, so the buckets follow the key order, and a key's rank (the
+// number of smaller keys) is its bucket's offset plus the number of smaller
+// keys in its bucket.  Owner ids spread over the range, and nbk is the power
+// of two at least nb (at most kRankBucketsMax): about one key per bucket.
+// Three launches: k_rank_count (whose last workgroup turns the counts into
+// offsets), k_rank_deal, then the numbering kernel, which ranks with
+// rank_dealt.  List 0: the first-order newborns left to the grid; list 1:
+// the collision newborns left by the event end. ----
+struct RankList {
+  const uint64_t *keys;
+  uint32_t nb, shift, id_end, nbk;
+};
+
+__device__ __forceinline__ RankList make_rank_list(const uint64_t *keys, uint32_t nb,
+                                                   uint32_t shift, uint32_t id_end) {
+  RankList R{keys, nb, shift, max(id_end, 1u), 1u};
+  while (R.nbk < nb && R.nbk < kRankBucketsMax) R.nbk <<= 1;
+  return R;
+}
+
+template <int LIST>
+__device__ __forceinline__ RankList rank_list(const LatDev &L) {
+  if (LIST == 0)
+    return make_rank_list(L.birth_key, min(*L.birth_count, (uint32_t)L.birth_cap), 31, *L.next_id);
+  return make_rank_list(L.wb_key, min(*L.wb_count, (uint32_t)L.wb_cap), 32, *L.next_id);
+}
+
+__device__ __forceinline__ uint32_t rank_bucket(const RankList &R, uint64_t key) {
+  const uint64_t id = key >> R.shift;  // < id_end: owners exist before the numbering
+  return (uint32_t)min(id * R.nbk / R.id_end, (uint64_t)(R.nbk - 1u));
+}
+
+template <int LIST>
+__global__ void __launch_bounds__(kStageThreads) k_rank_count(const LatDev *__restrict__ Lp) {
+  __shared__ uint32_t s_sum[kStageThreads];
+  const LatDev &L = *Lp;
+  const RankList R = rank_list<LIST>(L);
+  if (R.nb == 0 || (LIST == 1 && R.nb <= kSortLds)) return;  // nothing left to the grid
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < R.nb; q += gridDim.x * blockDim.x)
+    atomicAdd(&L.rank_hist[rank_bucket(R, R.keys[q])], 1u);
+  if (!last_workgroup(L.end_done)) return;
+  // the last workgroup: exclusive prefix sums of the counts, each thread
+  // over a run of per buckets (read through L2: other workgroups' atomics)
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (R.nbk + blockDim.x - 1) / blockDim.x;
+  const uint32_t b0 = min(tid * per, R.nbk), b1 = min(b0 + per, R.nbk);
+  uint32_t sum = 0;
+  for (uint32_t b = b0; b < b1; ++b)
+    sum += __hip_atomic_load(&L.rank_hist[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  s_sum[tid] = sum;
+  __syncthreads();
+  for (uint32_t d = 1; d < blockDim.x; d <<= 1) {
+    const uint32_t add = tid >= d ? s_sum[tid - d] : 0u;
+    __syncthreads();
+    s_sum[tid] += add;
+    __syncthreads();
+  }
+  uint32_t run = s_sum[tid] - sum;
+  for (uint32_t b = b0; b < b1; ++b) {
+    L.rank_off[b] = run;
+    run += __hip_atomic_load(&L.rank_hist[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (tid == 0) L.rank_off[R.nbk] = R.nb;
+}
+
+// deals the keys into bucket order; the counts return to zero
+template <int LIST>
+__global__ void __launch_bounds__(kStageThreads) k_rank_deal(const LatDev *__restrict__ Lp) {
+  const LatDev &L = *Lp;
+  const RankList R = rank_list<LIST>(L);
+  if (R.nb == 0 || (LIST == 1 && R.nb <= kSortLds)) return;
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < R.nb; q += gridDim.x * blockDim.x) {
+    const uint64_t key = R.keys[q];
+    const uint32_t b = rank_bucket(R, key);
+    const uint32_t k = atomicSub(&L.rank_hist[b], 1u) - 1u;
+    L.rank_keys[L.rank_off[b] + k] = key;
+  }
+}
+
+// f(true, key, rank) for every dealt key; every thread of a workgroup calls
+// f once per pass (f(false, ...) past the end)
+template <class F>
+__device__ __forceinline__ void rank_dealt(const LatDev &L, const RankList &R, F f) {
+  for (uint32_t base = blockIdx.x * blockDim.x; base < R.nb; base += gridDim.x * blockDim.x) {
+    const uint32_t p = base + threadIdx.x;
+    const bool valid = p < R.nb;
+    uint64_t key = 0;
+    uint32_t rank = 0;
+    if (valid) {
+      key = L.rank_keys[p];
+      const uint32_t b = rank_bucket(R, key);
+      const uint32_t lo = L.rank_off[b], hi = L.rank_off[b + 1];
+      rank = lo;
+      for (uint32_t j = lo; j < hi; ++j) rank += L.rank_keys[j] < key ? 1u : 0u;
+    }
+    f(valid, key, rank);
+  }
 }
 
 // The first-order reaction that the candidate at (colour c, position pos)
@@ -629,18 +703,19 @@ __global__ void __launch_bounds__(kStageThreads) k_fo_stage(const LatDev *__rest
 __global__ void __launch_bounds__(kStageThreads) k_births(const LatDev *__restrict__ Lp,
                                                           int finish) {
   const LatDev &L = *Lp;
-  uint32_t nb = min(*L.birth_count, (uint32_t)L.birth_cap);
-  if (nb == 0 && !finish) return;  // k_begin numbered this event's newborns (or had none)
+  RankList R = rank_list<0>(L);
+  if (R.nb == 0 && !finish) return;  // k_begin numbered this event's newborns (or had none)
   const uint64_t e = *L.ev;
   const Bins &in = L.bins[e & 1];
   const uint32_t base_id = *L.next_id;
-  if ((uint64_t)base_id + nb >= 0xFFFFFFFFull) {
+  if ((uint64_t)base_id + R.nb >= 0xFFFFFFFFull) {
     if (blockIdx.x == 0 && threadIdx.x == 0) set_error(L, kErrIds);
-    nb = 0;
+    R.nb = 0;
   }
+  const uint32_t nb = R.nb;
   __shared__ WgBins s_wb;
   if (nb)
-    rank_keys_grid(L.birth_key, nb, [&](bool valid, uint64_t k, uint32_t r) {
+    rank_dealt(L, R, [&](bool valid, uint64_t k, uint32_t r) {
       bin_first_order_births(L, in, valid, k, base_id + r, s_wb);
     });
   if (!last_workgroup(L.end_done)) return;
@@ -853,7 +928,8 @@ __global__ void __launch_bounds__(kEndThreads) k_end_multi(const LatDev *__restr
 // has advanced the event counter: the walk was event *ev - 1.
 __global__ void __launch_bounds__(kStageThreads) k_end_births(const LatDev *__restrict__ Lp) {
   const LatDev &L = *Lp;
-  const uint32_t nb = min(*L.wb_count, (uint32_t)L.wb_cap);
+  const RankList R = rank_list<1>(L);
+  const uint32_t nb = R.nb;
   if (nb == 0) return;  // numbered by k_end, or none
   const uint64_t e = *L.ev - 1;
   const uint32_t base_id = *L.next_id;
@@ -865,7 +941,7 @@ __global__ void __launch_bounds__(kStageThreads) k_end_births(const LatDev *__re
   const uint32_t cnext = (uint32_t)((e + 1) & 1);
   const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
   __shared__ WgBirthBins s_wb;
-  rank_keys_grid(L.wb_key, nb, [&](bool valid, uint64_t k, uint32_t r) {
+  rank_dealt(L, R, [&](bool valid, uint64_t k, uint32_t r) {
     bin_collision_birth(L, e, out, cnext, cmax_next, valid, k, base_id + r, s_wb);
   });
   if (!last_workgroup(L.end_done)) return;
@@ -940,6 +1016,10 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+// workgroups of the count and deal launches of the newborn ranking (a
+// grid-stride pass each; the count's last workgroup waits on all of them)
+constexpr int kRankGrid = 256;
+
 hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t s) {
   if (b.decide > 0) hipLaunchKernelGGL(k_decide, dim3(b.decide), dim3(kStageThreads), 0, s, dL);
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, b.decide > 0 ? 1 : 0,
@@ -947,9 +1027,13 @@ hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, 
   if (b.apply > 0)
     for (uint32_t g = 0; g < stages; ++g)
       hipLaunchKernelGGL(k_fo_stage, dim3(b.apply), dim3(kStageThreads), 0, s, dL, g);
-  if (b.births > 0 || b.apply > 0)
-    hipLaunchKernelGGL(k_births, dim3(b.births > 0 ? b.births : 1), dim3(kStageThreads), 0, s, dL,
-                       b.apply > 0 ? 1 : 0);
+  if (b.births > 0 || b.apply > 0) {
+    const int grid = b.births > 0 ? b.births : 1;
+    const int rank_grid = std::min(grid, kRankGrid);
+    hipLaunchKernelGGL(k_rank_count<0>, dim3(rank_grid), dim3(kStageThreads), 0, s, dL);
+    hipLaunchKernelGGL(k_rank_deal<0>, dim3(rank_grid), dim3(kStageThreads), 0, s, dL);
+    hipLaunchKernelGGL(k_births, dim3(grid), dim3(kStageThreads), 0, s, dL, b.apply > 0 ? 1 : 0);
+  }
   return hipGetLastError();
 }
 
@@ -959,13 +1043,15 @@ hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool 
              : launch_stage_lat<0>(dL, g, grid, items, disp, s);
 }
 
-// grid of the ranking of many collision newborns (a pass ranks this many
+// grid of the numbering of many collision newborns (a pass ranks this many
 // times 256 keys; further ones take more passes)
 constexpr int kEndBirthsGrid = 512;
 
 hipError_t launch_end(const LatDev *dL, bool births, hipStream_t s) {
   if (births) {
     hipLaunchKernelGGL(k_end<true>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL, 1);
+    hipLaunchKernelGGL(k_rank_count<1>, dim3(kRankGrid), dim3(kStageThreads), 0, s, dL);
+    hipLaunchKernelGGL(k_rank_deal<1>, dim3(kRankGrid), dim3(kStageThreads), 0, s, dL);
     hipLaunchKernelGGL(k_end_births, dim3(kEndBirthsGrid), dim3(kStageThreads), 0, s, dL);
   } else {
     hipLaunchKernelGGL(k_end<false>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL, 0);

@@ -459,8 +459,8 @@ struct BeginShape {
 };
 // fire-list entries an application workgroup scans per pass
 constexpr uint32_t kFoTile = 2048;
-// most buckets of the grid-wide newborn ranking
-constexpr uint32_t kRankBucketsMax = 65536;
+// most buckets of the grid-wide newborn ranking (their counts fit in LDS)
+constexpr uint32_t kRankBucketsMax = 8192;
 // births: the lattice (any member) has collision reactions with more than
 // two products, whose newborns the event end numbers
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,

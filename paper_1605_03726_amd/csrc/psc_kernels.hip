@@ -292,7 +292,7 @@ __device__ __forceinline__ bool last_workgroup(uint32_t *done) {
 // equal ranges, so the buckets follow the key order, and a key's rank (the
 // number of smaller keys) is its bucket's offset plus the number of smaller
 // keys in its bucket.  Owner ids spread over the range, and nbk is the power
-// of two at least nb (at most kRankBucketsMax): about one key per bucket.
+// of two at least nb / 4 (at most kRankBucketsMax): a few keys per bucket.
 // Three launches: k_rank_count (whose last workgroup turns the counts into
 // offsets), k_rank_deal, then the numbering kernel, which ranks with
 // rank_dealt.  List 0: the first-order newborns left to the grid; list 1:
@@ -305,7 +305,7 @@ struct RankList {
 __device__ __forceinline__ RankList make_rank_list(const uint64_t *keys, uint32_t nb,
                                                    uint32_t shift, uint32_t id_end) {
   RankList R{keys, nb, shift, max(id_end, 1u), 1u};
-  while (R.nbk < nb && R.nbk < kRankBucketsMax) R.nbk <<= 1;
+  while (R.nbk * 4u < nb && R.nbk < kRankBucketsMax) R.nbk <<= 1;
   return R;
 }
 
@@ -324,20 +324,24 @@ __device__ __forceinline__ uint32_t rank_bucket(const RankList &R, uint64_t key)
 template <int LIST>
 __global__ void __launch_bounds__(kStageThreads) k_rank_count(const LatDev *__restrict__ Lp) {
   __shared__ uint32_t s_sum[kStageThreads];
+  __shared__ uint32_t s_hist[kRankBucketsMax];
   const LatDev &L = *Lp;
   const RankList R = rank_list<LIST>(L);
   if (R.nb == 0 || (LIST == 1 && R.nb <= kSortLds)) return;  // nothing left to the grid
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < R.nb; q += gridDim.x * blockDim.x)
     atomicAdd(&L.rank_hist[rank_bucket(R, R.keys[q])], 1u);
   if (!last_workgroup(L.end_done)) return;
-  // the last workgroup: exclusive prefix sums of the counts, each thread
-  // over a run of per buckets (read through L2: other workgroups' atomics)
+  // the last workgroup: exclusive prefix sums of the counts.  They are read
+  // through L2 (other workgroups' atomics), a coalesced row per pass, into
+  // LDS; each thread then sums a run of per buckets.
   const uint32_t tid = threadIdx.x;
+  for (uint32_t b = tid; b < R.nbk; b += blockDim.x)
+    s_hist[b] = __hip_atomic_load(&L.rank_hist[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
   const uint32_t per = (R.nbk + blockDim.x - 1) / blockDim.x;
   const uint32_t b0 = min(tid * per, R.nbk), b1 = min(b0 + per, R.nbk);
   uint32_t sum = 0;
-  for (uint32_t b = b0; b < b1; ++b)
-    sum += __hip_atomic_load(&L.rank_hist[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t b = b0; b < b1; ++b) sum += s_hist[b];
   s_sum[tid] = sum;
   __syncthreads();
   for (uint32_t d = 1; d < blockDim.x; d <<= 1) {
@@ -348,9 +352,12 @@ __global__ void __launch_bounds__(kStageThreads) k_rank_count(const LatDev *__re
   }
   uint32_t run = s_sum[tid] - sum;
   for (uint32_t b = b0; b < b1; ++b) {
-    L.rank_off[b] = run;
-    run += __hip_atomic_load(&L.rank_hist[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t n = s_hist[b];
+    s_hist[b] = run;
+    run += n;
   }
+  __syncthreads();
+  for (uint32_t b = tid; b < R.nbk; b += blockDim.x) L.rank_off[b] = s_hist[b];
   if (tid == 0) L.rank_off[R.nbk] = R.nb;
 }
 

@@ -631,3 +631,60 @@ def test_second_order_reaction_limited_rate_at_scale():
     ratio = float((inv * ts).sum() / (ts * ts).sum()) * V / kf
     expect = 1.0 / (1.0 + p * (1.345 - 1.0))
     assert abs(ratio / expect - 1.0) < 0.03, (ratio, expect)
+
+
+def reversible_workload(dims, n0, kf, kb, seed, events):
+    """B + C <-> A (3.2.2): D = 10 um^2/s, r = 5 nm, A alone at the start"""
+    return dict(name="reversible", dims=dims, rv=5e-9, seed=seed,
+                species=[("A", 10e-12), ("B", 10e-12), ("C", 10e-12)],
+                reactions=[((2, 3), (1,), kf), ((1,), (2, 3), kb)],
+                place=[(1, n0)], events=events)
+
+
+def test_reversible_reaction_equals_the_oracle():
+    """B + C <-> A on 48^3 voxels from 4,000 A over 150 events, rates set
+    (k_b tau = 1/600) so that about 950 A dissociate and, as B and C build
+    up, a few dozen pairs associate."""
+    rv, D, dims, n0 = 5e-9, 10e-12, (48, 48, 48), 4000
+    V = dims[0] * dims[1] * dims[2] * 4.0 * np.sqrt(2.0) * rv ** 3
+    kb = 3.0 * D / (2.0 * rv * rv) / 600.0
+    w = reversible_workload(dims, n0, kb * V / (n0 / 2), kb, 43, 150)
+    g, s = run_pair(w, 150, chunks=3, max_molecules=2 * n0 + 1024)
+    assert s["fired"][0] > 20 and s["fired"][1] > 500, s["fired"]
+
+
+@pytest.mark.timeout(600)
+def test_reversible_reaction_equilibrium_at_scale():
+    """The reversible check of 3.2.2 at the paper's parameters (k_f = 0.027
+    1/(nM s), k_b = 1.35 1/s, D = 10 um^2/s, r = 5 nm, 64,000 A to start:
+    the text's 0, 0, 64,000 for A, B, C cannot react, its figure's caption
+    has A dissociating) on an eighth of its 1000 x 960 x 1100 lattice
+    (500 x 480 x 552) with both rate constants times 4 (p = 0.21), so that
+    the relaxation takes about 12,000 events instead of a few hundred
+    thousand.  The equilibrium is where the mean fluxes balance,
+    k_f <N_B N_C> / V = k_b <N_A>, which this volume puts at about 51,800 A
+    and 12,200 B and C.  After 60,000 events (5 relaxation times) the means
+    over 40,000 more meet it within 3 % (spread about 1 %)."""
+    rv, D, dims, n0 = 5e-9, 10e-12, (500, 480, 552), 64000
+    kf = 4 * 0.027 * 1e9 * 1e-3 / 6.02214076e23
+    kb = 4 * 1.35
+    V = dims[0] * dims[1] * dims[2] * 4.0 * np.sqrt(2.0) * rv ** 3
+    p = kf / (6.0 * np.sqrt(2.0) * 2.0 * D * rv)
+    assert 0.2 < p < 0.22
+    w = reversible_workload(dims, n0, kf, kb, 47, 100000)
+    lat = build_gpu(w, max_molecules=2 * n0 + 4096)
+    lat.step(60000)
+    na, nbc = [], []
+    for _ in range(40):
+        lat.step(1000)
+        c = lat.stats()["species_count"].astype(np.float64)
+        assert c[2] == c[3] and c[1] + c[2] == n0
+        na.append(c[1])
+        nbc.append(c[2] * c[3])
+    ratio = kf * np.mean(nbc) / (V * kb * np.mean(na))
+    x = kf / (V * kb)
+    b_eq = (-1.0 + np.sqrt(1.0 + 4.0 * x * n0)) / (2.0 * x)
+    print("reversible: mean A %.0f (mass action %.0f), flux ratio %.4f"
+          % (np.mean(na), n0 - b_eq, ratio), flush=True)
+    assert abs(ratio - 1.0) < 0.03, ratio
+    lat.close()

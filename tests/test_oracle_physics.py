@@ -6,6 +6,9 @@
 * First-order reactions (2.4.1; closed form of 3.2.1):
   [A_t] = [A_0] exp(-k t), [B_t] = [A_0](1 - exp(-k t)), at the paper's three
   rate constants 0.135, 1.35 and 13.5 1/s, for both laws.
+* Reversible reactions (3.2.2): B + C <-> A started from A alone settles
+  where the mean association flux equals the mean dissociation flux,
+  k_f <N_B N_C> / V = k_b <N_A> (the law of mass action at equilibrium).
 * Second-order reactions (2.4.2, eq. 6): with p = k / (6 sqrt2 (DA+DB) r) the
   reaction-limited rate is the mass-action rate k (checked at the paper's
   k_f = 0.027 1/(nM s), D = 10 um^2/s, r = 5 nm where p = 0.053); in the
@@ -229,3 +232,43 @@ def test_first_order_branching_follows_rate_constants(mode):
     assert nb + nc > 15000
     frac = nb / (nb + nc)
     assert abs(frac - k1 / (k1 + k2)) < 0.02
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_reversible_reaction_settles_at_mass_action_equilibrium(mode):
+    """The reversible check of 3.2.2, B + C <-> A with D = 10 um^2/s and
+    r = 5 nm, started from A alone (the text's initial numbers 0, 0, 64,000
+    for A, B, C could not react at all; the figure's caption has A
+    dissociating, so A starts at 64,000), scaled to 400 molecules on 40^3
+    voxels with k_b = 1 / (600 tau) and k_f = k_b V / 200 (p = 0.27), so that
+    equilibrium falls at N_A = N_B = 200 and is reached within a few hundred
+    events.  The spatial model has no closed form in time (the paper compares
+    with its serial program), but its equilibrium does: the mean fluxes
+    balance, k_f <N_B N_C> / V = k_b <N_A>, because a dissociation places C
+    on a uniformly chosen vacant neighbour and the walk leaves B-C pair
+    placements uniform (the 12 contact states of a pair then react at the
+    summed rate p (1/tau_B + 1/tau_C) / 12 each, which eq. 6 makes
+    k_f / V per pair).  Averaged over 50,000 events (about 80 relaxation
+    times; spread of the mean below 1 %), at 0.6 % occupancy (crowding
+    shifts it by about that much)."""
+    rv, D, dims, n0 = 5e-9, 10e-12, (40, 40, 40), 400
+    V = dims[0] * dims[1] * dims[2] * voxel_volume(rv)
+    tau = 2.0 * rv * rv / (3.0 * D)
+    kb = 1.0 / (600.0 * tau)
+    kf = kb * V / (n0 / 2)
+    o = oracle.Oracle(dims, rv, 31 + mode)
+    for _ in range(3):
+        o.add_species(D)                  # A, B, C
+    o.add_reaction((2, 3), (1,), kf)      # B + C -> A
+    o.add_reaction((1,), (2, 3), kb)      # A -> B + C
+    o.place_uniform(1, n0)
+    o.run(2000, mode)
+    na, nbc = [], []
+    for _ in range(1000):
+        o.run(50, mode)
+        sp_count = np.bincount(o.state(with_occ=False)["species"], minlength=4)
+        assert sp_count[2] == sp_count[3] and sp_count[1] + sp_count[2] == n0
+        na.append(sp_count[1])
+        nbc.append(sp_count[2] * sp_count[3])
+    ratio = kf * np.mean(nbc) / (V * kb * np.mean(na))
+    assert abs(ratio - 1.0) < 0.04, ratio

@@ -89,6 +89,32 @@ __host__ __device__ inline uint32_t scale32(uint32_t r, uint32_t m) {
   return (uint32_t)(((uint64_t)r * (uint64_t)m) >> 32);
 }
 
+// ---- stage order of event e: Fisher-Yates over the n <= 16 colours, slot
+// i = n-1..1 swapping with floor(r (i+1) / 2^32), r in sequence from the
+// words of Philox(key; e, 0xFFFFFFFF, phase 2, block 0, 1, ...).  The
+// device draws it at the start of each event; the host draws the same to
+// hand each stage launch its colour. ----
+static_assert(kMaxColours <= 16, "the stage order draws one Philox block per 4 colours");
+__host__ __device__ inline void stage_order_of(uint32_t key0, uint32_t key1, uint64_t e,
+                                               uint32_t n, uint32_t *perm) {
+  uint32_t w[16];
+  for (uint32_t b = 0; 4 * b < n; ++b) {
+    const U4 r = philox((uint32_t)e, 0xFFFFFFFFu, kPhaseStage, b, key0, key1);
+    w[4 * b + 0] = r.x;
+    w[4 * b + 1] = r.y;
+    w[4 * b + 2] = r.z;
+    w[4 * b + 3] = r.w;
+  }
+  for (uint32_t c = 0; c < n; ++c) perm[c] = c;
+  int idx = 0;
+  for (int i = (int)n - 1; i >= 1; --i) {
+    const uint32_t j = scale32(w[idx++], (uint32_t)(i + 1));
+    const uint32_t t = perm[i];
+    perm[i] = perm[j];
+    perm[j] = t;
+  }
+}
+
 // ---- division by an invariant 32-bit divisor ------------------------------
 // Granlund & Montgomery, "Division by invariant integers using
 // multiplication" (PLDI 1994), unsigned case: with l = ceil(log2 d),
@@ -465,6 +491,17 @@ constexpr uint32_t kRankBucketsMax = 8192;
 // two products, whose newborns the event end numbers
 hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool fcc,
                         const BeginShape &b, bool births, hipStream_t s);
+// event e of a lattice launched from the host, which holds its record L
+// (equal to *dL) and its tape: the stages take the record, their colour, the
+// event, the species due in it (tape_due[e]) and the next event's largest
+// first-order threshold (0 when none or past the tape) as arguments
+// (k_stage_direct)
+hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, uint64_t due,
+                               uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
+                               const BeginShape &b, bool births, hipStream_t s);
+hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t due,
+                               uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
+                               hipStream_t s);
 // stages: the most stages of any member (16)
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, bool births, hipStream_t s);
@@ -476,6 +513,10 @@ hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool 
 template <int LAT>
 hipError_t launch_stage_lat(const LatDev *dL, uint32_t g, int grid, int items, bool disp,
                             hipStream_t s);
+template <int LAT>
+hipError_t launch_stage_direct_lat(const LatDev &L, uint32_t c, uint64_t e, uint64_t due,
+                                   uint32_t cmax_next, int grid, int items, bool disp,
+                                   hipStream_t s);
 hipError_t launch_stage_multi(const LatDev *lats, uint32_t R, uint32_t g, int grid, int items,
                               hipStream_t s);
 uint32_t max_members();

@@ -20,28 +20,9 @@ __device__ __forceinline__ uint32_t colour_of_voxel(const Geo &g, uint32_t v) {
 
 __device__ __forceinline__ void set_error(const LatDev &L, uint32_t bit) { atomicOr(L.error, bit); }
 
-// ---- stage order ---------------------------------------------------------------
-// Fisher-Yates over the n colours, slot i = n-1..1 swapping with
-// floor(r (i+1) / 2^32), r in sequence from the words of
-// Philox(seed; e, 0xFFFFFFFF, phase 2, block 0, 1, ...).
+// ---- stage order (stage_order_of) ------------------------------------------------
 __device__ __forceinline__ void stage_order(const LatDev &L, uint64_t e, uint32_t *perm) {
-  const uint32_t n = L.ncol;
-  uint32_t w[kMaxColours];
-  for (uint32_t b = 0; 4 * b < n; ++b) {
-    const U4 r = philox((uint32_t)e, 0xFFFFFFFFu, kPhaseStage, b, L.key0, L.key1);
-    w[4 * b + 0] = r.x;
-    w[4 * b + 1] = r.y;
-    w[4 * b + 2] = r.z;
-    w[4 * b + 3] = r.w;
-  }
-  for (uint32_t c = 0; c < n; ++c) perm[c] = c;
-  int idx = 0;
-  for (int i = (int)n - 1; i >= 1; --i) {
-    const uint32_t j = scale32(w[idx++], (uint32_t)(i + 1));
-    const uint32_t t = perm[i];
-    perm[i] = perm[j];
-    perm[j] = t;
-  }
+  stage_order_of(L.key0, L.key1, e, L.ncol, perm);
 }
 
 // first-order reaction fired by a molecule of species sp with first draw r0,
@@ -219,8 +200,21 @@ __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh,
   atomicAdd(&stat_fired(L)[rx], 1ull);
 }
 
-template <int ITEMS, int DM, int LAT>
+// the event's tape words the walk reads: the species due in event e, and
+// the largest first-order threshold of event e + 1 (0: no candidates to
+// collect)
+__device__ __forceinline__ uint64_t due_of(const LatDev &L, uint64_t e) { return L.tape_due[e]; }
+__device__ __forceinline__ uint32_t cmax_after(const LatDev &L, uint64_t e) {
+  return (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
+}
+
+// SPEC: the chunk's entries are read before the bin's count arrives (n is
+// then ignored and read here): lanes clamp to the bin's capacity and are
+// marked dead once the count is known, one dependent read shorter.
+// due, cmax_next: due_of(L, e) and cmax_after(L, e)
+template <int ITEMS, int DM, int LAT, bool SPEC = false>
 __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t base, uint32_t n,
+                            uint64_t due, uint32_t cmax_next,
                             StageShared &S, StageStaging<ITEMS> &stg) {
   constexpr uint32_t NC = LAT ? kColoursFcc : kColoursHcp;
   StageShared *sh = &S;
@@ -228,10 +222,10 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
   const uint32_t buf = (uint32_t)(e & 1);
   const Bins &in = L.bins[buf];
   const Bins &out = L.bins[buf ^ 1];
-  const uint64_t due = L.tape_due[e];
-  const uint32_t cmax_next = (L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u;
   const uint32_t cnext = (uint32_t)((e + 1) & 1);
   const uint64_t cap = L.cap;
+  if (SPEC) n = in.count[c];  // issued with the entries below, used after them
+  const uint64_t last = SPEC ? cap - 1 : (uint64_t)n - 1;
   const bool disp = DM == 2 ? in.disp != nullptr : DM == 1;
   const auto hot = global(L.hot);
   const auto occ = global(L.occ);
@@ -243,28 +237,18 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
   uint32_t *s_cnt = sh->cnt, *s_base = sh->base;
   uint32_t &s_ncand = sh->ncand, &s_cand_base = sh->cand_base;
   uint32_t &s_nflag = sh->nflag, &s_flag_base = sh->flag_base;
-  if (tid < (int)NC) s_cnt[tid] = 0;
-  if (tid == 32) s_ncand = 0;
-  if (tid == 33) s_nflag = 0;
-  if (tid == 34) {
-    sh->att = 0;
-    sh->hop = 0;
-    sh->col = 0;
-    sh->any_rx = 0;
-  }
-  if (tid < 64) sh->dsp[tid] = 0;
-  __syncthreads();
 
   uint32_t vox[ITEMS], id[ITEMS], ocol[ITEMS], lpos[ITEMS], osp[ITEMS];
   int32_t d0[ITEMS], d1[ITEMS], d2[ITEMS];
   bool cand[ITEMS], flag[ITEMS];
   uint32_t ftgt[ITEMS];
 
-  // bin entries: lanes past the end read the last entry (base < n) and are
-  // then marked dead, so no load sits behind a branch
+  // bin entries: lanes past the end read the last entry (base < n, or the
+  // bin's last slot) and are then marked dead, so no load sits behind a
+  // branch
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
-    const uint64_t idx = min(base + (uint64_t)it * kStageThreads + tid, (uint64_t)n - 1);
+    const uint64_t idx = min(base + (uint64_t)it * kStageThreads + tid, last);
     vox[it] = ivox[c * cap + idx];
     id[it] = iid[c * cap + idx];
     osp[it] = isp[c * cap + idx];
@@ -273,18 +257,32 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
   if (disp) {
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
-      const uint64_t idx = min(base + (uint64_t)it * kStageThreads + tid, (uint64_t)n - 1);
+      const uint64_t idx = min(base + (uint64_t)it * kStageThreads + tid, last);
       d0[it] = idsp[(0 * NC + c) * cap + idx];
       d1[it] = idsp[(1 * NC + c) * cap + idx];
       d2[it] = idsp[(2 * NC + c) * cap + idx];
     }
+  }
+  if (SPEC) {
+    n = (uint32_t)min((uint64_t)n, cap);
+    // a workgroup past the count leaves once it is known; the empty asm
+    // keeps the entry reads above that test, where they overlap the count's
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) asm volatile("" ::"v"(vox[it]), "v"(id[it]), "v"(osp[it]));
+    if (base >= n) return;
   }
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     ocol[it] = 0xFFu;
     cand[it] = false;
     flag[it] = false;
-    if (base + (uint64_t)it * kStageThreads + tid >= n) id[it] = kDeadId;
+    if (base + (uint64_t)it * kStageThreads + tid >= n) {
+      id[it] = kDeadId;
+      if (SPEC) {  // a slot past the count may hold anything: voxel 0, vacant
+        vox[it] = 0;
+        osp[it] = 0;
+      }
+    }
   }
 
   constexpr uint32_t kWallBit = 1u << 16;  // in mv: the target lies beyond a wall
@@ -317,6 +315,21 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     loaded[it] = ((due >> (osp[it] & 63u)) & 1ull) != 0;
     wt[it] = occ[loaded[it] ? tgt[it] : 0u];
   }
+
+  // The chunk's LDS counters, cleared only now: the barrier waits for every
+  // scalar read in flight, and the reads above (entries, targets) are then
+  // already under way.  The previous chunk's copy-out reads none of them.
+  if (tid < (int)NC) s_cnt[tid] = 0;
+  if (tid == 32) s_ncand = 0;
+  if (tid == 33) s_nflag = 0;
+  if (tid == 34) {
+    sh->att = 0;
+    sh->hop = 0;
+    sh->col = 0;
+    sh->any_rx = 0;
+  }
+  if (tid < 64) sh->dsp[tid] = 0;
+  __syncthreads();
 
   // Commit phase.
 #pragma unroll

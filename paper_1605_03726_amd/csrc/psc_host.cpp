@@ -1011,6 +1011,11 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   };
   const uint64_t e0 = h->events_done;
   const bool disp = h->L.bins[0].disp != nullptr, births = h->L.wb_count != nullptr;
+  // the tape words the walk of event e reads (as the device reads them)
+  auto due_of = [&](uint64_t e) -> uint64_t { return h->tape_due[e]; };
+  auto cmax_after = [&](uint64_t e) -> uint32_t {
+    return (h->L.n_fo && e + 1 < h->L.tape_horizon) ? h->tape_cmax[e + 1] : 0u;
+  };
   if (!h->timing && h->use_graph) {
     psc_status st = ensure_lattice_graph(h);
     if (st) return st;
@@ -1023,8 +1028,9 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
     }
   } else if (!h->timing) {
     for (uint64_t e = 0; e < n_events; ++e)
-      HIP_OK(h, launch_event(h->dL, h->grid, h->items, disp, h->geo.fcc != 0, shape(e0 + e),
-                             births, stream));
+      HIP_OK(h, launch_event_direct(h->dL, h->L, e0 + e, due_of(e0 + e), cmax_after(e0 + e),
+                                    h->grid, h->items, disp, h->geo.fcc != 0, shape(e0 + e),
+                                    births, stream));
   } else {
     auto ev = [&](hipEvent_t *out) -> hipError_t {
       if (!h->event_pool.empty()) {
@@ -1036,6 +1042,8 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
     };
     for (uint64_t e = 0; e < n_events; ++e) {
       const int stages = (int)n_colours(h->geo);
+      uint32_t perm[kMaxColours];
+      stage_order_of(h->L.key0, h->L.key1, e0 + e, (uint32_t)stages, perm);
       for (int g = -1; g <= stages; ++g) {
         psc_lattice::Timed t;
         t.kind = g < 0 ? 0 : (g < stages ? 1 : 2);
@@ -1044,6 +1052,10 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
         HIP_OK(h, hipEventRecord(t.a, stream));
         if (g < 0)
           HIP_OK(h, launch_begin(h->dL, shape(e0 + e), (uint32_t)stages, stream));
+        else if (g < stages && h->items <= 4)
+          HIP_OK(h, launch_stage_direct(h->L, perm[g], e0 + e, due_of(e0 + e),
+                                        cmax_after(e0 + e), h->grid, h->items,
+                                        h->L.bins[0].disp != nullptr, h->geo.fcc != 0, stream));
         else if (g < stages)
           HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, h->items,
                                  h->L.bins[0].disp != nullptr, h->geo.fcc != 0, stream));

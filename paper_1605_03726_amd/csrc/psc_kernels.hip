@@ -1050,6 +1050,13 @@ hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool 
              : launch_stage_lat<0>(dL, g, grid, items, disp, s);
 }
 
+hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t due,
+                               uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
+                               hipStream_t s) {
+  return fcc ? launch_stage_direct_lat<1>(L, c, e, due, cmax_next, grid, items, disp, s)
+             : launch_stage_direct_lat<0>(L, c, e, due, cmax_next, grid, items, disp, s);
+}
+
 // grid of the numbering of many collision newborns (a pass ranks this many
 // times 256 keys; further ones take more passes)
 constexpr int kEndBirthsGrid = 512;
@@ -1072,6 +1079,20 @@ hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool f
   hipError_t err = launch_begin(dL, b, stages, s);
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
     err = launch_stage(dL, g, grid, items, disp, fcc, s);
+  if (err == hipSuccess) err = launch_end(dL, births, s);
+  return err;
+}
+
+hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, uint64_t due,
+                               uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
+                               const BeginShape &b, bool births, hipStream_t s) {
+  const uint32_t stages = fcc ? kColoursFcc : kColoursHcp;
+  uint32_t perm[kMaxColours];
+  stage_order_of(L.key0, L.key1, e, stages, perm);
+  hipError_t err = launch_begin(dL, b, stages, s);
+  for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
+    err = items <= 4 ? launch_stage_direct(L, perm[g], e, due, cmax_next, grid, items, disp, fcc, s)
+                     : launch_stage(dL, g, grid, items, disp, fcc, s);
   if (err == hipSuccess) err = launch_end(dL, births, s);
   return err;
 }

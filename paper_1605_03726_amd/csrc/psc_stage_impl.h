@@ -16,8 +16,62 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
   const uint64_t e = d.z | ((uint64_t)d.w << 32);
   const uint32_t c = d.x, n = d.y;
   const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
+  if ((uint64_t)blockIdx.x * chunk >= n) return;
+  const uint64_t due = due_of(L, e);
+  const uint32_t cmax_next = cmax_after(L, e);
   for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk)
-    stage_chunk<ITEMS, DM, LAT>(L, e, c, base, n, S, T);
+    stage_chunk<ITEMS, DM, LAT>(L, e, c, base, n, due, cmax_next, S, T);
+}
+
+// The direct form, for launches made one event at a time from the host: the
+// lattice record, the stage's colour, the event and its two tape words
+// arrive as arguments (the host draws the stage order as k_begin does and
+// holds the tape), and the first chunk's entries are read alongside the
+// bin's count.  Its chain of dependent reads before the entries is one
+// (the arguments) instead of four (record pointer, stage descriptor, count,
+// tape).  PAR is the event's parity, so that every field of the record
+// that the stage reads sits at an offset known when compiling and all are
+// read in one round.
+template <int ITEMS, int DM, int LAT, int PAR>
+__global__ void __launch_bounds__(kStageThreads) k_stage_direct(const LatDev L, uint32_t c,
+                                                                 uint64_t e_arg, uint64_t due,
+                                                                 uint32_t cmax_next) {
+  __shared__ StageShared S;
+  __shared__ StageStaging<ITEMS> T;
+  const uint64_t e = (e_arg & ~1ull) | (uint64_t)PAR;  // = e_arg
+  const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
+  const uint64_t base0 = (uint64_t)blockIdx.x * chunk;
+  stage_chunk<ITEMS, DM, LAT, true>(L, e, c, base0, 0, due, cmax_next, S, T);
+  const uint32_t n = (uint32_t)min((uint64_t)L.bins[e & 1].count[c], L.cap);
+  for (uint64_t base = base0 + (uint64_t)gridDim.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk)
+    stage_chunk<ITEMS, DM, LAT>(L, e, c, base, n, due, cmax_next, S, T);
+}
+
+template <int DM, int LAT, int PAR>
+static void launch_stage_direct_par(const LatDev &L, uint32_t c, uint64_t e, uint64_t due,
+                                    uint32_t cmax_next, int grid, int items, hipStream_t s) {
+  const dim3 G(grid), B(kStageThreads);
+  switch (items) {
+  case 1: hipLaunchKernelGGL((k_stage_direct<1, DM, LAT, PAR>), G, B, 0, s, L, c, e, due, cmax_next); break;
+  case 2: hipLaunchKernelGGL((k_stage_direct<2, DM, LAT, PAR>), G, B, 0, s, L, c, e, due, cmax_next); break;
+  default: hipLaunchKernelGGL((k_stage_direct<4, DM, LAT, PAR>), G, B, 0, s, L, c, e, due, cmax_next); break;
+  }
+}
+
+// items: 1, 2 or 4 (the shapes the host picks for single lattices; larger
+// chunks take the descriptor form)
+template <int LAT>
+hipError_t launch_stage_direct_lat(const LatDev &L, uint32_t c, uint64_t e, uint64_t due,
+                                   uint32_t cmax_next, int grid, int items, bool disp,
+                                   hipStream_t s) {
+  if (disp) {
+    if (e & 1) launch_stage_direct_par<1, LAT, 1>(L, c, e, due, cmax_next, grid, items, s);
+    else launch_stage_direct_par<1, LAT, 0>(L, c, e, due, cmax_next, grid, items, s);
+  } else {
+    if (e & 1) launch_stage_direct_par<0, LAT, 1>(L, c, e, due, cmax_next, grid, items, s);
+    else launch_stage_direct_par<0, LAT, 0>(L, c, e, due, cmax_next, grid, items, s);
+  }
+  return hipGetLastError();
 }
 
 template <int DM, int LAT>

@@ -53,8 +53,12 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
     const LatDev &L = lats[a];
     const uint4 d = L.sdesc[g];
     const uint64_t e = d.z | ((uint64_t)d.w << 32);
-    if (L.geo.fcc) stage_chunk<ITEMS, 2, 1>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, S, T);
-    else stage_chunk<ITEMS, 2, 0>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, S, T);
+    const uint64_t due = due_of(L, e);
+    const uint32_t cmax_next = cmax_after(L, e);
+    if (L.geo.fcc)
+      stage_chunk<ITEMS, 2, 1>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, due, cmax_next, S, T);
+    else
+      stage_chunk<ITEMS, 2, 0>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, due, cmax_next, S, T);
   }
 }
 

@@ -163,6 +163,34 @@ hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool f
   for (uint32_t g = 0; g < (uint32_t)kMaxColours; ++g) launch_stage(dL, g, grid, items, disp, fcc, s);
   return launch_end(dL, births, s);
 }
+hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t due,
+                               uint32_t cmax_next, int grid, int items, bool, bool, hipStream_t) {
+  ++g_launches;
+  if (c >= (uint32_t)kMaxColours) bad("stage colour");
+  if (e >= L.tape_horizon) bad("stage event beyond the tape");
+  // the tape words must be those on the device
+  if (due != L.tape_due[e]) bad("stage due word");
+  if (cmax_next != ((L.n_fo && e + 1 < L.tape_horizon) ? L.tape_cmax[e + 1] : 0u))
+    bad("stage next-event threshold");
+  if (grid < 1 || grid > 65536) bad("stage grid");
+  if (items != 1 && items != 2 && items != 4) bad("direct items");
+  check_record(&L);
+  return hipSuccess;
+}
+hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, uint64_t due,
+                               uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
+                               const BeginShape &b, bool births, hipStream_t s) {
+  // the record handed to the stages by value must be the one on the device
+  if (std::memcmp(dL, &L, sizeof(LatDev)) != 0) bad("stale host record");
+  uint32_t perm[kMaxColours];
+  stage_order_of(L.key0, L.key1, e, kMaxColours, perm);
+  launch_begin(dL, b, kMaxColours, s);
+  for (uint32_t g = 0; g < (uint32_t)kMaxColours; ++g) {
+    if (items <= 4) launch_stage_direct(L, perm[g], e, due, cmax_next, grid, items, disp, fcc, s);
+    else launch_stage(dL, g, grid, items, disp, fcc, s);
+  }
+  return launch_end(dL, births, s);
+}
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, bool births, hipStream_t) {
   ++g_launches;

@@ -89,6 +89,25 @@ __host__ __device__ inline uint32_t scale32(uint32_t r, uint32_t m) {
   return (uint32_t)(((uint64_t)r * (uint64_t)m) >> 32);
 }
 
+// ---- the walk's reaction tables packed into 32-bit words, as the stage
+// kernels copy them into LDS: offsets in words of the pair table's rows 0..ns
+// (64 int16 each), the thresholds (n_rx words), the products (12 uint16 per
+// reaction), the product counts and the always-fire flags (a byte per
+// reaction each) ----
+struct StageTabLayout {
+  uint32_t pair, thr, prod, nprod, always, words;
+};
+__host__ __device__ constexpr StageTabLayout stage_tab_layout(uint32_t n_species, uint32_t n_rx) {
+  return StageTabLayout{0,
+                        (n_species + 1) * 32,
+                        (n_species + 1) * 32 + n_rx,
+                        (n_species + 1) * 32 + n_rx * 7,
+                        (n_species + 1) * 32 + n_rx * 7 + (n_rx + 3) / 4,
+                        (n_species + 1) * 32 + n_rx * 7 + 2 * ((n_rx + 3) / 4)};
+}
+// the largest packing: 63 species, 255 reactions
+constexpr uint32_t kStageTabWordsMax = stage_tab_layout(kMaxSpecies, kMaxReactions).words;
+
 // ---- stage order of event e: Fisher-Yates over the n <= 16 colours, slot
 // i = n-1..1 swapping with floor(r (i+1) / 2^32), r in sequence from the
 // words of Philox(key; e, 0xFFFFFFFF, phase 2, block 0, 1, ...).  The
@@ -438,6 +457,11 @@ struct LatDev {
   const uint8_t *rx_always;        // [n_rx]
   const uint8_t *rx_nprod;         // [n_rx]
   const uint16_t *rx_prod;         // [n_rx * 12]
+  // the four tables above packed for the stage kernels' copies in LDS
+  // (stage_tab_layout): rows 0..n_species of pair_rx, then rx_thr, rx_prod,
+  // rx_nprod and rx_always
+  const uint32_t *stage_tab;
+  uint32_t stage_tab_words;
   const uint16_t *fo_first;        // [64] first slot of the species
   const uint8_t *fo_n;             // [64] slots of the species
   const uint16_t *fo_rx;           // [n_fo] reaction of each slot

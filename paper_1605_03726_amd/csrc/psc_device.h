@@ -113,6 +113,34 @@ __device__ __forceinline__ gptr<T> global(T *p) {
   return (gptr<T>)p;
 }
 
+// The walk's reaction tables as a stage reads them: from the lattice record
+// (global memory; the batched kernel) or from the workgroup's packed copy in
+// LDS (stage_tab_layout).  A collision looks up the pair's reaction, its
+// threshold and products one after the other: from LDS that chain costs
+// tens of cycles instead of three global round trips behind the stage's
+// random reads.
+struct RxTabGlobal {
+  const LatDev &L;
+  __device__ int pair(uint32_t a, uint32_t b) const { return L.pair_rx[a * 64 + b]; }
+  __device__ uint32_t thr(int rx) const { return L.rx_thr[rx]; }
+  __device__ bool always(int rx) const { return L.rx_always[rx] != 0; }
+  __device__ uint32_t nprod(int rx) const { return L.rx_nprod[rx]; }
+  __device__ uint32_t prod(int rx, uint32_t k) const { return L.rx_prod[rx * 12 + k]; }
+};
+struct RxTabLds {
+  const uint32_t *w;  // the workgroup's copy (LDS)
+  StageTabLayout t;
+  __device__ int pair(uint32_t a, uint32_t b) const {
+    return ((const int16_t *)(w + t.pair))[a * 64 + b];
+  }
+  __device__ uint32_t thr(int rx) const { return w[t.thr + rx]; }
+  __device__ bool always(int rx) const { return ((const uint8_t *)(w + t.always))[rx] != 0; }
+  __device__ uint32_t nprod(int rx) const { return ((const uint8_t *)(w + t.nprod))[rx]; }
+  __device__ uint32_t prod(int rx, uint32_t k) const {
+    return ((const uint16_t *)(w + t.prod))[rx * 12 + k];
+  }
+};
+
 // DM: displacement planes never (0), always (1), or as the lattice says (2)
 // A collision of the mover (id, species sp, voxel v) with the partner at t
 // (species psp) fires reaction rx (2.4.2).  The first product takes the
@@ -125,13 +153,13 @@ __device__ __forceinline__ gptr<T> global(T *p) {
 // of the k vacant neighbours left in stencil order, w = r2, r3 of the walk
 // draw, then further blocks; they are numbered at the end of the event.
 // EXTRA: the reaction may have more than two products; LAT: 0 HCP, 1 FCC
-template <bool EXTRA, int LAT, class OccP, class HotP>
-__device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh, uint64_t e,
+template <bool EXTRA, int LAT, class OccP, class HotP, class Tab>
+__device__ __forceinline__ void fire_collision(const LatDev &L, const Tab &tab, StageShared &sh, uint64_t e,
                                                uint32_t buf, uint32_t hbits, OccP occ, HotP hot,
                                                int rx, uint32_t v, uint32_t t, uint32_t sp,
                                                uint32_t psp, uint32_t id, uint32_t &osp,
                                                uint32_t &ocol, bool &flag, uint32_t &ftgt) {
-  const uint32_t m = EXTRA ? L.rx_nprod[rx] : min(L.rx_nprod[rx], 2u);
+  const uint32_t m = EXTRA ? tab.nprod(rx) : min(tab.nprod(rx), 2u);
   // the mover's compartment, which the partner shares: every product stays in it
   const uint32_t comp = osp & kCompBits;
   uint32_t vmask = 0;
@@ -148,20 +176,21 @@ __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh,
       return;
     }
   }
-  const uint16_t *prod = L.rx_prod + rx * 12;
-  occ[t] = (uint16_t)(prod[0] | comp | kReactedFlag);
+  const uint32_t prod0 = tab.prod(rx, 0);
+  occ[t] = (uint16_t)(prod0 | comp | kReactedFlag);
   const uint32_t ht = hot_hash(t, hbits);
   atomicOr((uint32_t *)&hot[ht >> 4], 1u << (((ht & 15u) << 1) | buf));
   flag = true;
   ftgt = t;
   atomicSub(&sh.dsp[sp], 1);
   atomicSub(&sh.dsp[psp], 1);
-  atomicAdd(&sh.dsp[prod[0] & 63u], 1);
+  atomicAdd(&sh.dsp[prod0 & 63u], 1);
   sh.any_rx = 1;
   if (m >= 2) {
-    occ[v] = (uint16_t)(prod[1] | comp);
-    osp = prod[1] | comp;
-    atomicAdd(&sh.dsp[prod[1] & 63u], 1);
+    const uint32_t prod1 = tab.prod(rx, 1);
+    occ[v] = (uint16_t)(prod1 | comp);
+    osp = prod1 | comp;
+    atomicAdd(&sh.dsp[prod1 & 63u], 1);
   } else {
     occ[v] = (uint16_t)comp;
     ocol = 0xFFu;
@@ -186,7 +215,7 @@ __device__ __forceinline__ void fire_collision(const LatDev &L, StageShared &sh,
     Coord cn;
     step_target_t<LAT>(L.geo, cv, n, cn);
     const uint32_t u = index_of(L.geo, cn);
-    const uint16_t ps = prod[2 + q];
+    const uint16_t ps = (uint16_t)tab.prod(rx, 2 + q);
     occ[u] = (uint16_t)(ps | comp);
     atomicAdd(&sh.dsp[ps & 63u], 1);
     const uint32_t slot = atomicAdd(L.wb_count, 1u);
@@ -211,10 +240,12 @@ __device__ __forceinline__ uint32_t cmax_after(const LatDev &L, uint64_t e) {
 // SPEC: the chunk's entries are read before the bin's count arrives (n is
 // then ignored and read here): lanes clamp to the bin's capacity and are
 // marked dead once the count is known, one dependent read shorter.
-// due, cmax_next: due_of(L, e) and cmax_after(L, e)
-template <int ITEMS, int DM, int LAT, bool SPEC = false>
+// due, cmax_next: due_of(L, e) and cmax_after(L, e); tab: the reaction
+// tables; tab_fill: the workgroup's LDS copy that this chunk fills from the
+// record's packed tables (the workgroup's first chunk), else null
+template <int ITEMS, int DM, int LAT, bool SPEC = false, class Tab>
 __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_t c, uint64_t base, uint32_t n,
-                            uint64_t due, uint32_t cmax_next,
+                            uint64_t due, uint32_t cmax_next, const Tab &tab, uint32_t *tab_fill,
                             StageShared &S, StageStaging<ITEMS> &stg) {
   constexpr uint32_t NC = LAT ? kColoursFcc : kColoursHcp;
   StageShared *sh = &S;
@@ -263,6 +294,13 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
       d2[it] = idsp[(2 * NC + c) * cap + idx];
     }
   }
+  // the packed tables when this chunk fills the LDS copy: up to two words
+  // per thread read now, behind the entries, and stored before the barrier
+  // that precedes their first use
+  const uint32_t tw = tab_fill ? L.stage_tab_words : 0u;
+  uint32_t tw0 = 0, tw1 = 0;
+  if ((uint32_t)tid < tw) tw0 = L.stage_tab[tid];
+  if ((uint32_t)tid + kStageThreads < tw) tw1 = L.stage_tab[tid + kStageThreads];
   if (SPEC) {
     n = (uint32_t)min((uint64_t)n, cap);
     // a workgroup past the count leaves once it is known; the empty asm
@@ -329,6 +367,11 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     sh->any_rx = 0;
   }
   if (tid < 64) sh->dsp[tid] = 0;
+  if (tw) {
+    if ((uint32_t)tid < tw) tab_fill[tid] = tw0;
+    if ((uint32_t)tid + kStageThreads < tw) tab_fill[tid + kStageThreads] = tw1;
+    for (uint32_t i = tid + 2 * kStageThreads; i < tw; i += kStageThreads) tab_fill[i] = L.stage_tab[i];
+  }
   __syncthreads();
 
   // Commit phase.
@@ -369,22 +412,22 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     }
     ++n_col;
     const uint32_t psp = w_t & kSpeciesBits;
-    const int rx = L.pair_rx[sp * 64 + psp];
+    const int rx = tab.pair(sp, psp);
     if (rx < 0) continue;
-    if (!L.rx_always[rx] && !(ry[it] < L.rx_thr[rx])) continue;
-    if (L.rx_nprod[rx] > 2) {
+    if (!tab.always(rx) && !(ry[it] < tab.thr(rx))) continue;
+    if (tab.nprod(rx) > 2) {
       // more than two products: applied after this loop (rare), where fewer
       // of the items' values are live
       drx[it] = rx | (int)(psp << 8);
       continue;
     }
-    fire_collision<false, LAT>(L, *sh, e, buf, hbits, occ, hot, rx, v, t, sp, psp, id[it],
+    fire_collision<false, LAT>(L, tab, *sh, e, buf, hbits, occ, hot, rx, v, t, sp, psp, id[it],
                                osp[it], ocol[it], flag[it], ftgt[it]);
   }
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it)
     if (drx[it] >= 0)
-      fire_collision<true, LAT>(L, *sh, e, buf, hbits, occ, hot, drx[it] & 0xFF, vox[it],
+      fire_collision<true, LAT>(L, tab, *sh, e, buf, hbits, occ, hot, drx[it] & 0xFF, vox[it],
                                 tgt[it], osp[it] & 63u, (uint32_t)drx[it] >> 8, id[it], osp[it],
                                 ocol[it], flag[it], ftgt[it]);
 

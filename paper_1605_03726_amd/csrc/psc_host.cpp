@@ -386,6 +386,8 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   auto *d_always = alloc_n<uint8_t>(h, always.size());
   auto *d_nprod = alloc_n<uint8_t>(h, nprod.size());
   auto *d_prod = alloc_n<uint16_t>(h, prod.size());
+  const StageTabLayout tl = stage_tab_layout((uint32_t)(S - 1), R);
+  auto *d_tab = alloc_n<uint32_t>(h, tl.words);
   auto *d_fo_first = alloc_n<uint16_t>(h, 64);
   auto *d_fo_n = alloc_n<uint8_t>(h, 64);
   auto *d_fo_rx = alloc_n<uint16_t>(h, std::max<size_t>(h->fo_rx.size(), 1));
@@ -401,7 +403,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   h->dL = alloc_n<LatDev>(h, 1);
   if (!L.occ || !L.cand_count || !L.flag_vox[0] || !L.flag_vox[1] || !L.flag_count || !L.birth_key || !L.birth_vox ||
       !L.birth_sp || !L.birth_count || !L.fire_pos || !L.fire_id || !L.fire_col || !L.fire_count ||
-      !L.fire_rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod ||
+      !L.fire_rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod || !d_tab ||
       !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.sdesc || !L.next_id || !L.cnt || !L.sp_count ||
       !L.fired || !L.error || !h->dL || !L.hot || !L.end_done || !L.nbr_cnt ||
       (collision_births && (!L.wb_vox || !L.wb_key || !L.wb_count)))
@@ -412,6 +414,8 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.rx_always = d_always;
   L.rx_nprod = d_nprod;
   L.rx_prod = d_prod;
+  L.stage_tab = d_tab;
+  L.stage_tab_words = tl.words;
   L.fo_first = d_fo_first;
   L.fo_n = d_fo_n;
   L.fo_rx = d_fo_rx;
@@ -425,6 +429,17 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   HIP_OK(h, up(d_always, always.data(), always.size()));
   HIP_OK(h, up(d_nprod, nprod.data(), nprod.size()));
   HIP_OK(h, up(d_prod, prod.data(), prod.size() * sizeof(uint16_t)));
+  {
+    std::vector<uint32_t> tab(tl.words, 0);
+    std::memcpy(tab.data() + tl.pair, pair.data(), S * 64 * sizeof(int16_t));
+    if (R) {
+      std::memcpy(tab.data() + tl.thr, thr.data(), R * sizeof(uint32_t));
+      std::memcpy(tab.data() + tl.prod, prod.data(), R * 12 * sizeof(uint16_t));
+      std::memcpy(tab.data() + tl.nprod, nprod.data(), R);
+      std::memcpy(tab.data() + tl.always, always.data(), R);
+    }
+    HIP_OK(h, up(d_tab, tab.data(), tab.size() * sizeof(uint32_t)));
+  }
   HIP_OK(h, up(d_fo_first, h->fo_first.data(), 64 * sizeof(uint16_t)));
   HIP_OK(h, up(d_fo_n, h->fo_n.data(), 64));
   if (!h->fo_rx.empty()) HIP_OK(h, up(d_fo_rx, h->fo_rx.data(), h->fo_rx.size() * sizeof(uint16_t)));
@@ -576,6 +591,7 @@ uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool dis
   t += r(cap * 4) * 2 + r(cap) * 2 + r(4);
   const uint64_t R = std::max<uint32_t>(n_reactions, 1);
   t += r(64) + r(64 * 64 * 2) + r(R * 4) + r(R) * 2 + r(R * 24) + r(128) + r(64);
+  t += r(kStageTabWordsMax * 4);
   t += r(kStatRep * kSpStride * 8) + r(kStatRep * kCntStride * 8) +
        r((uint64_t)kStatRep * fired_stride((uint32_t)R) * 8);
   t += r(8) + r(64) + r(4) + r(4) + r(sizeof(LatDev));

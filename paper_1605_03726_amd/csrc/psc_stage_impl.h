@@ -11,6 +11,7 @@ template <int ITEMS, int DM, int LAT>
 __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restrict__ Lp, uint32_t g) {
   __shared__ StageShared S;
   __shared__ StageStaging<ITEMS> T;
+  __shared__ uint32_t s_tab[kStageTabWordsMax];
   const LatDev &L = *Lp;
   const uint4 d = L.sdesc[g];  // empty when the lattice does not run this event
   const uint64_t e = d.z | ((uint64_t)d.w << 32);
@@ -19,8 +20,10 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(const LatDev *__restric
   if ((uint64_t)blockIdx.x * chunk >= n) return;
   const uint64_t due = due_of(L, e);
   const uint32_t cmax_next = cmax_after(L, e);
+  const RxTabLds tab{s_tab, stage_tab_layout(L.n_species, L.n_rx)};
   for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk)
-    stage_chunk<ITEMS, DM, LAT>(L, e, c, base, n, due, cmax_next, S, T);
+    stage_chunk<ITEMS, DM, LAT>(L, e, c, base, n, due, cmax_next, tab,
+                                base == (uint64_t)blockIdx.x * chunk ? s_tab : nullptr, S, T);
 }
 
 // The direct form, for launches made one event at a time from the host: the
@@ -38,13 +41,15 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_direct(const LatDev L, 
                                                                  uint32_t cmax_next) {
   __shared__ StageShared S;
   __shared__ StageStaging<ITEMS> T;
+  __shared__ uint32_t s_tab[kStageTabWordsMax];
   const uint64_t e = (e_arg & ~1ull) | (uint64_t)PAR;  // = e_arg
   const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
   const uint64_t base0 = (uint64_t)blockIdx.x * chunk;
-  stage_chunk<ITEMS, DM, LAT, true>(L, e, c, base0, 0, due, cmax_next, S, T);
+  const RxTabLds tab{s_tab, stage_tab_layout(L.n_species, L.n_rx)};
+  stage_chunk<ITEMS, DM, LAT, true>(L, e, c, base0, 0, due, cmax_next, tab, s_tab, S, T);
   const uint32_t n = (uint32_t)min((uint64_t)L.bins[e & 1].count[c], L.cap);
   for (uint64_t base = base0 + (uint64_t)gridDim.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk)
-    stage_chunk<ITEMS, DM, LAT>(L, e, c, base, n, due, cmax_next, S, T);
+    stage_chunk<ITEMS, DM, LAT>(L, e, c, base, n, due, cmax_next, tab, nullptr, S, T);
 }
 
 template <int DM, int LAT, int PAR>

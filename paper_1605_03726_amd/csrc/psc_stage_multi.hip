@@ -55,10 +55,13 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
     const uint64_t e = d.z | ((uint64_t)d.w << 32);
     const uint64_t due = due_of(L, e);
     const uint32_t cmax_next = cmax_after(L, e);
+    const RxTabGlobal tab{L};
     if (L.geo.fcc)
-      stage_chunk<ITEMS, 2, 1>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, due, cmax_next, S, T);
+      stage_chunk<ITEMS, 2, 1>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, due, cmax_next,
+                               tab, nullptr, S, T);
     else
-      stage_chunk<ITEMS, 2, 0>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, due, cmax_next, S, T);
+      stage_chunk<ITEMS, 2, 0>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, due, cmax_next,
+                               tab, nullptr, S, T);
   }
 }
 

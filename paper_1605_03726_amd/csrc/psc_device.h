@@ -248,6 +248,7 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
                             uint64_t due, uint32_t cmax_next, const Tab &tab, uint32_t *tab_fill,
                             StageShared &S, StageStaging<ITEMS> &stg) {
   constexpr uint32_t NC = LAT ? kColoursFcc : kColoursHcp;
+  static_assert(64 * ITEMS < (1 << 21), "a wave's counts fill 21-bit fields");
   StageShared *sh = &S;
   const int tid = threadIdx.x;
   const uint32_t buf = (uint32_t)(e & 1);
@@ -449,9 +450,20 @@ __device__ __forceinline__ void stage_chunk(const LatDev &L, uint64_t e, uint32_
     }
     if (flag[it]) fslot[it] = atomicAdd(&s_nflag, 1u);
   }
-  if (n_att) atomicAdd(&sh->att, n_att);
-  if (n_hop) atomicAdd(&sh->hop, n_hop);
-  if (n_col) atomicAdd(&sh->col, n_col);
+  // the chunk's counters: summed over the wave first, then one LDS atomic
+  // per wave and counter (64-bit LDS atomics from every lane to one address
+  // take microseconds).  Per thread each count is at most ITEMS, per wave at
+  // most 64 ITEMS < 2^21: three fields of one 64-bit word.
+  {
+    constexpr unsigned long long kField = (1ull << 21) - 1;
+    unsigned long long pk = n_att | (n_hop << 21) | (n_col << 42);
+    for (int off = 32; off > 0; off >>= 1) pk += __shfl_xor(pk, off, 64);
+    if ((tid & 63) == 0) {
+      if (pk & kField) atomicAdd(&sh->att, pk & kField);
+      if ((pk >> 21) & kField) atomicAdd(&sh->hop, (pk >> 21) & kField);
+      if (pk >> 42) atomicAdd(&sh->col, pk >> 42);
+    }
+  }
   __syncthreads();
   // one wave per job: bin reservations; flag and candidate reservations;
   // local colour offsets and the chunk's counters; species count changes

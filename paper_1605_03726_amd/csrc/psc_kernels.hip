@@ -163,7 +163,9 @@ struct FoPlan {
   uint64_t at;          // bin entry
   uint32_t v, w0, rx, id, m;
   bool ok;              // false: a placement failure
-  uint32_t dest[kMaxProducts - 1];
+  // stencil direction of the neighbour product a + 1 takes, 4 bits each (a
+  // register word rather than an indexed array, which would live in scratch)
+  uint64_t dirs;
 };
 
 // the number of newborns the firing will have (its slots to reserve)
@@ -177,27 +179,33 @@ __device__ __forceinline__ uint32_t plan_first_order(const LatDev &L, uint64_t e
   p.m = L.rx_nprod[rx];
   p.w0 = L.occ[p.v];
   p.ok = true;
+  p.dirs = 0;
   if (p.m <= 1) return 0;
   const uint32_t comp = p.w0 & kCompBits;
-  uint32_t vac[12];
-  int nv = 0;
+  // vacant neighbours of the same compartment, as a mask in stencil order
+  uint32_t vmask = 0;
   const Coord cv = coord_of(L.geo, p.v);
   for (uint32_t n = 0; n < 12; ++n) {
     Coord ct;
     if (!step_target(L.geo, cv, n, ct)) continue;  // beyond a wall
-    const uint32_t t = index_of(L.geo, ct);
-    if (L.occ[t] == comp) vac[nv++] = t;  // vacant, same compartment
+    if (L.occ[index_of(L.geo, ct)] == comp) vmask |= 1u << n;
   }
-  if (nv < (int)(p.m - 1)) {
+  if (__popc(vmask) < (int)(p.m - 1)) {
     p.ok = false;
     return 0;
   }
+  // product a + 1 takes the x-th of the vacancies left, in stencil order
   const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
   for (uint32_t a = 0; a + 1 < p.m; ++a) {
-    const uint32_t x = scale32(placement_word(L, e, id, r, (int)a), (uint32_t)nv);
-    p.dest[a] = vac[x];
-    for (int y = (int)x; y + 1 < nv; ++y) vac[y] = vac[y + 1];
-    --nv;
+    uint32_t x = scale32(placement_word(L, e, id, r, (int)a), (uint32_t)__popc(vmask));
+    uint32_t n = 0;
+    for (;; ++n) {
+      if (!((vmask >> n) & 1u)) continue;
+      if (x == 0) break;
+      --x;
+    }
+    vmask &= ~(1u << n);
+    p.dirs |= (uint64_t)n << (4 * a);
   }
   return p.m - 1;
 }
@@ -223,13 +231,17 @@ __device__ __forceinline__ void commit_first_order(const LatDev &L, const Bins &
   L.occ[p.v] = (uint16_t)(prod[0] | comp);
   in.sp[p.at] = (uint16_t)(prod[0] | comp);  // the entry stays; its cached word follows
   atomicAdd(&T->dsp[prod[0] & 63u], 1);
+  const Coord cv = coord_of(L.geo, p.v);
   for (uint32_t a = 0; a + 1 < p.m; ++a) {
-    L.occ[p.dest[a]] = (uint16_t)(prod[a + 1] | comp);
+    Coord ct;
+    step_target(L.geo, cv, (uint32_t)(p.dirs >> (4 * a)) & 15u, ct);
+    const uint32_t dest = index_of(L.geo, ct);
+    L.occ[dest] = (uint16_t)(prod[a + 1] | comp);
     atomicAdd(&T->dsp[prod[a + 1] & 63u], 1);
     const uint32_t b = b0 + a;
     if (b < L.birth_cap) {
       L.birth_key[b] = ((uint64_t)p.id << 31) | ((uint64_t)(a + 1) << 27) | b;
-      L.birth_vox[b] = p.dest[a];
+      L.birth_vox[b] = dest;
       L.birth_sp[b] = (uint16_t)(prod[a + 1] | comp);
     } else {
       atomicOr(L.error, kErrBirthOverflow);

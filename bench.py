@@ -32,9 +32,10 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 CROSS_BRICK_FRACTION = {"hcp": 11.0 / 32.0, "fcc": 45.0 / 128.0}
 
 
-# the device code of the library (every kernel and the headers they include)
-KERNEL_SOURCES = ("psc_kernels.hip", "psc_stage_hcp.hip", "psc_stage_fcc.hip",
-                  "psc_stage_multi.hip", "psc_noalloc.hip", "psc_stage_impl.h", "psc_device.h",
+# the device code of the walk-stage kernel whose traffic the counter summary
+# holds (its translation units and every header they include): a change to
+# any of them makes the summary stale
+KERNEL_SOURCES = ("psc_stage_hcp.hip", "psc_stage_fcc.hip", "psc_stage_impl.h", "psc_device.h",
                   "psc_core.h")
 
 

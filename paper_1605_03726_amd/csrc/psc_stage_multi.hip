@@ -15,6 +15,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
   __shared__ StageStaging<ITEMS> T;
   __shared__ uint32_t s_pre[kMaxMembers + 1];
   __shared__ uint32_t s_part[kStageThreads];
+  __shared__ uint32_t s_tab[kStageTabWordsMax];  // the tables of the chunk's member
   const int tid = threadIdx.x;
   const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
   // chunks per member (contiguous slices of members per thread), then an
@@ -42,6 +43,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
   for (uint32_t r = lo; r < hi; ++r) s_pre[r] += s_part[tid];
   __syncthreads();
   const uint32_t total = s_pre[R];
+  uint32_t tab_member = ~0u;  // whose tables s_tab holds
   for (uint32_t q = blockIdx.x; q < total; q += gridDim.x) {
     // member owning chunk q: last r with s_pre[r] <= q
     uint32_t a = 0, b = R;
@@ -55,13 +57,12 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
     const uint64_t e = d.z | ((uint64_t)d.w << 32);
     const uint64_t due = due_of(L, e);
     const uint32_t cmax_next = cmax_after(L, e);
-    const RxTabGlobal tab{L};
-    if (L.geo.fcc)
-      stage_chunk<ITEMS, 2, 1>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, due, cmax_next,
-                               tab, nullptr, S, T);
-    else
-      stage_chunk<ITEMS, 2, 0>(L, e, d.x, (uint64_t)(q - s_pre[a]) * chunk, d.y, due, cmax_next,
-                               tab, nullptr, S, T);
+    const uint64_t base = (uint64_t)(q - s_pre[a]) * chunk;
+    const RxTabLds tab{s_tab, stage_tab_layout(L.n_species, L.n_rx)};
+    uint32_t *fill = tab_member == a ? nullptr : s_tab;  // a new member: load its tables
+    tab_member = a;
+    if (L.geo.fcc) stage_chunk<ITEMS, 2, 1>(L, e, d.x, base, d.y, due, cmax_next, tab, fill, S, T);
+    else stage_chunk<ITEMS, 2, 0>(L, e, d.x, base, d.y, due, cmax_next, tab, fill, S, T);
   }
 }
 

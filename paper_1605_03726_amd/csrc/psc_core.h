@@ -444,6 +444,11 @@ struct LatDev {
   uint8_t *fire_col, *fire_rx;
   uint32_t *fire_count;
 
+  // the last event's first-order fire list length, first-order newborn
+  // count and collision newborn count: the host sizes later events'
+  // launches from them
+  uint32_t *recent;  // [kRecentN]
+
   // first-order conflict test: per hashed voxel, how many firing molecules
   // have it in their closed neighbourhood (zero between events)
   uint32_t *nbr_cnt;
@@ -509,6 +514,8 @@ struct BeginShape {
 };
 // fire-list entries an application workgroup scans per pass
 constexpr uint32_t kFoTile = 2048;
+// the last event's counts (LatDev::recent)
+enum { kRecentFire = 0, kRecentFoBirths = 1, kRecentColBirths = 2, kRecentN = 3 };
 // most buckets of the grid-wide newborn ranking (their counts fit in LDS)
 constexpr uint32_t kRankBucketsMax = 8192;
 // births: the lattice (any member) has collision reactions with more than
@@ -522,7 +529,8 @@ hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool f
 // (k_stage_direct)
 hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, uint64_t due,
                                uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
-                               const BeginShape &b, bool births, hipStream_t s);
+                               const BeginShape &b, bool births, bool births_defer,
+                               hipStream_t s);
 hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t due,
                                uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
                                hipStream_t s);
@@ -548,7 +556,10 @@ hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t s);
 // occupancy between the linear (ABI) order and the lattice's layout
 hipError_t launch_relayout(const Geo &g, uint64_t nv, const uint16_t *src, uint16_t *dst,
                            bool to_layout_order, hipStream_t s);
-hipError_t launch_end(const LatDev *dL, bool births, hipStream_t s);
+// births: the lattice has collision newborns to number; defer: more than
+// one workgroup ranks in LDS go to a grid-wide numbering that follows
+// (else the end's own workgroup numbers them all)
+hipError_t launch_end(const LatDev *dL, bool births, hipStream_t s, bool defer = true);
 int stage_items();
 int stage_threads();
 

@@ -377,6 +377,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   L.fire_col = alloc_n<uint8_t>(h, cap);
   L.fire_rx = alloc_n<uint8_t>(h, cap);
   L.fire_count = alloc_n<uint32_t>(h, 1);
+  L.recent = alloc_n<uint32_t>(h, kRecentN);
   L.n_species = (uint32_t)(S - 1);
   L.n_rx = R;
   L.n_fo = h->n_fo;
@@ -403,7 +404,8 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   h->dL = alloc_n<LatDev>(h, 1);
   if (!L.occ || !L.cand_count || !L.flag_vox[0] || !L.flag_vox[1] || !L.flag_count || !L.birth_key || !L.birth_vox ||
       !L.birth_sp || !L.birth_count || !L.fire_pos || !L.fire_id || !L.fire_col || !L.fire_count ||
-      !L.fire_rx || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod || !d_prod || !d_tab ||
+      !L.fire_rx || !L.recent || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod ||
+      !d_prod || !d_tab ||
       !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.sdesc || !L.next_id || !L.cnt || !L.sp_count ||
       !L.fired || !L.error || !h->dL || !L.hot || !L.end_done || !L.nbr_cnt ||
       (collision_births && (!L.wb_vox || !L.wb_key || !L.wb_count)))
@@ -511,6 +513,9 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   if (L.wb_count) HIP_OK(h, hipMemset(L.wb_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.birth_count, 0, sizeof(uint32_t)));
   HIP_OK(h, hipMemset(L.fire_count, 0, sizeof(uint32_t)));
+  HIP_OK(h, hipMemset(L.recent, 0, kRecentN * sizeof(uint32_t)));
+  h->recent_valid = false;   // counts of the state before this one do not apply
+  h->recent_pending = false;
   HIP_OK(h, hipMemset(L.cnt, 0, kStatRep * kCntStride * sizeof(unsigned long long)));
   {
     // the initial counts in replica 0, the other replicas at zero
@@ -740,6 +745,8 @@ void psc_destroy(psc_lattice *h) {
     (void)hipEventDestroy(t.b);
   }
   for (auto &e : h->event_pool) (void)hipEventDestroy(e);
+  if (h->recent_ev) (void)hipEventDestroy(h->recent_ev);
+  if (h->h_recent) (void)hipHostFree(h->h_recent);
   if (h->exec) (void)hipGraphExecDestroy(h->exec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -986,6 +993,15 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
     psc_status st = sync_tape(h, stream);
     if (st) return st;
   }
+  // The device's counts of the last event before the previous step ended,
+  // if their copy is done (no wait): launches sized for the expectations
+  // below are dropped when recent events did not need them.  Only the speed
+  // depends on it: a short path handles any count, more slowly.
+  if (h->recent_pending && hipEventQuery(h->recent_ev) == hipSuccess) {
+    for (int k = 0; k < kRecentN; ++k) h->recent[k] = h->h_recent[k];
+    h->recent_valid = true;
+    h->recent_pending = false;
+  }
   // First-order decisions run inside k_begin (one workgroup) unless an event
   // expects many candidates (the event's largest threshold times the
   // walkers): then a launch of their own spreads them over workgroups.
@@ -1002,6 +1018,8 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   // that exceed the limit fall back to k_begin's slower sort.
   auto births_grid = [&](uint64_t e) -> int {
     if (!h->fo_extra_max) return 0;
+    // the last event's newborns fit k_begin's ranking with room to spare
+    if (h->recent_valid && h->recent[kRecentFoBirths] <= 1024) return 0;
     const double expect = (double)h->tape_cmax[e] * (1.0 / 4294967296.0) *
                           (double)h->walkers0 * (double)h->fo_extra_max;
     if (expect < 4096.0) return 0;
@@ -1014,6 +1032,8 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   // find the list empty when k_begin applied it itself.
   auto apply_grid = [&](uint64_t e) -> int {
     if (!h->n_fo) return 0;
+    // the last event's firings took half of k_begin's threads or fewer
+    if (h->recent_valid && h->recent[kRecentFire] <= 512) return 0;
     const double expect = (double)h->tape_cmax[e] * (1.0 / 4294967296.0) * (double)h->walkers0;
     if (expect < 4096.0) return 0;
     return (int)std::min(std::max(std::ceil(expect / kFoTile), 1.0), 1024.0);
@@ -1027,6 +1047,9 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   };
   const uint64_t e0 = h->events_done;
   const bool disp = h->L.bins[0].disp != nullptr, births = h->L.wb_count != nullptr;
+  // collision newborns beyond the event end's own ranking get the grid-wide
+  // numbering unless the last event's fitted with room to spare
+  const bool births_defer = !(h->recent_valid && h->recent[kRecentColBirths] <= 1024);
   // the tape words the walk of event e reads (as the device reads them)
   auto due_of = [&](uint64_t e) -> uint64_t { return h->tape_due[e]; };
   auto cmax_after = [&](uint64_t e) -> uint32_t {
@@ -1046,7 +1069,7 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
     for (uint64_t e = 0; e < n_events; ++e)
       HIP_OK(h, launch_event_direct(h->dL, h->L, e0 + e, due_of(e0 + e), cmax_after(e0 + e),
                                     h->grid, h->items, disp, h->geo.fcc != 0, shape(e0 + e),
-                                    births, stream));
+                                    births, births_defer, stream));
   } else {
     auto ev = [&](hipEvent_t *out) -> hipError_t {
       if (!h->event_pool.empty()) {
@@ -1075,7 +1098,7 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
         else if (g < stages)
           HIP_OK(h, launch_stage(h->dL, (uint32_t)g, h->grid, h->items,
                                  h->L.bins[0].disp != nullptr, h->geo.fcc != 0, stream));
-        else HIP_OK(h, launch_end(h->dL, h->L.wb_count != nullptr, stream));
+        else HIP_OK(h, launch_end(h->dL, births, stream, births_defer));
         HIP_OK(h, hipEventRecord(t.b, stream));
         h->timed.push_back(t);
       }
@@ -1083,6 +1106,18 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
   }
   h->events_done = end;
   h->last_stream = stream;
+  // copy the last event's counts back for the next step (no wait)
+  if (!h->recent_pending) {
+    if (!h->h_recent) {
+      HIP_OK(h, hipHostMalloc((void **)&h->h_recent, kRecentN * sizeof(uint32_t),
+                              hipHostMallocDefault));
+      HIP_OK(h, hipEventCreateWithFlags(&h->recent_ev, hipEventDisableTiming));
+    }
+    HIP_OK(h, hipMemcpyAsync(h->h_recent, h->L.recent, kRecentN * sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, stream));
+    HIP_OK(h, hipEventRecord(h->recent_ev, stream));
+    h->recent_pending = true;
+  }
   return PSC_OK;
 }
 

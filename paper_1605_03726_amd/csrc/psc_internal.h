@@ -97,6 +97,15 @@ struct psc_lattice {
   hipGraphExec_t exec = nullptr;
   int graph_grid = 0, graph_items = 0;
 
+  // the device's last-event counts (LatDev::recent), copied back without a
+  // wait at the end of each step and read at the next one that finds the
+  // copy done: they drop launches that recent events did not need
+  uint32_t *h_recent = nullptr;  // pinned, [kRecentN]
+  hipEvent_t recent_ev = nullptr;
+  bool recent_pending = false;
+  bool recent_valid = false;
+  uint32_t recent[psc::kRecentN] = {};
+
   // per-launch timing: kind (0 begin, 1 stage, 2 end) and its event pair
   bool timing = false;
   struct Timed {

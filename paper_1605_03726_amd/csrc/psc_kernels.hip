@@ -491,6 +491,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
                   (uint32_t)L.cap);
   __syncthreads();
   const uint32_t nfire = s_nfire;
+  if (tid == 0) L.recent[kRecentFire] = nfire;
   if (apply && nfire > blockDim.x) {
     if (tid == 0) {
       if (!decided) *L.fire_count = nfire;  // the list the stage launches apply
@@ -577,6 +578,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
   // plus the number of smaller keys: counted in LDS up to kSortLds newborns,
   // else read off a bitonic sort in global memory ----
   const uint32_t nb = min(s_nb, (uint32_t)L.birth_cap);
+  if (tid == 0) L.recent[kRecentFoBirths] = nb;
   if (nb == 0) return;
   const uint32_t base_id = s_next;
   if ((uint64_t)base_id + nb >= 0xFFFFFFFFull) {
@@ -732,6 +734,7 @@ __global__ void __launch_bounds__(kStageThreads) k_births(const LatDev *__restri
     R.nb = 0;
   }
   const uint32_t nb = R.nb;
+  if (blockIdx.x == 0 && threadIdx.x == 0) L.recent[kRecentFoBirths] = nb;
   __shared__ WgBins s_wb;
   if (nb)
     rank_dealt(L, R, [&](bool valid, uint64_t k, uint32_t r) {
@@ -923,7 +926,11 @@ __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t
     // the last workgroup: every other one has finished its sweeps
     __threadfence();
   }
-  if (BIRTHS && L.wb_count && !(defer && *L.wb_count > kSortLds)) number_births(L, e);
+  if (BIRTHS && L.wb_count) {
+    const uint32_t nwb = *L.wb_count;
+    if (threadIdx.x == 0) L.recent[kRecentColBirths] = nwb;
+    if (!(defer && nwb > kSortLds)) number_births(L, e);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     L.flag_count[prv] = 0;  // the next walk fills this list
@@ -1073,12 +1080,14 @@ hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t
 // times 256 keys; further ones take more passes)
 constexpr int kEndBirthsGrid = 512;
 
-hipError_t launch_end(const LatDev *dL, bool births, hipStream_t s) {
-  if (births) {
+hipError_t launch_end(const LatDev *dL, bool births, hipStream_t s, bool defer) {
+  if (births && defer) {
     hipLaunchKernelGGL(k_end<true>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL, 1);
     hipLaunchKernelGGL(k_rank_count<1>, dim3(kRankGrid), dim3(kStageThreads), 0, s, dL);
     hipLaunchKernelGGL(k_rank_deal<1>, dim3(kRankGrid), dim3(kStageThreads), 0, s, dL);
     hipLaunchKernelGGL(k_end_births, dim3(kEndBirthsGrid), dim3(kStageThreads), 0, s, dL);
+  } else if (births) {
+    hipLaunchKernelGGL(k_end<true>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL, 0);
   } else {
     hipLaunchKernelGGL(k_end<false>, dim3(kEndBlocks), dim3(kEndThreads), 0, s, dL, 0);
   }
@@ -1097,7 +1106,8 @@ hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool f
 
 hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, uint64_t due,
                                uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
-                               const BeginShape &b, bool births, hipStream_t s) {
+                               const BeginShape &b, bool births, bool births_defer,
+                               hipStream_t s) {
   const uint32_t stages = fcc ? kColoursFcc : kColoursHcp;
   uint32_t perm[kMaxColours];
   stage_order_of(L.key0, L.key1, e, stages, perm);
@@ -1105,7 +1115,7 @@ hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, ui
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
     err = items <= 4 ? launch_stage_direct(L, perm[g], e, due, cmax_next, grid, items, disp, fcc, s)
                      : launch_stage(dL, g, grid, items, disp, fcc, s);
-  if (err == hipSuccess) err = launch_end(dL, births, s);
+  if (err == hipSuccess) err = launch_end(dL, births, s, births_defer);
   return err;
 }
 

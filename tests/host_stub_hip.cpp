@@ -78,6 +78,10 @@ hipError_t hipEventDestroy(hipEvent_t e) {
   return hipSuccess;
 }
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { return e ? hipSuccess : hipErrorInvalidValue; }
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { return hipEventCreate(e); }
+hipError_t hipEventQuery(hipEvent_t e) { return e ? hipSuccess : hipErrorInvalidValue; }
+hipError_t hipHostMalloc(void **p, size_t n, unsigned) { return hipMalloc(p, n); }
+hipError_t hipHostFree(void *p) { return hipFree(p); }
 hipError_t hipEventSynchronize(hipEvent_t e) { return e ? hipSuccess : hipErrorInvalidValue; }
 hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
   *ms = 0.01f;
@@ -123,6 +127,8 @@ static void check_record(const LatDev *L) {
   x += L->nbr_cnt[(1ull << L->nbr_bits) - 1];
   x += (uint32_t)L->tape_due[L->tape_horizon - 1];
   x += L->tape_cmax[L->tape_horizon - 1];
+  x += L->recent[kRecentN - 1];
+  x += L->stage_tab[L->stage_tab_words - 1];
   if (L->n_fo) x += L->tape_thr[L->tape_horizon * L->n_fo - 1];
   (void)x;
 }
@@ -151,7 +157,7 @@ hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool,
   check_record(dL);
   return hipSuccess;
 }
-hipError_t launch_end(const LatDev *dL, bool births, hipStream_t) {
+hipError_t launch_end(const LatDev *dL, bool births, hipStream_t, bool) {
   if (births != (dL->wb_count != nullptr)) bad("end births");
   ++g_launches;
   check_record(dL);
@@ -179,7 +185,8 @@ hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t
 }
 hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, uint64_t due,
                                uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
-                               const BeginShape &b, bool births, hipStream_t s) {
+                               const BeginShape &b, bool births, bool births_defer,
+                               hipStream_t s) {
   // the record handed to the stages by value must be the one on the device
   if (std::memcmp(dL, &L, sizeof(LatDev)) != 0) bad("stale host record");
   uint32_t perm[kMaxColours];
@@ -189,7 +196,7 @@ hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, ui
     if (items <= 4) launch_stage_direct(L, perm[g], e, due, cmax_next, grid, items, disp, fcc, s);
     else launch_stage(dL, g, grid, items, disp, fcc, s);
   }
-  return launch_end(dL, births, s);
+  return launch_end(dL, births, s, births_defer);
 }
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, bool births, hipStream_t) {

@@ -688,3 +688,33 @@ def test_reversible_reaction_equilibrium_at_scale():
           % (np.mean(na), n0 - b_eq, ratio), flush=True)
     assert abs(ratio - 1.0) < 0.03, ratio
     lat.close()
+
+
+def test_launch_shapes_follow_recent_counts_as_firings_grow():
+    """Launch shapes for an event come partly from the counts of the last
+    event of the previous step (first-order firings and newborns).  An
+    autocatalytic A -> A + A on 64^3 (k tau = 0.5: about 40 % of the A fire
+    per event) starts with 300 A among 20,000 inert walkers B: the
+    candidates expected from the walkers call for the first-order launches
+    over the GPU, but the first steps see few firings and drop them; the
+    A then grow within one step to thousands of firings and newborns per
+    event (past one workgroup's threads and its LDS ranking), handled by the
+    one-workgroup path, before the last step takes the launches again.
+    Stepped in chunks of 1, 1, 2, 8 and 2 events, against the oracle."""
+    rv, D = 4.4e-9, 1e-12
+    tau = 2.0 * rv * rv / (3.0 * D)
+    w = dict(name="growth", dims=(64, 64, 64), rv=rv, seed=53,
+             species=[("A", D), ("B", D)],
+             reactions=[((1,), (1, 1), 0.5 / tau)],
+             place=[(1, 300), (2, 20000)], events=14, track_displacement=True)
+    lat = build_gpu(w, max_molecules=64 ** 3)
+    o = build_oracle(w)
+    done = 0
+    for n in (1, 1, 2, 8, 2):
+        lat.step(n)
+        done += n
+    o.run(done, oracle.MODE_C)
+    s = o.state()
+    assert_same(lat.read_state(), s)
+    n_a = int(np.count_nonzero(s["species"] == 1))
+    assert n_a > 10000 and s["fired"][0] > 10000, (n_a, s["fired"])

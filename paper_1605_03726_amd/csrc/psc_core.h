@@ -537,7 +537,10 @@ hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t
 // stages: the most stages of any member (16)
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, bool births, hipStream_t s);
-hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t s);
+// desc: write the stage descriptors that the descriptor-form stage kernels
+// read (the direct form does not need them)
+hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t s,
+                        bool desc = true);
 hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp, bool fcc,
                         hipStream_t s);
 // the stage kernels of one lattice kind (LAT: 0 HCP, 1 FCC) and the batched

@@ -25,13 +25,50 @@ __device__ __forceinline__ void stage_order(const LatDev &L, uint64_t e, uint32_
   stage_order_of(L.key0, L.key1, e, L.ncol, perm);
 }
 
+// The first-order tables of event e as a decision reads them: per species
+// its flags, first slot and slot count; per slot its cumulative threshold
+// (this event's tape row) and reaction.  From the lattice record, or from a
+// workgroup's copy in LDS (FoTabLds::fill), which turns a decision's chain
+// of global lookups into LDS reads.
+struct FoTabGlobal {
+  const LatDev &L;
+  uint64_t e;
+  __device__ uint32_t flags(uint32_t sp) const { return L.sp_flags[sp]; }
+  __device__ uint32_t first(uint32_t sp) const { return L.fo_first[sp]; }
+  __device__ uint32_t count(uint32_t sp) const { return L.fo_n[sp]; }
+  __device__ uint32_t thr(uint32_t slot) const { return L.tape_thr[e * (uint64_t)L.n_fo + slot]; }
+  __device__ uint32_t rx(uint32_t slot) const { return L.fo_rx[slot]; }
+};
+struct FoTabLds {
+  uint8_t flags_[64], count_[64];
+  uint16_t first_[64], rx_[kMaxReactions];
+  uint32_t thr_[kMaxReactions];
+  __device__ uint32_t flags(uint32_t sp) const { return flags_[sp]; }
+  __device__ uint32_t first(uint32_t sp) const { return first_[sp]; }
+  __device__ uint32_t count(uint32_t sp) const { return count_[sp]; }
+  __device__ uint32_t thr(uint32_t slot) const { return thr_[slot]; }
+  __device__ uint32_t rx(uint32_t slot) const { return rx_[slot]; }
+  // by the whole workgroup; the caller's barrier publishes it
+  __device__ void fill(const LatDev &L, uint64_t e) {
+    for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x) {
+      flags_[i] = L.sp_flags[i];
+      count_[i] = L.fo_n[i];
+      first_[i] = L.fo_first[i];
+    }
+    for (uint32_t i = threadIdx.x; i < L.n_fo; i += blockDim.x) {
+      rx_[i] = L.fo_rx[i];
+      thr_[i] = L.tape_thr[e * (uint64_t)L.n_fo + i];
+    }
+  }
+};
+
 // first-order reaction fired by a molecule of species sp with first draw r0,
 // or -1: the slot whose cumulative threshold first exceeds r0
-__device__ __forceinline__ int first_order_choice(const LatDev &L, uint64_t e, uint32_t sp, uint32_t r0) {
-  const uint32_t first = L.fo_first[sp], n = L.fo_n[sp];
-  const uint32_t *C = L.tape_thr + e * (uint64_t)L.n_fo + first;
+template <class FoTab>
+__device__ __forceinline__ int first_order_choice(const FoTab &ft, uint32_t sp, uint32_t r0) {
+  const uint32_t first = ft.first(sp), n = ft.count(sp);
   for (uint32_t a = 0; a < n; ++a)
-    if (r0 < C[a]) return (int)L.fo_rx[first + a];
+    if (r0 < ft.thr(first + a)) return (int)ft.rx(first + a);
   return -1;
 }
 

@@ -1090,7 +1090,7 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
         HIP_OK(h, ev(&t.b));
         HIP_OK(h, hipEventRecord(t.a, stream));
         if (g < 0)
-          HIP_OK(h, launch_begin(h->dL, shape(e0 + e), (uint32_t)stages, stream));
+          HIP_OK(h, launch_begin(h->dL, shape(e0 + e), (uint32_t)stages, stream, h->items > 4));
         else if (g < stages && h->items <= 4)
           HIP_OK(h, launch_stage_direct(h->L, perm[g], e0 + e, due_of(e0 + e),
                                         cmax_after(e0 + e), h->grid, h->items,

@@ -413,25 +413,29 @@ __device__ __forceinline__ void rank_dealt(const LatDev &L, const RankList &R, F
 // threshold its draw falls under.  Independent of order (a candidate's
 // species cannot change before its own turn), so any number of threads and
 // workgroups may share the decisions of an event.
-__device__ __forceinline__ int first_order_decision(const LatDev &L, uint64_t e, const Bins &in,
-                                                    uint32_t c, uint32_t pos, uint32_t id) {
+template <class FoTab>
+__device__ __forceinline__ int first_order_decision(const LatDev &L, const FoTab &ft, uint64_t e,
+                                                    const Bins &in, uint32_t c, uint32_t pos,
+                                                    uint32_t id) {
   const uint32_t v = in.vox[c * L.cap + pos];
   const uint32_t sp = L.occ[v] & kSpeciesBits;
-  if (!(L.sp_flags[sp] & kSpFirstOrder)) return -1;
+  if (!(ft.flags(sp) & kSpFirstOrder)) return -1;
   const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
-  return first_order_choice(L, e, sp, r.x);
+  return first_order_choice(ft, sp, r.x);
 }
 
 // the decisions of event e for candidates [first, ...) with the given
 // stride, by one workgroup: the fire list is counted in *nfire (LDS)
-__device__ __forceinline__ void decide_first_order(const LatDev &L, uint64_t e, uint32_t first,
-                                                   uint32_t stride, uint32_t *nfire) {
+template <class FoTab>
+__device__ __forceinline__ void decide_first_order(const LatDev &L, const FoTab &ft, uint64_t e,
+                                                   uint32_t first, uint32_t stride,
+                                                   uint32_t *nfire) {
   const uint32_t buf = (uint32_t)(e & 1);
   const Bins &in = L.bins[buf];
   const uint32_t ncand = L.n_fo ? min(L.cand_count[buf], (uint32_t)L.cand_cap) : 0u;
   for (uint32_t q = first; q < ncand; q += stride) {
     const uint32_t c = L.cand_col[buf][q], pos = L.cand_pos[buf][q], id = L.cand_id[buf][q];
-    const int rx = first_order_decision(L, e, in, c, pos, id);
+    const int rx = first_order_decision(L, ft, e, in, c, pos, id);
     if (rx < 0) continue;
     const uint32_t slot = atomicAdd(nfire, 1u);
     L.fire_pos[slot] = pos;
@@ -458,6 +462,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
   __shared__ uint32_t s_perm[kMaxColours], s_colcnt[kMaxColours];
   __shared__ uint32_t s_nfire, s_nb, s_next;
   __shared__ uint64_t s_keys[kSortLds];
+  __shared__ FoTabLds s_fo;
   const uint64_t e = *L.ev;
   const int tid = threadIdx.x;
   if (e >= L.stop_event) return;  // an idle member of an ensemble
@@ -465,6 +470,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
     if (tid == 0) set_error(L, kErrTape);
     return;
   }
+  if (!decided && L.n_fo) s_fo.fill(L, e);  // published by the barrier below
   const uint32_t buf = (uint32_t)(e & 1);
   const Bins &in = L.bins[buf];
   const Bins &out = L.bins[buf ^ 1];
@@ -485,7 +491,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
 
   // ---- first-order decisions ----
   if (!decided)
-    decide_first_order(L, e, tid, blockDim.x, &s_nfire);
+    decide_first_order(L, s_fo, e, tid, blockDim.x, &s_nfire);
   else if (tid == 0)
     s_nfire = min(__hip_atomic_load(L.fire_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                   (uint32_t)L.cap);
@@ -633,7 +639,9 @@ __device__ __forceinline__ void write_stage_descriptors(const LatDev &L, uint32_
   }
 }
 
-__device__ __forceinline__ void begin_body(const LatDev &L, bool decided, bool defer, bool apply) {
+// desc: write the stage descriptors (for stage launches that read them)
+__device__ __forceinline__ void begin_body(const LatDev &L, bool decided, bool defer, bool apply,
+                                          bool desc = true) {
   __shared__ uint32_t s_deferred;
   __shared__ FirstOrderTally T;
   const uint32_t tid = threadIdx.x;
@@ -651,14 +659,15 @@ __device__ __forceinline__ void begin_body(const LatDev &L, bool decided, bool d
   if (tid == 0 && T.fail) atomicAdd(&stat_cnt(L)[3], (unsigned long long)T.fail);
   if (s_deferred) return;  // k_births finishes the pass
   if (tid == 0 && decided) *L.fire_count = 0;  // k_decide's list has been applied
-  write_stage_descriptors(L, tid);
+  if (desc) write_stage_descriptors(L, tid);
 }
 
 // defer: k_births follows (newborns beyond the LDS ranking are left to it);
 // apply: k_fo_stage launches apply the firings, then k_births
 __global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restrict__ Lp,
-                                                         int decided, int defer, int apply) {
-  begin_body(*Lp, decided != 0, defer != 0, apply != 0);
+                                                         int decided, int defer, int apply,
+                                                         int desc) {
+  begin_body(*Lp, decided != 0, defer != 0, apply != 0, desc != 0);
 }
 
 // one workgroup per member lattice of an ensemble
@@ -754,9 +763,12 @@ __global__ void __launch_bounds__(kStageThreads) k_births(const LatDev *__restri
 // (the fire list grows by one reservation per workgroup and pass)
 __global__ void __launch_bounds__(kStageThreads) k_decide(const LatDev *__restrict__ Lp) {
   __shared__ WgSlots s_slots;
+  __shared__ FoTabLds s_fo;
   const LatDev &L = *Lp;
   const uint64_t e = *L.ev;
   if (e >= L.stop_event || e >= L.tape_horizon) return;
+  s_fo.fill(L, e);
+  __syncthreads();
   const uint32_t buf = (uint32_t)(e & 1);
   const Bins &in = L.bins[buf];
   const uint32_t ncand = L.n_fo ? min(L.cand_count[buf], (uint32_t)L.cand_cap) : 0u;
@@ -768,7 +780,7 @@ __global__ void __launch_bounds__(kStageThreads) k_decide(const LatDev *__restri
       c = L.cand_col[buf][q];
       pos = L.cand_pos[buf][q];
       id = L.cand_id[buf][q];
-      rx = first_order_decision(L, e, in, c, pos, id);
+      rx = first_order_decision(L, s_fo, e, in, c, pos, id);
     }
     const uint32_t slot = wg_reserve(L.fire_count, rx >= 0 ? 1u : 0u, s_slots);
     if (rx >= 0 && slot < L.cap) {
@@ -1046,10 +1058,11 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s) {
 // grid-stride pass each; the count's last workgroup waits on all of them)
 constexpr int kRankGrid = 256;
 
-hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t s) {
+hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t s,
+                        bool desc) {
   if (b.decide > 0) hipLaunchKernelGGL(k_decide, dim3(b.decide), dim3(kStageThreads), 0, s, dL);
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, b.decide > 0 ? 1 : 0,
-                     b.births > 0 ? 1 : 0, b.apply > 0 ? 1 : 0);
+                     b.births > 0 ? 1 : 0, b.apply > 0 ? 1 : 0, desc ? 1 : 0);
   if (b.apply > 0)
     for (uint32_t g = 0; g < stages; ++g)
       hipLaunchKernelGGL(k_fo_stage, dim3(b.apply), dim3(kStageThreads), 0, s, dL, g);
@@ -1111,7 +1124,9 @@ hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, ui
   const uint32_t stages = fcc ? kColoursFcc : kColoursHcp;
   uint32_t perm[kMaxColours];
   stage_order_of(L.key0, L.key1, e, stages, perm);
-  hipError_t err = launch_begin(dL, b, stages, s);
+  // the direct stage kernels take their colour and count without the
+  // descriptors; larger chunks take the descriptor form
+  hipError_t err = launch_begin(dL, b, stages, s, items > 4);
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
     err = items <= 4 ? launch_stage_direct(L, perm[g], e, due, cmax_next, grid, items, disp, fcc, s)
                      : launch_stage(dL, g, grid, items, disp, fcc, s);

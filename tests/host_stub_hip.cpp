@@ -139,7 +139,7 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t) {
   check_record(dL);
   return hipSuccess;
 }
-hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t) {
+hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t, bool) {
   ++g_launches;
   if (b.decide < 0 || b.decide > 1024) bad("decide grid");
   if (b.births < 0 || b.births > 2048) bad("births grid");
@@ -191,7 +191,7 @@ hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, ui
   if (std::memcmp(dL, &L, sizeof(LatDev)) != 0) bad("stale host record");
   uint32_t perm[kMaxColours];
   stage_order_of(L.key0, L.key1, e, kMaxColours, perm);
-  launch_begin(dL, b, kMaxColours, s);
+  launch_begin(dL, b, kMaxColours, s, items > 4);
   for (uint32_t g = 0; g < (uint32_t)kMaxColours; ++g) {
     if (items <= 4) launch_stage_direct(L, perm[g], e, due, cmax_next, grid, items, disp, fcc, s);
     else launch_stage(dL, g, grid, items, disp, fcc, s);

@@ -440,7 +440,7 @@ struct LatDev {
 
   // scratch of the first-order pass: molecules firing this event, and their
   // count (zero between events)
-  uint32_t *fire_pos, *fire_id;
+  uint32_t *fire_pos, *fire_id, *fire_vox;  // fire_vox: the firing molecule's voxel
   uint8_t *fire_col, *fire_rx;
   uint32_t *fire_count;
 
@@ -538,9 +538,12 @@ hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, bool births, hipStream_t s);
 // desc: write the stage descriptors that the descriptor-form stage kernels
-// read (the direct form does not need them)
+// read (the direct form does not need them); Lh, perm, e: the host's copy of
+// the record, the event's stage order and the event, for the first-order
+// stage launches to take as arguments (null: they read the device's)
 hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t s,
-                        bool desc = true);
+                        bool desc = true, const LatDev *Lh = nullptr,
+                        const uint32_t *perm = nullptr, uint64_t e = 0);
 hipError_t launch_stage(const LatDev *dL, uint32_t g, int grid, int items, bool disp, bool fcc,
                         hipStream_t s);
 // the stage kernels of one lattice kind (LAT: 0 HCP, 1 FCC) and the batched

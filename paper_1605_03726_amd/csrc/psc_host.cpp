@@ -373,6 +373,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   while (L.nbr_bits < 22 && (1ull << L.nbr_bits) < 8 * cap) ++L.nbr_bits;
   L.nbr_cnt = alloc_n<uint32_t>(h, 1ull << L.nbr_bits);
   L.fire_pos = alloc_n<uint32_t>(h, cap);
+  L.fire_vox = alloc_n<uint32_t>(h, cap);
   L.fire_id = alloc_n<uint32_t>(h, cap);
   L.fire_col = alloc_n<uint8_t>(h, cap);
   L.fire_rx = alloc_n<uint8_t>(h, cap);
@@ -404,7 +405,7 @@ psc_status freeze(psc_lattice *h, hipStream_t stream) {
   h->dL = alloc_n<LatDev>(h, 1);
   if (!L.occ || !L.cand_count || !L.flag_vox[0] || !L.flag_vox[1] || !L.flag_count || !L.birth_key || !L.birth_vox ||
       !L.birth_sp || !L.birth_count || !L.fire_pos || !L.fire_id || !L.fire_col || !L.fire_count ||
-      !L.fire_rx || !L.recent || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod ||
+      !L.fire_rx || !L.fire_vox || !L.recent || !d_flags || !d_pair || !d_thr || !d_always || !d_nprod ||
       !d_prod || !d_tab ||
       !d_fo_first || !d_fo_n || !d_fo_rx || !L.ev || !L.perm || !L.sdesc || !L.next_id || !L.cnt || !L.sp_count ||
       !L.fired || !L.error || !h->dL || !L.hot || !L.end_done || !L.nbr_cnt ||
@@ -593,7 +594,7 @@ uint64_t estimate_device_bytes(uint64_t voxels, uint64_t max_molecules, bool dis
   uint32_t nb = 12;
   while (nb < 22 && (1ull << nb) < 8 * cap) ++nb;
   t += r((1ull << nb) * 4);
-  t += r(cap * 4) * 2 + r(cap) * 2 + r(4);
+  t += r(cap * 4) * 3 + r(cap) * 2 + r(4);
   const uint64_t R = std::max<uint32_t>(n_reactions, 1);
   t += r(64) + r(64 * 64 * 2) + r(R * 4) + r(R) * 2 + r(R * 24) + r(128) + r(64);
   t += r(kStageTabWordsMax * 4);
@@ -1090,7 +1091,8 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
         HIP_OK(h, ev(&t.b));
         HIP_OK(h, hipEventRecord(t.a, stream));
         if (g < 0)
-          HIP_OK(h, launch_begin(h->dL, shape(e0 + e), (uint32_t)stages, stream, h->items > 4));
+          HIP_OK(h, launch_begin(h->dL, shape(e0 + e), (uint32_t)stages, stream, h->items > 4,
+                                 &h->L, perm, e0 + e));
         else if (g < stages && h->items <= 4)
           HIP_OK(h, launch_stage_direct(h->L, perm[g], e0 + e, due_of(e0 + e),
                                         cmax_after(e0 + e), h->grid, h->items,

@@ -168,15 +168,17 @@ struct FoPlan {
   uint64_t dirs;
 };
 
-// the number of newborns the firing will have (its slots to reserve)
-__device__ __forceinline__ uint32_t plan_first_order(const LatDev &L, uint64_t e, const Bins &in,
+// the number of newborns the firing will have (its slots to reserve); v:
+// the molecule's voxel (its bin entry's, recorded in the fire list)
+template <class Tab>
+__device__ __forceinline__ uint32_t plan_first_order(const LatDev &L, const Tab &tab, uint64_t e,
                                                      uint32_t c, uint32_t pos, uint32_t id,
-                                                     uint32_t rx, FoPlan &p) {
+                                                     uint32_t rx, uint32_t v, FoPlan &p) {
   p.at = c * L.cap + pos;
-  p.v = in.vox[p.at];
+  p.v = v;
   p.rx = rx;
   p.id = id;
-  p.m = L.rx_nprod[rx];
+  p.m = tab.nprod(rx);
   p.w0 = L.occ[p.v];
   p.ok = true;
   p.dirs = 0;
@@ -211,7 +213,8 @@ __device__ __forceinline__ uint32_t plan_first_order(const LatDev &L, uint64_t e
 }
 
 // b0: the first of the plan's newborn slots
-__device__ __forceinline__ void commit_first_order(const LatDev &L, const Bins &in,
+template <class Tab>
+__device__ __forceinline__ void commit_first_order(const LatDev &L, const Tab &tab, const Bins &in,
                                                    const FoPlan &p, uint32_t b0,
                                                    FirstOrderTally *T) {
   const uint32_t sp0 = p.w0 & kSpeciesBits;
@@ -227,22 +230,23 @@ __device__ __forceinline__ void commit_first_order(const LatDev &L, const Bins &
     in.id[p.at] = kDeadId;
     return;
   }
-  const uint16_t *prod = L.rx_prod + p.rx * 12;
-  L.occ[p.v] = (uint16_t)(prod[0] | comp);
-  in.sp[p.at] = (uint16_t)(prod[0] | comp);  // the entry stays; its cached word follows
-  atomicAdd(&T->dsp[prod[0] & 63u], 1);
+  const uint32_t prod0 = tab.prod(p.rx, 0);
+  L.occ[p.v] = (uint16_t)(prod0 | comp);
+  in.sp[p.at] = (uint16_t)(prod0 | comp);  // the entry stays; its cached word follows
+  atomicAdd(&T->dsp[prod0 & 63u], 1);
   const Coord cv = coord_of(L.geo, p.v);
   for (uint32_t a = 0; a + 1 < p.m; ++a) {
     Coord ct;
     step_target(L.geo, cv, (uint32_t)(p.dirs >> (4 * a)) & 15u, ct);
     const uint32_t dest = index_of(L.geo, ct);
-    L.occ[dest] = (uint16_t)(prod[a + 1] | comp);
-    atomicAdd(&T->dsp[prod[a + 1] & 63u], 1);
+    const uint32_t pa = tab.prod(p.rx, a + 1);
+    L.occ[dest] = (uint16_t)(pa | comp);
+    atomicAdd(&T->dsp[pa & 63u], 1);
     const uint32_t b = b0 + a;
     if (b < L.birth_cap) {
       L.birth_key[b] = ((uint64_t)p.id << 31) | ((uint64_t)(a + 1) << 27) | b;
       L.birth_vox[b] = dest;
-      L.birth_sp[b] = (uint16_t)(prod[a + 1] | comp);
+      L.birth_sp[b] = (uint16_t)(pa | comp);
     } else {
       atomicOr(L.error, kErrBirthOverflow);
     }
@@ -252,11 +256,12 @@ __device__ __forceinline__ void commit_first_order(const LatDev &L, const Bins &
 // plan and commit at once, newborn slots from *s_nb (LDS: one workgroup)
 __device__ __forceinline__ void apply_first_order(const LatDev &L, uint64_t e, const Bins &in,
                                                   uint32_t c, uint32_t pos, uint32_t id,
-                                                  uint32_t rx, uint32_t *s_nb,
+                                                  uint32_t rx, uint32_t v, uint32_t *s_nb,
                                                   FirstOrderTally *T) {
+  const RxTabGlobal tab{L};
   FoPlan p;
-  const uint32_t nb = plan_first_order(L, e, in, c, pos, id, rx, p);
-  commit_first_order(L, in, p, nb ? atomicAdd(s_nb, nb) : 0u, T);
+  const uint32_t nb = plan_first_order(L, tab, e, c, pos, id, rx, v, p);
+  commit_first_order(L, tab, in, p, nb ? atomicAdd(s_nb, nb) : 0u, T);
 }
 
 // First-order newborns (key = parent id << 31 | product index << 27 | slot)
@@ -413,11 +418,12 @@ __device__ __forceinline__ void rank_dealt(const LatDev &L, const RankList &R, F
 // threshold its draw falls under.  Independent of order (a candidate's
 // species cannot change before its own turn), so any number of threads and
 // workgroups may share the decisions of an event.
+// (v: the candidate's voxel)
 template <class FoTab>
 __device__ __forceinline__ int first_order_decision(const LatDev &L, const FoTab &ft, uint64_t e,
                                                     const Bins &in, uint32_t c, uint32_t pos,
-                                                    uint32_t id) {
-  const uint32_t v = in.vox[c * L.cap + pos];
+                                                    uint32_t id, uint32_t &v) {
+  v = in.vox[c * L.cap + pos];
   const uint32_t sp = L.occ[v] & kSpeciesBits;
   if (!(ft.flags(sp) & kSpFirstOrder)) return -1;
   const U4 r = philox((uint32_t)e, id, kPhaseFirst, 0, L.key0, L.key1);
@@ -435,10 +441,12 @@ __device__ __forceinline__ void decide_first_order(const LatDev &L, const FoTab 
   const uint32_t ncand = L.n_fo ? min(L.cand_count[buf], (uint32_t)L.cand_cap) : 0u;
   for (uint32_t q = first; q < ncand; q += stride) {
     const uint32_t c = L.cand_col[buf][q], pos = L.cand_pos[buf][q], id = L.cand_id[buf][q];
-    const int rx = first_order_decision(L, ft, e, in, c, pos, id);
+    uint32_t v;
+    const int rx = first_order_decision(L, ft, e, in, c, pos, id, v);
     if (rx < 0) continue;
     const uint32_t slot = atomicAdd(nfire, 1u);
     L.fire_pos[slot] = pos;
+    L.fire_vox[slot] = v;
     L.fire_id[slot] = id;
     L.fire_col[slot] = (uint8_t)c;
     L.fire_rx[slot] = (uint8_t)rx;
@@ -522,14 +530,14 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
     // the count, the test, the application and the cleanup
     const uint32_t nb_bits = L.nbr_bits;
     const bool mine = (uint32_t)tid < nfire;
-    uint32_t c = 0, pos = 0, id = 0, rx = 0, h[13];
+    uint32_t c = 0, pos = 0, id = 0, rx = 0, v = 0, h[13];
     bool deferred = false;
     if (mine) {
       c = fire_col[tid];
       pos = fire_pos[tid];
       id = fire_id[tid];
       rx = fire_rx[tid];
-      const uint32_t v = in.vox[c * L.cap + pos];
+      v = L.fire_vox[tid];
       const Coord cv = coord_of(L.geo, v);
       h[0] = hot_hash(v, nb_bits);
 #pragma unroll
@@ -545,7 +553,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
       for (int a = 0; a < 13; ++a)
         other |= __hip_atomic_load(&L.nbr_cnt[h[a]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ^ 1u;
       if (other == 0u) {
-        apply_first_order(L, e, in, c, pos, id, rx, &s_nb, T);
+        apply_first_order(L, e, in, c, pos, id, rx, v, &s_nb, T);
       } else {
         deferred = true;  // to the staged pass
         atomicAdd(&s_colcnt[c], 1u);
@@ -555,7 +563,7 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
     for (uint32_t g = 0; g < ncol; ++g) {
       const uint32_t cg = s_perm[g];
       if (s_colcnt[cg] == 0) continue;
-      if (deferred && c == cg) apply_first_order(L, e, in, c, pos, id, rx, &s_nb, T);
+      if (deferred && c == cg) apply_first_order(L, e, in, c, pos, id, rx, v, &s_nb, T);
       __syncthreads();
     }
     // leave the counts at zero for the next event
@@ -574,7 +582,8 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
       const uint32_t cg = s_perm[g];
       for (uint32_t q = tid; q < nfire; q += blockDim.x)
         if (fire_col[q] == cg)
-          apply_first_order(L, e, in, cg, fire_pos[q], fire_id[q], fire_rx[q], &s_nb, T);
+          apply_first_order(L, e, in, cg, fire_pos[q], fire_id[q], fire_rx[q], L.fire_vox[q],
+                            &s_nb, T);
       __syncthreads();
     }
   }
@@ -676,34 +685,56 @@ __global__ void __launch_bounds__(kBeginThreads) k_begin_multi(const LatDev *__r
 }
 
 // Stage g of the first-order application over many workgroups (events with
-// many firings): every firing of the stage's colour, at once -- their closed
-// neighbourhoods are disjoint.  A workgroup takes kFoTile entries of the
-// fire list per pass and gathers those of the stage's colour in LDS, so its
-// lanes work on firings, not on skipped entries; newborns take slots from
-// *birth_count, one reservation per workgroup and pass.
-__global__ void __launch_bounds__(kStageThreads) k_fo_stage(const LatDev *__restrict__ Lp,
-                                                            uint32_t g) {
+// many firings): every firing of the stage's colour cg, at once -- their
+// closed neighbourhoods are disjoint.  A workgroup takes kFoTile entries of
+// the fire list per pass and gathers those of the stage's colour in LDS, so
+// its lanes work on firings, not on skipped entries; newborns take slots
+// from *birth_count, one reservation per workgroup and pass.  The first
+// tile's colours and the reaction tables are read alongside the list's
+// length (lanes past it are dropped once it arrives).
+__device__ __forceinline__ void fo_stage_body(const LatDev &L, uint64_t e, uint32_t cg) {
+  constexpr int PER = kFoTile / kStageThreads;
   __shared__ FirstOrderTally T;
   __shared__ uint32_t s_idx[kFoTile];
   __shared__ uint32_t s_n;
   __shared__ WgSlots s_slots;
+  __shared__ uint32_t s_tab[kStageTabWordsMax];
   const uint32_t tid = threadIdx.x;
+  const Bins &in = L.bins[e & 1];
+  const uint64_t cap = L.cap;
+  const uint32_t nraw = *L.fire_count;
+  const uint32_t t0 = blockIdx.x * kFoTile;
+  uint32_t col0[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    col0[k] = L.fire_col[min((uint64_t)t0 + k * kStageThreads + tid, cap - 1)];
+  const uint32_t tw = L.stage_tab_words;
+  uint32_t tw0 = 0, tw1 = 0;
+  if (tid < tw) tw0 = L.stage_tab[tid];
+  if (tid + kStageThreads < tw) tw1 = L.stage_tab[tid + kStageThreads];
   if (tid == 0) T.fail = 0;
   if (tid < 64) T.dsp[tid] = 0;
   for (uint32_t r = tid; r < (uint32_t)kMaxReactions; r += blockDim.x) T.fired[r] = 0;
+  if (tid < tw) s_tab[tid] = tw0;
+  if (tid + kStageThreads < tw) s_tab[tid + kStageThreads] = tw1;
+  for (uint32_t i = tid + 2 * kStageThreads; i < tw; i += kStageThreads) s_tab[i] = L.stage_tab[i];
+  const uint32_t nfire = (uint32_t)min((uint64_t)nraw, cap);
   __syncthreads();
-  const LatDev &L = *Lp;
-  const uint64_t e = *L.ev;
-  if (e >= L.stop_event || e >= L.tape_horizon) return;
-  const uint32_t nfire = min(*L.fire_count, (uint32_t)L.cap);
-  const uint32_t cg = L.perm[g];
-  const Bins &in = L.bins[e & 1];
-  for (uint32_t t0 = blockIdx.x * kFoTile; t0 < nfire; t0 += gridDim.x * kFoTile) {
-    const uint32_t t1 = min(t0 + kFoTile, nfire);
+  const RxTabLds tab{s_tab, stage_tab_layout(L.n_species, L.n_rx)};
+  for (uint32_t t = t0; t < nfire; t += gridDim.x * kFoTile) {
+    const uint32_t t1 = min(t + kFoTile, nfire);
     if (tid == 0) s_n = 0;
     __syncthreads();
-    for (uint32_t q = t0 + tid; q < t1; q += blockDim.x)
-      if (L.fire_col[q] == cg) s_idx[atomicAdd(&s_n, 1u)] = q;
+    if (t == t0) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const uint32_t q = t + k * kStageThreads + tid;
+        if (q < t1 && col0[k] == cg) s_idx[atomicAdd(&s_n, 1u)] = q;
+      }
+    } else {
+      for (uint32_t q = t + tid; q < t1; q += blockDim.x)
+        if (L.fire_col[q] == cg) s_idx[atomicAdd(&s_n, 1u)] = q;
+    }
     __syncthreads();
     const uint32_t n = s_n;
     for (uint32_t k0 = 0; k0 < n; k0 += blockDim.x) {
@@ -712,10 +743,11 @@ __global__ void __launch_bounds__(kStageThreads) k_fo_stage(const LatDev *__rest
       uint32_t nb = 0;
       if (k < n) {
         const uint32_t q = s_idx[k];
-        nb = plan_first_order(L, e, in, cg, L.fire_pos[q], L.fire_id[q], L.fire_rx[q], p);
+        nb = plan_first_order(L, tab, e, cg, L.fire_pos[q], L.fire_id[q], L.fire_rx[q],
+                              L.fire_vox[q], p);
       }
       const uint32_t b0 = wg_reserve(L.birth_count, nb, s_slots);
-      if (k < n) commit_first_order(L, in, p, b0, &T);
+      if (k < n) commit_first_order(L, tab, in, p, b0, &T);
     }
     __syncthreads();  // s_idx and s_n serve the next pass
   }
@@ -723,6 +755,22 @@ __global__ void __launch_bounds__(kStageThreads) k_fo_stage(const LatDev *__rest
   for (uint32_t r = tid; r < L.n_rx; r += blockDim.x)
     if (T.fired[r]) atomicAdd(&stat_fired(L)[r], (unsigned long long)T.fired[r]);
   if (tid == 0 && T.fail) atomicAdd(&stat_cnt(L)[3], (unsigned long long)T.fail);
+}
+
+// the stage's colour from the event's stage order on the device
+__global__ void __launch_bounds__(kStageThreads) k_fo_stage(const LatDev *__restrict__ Lp,
+                                                            uint32_t g) {
+  const LatDev &L = *Lp;
+  const uint64_t e = *L.ev;
+  if (e >= L.stop_event || e >= L.tape_horizon) return;
+  fo_stage_body(L, e, L.perm[g]);
+}
+
+// the record, the stage's colour and the event from the host (a lattice
+// stepped one event at a time from the host, within its tape)
+__global__ void __launch_bounds__(kStageThreads) k_fo_stage_direct(const LatDev L, uint32_t cg,
+                                                                   uint64_t e) {
+  fo_stage_body(L, e, cg);
 }
 
 // The first-order newborns left to it (more than k_begin ranks in LDS, or
@@ -774,17 +822,18 @@ __global__ void __launch_bounds__(kStageThreads) k_decide(const LatDev *__restri
   const uint32_t ncand = L.n_fo ? min(L.cand_count[buf], (uint32_t)L.cand_cap) : 0u;
   for (uint32_t base = blockIdx.x * blockDim.x; base < ncand; base += gridDim.x * blockDim.x) {
     const uint32_t q = base + threadIdx.x;
-    uint32_t c = 0, pos = 0, id = 0;
+    uint32_t c = 0, pos = 0, id = 0, v = 0;
     int rx = -1;
     if (q < ncand) {
       c = L.cand_col[buf][q];
       pos = L.cand_pos[buf][q];
       id = L.cand_id[buf][q];
-      rx = first_order_decision(L, s_fo, e, in, c, pos, id);
+      rx = first_order_decision(L, s_fo, e, in, c, pos, id, v);
     }
     const uint32_t slot = wg_reserve(L.fire_count, rx >= 0 ? 1u : 0u, s_slots);
     if (rx >= 0 && slot < L.cap) {
       L.fire_pos[slot] = pos;
+      L.fire_vox[slot] = v;
       L.fire_id[slot] = id;
       L.fire_col[slot] = (uint8_t)c;
       L.fire_rx[slot] = (uint8_t)rx;
@@ -1059,13 +1108,17 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t s) {
 constexpr int kRankGrid = 256;
 
 hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t s,
-                        bool desc) {
+                        bool desc, const LatDev *Lh, const uint32_t *perm, uint64_t e) {
   if (b.decide > 0) hipLaunchKernelGGL(k_decide, dim3(b.decide), dim3(kStageThreads), 0, s, dL);
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, b.decide > 0 ? 1 : 0,
                      b.births > 0 ? 1 : 0, b.apply > 0 ? 1 : 0, desc ? 1 : 0);
   if (b.apply > 0)
-    for (uint32_t g = 0; g < stages; ++g)
-      hipLaunchKernelGGL(k_fo_stage, dim3(b.apply), dim3(kStageThreads), 0, s, dL, g);
+    for (uint32_t g = 0; g < stages; ++g) {
+      if (Lh)
+        hipLaunchKernelGGL(k_fo_stage_direct, dim3(b.apply), dim3(kStageThreads), 0, s, *Lh,
+                           perm[g], e);
+      else hipLaunchKernelGGL(k_fo_stage, dim3(b.apply), dim3(kStageThreads), 0, s, dL, g);
+    }
   if (b.births > 0 || b.apply > 0) {
     const int grid = b.births > 0 ? b.births : 1;
     const int rank_grid = std::min(grid, kRankGrid);
@@ -1126,7 +1179,7 @@ hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, ui
   stage_order_of(L.key0, L.key1, e, stages, perm);
   // the direct stage kernels take their colour and count without the
   // descriptors; larger chunks take the descriptor form
-  hipError_t err = launch_begin(dL, b, stages, s, items > 4);
+  hipError_t err = launch_begin(dL, b, stages, s, items > 4, &L, perm, e);
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
     err = items <= 4 ? launch_stage_direct(L, perm[g], e, due, cmax_next, grid, items, disp, fcc, s)
                      : launch_stage(dL, g, grid, items, disp, fcc, s);

@@ -128,6 +128,7 @@ static void check_record(const LatDev *L) {
   x += (uint32_t)L->tape_due[L->tape_horizon - 1];
   x += L->tape_cmax[L->tape_horizon - 1];
   x += L->recent[kRecentN - 1];
+  x += L->fire_vox[L->cap - 1];
   x += L->stage_tab[L->stage_tab_words - 1];
   if (L->n_fo) x += L->tape_thr[L->tape_horizon * L->n_fo - 1];
   (void)x;
@@ -139,7 +140,13 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t) {
   check_record(dL);
   return hipSuccess;
 }
-hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t, bool) {
+hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t, bool,
+                        const LatDev *Lh, const uint32_t *perm, uint64_t e) {
+  if (Lh && std::memcmp(dL, Lh, sizeof(LatDev)) != 0) bad("stale host record at begin");
+  if (Lh && (!perm || e >= Lh->tape_horizon)) bad("first-order stage arguments");
+  if (perm)
+    for (uint32_t g = 0; g < stages; ++g)
+      if (perm[g] >= (uint32_t)kMaxColours) bad("stage order");
   ++g_launches;
   if (b.decide < 0 || b.decide > 1024) bad("decide grid");
   if (b.births < 0 || b.births > 2048) bad("births grid");
@@ -191,7 +198,7 @@ hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, ui
   if (std::memcmp(dL, &L, sizeof(LatDev)) != 0) bad("stale host record");
   uint32_t perm[kMaxColours];
   stage_order_of(L.key0, L.key1, e, kMaxColours, perm);
-  launch_begin(dL, b, kMaxColours, s, items > 4);
+  launch_begin(dL, b, kMaxColours, s, items > 4, &L, perm, e);
   for (uint32_t g = 0; g < (uint32_t)kMaxColours; ++g) {
     if (items <= 4) launch_stage_direct(L, perm[g], e, due, cmax_next, grid, items, disp, fcc, s);
     else launch_stage(dL, g, grid, items, disp, fcc, s);

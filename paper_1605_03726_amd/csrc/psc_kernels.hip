@@ -55,6 +55,8 @@ __global__ void __launch_bounds__(kStageThreads) k_scan_candidates(const LatDev 
 // k_begin: stage order, first-order pass, newborn ids
 // =============================================================================
 constexpr uint32_t kSortLds = 2048;  // newborn keys ranked in LDS up to this count
+// fire lists up to this long test overlaps voxel by voxel in LDS
+constexpr uint32_t kFewFirings = 8;
 
 __device__ __forceinline__ void bitonic_sort_keys(uint64_t *keys, uint32_t n2, int tid, int nthreads) {
   for (uint32_t k = 2; k <= n2; k <<= 1) {
@@ -521,10 +523,43 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
   // neighbourhood N[v] (its voxel and the 12 neighbours).  Molecules whose
   // N[v] meets no other firing molecule's commute with everything and are
   // applied at once; the others (rare) are applied stage by stage in the
-  // event's order.  Overlaps are found by counting, per hashed voxel, the
+  // event's order.  A few firings compare their neighbourhoods voxel by
+  // voxel in LDS; more are tested by counting, per hashed voxel, the
   // neighbourhoods that contain it (a hash collision only sends a molecule
   // to the staged path, which is always correct). ----
-  if (nfire > 0 && nfire <= blockDim.x) {
+  __shared__ uint32_t s_nbv[kFewFirings][13];
+  if (nfire > 0 && nfire <= kFewFirings) {
+    const bool mine = (uint32_t)tid < nfire;
+    uint32_t c = 0, pos = 0, id = 0, rx = 0, v = 0;
+    if (mine) {
+      c = fire_col[tid];
+      pos = fire_pos[tid];
+      id = fire_id[tid];
+      rx = fire_rx[tid];
+      v = L.fire_vox[tid];
+      const Coord cv = coord_of(L.geo, v);
+      s_nbv[tid][0] = v;
+#pragma unroll
+      for (uint32_t n = 0; n < 12; ++n) s_nbv[tid][n + 1] = index_of(L.geo, step_coord(L.geo, cv, n));
+    }
+    __syncthreads();
+    bool overlap = false;
+    if (mine)
+      for (uint32_t j = 0; j < nfire && !overlap; ++j) {
+        if (j == (uint32_t)tid) continue;
+        for (int a = 0; a < 13 && !overlap; ++a)
+          for (int b = 0; b < 13; ++b) overlap |= s_nbv[tid][a] == s_nbv[j][b];
+      }
+    if (mine && !overlap) apply_first_order(L, e, in, c, pos, id, rx, v, &s_nb, T);
+    if (mine && overlap) atomicAdd(&s_colcnt[c], 1u);
+    __syncthreads();
+    for (uint32_t g = 0; g < ncol; ++g) {
+      const uint32_t cg = s_perm[g];
+      if (s_colcnt[cg] == 0) continue;
+      if (mine && overlap && c == cg) apply_first_order(L, e, in, c, pos, id, rx, v, &s_nb, T);
+      __syncthreads();
+    }
+  } else if (nfire > 0 && nfire <= blockDim.x) {
     // one firing per thread: its colour, position, draw owner, reaction and
     // the 13 hashed voxels of its neighbourhood stay in registers through
     // the count, the test, the application and the cleanup

@@ -534,7 +534,14 @@ hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, ui
 hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t due,
                                uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
                                hipStream_t s);
-// stages: the most stages of any member (16)
+// device bytes of an ensemble's member records: n records, then room for
+// each stage's chunk prefix over the members (launch_event_multi writes it
+// after R <= n records)
+inline size_t member_records_bytes(uint32_t n) {
+  return (size_t)n * sizeof(LatDev) + (size_t)kMaxColours * (n + 1) * sizeof(uint32_t);
+}
+// stages: the most stages of any member (16); lats: member_records_bytes(R)
+// bytes or more
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, bool births, hipStream_t s);
 // desc: write the stage descriptors that the descriptor-form stage kernels
@@ -557,6 +564,10 @@ hipError_t launch_stage_direct_lat(const LatDev &L, uint32_t c, uint64_t e, uint
                                    hipStream_t s);
 hipError_t launch_stage_multi(const LatDev *lats, uint32_t R, uint32_t g, int grid, int items,
                               hipStream_t s);
+// each stage's chunk prefix over the members, for the batched stage launches
+// of the same chunk size
+hipError_t launch_multi_prefix(const LatDev *lats, uint32_t R, uint32_t stages, int items,
+                               hipStream_t s);
 uint32_t max_members();
 hipError_t launch_msd(const LatDev *dL, unsigned long long *out, hipStream_t s);
 // occupancy between the linear (ABI) order and the lattice's layout

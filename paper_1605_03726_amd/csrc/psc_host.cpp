@@ -1597,7 +1597,7 @@ psc_status psc_ensemble_create(psc_lattice *const *members, uint32_t n, psc_ense
     }
   }
   if (hipSetDevice(E->device) != hipSuccess ||
-      hipMalloc(&E->d_lats, (size_t)n * sizeof(LatDev)) != hipSuccess) {
+      hipMalloc(&E->d_lats, member_records_bytes(n)) != hipSuccess) {
     g_create_error = "device allocation of the member records failed";
     delete E;
     return PSC_ENOMEM;

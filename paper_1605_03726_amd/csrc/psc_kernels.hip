@@ -1227,6 +1227,7 @@ hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, i
   if (R == 0 || R > max_members() || stages > (uint32_t)kMaxColours) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_begin_multi, dim3(R), dim3(kBeginThreads), 0, s, lats);
   hipError_t err = hipGetLastError();
+  if (err == hipSuccess) err = launch_multi_prefix(lats, R, stages, items, s);
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
     err = launch_stage_multi(lats, R, g, grid, items, s);
   if (err != hipSuccess) return err;

@@ -220,7 +220,7 @@ void worker_main(psc_server *S) {
         if (E.d_lats) (void)hipFree(E.d_lats);
         E.d_lats = nullptr;
         S->ens_capacity = std::max<uint64_t>(E.members.size(), 2 * S->ens_capacity);
-        if (hipMalloc(&E.d_lats, S->ens_capacity * sizeof(LatDev)) != hipSuccess) {
+        if (hipMalloc(&E.d_lats, member_records_bytes((uint32_t)S->ens_capacity)) != hipSuccess) {
           S->err = "device allocation of the member records failed";
           for (Job *j : S->active) {
             release_lattice(S, j);

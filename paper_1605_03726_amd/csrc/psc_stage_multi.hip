@@ -4,9 +4,42 @@
 namespace psc {
 
 // Stage g of every member lattice of an ensemble in one launch: the chunks of
-// all members' stage bins form one work list (prefix over members, built in
-// LDS by every workgroup), so lattices of any size share the GPU evenly.
+// all members' stage bins form one work list, so lattices of any size share
+// the GPU evenly.  The list's prefix over members (chunks before member r,
+// R + 1 entries per stage) is computed once per event by k_multi_prefix,
+// after the member records.
 constexpr uint32_t kMaxMembers = 4096;
+
+__device__ __forceinline__ uint32_t *chunk_prefix(const LatDev *lats, uint32_t R, uint32_t g) {
+  return (uint32_t *)(lats + R) + (size_t)g * (R + 1);
+}
+
+// one workgroup per stage: chunks per member (contiguous slices of members
+// per thread), then an exclusive scan over the slices
+__global__ void __launch_bounds__(kStageThreads) k_multi_prefix(const LatDev *__restrict__ lats,
+                                                                uint32_t R, uint32_t chunk) {
+  __shared__ uint32_t s_part[kStageThreads];
+  const uint32_t g = blockIdx.x, tid = threadIdx.x;
+  uint32_t *pre = chunk_prefix(lats, R, g);
+  const uint32_t per = (R + kStageThreads - 1) / kStageThreads;
+  const uint32_t lo = min(tid * per, R), hi = min(lo + per, R);
+  uint32_t run = 0;
+  for (uint32_t r = lo; r < hi; ++r) run += (lats[r].sdesc[g].y + chunk - 1) / chunk;
+  s_part[tid] = run;
+  __syncthreads();
+  for (uint32_t d = 1; d < kStageThreads; d <<= 1) {
+    const uint32_t add = tid >= d ? s_part[tid - d] : 0u;
+    __syncthreads();
+    s_part[tid] += add;
+    __syncthreads();
+  }
+  uint32_t acc = s_part[tid] - run;
+  for (uint32_t r = lo; r < hi; ++r) {
+    pre[r] = acc;
+    acc += (lats[r].sdesc[g].y + chunk - 1) / chunk;
+  }
+  if (tid == kStageThreads - 1) pre[R] = s_part[tid];
+}
 
 template <int ITEMS>
 __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__restrict__ lats,
@@ -14,33 +47,11 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
   __shared__ StageShared S;
   __shared__ StageStaging<ITEMS> T;
   __shared__ uint32_t s_pre[kMaxMembers + 1];
-  __shared__ uint32_t s_part[kStageThreads];
   __shared__ uint32_t s_tab[kStageTabWordsMax];  // the tables of the chunk's member
   const int tid = threadIdx.x;
   const uint64_t chunk = (uint64_t)kStageThreads * ITEMS;
-  // chunks per member (contiguous slices of members per thread), then an
-  // exclusive scan over the slices
-  const uint32_t per = (R + kStageThreads - 1) / kStageThreads;
-  const uint32_t lo = min((uint32_t)tid * per, R), hi = min(lo + per, R);
-  uint32_t run = 0;
-  for (uint32_t r = lo; r < hi; ++r) {
-    const uint32_t n = lats[r].sdesc[g].y;
-    s_pre[r] = run;
-    run += (uint32_t)((n + chunk - 1) / chunk);
-  }
-  s_part[tid] = run;
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t acc = 0;
-    for (int t = 0; t < kStageThreads; ++t) {
-      const uint32_t x = s_part[t];
-      s_part[t] = acc;
-      acc += x;
-    }
-    s_pre[R] = acc;
-  }
-  __syncthreads();
-  for (uint32_t r = lo; r < hi; ++r) s_pre[r] += s_part[tid];
+  const uint32_t *pre = chunk_prefix(lats, R, g);
+  for (uint32_t r = tid; r <= R; r += kStageThreads) s_pre[r] = pre[r];
   __syncthreads();
   const uint32_t total = s_pre[R];
   uint32_t tab_member = ~0u;  // whose tables s_tab holds
@@ -64,6 +75,14 @@ __global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__r
     if (L.geo.fcc) stage_chunk<ITEMS, 2, 1>(L, e, d.x, base, d.y, due, cmax_next, tab, fill, S, T);
     else stage_chunk<ITEMS, 2, 0>(L, e, d.x, base, d.y, due, cmax_next, tab, fill, S, T);
   }
+}
+
+hipError_t launch_multi_prefix(const LatDev *lats, uint32_t R, uint32_t stages, int items,
+                               hipStream_t s) {
+  const int it = items == 1 || items == 2 || items == 8 ? items : 4;  // as launch_stage_multi
+  hipLaunchKernelGGL(k_multi_prefix, dim3(stages), dim3(kStageThreads), 0, s, lats, R,
+                     (uint32_t)(kStageThreads * it));
+  return hipGetLastError();
 }
 
 hipError_t launch_stage_multi(const LatDev *lats, uint32_t R, uint32_t g, int grid, int items,

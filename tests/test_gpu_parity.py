@@ -180,7 +180,7 @@ def test_many_products_and_placement_failures():
 
 
 @pytest.mark.timeout(1200)
-def test_mapk_full_size_prefix():
+def test_mapk_full_size_prefix(capsys):
     # the 2^32-voxel workload at full size (8 GiB occupancy, 12.9 M molecules)
     # in the benchmark's launch shape, against the oracle after 6 events (the
     # partner marks and flags carried across event parities) and after 60
@@ -195,7 +195,8 @@ def test_mapk_full_size_prefix():
         while done < events:   # a few seconds per oracle event: report progress
             o.run(6, oracle.MODE_C)
             done += 6
-            print("oracle at event %d" % done, flush=True)
+            with capsys.disabled():  # shown even when output is captured
+                print("oracle at event %d" % done, flush=True)
         s = o.state()
         assert_same(g, s, disp=False)
         del g, s

@@ -515,7 +515,7 @@ struct BeginShape {
 // fire-list entries an application workgroup scans per pass
 constexpr uint32_t kFoTile = 2048;
 // the last event's counts (LatDev::recent)
-enum { kRecentFire = 0, kRecentFoBirths = 1, kRecentColBirths = 2, kRecentN = 3 };
+enum { kRecentFire = 0, kRecentFoBirths = 1, kRecentColBirths = 2, kRecentFlags = 3, kRecentN = 4 };
 // most buckets of the grid-wide newborn ranking (their counts fit in LDS)
 constexpr uint32_t kRankBucketsMax = 8192;
 // births: the lattice (any member) has collision reactions with more than
@@ -527,10 +527,15 @@ hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool f
 // event, the species due in it (tape_due[e]) and the next event's largest
 // first-order threshold (0 when none or past the tape) as arguments
 // (k_stage_direct)
+// open_with_end: the previous event's end was left to this launch, which runs
+// it with this event's opening in one kernel (k_end_begin; only without
+// collision births and for an opening with no launches of its own, else
+// hipErrorInvalidValue); close: launch this event's end (else the next
+// event's opening runs it)
 hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, uint64_t due,
                                uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
                                const BeginShape &b, bool births, bool births_defer,
-                               hipStream_t s);
+                               hipStream_t s, bool open_with_end = false, bool close = true);
 hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t due,
                                uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
                                hipStream_t s);

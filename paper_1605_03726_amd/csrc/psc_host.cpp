@@ -1067,10 +1067,31 @@ psc_status psc_step(psc_lattice *h, uint64_t n_events, void *stream_) {
       else HIP_OK(h, hipGraphLaunch(h->exec, stream));
     }
   } else if (!h->timing) {
-    for (uint64_t e = 0; e < n_events; ++e)
+    // An event's end is left to the next event's opening (one kernel for
+    // both) when neither needs launches of its own: no collision newborns to
+    // number, and a next opening that k_begin does alone.  One workgroup
+    // then sweeps the end's lists of reacted partners, each entry a scattered
+    // read and write of the lattice, so only while the last event's list was
+    // short, or of moderate length on a lattice small enough (2^27 voxels,
+    // 256 MB of words) that those accesses stay in the caches.  On the 2^32
+    // MAPK lattice (~8,000 partners per event) the end is faster over many
+    // workgroups; on a crowded 256^3 lattice (up to 11,000) the single
+    // launch wins.  The last event of the call always ends in its own launch.
+    auto plain = [](const BeginShape &b) { return b.decide == 0 && b.births == 0 && b.apply == 0; };
+    const uint32_t partners = h->recent[kRecentFlags];
+    const bool fuse = h->recent_valid && (partners <= 1024 ||
+                                          (h->nv <= (1ull << 27) && partners <= 16384));
+    bool open_with_end = false;
+    BeginShape b = shape(e0);
+    for (uint64_t e = 0; e < n_events; ++e) {
+      const BeginShape next = e + 1 < n_events ? shape(e0 + e + 1) : BeginShape{};
+      const bool leave_end = fuse && !births && e + 1 < n_events && plain(next);
       HIP_OK(h, launch_event_direct(h->dL, h->L, e0 + e, due_of(e0 + e), cmax_after(e0 + e),
-                                    h->grid, h->items, disp, h->geo.fcc != 0, shape(e0 + e),
-                                    births, births_defer, stream));
+                                    h->grid, h->items, disp, h->geo.fcc != 0, b, births,
+                                    births_defer, stream, open_with_end, !leave_end));
+      open_with_end = leave_end;
+      b = next;
+    }
   } else {
     auto ev = [&](hipEvent_t *out) -> hipError_t {
       if (!h->event_pool.empty()) {

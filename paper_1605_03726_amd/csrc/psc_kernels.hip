@@ -986,7 +986,8 @@ __device__ __forceinline__ void number_births(const LatDev &L, uint64_t e) {
 // (the numbering's registers and LDS would otherwise limit every end kernel)
 // defer: newborns beyond what one workgroup ranks in LDS are left to
 // k_end_births, which follows
-template <bool BIRTHS>
+// SB: list entries a thread sweeps at a time (more for fewer threads)
+template <bool BIRTHS, int SB = 1>
 __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t nblk,
                                          bool defer) {
   const uint64_t e = *L.ev;
@@ -996,15 +997,44 @@ __device__ __forceinline__ void end_body(const LatDev &L, uint32_t bid, uint32_t
   const uint32_t me = bid * blockDim.x + threadIdx.x;
   // this walk's partners may walk again from the next event on
   const uint32_t nf = min(L.flag_count[cur], (uint32_t)L.flag_cap);
-  for (uint32_t q = me; q < nf; q += stride) {
-    const uint32_t v = L.flag_vox[cur][q];
-    L.occ[v] = (uint16_t)(L.occ[v] & kWordMask);
+  if (bid == 0 && threadIdx.x == 0) L.recent[kRecentFlags] = nf;
+  // Both sweeps take SB entries per thread at a time, each step's loads
+  // issued for all of them before the next step uses any, so that one
+  // workgroup sweeps long lists with the loads overlapped.  A slot past the
+  // list repeats entry q0 and stores nothing.  A voxel listed twice (a
+  // product that reacted again as a partner) gets the same word from every
+  // thread that clears it.
+  constexpr int kSweepBatch = SB;
+  const uint64_t step = (uint64_t)kSweepBatch * stride;
+  for (uint64_t q0 = me; q0 < nf; q0 += step) {
+    uint32_t v[kSweepBatch];
+    uint16_t w[kSweepBatch];
+#pragma unroll
+    for (int b = 0; b < kSweepBatch; ++b) {
+      const uint64_t q = q0 + (uint64_t)b * stride;
+      v[b] = L.flag_vox[cur][q < nf ? q : q0];
+    }
+#pragma unroll
+    for (int b = 0; b < kSweepBatch; ++b) w[b] = L.occ[v[b]];
+#pragma unroll
+    for (int b = 0; b < kSweepBatch; ++b)
+      if (q0 + (uint64_t)b * stride < nf) L.occ[v[b]] = (uint16_t)(w[b] & kWordMask);
   }
   // the previous walk's hot marks have served both of their events
   const uint32_t np = min(L.flag_count[prv], (uint32_t)L.flag_cap);
-  for (uint32_t q = me; q < np; q += stride) {
-    const uint32_t h = hot_hash(L.flag_vox[prv][q], L.hot_bits);
-    atomicAnd(&L.hot[h >> 4], ~(1u << (((h & 15u) << 1) | prv)));
+  for (uint64_t q0 = me; q0 < np; q0 += step) {
+    uint32_t v[kSweepBatch];
+#pragma unroll
+    for (int b = 0; b < kSweepBatch; ++b) {
+      const uint64_t q = q0 + (uint64_t)b * stride;
+      v[b] = L.flag_vox[prv][q < np ? q : q0];
+    }
+#pragma unroll
+    for (int b = 0; b < kSweepBatch; ++b) {
+      if (q0 + (uint64_t)b * stride >= np) continue;
+      const uint32_t h = hot_hash(v[b], L.hot_bits);
+      atomicAnd(&L.hot[h >> 4], ~(1u << (((h & 15u) << 1) | prv)));
+    }
   }
   // No release fence before counting in (on this part it writes back the
   // L2 of the workgroup's XCD, and a batched launch has thousands of
@@ -1043,6 +1073,21 @@ __global__ void __launch_bounds__(kEndThreads) k_end(const LatDev *__restrict__ 
 template <bool BIRTHS>
 __global__ void __launch_bounds__(kEndThreads) k_end_multi(const LatDev *__restrict__ lats) {
   end_body<BIRTHS>(lats[blockIdx.y], blockIdx.x, gridDim.x, false);
+}
+
+// The end of the previous event and the opening of the next in one
+// workgroup, one launch instead of two, for a lattice without collision
+// newborns to number and an opening that k_begin does alone (no decision,
+// application or ranking launches): the end's sweeps take the whole
+// workgroup, and the barrier between the two parts orders its stores (the
+// cleared flags, the advanced event counter) before the opening's loads,
+// every wave of the workgroup running on one compute unit.
+// desc: as k_begin
+__global__ void __launch_bounds__(kBeginThreads) k_end_begin(const LatDev *__restrict__ Lp,
+                                                             int desc) {
+  end_body<false, 4>(*Lp, 0, 1, false);
+  __syncthreads();
+  begin_body(*Lp, false, false, false, desc != 0);
 }
 
 // The collision newborns k_end left (more than one workgroup ranks in LDS):
@@ -1208,17 +1253,25 @@ hipError_t launch_event(const LatDev *dL, int grid, int items, bool disp, bool f
 hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, uint64_t due,
                                uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
                                const BeginShape &b, bool births, bool births_defer,
-                               hipStream_t s) {
+                               hipStream_t s, bool open_with_end, bool close) {
   const uint32_t stages = fcc ? kColoursFcc : kColoursHcp;
+  const bool plain = b.decide == 0 && b.births == 0 && b.apply == 0;
+  if (open_with_end && (births || !plain)) return hipErrorInvalidValue;
   uint32_t perm[kMaxColours];
   stage_order_of(L.key0, L.key1, e, stages, perm);
   // the direct stage kernels take their colour and count without the
   // descriptors; larger chunks take the descriptor form
-  hipError_t err = launch_begin(dL, b, stages, s, items > 4, &L, perm, e);
+  hipError_t err;
+  if (open_with_end) {
+    hipLaunchKernelGGL(k_end_begin, dim3(1), dim3(kBeginThreads), 0, s, dL, items > 4 ? 1 : 0);
+    err = hipGetLastError();
+  } else {
+    err = launch_begin(dL, b, stages, s, items > 4, &L, perm, e);
+  }
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)
     err = items <= 4 ? launch_stage_direct(L, perm[g], e, due, cmax_next, grid, items, disp, fcc, s)
                      : launch_stage(dL, g, grid, items, disp, fcc, s);
-  if (err == hipSuccess) err = launch_end(dL, births, s, births_defer);
+  if (err == hipSuccess && close) err = launch_end(dL, births, s, births_defer);
   return err;
 }
 

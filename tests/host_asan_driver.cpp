@@ -13,6 +13,7 @@
 #include "psc.h"
 
 extern "C" int stub_launch_errors();
+extern "C" int stub_open_ends();
 extern "C" unsigned long long stub_launches();
 
 #define OK(call)                                                         \
@@ -277,6 +278,7 @@ int main() {
     psc_server_destroy(S);
   }
   for (psc_lattice *x : lats) psc_destroy(x);
-  printf("launches %llu, launch check failures %d\n", stub_launches(), stub_launch_errors());
-  return stub_launch_errors() ? 1 : 0;
+  printf("launches %llu, launch check failures %d, event ends left open %d\n", stub_launches(),
+         stub_launch_errors(), stub_open_ends());
+  return stub_launch_errors() || stub_open_ends() ? 1 : 0;
 }

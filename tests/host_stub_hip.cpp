@@ -8,6 +8,8 @@
 #include <hip/hip_runtime_api.h>
 
 #include <atomic>
+#include <mutex>
+#include <set>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -17,6 +19,10 @@
 // the serving loop launches from two threads
 static std::atomic<int> g_launch_errors{0};
 static std::atomic<unsigned long long> g_launches{0};
+// lattices whose last directly launched event left its end to the next
+// event's opening
+static std::mutex g_open_mu;
+static std::set<const psc::LatDev *> g_open_ends;
 
 static void bad(const char *what) {
   fprintf(stderr, "launch check failed: %s\n", what);
@@ -26,6 +32,8 @@ static void bad(const char *what) {
 extern "C" {
 
 int stub_launch_errors() { return g_launch_errors.load(); }
+// lattices whose event end is still left open (every step must close its last event)
+int stub_open_ends();
 unsigned long long stub_launches() { return g_launches.load(); }
 
 hipError_t hipMalloc(void **p, size_t n) {
@@ -142,6 +150,10 @@ hipError_t launch_scan(const LatDev *dL, int grid, hipStream_t) {
 }
 hipError_t launch_begin(const LatDev *dL, const BeginShape &b, uint32_t stages, hipStream_t, bool,
                         const LatDev *Lh, const uint32_t *perm, uint64_t e) {
+  {
+    std::lock_guard<std::mutex> g(g_open_mu);
+    if (g_open_ends.count(dL)) bad("an opening launched while the last event's end is left open");
+  }
   if (Lh && std::memcmp(dL, Lh, sizeof(LatDev)) != 0) bad("stale host record at begin");
   if (Lh && (!perm || e >= Lh->tape_horizon)) bad("first-order stage arguments");
   if (perm)
@@ -190,20 +202,35 @@ hipError_t launch_stage_direct(const LatDev &L, uint32_t c, uint64_t e, uint64_t
   check_record(&L);
   return hipSuccess;
 }
+static bool take_open_end(const LatDev *dL) {
+  std::lock_guard<std::mutex> g(g_open_mu);
+  return g_open_ends.erase(dL) != 0;
+}
 hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, uint64_t due,
                                uint32_t cmax_next, int grid, int items, bool disp, bool fcc,
                                const BeginShape &b, bool births, bool births_defer,
-                               hipStream_t s) {
+                               hipStream_t s, bool open_with_end, bool close) {
   // the record handed to the stages by value must be the one on the device
   if (std::memcmp(dL, &L, sizeof(LatDev)) != 0) bad("stale host record");
+  // an end left open is picked up by the very next event, and only then
+  if (take_open_end(dL) != open_with_end) bad("event end left open or picked up out of turn");
   uint32_t perm[kMaxColours];
   stage_order_of(L.key0, L.key1, e, kMaxColours, perm);
-  launch_begin(dL, b, kMaxColours, s, items > 4, &L, perm, e);
+  if (open_with_end) {
+    if (births || b.decide || b.births || b.apply) bad("fused end and opening with launches of their own");
+    ++g_launches;
+    check_record(dL);
+  } else {
+    launch_begin(dL, b, kMaxColours, s, items > 4, &L, perm, e);
+  }
   for (uint32_t g = 0; g < (uint32_t)kMaxColours; ++g) {
     if (items <= 4) launch_stage_direct(L, perm[g], e, due, cmax_next, grid, items, disp, fcc, s);
     else launch_stage(dL, g, grid, items, disp, fcc, s);
   }
-  return launch_end(dL, births, s, births_defer);
+  if (close) return launch_end(dL, births, s, births_defer);
+  std::lock_guard<std::mutex> g(g_open_mu);
+  g_open_ends.insert(dL);
+  return hipSuccess;
 }
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, bool births, hipStream_t) {
@@ -240,3 +267,8 @@ int stage_items() { return 4; }
 int stage_threads() { return 256; }
 
 }  // namespace psc
+
+extern "C" int stub_open_ends() {
+  std::lock_guard<std::mutex> g(g_open_mu);
+  return (int)g_open_ends.size();
+}

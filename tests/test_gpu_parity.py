@@ -81,6 +81,35 @@ def test_small_reactive_shapes(dims):
     run_pair(w, 30)
 
 
+@pytest.mark.parametrize("name,kw,events", [("small_reactive", dict(seed=7), 60),
+                                            ("small_reactive", dict(dims=(20, 4, 8), seed=12), 60),
+                                            ("cfg1", dict(), 150)])
+def test_event_end_fused_with_next_opening(name, kw, events):
+    """A step of many events, once the last event reported few reacted
+    partners, runs each event's end in one kernel with the next event's
+    opening; a step of one event always ends in its own launch.  Both leave
+    the oracle's state."""
+    w = workload(name, **kw)
+    single = build_gpu(w)
+    for _ in range(events):
+        single.step(1)
+    a = single.read_state()
+    fused = build_gpu(w)
+    fused.step(1)
+    fused.sync()  # the event's counts are on the host before the next step starts
+    fused.step(events - 1)
+    b = fused.read_state()
+    o = build_oracle(w)
+    o.run(events, oracle.MODE_C)
+    s = o.state()
+    disp = w.get("track_displacement", False)
+    assert_same(a, s, disp=disp)
+    assert_same(b, s, disp=disp)
+    assert s["hops"] > 0
+    if name == "small_reactive":
+        assert np.all(s["fired"] > 0), s["fired"]
+
+
 def test_diffusion_64cubed_full_run():
     w = workload("cfg1")
     g, s = run_pair(w, w["events"], chunks=4)

@@ -81,15 +81,26 @@ def test_small_reactive_shapes(dims):
     run_pair(w, 30)
 
 
-@pytest.mark.parametrize("name,kw,events", [("small_reactive", dict(seed=7), 60),
-                                            ("small_reactive", dict(dims=(20, 4, 8), seed=12), 60),
-                                            ("cfg1", dict(), 150)])
-def test_event_end_fused_with_next_opening(name, kw, events):
+def fused_case(case):
+    if case == "reactive":
+        return workload("small_reactive", seed=7), 60
+    if case == "reactive_ragged":
+        return workload("small_reactive", dims=(20, 4, 8), seed=12), 60
+    if case == "reactive_walls":
+        return dict(workload("small_reactive", seed=8), boundary="walls"), 60
+    if case == "reactive_fcc":
+        return dict(workload("small_reactive", seed=9, dims=(16, 16, 12)), lattice="fcc"), 60
+    return workload("cfg1"), 150
+
+
+@pytest.mark.parametrize("case", ["reactive", "reactive_ragged", "reactive_walls", "reactive_fcc",
+                                  "diffusion"])
+def test_event_end_fused_with_next_opening(case):
     """A step of many events, once the last event reported few reacted
     partners, runs each event's end in one kernel with the next event's
     opening; a step of one event always ends in its own launch.  Both leave
     the oracle's state."""
-    w = workload(name, **kw)
+    w, events = fused_case(case)
     single = build_gpu(w)
     for _ in range(events):
         single.step(1)
@@ -106,7 +117,7 @@ def test_event_end_fused_with_next_opening(name, kw, events):
     assert_same(a, s, disp=disp)
     assert_same(b, s, disp=disp)
     assert s["hops"] > 0
-    if name == "small_reactive":
+    if case != "diffusion":
         assert np.all(s["fired"] > 0), s["fired"]
 
 

@@ -463,6 +463,8 @@ __device__ __forceinline__ void decide_first_order(const LatDev &L, const FoTab 
 // apply: k_fo_stage launches, one per stage, and k_births follow; more
 // firings than this workgroup has threads are left to them (this pass then
 // ends after the decisions), fewer are applied here as without them
+// NT: the workgroup's threads
+template <int NT = kBeginThreads>
 __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool defer, bool apply,
                                            uint32_t *deferred, FirstOrderTally *T) {
   uint32_t *__restrict__ fire_pos = L.fire_pos;
@@ -649,8 +651,8 @@ __device__ __forceinline__ void begin_work(const LatDev &L, bool decided, bool d
   if (nb <= kSortLds) {
     for (uint32_t q = tid; q < nb; q += blockDim.x) s_keys[q] = L.birth_key[q];
     __syncthreads();
-    for_each_ranked<kSortLds / kBeginThreads>(
-        s_keys, nb, tid, kBeginThreads,
+    for_each_ranked<kSortLds / NT>(
+        s_keys, nb, tid, NT,
         [&](bool valid, uint64_t k, uint32_t r) { bin_birth(valid, k, base_id + r); });
   } else {
     uint32_t n2 = 1;
@@ -683,7 +685,9 @@ __device__ __forceinline__ void write_stage_descriptors(const LatDev &L, uint32_
   }
 }
 
-// desc: write the stage descriptors (for stage launches that read them)
+// desc: write the stage descriptors (for stage launches that read them);
+// NT: the workgroup's threads
+template <int NT = kBeginThreads>
 __device__ __forceinline__ void begin_body(const LatDev &L, bool decided, bool defer, bool apply,
                                           bool desc = true) {
   __shared__ uint32_t s_deferred;
@@ -696,7 +700,7 @@ __device__ __forceinline__ void begin_body(const LatDev &L, bool decided, bool d
   if (tid < 64) T.dsp[tid] = 0;
   if (tid < (uint32_t)kMaxReactions) T.fired[tid] = 0;
   __syncthreads();
-  begin_work(L, decided, defer, apply, &s_deferred, &T);
+  begin_work<NT>(L, decided, defer, apply, &s_deferred, &T);
   __syncthreads();  // every return of begin_work is taken by the whole block
   if (tid < 64 && T.dsp[tid]) atomicAdd(&stat_sp(L)[tid], (unsigned long long)(long long)T.dsp[tid]);
   if (tid < L.n_rx && T.fired[tid]) atomicAdd(&stat_fired(L)[tid], (unsigned long long)T.fired[tid]);
@@ -714,9 +718,13 @@ __global__ void __launch_bounds__(kBeginThreads) k_begin(const LatDev *__restric
   begin_body(*Lp, decided != 0, defer != 0, apply != 0, desc != 0);
 }
 
-// one workgroup per member lattice of an ensemble
-__global__ void __launch_bounds__(kBeginThreads) k_begin_multi(const LatDev *__restrict__ lats) {
-  begin_body(lats[blockIdx.x], false, false, false);
+// one workgroup per member lattice of an ensemble.  Half of k_begin's
+// threads: a member's lists are short, and three such workgroups fit on a
+// compute unit where one of k_begin's does, so that all members of a
+// 512-member ensemble open their event at once.
+constexpr int kBeginMultiThreads = 512;
+__global__ void __launch_bounds__(kBeginMultiThreads) k_begin_multi(const LatDev *__restrict__ lats) {
+  begin_body<kBeginMultiThreads>(lats[blockIdx.x], false, false, false);
 }
 
 // Stage g of the first-order application over many workgroups (events with
@@ -1278,7 +1286,7 @@ hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, ui
 hipError_t launch_event_multi(const LatDev *lats, uint32_t R, uint32_t stages, int grid,
                               int items, bool births, hipStream_t s) {
   if (R == 0 || R > max_members() || stages > (uint32_t)kMaxColours) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_begin_multi, dim3(R), dim3(kBeginThreads), 0, s, lats);
+  hipLaunchKernelGGL(k_begin_multi, dim3(R), dim3(kBeginMultiThreads), 0, s, lats);
   hipError_t err = hipGetLastError();
   if (err == hipSuccess) err = launch_multi_prefix(lats, R, stages, items, s);
   for (uint32_t g = 0; g < stages && err == hipSuccess; ++g)

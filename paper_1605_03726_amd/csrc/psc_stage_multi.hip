@@ -41,9 +41,12 @@ __global__ void __launch_bounds__(kStageThreads) k_multi_prefix(const LatDev *__
   if (tid == kStageThreads - 1) pre[R] = s_part[tid];
 }
 
+// The one- and two-item forms ask for four waves per SIMD: the two-item
+// form then fits in 128 VGPRs (four of its workgroups per compute unit
+// instead of three).  The larger forms need more registers than that.
 template <int ITEMS>
-__global__ void __launch_bounds__(kStageThreads) k_stage_multi(const LatDev *__restrict__ lats,
-                                                               uint32_t R, uint32_t g) {
+__global__ void __launch_bounds__(kStageThreads, ITEMS <= 2 ? 4 : 1)
+    k_stage_multi(const LatDev *__restrict__ lats, uint32_t R, uint32_t g) {
   __shared__ StageShared S;
   __shared__ StageStaging<ITEMS> T;
   __shared__ uint32_t s_pre[kMaxMembers + 1];

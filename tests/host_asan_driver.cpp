@@ -14,6 +14,7 @@
 
 extern "C" int stub_launch_errors();
 extern "C" int stub_open_ends();
+extern "C" unsigned long long stub_fused_openings();
 extern "C" unsigned long long stub_launches();
 
 #define OK(call)                                                         \
@@ -25,8 +26,9 @@ extern "C" unsigned long long stub_launches();
     }                                                                    \
   } while (0)
 
+// many: with the four-product collision (its newborns numbered at the event end)
 static psc_lattice *make(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t flags, uint64_t seed,
-                         uint64_t per_species) {
+                         uint64_t per_species, bool many = true) {
   psc_lattice_desc d{};
   d.ni = ni;
   d.nj = nj;
@@ -42,10 +44,10 @@ static psc_lattice *make(uint32_t ni, uint32_t nj, uint32_t nk, uint32_t flags, 
   for (int s = 0; s < 6; ++s)
     if (psc_add_species(h, "s", D[s], &sp[s])) return nullptr;
   const uint16_t ab[2] = {1, 2}, c1[1] = {3}, cc[1] = {3}, ab2[2] = {1, 2}, a4[2] = {1, 4},
-                 many[4] = {1, 2, 6, 6}, six[1] = {6}, d6[3] = {2, 6, 6};
+                 many_p[4] = {1, 2, 6, 6}, six[1] = {6}, d6[3] = {2, 6, 6};
   if (psc_add_reaction(h, ab, 2, c1, 1, 1e-18, nullptr)) return nullptr;        // A + B -> C
   if (psc_add_reaction(h, cc, 1, ab2, 2, 200.0, nullptr)) return nullptr;       // C -> A + B
-  if (psc_add_reaction(h, a4, 2, many, 4, 1e-18, nullptr)) return nullptr;      // A + O -> 4 products
+  if (many && psc_add_reaction(h, a4, 2, many_p, 4, 1e-18, nullptr)) return nullptr;  // A + O -> 4 products
   if (psc_add_reaction(h, six, 1, nullptr, 0, 50.0, nullptr)) return nullptr;   // F -> 0
   if (psc_add_reaction(h, six, 1, d6, 3, 30.0, nullptr)) return nullptr;        // F -> B + F + F
   for (uint16_t s = 1; s <= 6; ++s)
@@ -166,6 +168,16 @@ int main() {
     if (read_all(r)) return 1;
     psc_destroy(r);
   }
+  // no collision newborns: a step after one whose counts came back runs each
+  // event's end with the next event's opening
+  {
+    psc_lattice *f = make(32, 24, 16, PSC_TRACK_DISPLACEMENT, 21, 200, false);
+    if (!f) return 1;
+    OK(psc_step(f, 2, nullptr));
+    OK(psc_step(f, 6, nullptr));
+    if (read_all(f)) return 1;
+    psc_destroy(f);
+  }
   // an ensemble of fresh lattices: graph capture, autotuning, direct steps
   {
     std::vector<psc_lattice *> mem;
@@ -278,7 +290,9 @@ int main() {
     psc_server_destroy(S);
   }
   for (psc_lattice *x : lats) psc_destroy(x);
-  printf("launches %llu, launch check failures %d, event ends left open %d\n", stub_launches(),
-         stub_launch_errors(), stub_open_ends());
-  return stub_launch_errors() || stub_open_ends() ? 1 : 0;
+  printf("launches %llu, launch check failures %d, event ends left open %d, fused openings %llu\n",
+         stub_launches(), stub_launch_errors(), stub_open_ends(), stub_fused_openings());
+  // the steps above run the fused event end and opening (a step after one
+  // whose counts came back)
+  return stub_launch_errors() || stub_open_ends() || stub_fused_openings() == 0 ? 1 : 0;
 }

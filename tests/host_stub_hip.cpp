@@ -23,6 +23,7 @@ static std::atomic<unsigned long long> g_launches{0};
 // event's opening
 static std::mutex g_open_mu;
 static std::set<const psc::LatDev *> g_open_ends;
+static std::atomic<unsigned long long> g_fused_openings{0};
 
 static void bad(const char *what) {
   fprintf(stderr, "launch check failed: %s\n", what);
@@ -218,6 +219,7 @@ hipError_t launch_event_direct(const LatDev *dL, const LatDev &L, uint64_t e, ui
   stage_order_of(L.key0, L.key1, e, kMaxColours, perm);
   if (open_with_end) {
     if (births || b.decide || b.births || b.apply) bad("fused end and opening with launches of their own");
+    ++g_fused_openings;
     ++g_launches;
     check_record(dL);
   } else {
@@ -267,6 +269,8 @@ int stage_items() { return 4; }
 int stage_threads() { return 256; }
 
 }  // namespace psc
+
+extern "C" unsigned long long stub_fused_openings() { return g_fused_openings.load(); }
 
 extern "C" int stub_open_ends() {
   std::lock_guard<std::mutex> g(g_open_mu);
